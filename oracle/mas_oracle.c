@@ -1,0 +1,419 @@
+/*
+ * FP64 CPU ORACLE for the implicit viscous solve -- TEST INFRASTRUCTURE ONLY.
+ *
+ * Only the tests, the smoke check and the benchmark's CPU-baseline leg may
+ * load this library.  It shares no code, header, table or helper with the
+ * HIP library; it is a plain, slow, obviously-correct statement of what the
+ * GPU path computes, in double precision, without blocking, fusion or
+ * reordering beyond what the definitions below state.
+ *
+ * What is computed (the paper, Section 2: Eq. (1) viscosity term
+ * (1/rho) div(nu rho grad v); Section 2.2: the viscous term is advanced
+ * implicitly with a PCG solve using the inverse-diagonal (point-Jacobi, "PC1")
+ * preconditioner, on a non-uniform logically rectangular spherical grid;
+ * Section 4.1: the matrices are symmetric with few off-diagonal entries):
+ *
+ *   backward-Euler viscous step  (I - dt div(nu grad)) x = rhs
+ *   finite-volume form           A x = b,  b = V .* rhs,
+ *       (A x)_c = V_c x_c + sum_{faces f of c} c_f (x_c - x_nb(f))
+ *       c_f     = dt * nu_f * area_f / dist_f
+ *
+ * Readings of points the paper leaves open (one scalar field with rho = 1,
+ * cell-centred unknowns, homogeneous Dirichlet radial walls imposed at the
+ * face, zero-area pole faces, arithmetic-mean face viscosity, midpoint cell
+ * centres, metric distances r dtheta and r sin(theta) dphi) are the ones the
+ * design document lists; each function below names the reading it uses.
+ *
+ * Cell index c = (i*nt + j)*np + k, i = r (slowest), j = theta, k = phi
+ * (fastest, periodic).  Face arrays:
+ *   r faces  : (nr+1)*nt*np, face i sits at r_faces[i]      (i = 0, nr are walls)
+ *   th faces : nr*(nt+1)*np, face j sits at t_faces[j]      (j = 0, nt are poles)
+ *   ph faces : nr*nt*np,     face k lies between k and k+1 (mod np)
+ *
+ * Dot products: partial sums per r plane, accumulated serially over planes,
+ * so results do not depend on the OpenMP thread count.
+ */
+#include <math.h>
+#include <stddef.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define ORA_DIRICHLET 0
+#define ORA_NEUMANN 1
+
+typedef struct {
+    int32_t nr, nt, np;
+    const double *r_faces; /* nr+1 */
+    const double *t_faces; /* nt+1 */
+    int32_t bc_inner, bc_outer;
+} ora_grid;
+
+/* Geometry and operator, all owned by the caller (Python allocates). */
+typedef struct {
+    ora_grid g;
+    double dt;
+    double *V;      /* N              cell volumes                          */
+    double *Ar, *Hr; /* (nr+1)*nt*np  r-face area, centre-to-centre distance */
+    double *At, *Ht; /* nr*(nt+1)*np  theta-face area and distance           */
+    double *Ap, *Hp; /* N             phi-face area and distance             */
+    double *cr;     /* (nr+1)*nt*np   r-face conductance (0 if Neumann wall) */
+    double *ct;     /* nr*(nt+1)*np   theta-face conductance (0 at poles)    */
+    double *cp;     /* N              phi-face conductance                    */
+    double *diag;   /* N              A_cc                                    */
+} ora_op;
+
+static inline size_t cidx(const ora_grid *g, int i, int j, int k) {
+    return ((size_t)i * g->nt + j) * g->np + k;
+}
+static inline size_t ridx(const ora_grid *g, int i, int j, int k) { /* i in 0..nr */
+    return ((size_t)i * g->nt + j) * g->np + k;
+}
+static inline size_t tidx(const ora_grid *g, int i, int j, int k) { /* j in 0..nt */
+    return ((size_t)i * (g->nt + 1) + j) * g->np + k;
+}
+static inline size_t ncell(const ora_grid *g) {
+    return (size_t)g->nr * g->nt * g->np;
+}
+
+/* ------------------------------------------------------------------ geometry
+ * Cell volume of the spherical block [r-,r+] x [t-,t+] x [dphi]:
+ *     V = (r+^3 - r-^3)/3 * (cos t- - cos t+) * dphi
+ * evaluated without cancellation as (r+ - r-)(r+^2 + r+ r- + r-^2)/3 and
+ * 2 sin((t+ + t-)/2) sin((t+ - t-)/2).
+ * Cell centres are face midpoints.  Face areas are the exact areas of the
+ * spherical patches; distances are metric centre-to-centre lengths:
+ *     r face at r_f      area r_f^2 (cos t- - cos t+) dphi,  dist r_{i+1}-r_i
+ *                        (walls: dist from the wall to the first centre)
+ *     theta face at t_f  area sin(t_f) (r+^2 - r-^2)/2 dphi, dist r_i (t_{j+1}-t_j)
+ *                        (pole faces t_f = 0, pi: area exactly 0)
+ *     phi face           area (r+^2 - r-^2)/2 (t+ - t-),    dist r_i sin(t_j) dphi
+ */
+static double band(double ta, double tb) { /* cos ta - cos tb, ta < tb */
+    return 2.0 * sin(0.5 * (ta + tb)) * sin(0.5 * (tb - ta));
+}
+
+int ora_geometry(ora_op *op) {
+    const ora_grid *g = &op->g;
+    const int nr = g->nr, nt = g->nt, np = g->np;
+    const double *rf = g->r_faces, *tf = g->t_faces;
+    const double dphi = 2.0 * M_PI / np;
+    if (nr < 1 || nt < 1 || np < 1) return -1;
+
+#pragma omp parallel for schedule(static)
+    for (int i = 0; i < nr; i++) {
+        double rm = rf[i], rp = rf[i + 1];
+        double rc = 0.5 * (rm + rp);
+        for (int j = 0; j < nt; j++) {
+            double tm = tf[j], tp = tf[j + 1];
+            double tc = 0.5 * (tm + tp);
+            for (int k = 0; k < np; k++) {
+                size_t c = cidx(g, i, j, k);
+                op->V[c] = (rp - rm) * (rp * rp + rp * rm + rm * rm) / 3.0 * band(tm, tp) * dphi;
+                op->Ap[c] = 0.5 * (rp * rp - rm * rm) * (tp - tm);
+                op->Hp[c] = rc * sin(tc) * dphi;
+            }
+        }
+    }
+    /* r faces, including the two walls */
+#pragma omp parallel for schedule(static)
+    for (int i = 0; i <= nr; i++) {
+        double rfa = rf[i];
+        double h;
+        if (i == 0)
+            h = 0.5 * (rf[0] + rf[1]) - rf[0];
+        else if (i == nr)
+            h = rf[nr] - 0.5 * (rf[nr - 1] + rf[nr]);
+        else
+            h = 0.5 * (rf[i] + rf[i + 1]) - 0.5 * (rf[i - 1] + rf[i]);
+        for (int j = 0; j < nt; j++) {
+            double a = rfa * rfa * band(tf[j], tf[j + 1]) * dphi;
+            for (int k = 0; k < np; k++) {
+                op->Ar[ridx(g, i, j, k)] = a;
+                op->Hr[ridx(g, i, j, k)] = h;
+            }
+        }
+    }
+    /* theta faces, including the two poles */
+#pragma omp parallel for schedule(static)
+    for (int i = 0; i < nr; i++) {
+        double rm = rf[i], rp = rf[i + 1];
+        double rc = 0.5 * (rm + rp);
+        for (int j = 0; j <= nt; j++) {
+            double a, h;
+            if (j == 0 || j == nt) {
+                a = 0.0; /* zero-area pole face */
+                h = 1.0; /* unused */
+            } else {
+                a = sin(tf[j]) * 0.5 * (rp * rp - rm * rm) * dphi;
+                h = rc * (0.5 * (tf[j] + tf[j + 1]) - 0.5 * (tf[j - 1] + tf[j]));
+            }
+            for (int k = 0; k < np; k++) {
+                op->At[tidx(g, i, j, k)] = a;
+                op->Ht[tidx(g, i, j, k)] = h;
+            }
+        }
+    }
+    return 0;
+}
+
+/* ------------------------------------------------------------------ operator
+ * Face viscosity: arithmetic mean of the two cells on interior faces; the
+ * wall cell's own value on a Dirichlet wall face.  c_f = dt nu_f A_f / H_f.
+ * With np == 1 the phi face joins a cell to itself and carries nothing.
+ * Neumann walls carry no flux (c = 0).  Pole faces have zero area (c = 0).
+ * diag_c = V_c + sum of the six face conductances of c (walls included).
+ */
+int ora_assemble(ora_op *op, const double *nu) {
+    const ora_grid *g = &op->g;
+    const int nr = g->nr, nt = g->nt, np = g->np;
+    const double dt = op->dt;
+
+#pragma omp parallel for schedule(static)
+    for (int i = 0; i <= nr; i++)
+        for (int j = 0; j < nt; j++)
+            for (int k = 0; k < np; k++) {
+                size_t f = ridx(g, i, j, k);
+                double nuf;
+                if (i == 0)
+                    nuf = (g->bc_inner == ORA_DIRICHLET) ? nu[cidx(g, 0, j, k)] : 0.0;
+                else if (i == nr)
+                    nuf = (g->bc_outer == ORA_DIRICHLET) ? nu[cidx(g, nr - 1, j, k)] : 0.0;
+                else
+                    nuf = 0.5 * (nu[cidx(g, i - 1, j, k)] + nu[cidx(g, i, j, k)]);
+                op->cr[f] = dt * nuf * op->Ar[f] / op->Hr[f];
+            }
+
+#pragma omp parallel for schedule(static)
+    for (int i = 0; i < nr; i++)
+        for (int j = 0; j <= nt; j++)
+            for (int k = 0; k < np; k++) {
+                size_t f = tidx(g, i, j, k);
+                if (j == 0 || j == nt) {
+                    op->ct[f] = 0.0;
+                } else {
+                    double nuf = 0.5 * (nu[cidx(g, i, j - 1, k)] + nu[cidx(g, i, j, k)]);
+                    op->ct[f] = dt * nuf * op->At[f] / op->Ht[f];
+                }
+            }
+
+#pragma omp parallel for schedule(static)
+    for (int i = 0; i < nr; i++)
+        for (int j = 0; j < nt; j++)
+            for (int k = 0; k < np; k++) {
+                size_t f = cidx(g, i, j, k);
+                int kp = (k + 1) % np;
+                double nuf = 0.5 * (nu[f] + nu[cidx(g, i, j, kp)]);
+                /* with a single phi cell the face joins the cell to itself: no flux */
+                op->cp[f] = (np == 1) ? 0.0 : dt * nuf * op->Ap[f] / op->Hp[f];
+            }
+
+#pragma omp parallel for schedule(static)
+    for (int i = 0; i < nr; i++)
+        for (int j = 0; j < nt; j++)
+            for (int k = 0; k < np; k++) {
+                size_t c = cidx(g, i, j, k);
+                int km = (k + np - 1) % np;
+                double s = op->V[c];
+                s += op->cr[ridx(g, i, j, k)] + op->cr[ridx(g, i + 1, j, k)];
+                s += op->ct[tidx(g, i, j, k)] + op->ct[tidx(g, i, j + 1, k)];
+                s += op->cp[c] + op->cp[cidx(g, i, j, km)];
+                op->diag[c] = s;
+            }
+    return 0;
+}
+
+/* (A x)_c = V_c x_c + sum_f c_f (x_c - x_nb), x_nb = 0 beyond a wall. */
+void ora_apply(const ora_op *op, const double *x, double *y) {
+    const ora_grid *g = &op->g;
+    const int nr = g->nr, nt = g->nt, np = g->np;
+#pragma omp parallel for schedule(static)
+    for (int i = 0; i < nr; i++)
+        for (int j = 0; j < nt; j++)
+            for (int k = 0; k < np; k++) {
+                size_t c = cidx(g, i, j, k);
+                double xc = x[c];
+                double s = op->V[c] * xc;
+                /* -r face */
+                double xn = (i > 0) ? x[cidx(g, i - 1, j, k)] : 0.0;
+                s += op->cr[ridx(g, i, j, k)] * (xc - xn);
+                /* +r face */
+                xn = (i < nr - 1) ? x[cidx(g, i + 1, j, k)] : 0.0;
+                s += op->cr[ridx(g, i + 1, j, k)] * (xc - xn);
+                /* -theta face (zero conductance at the pole) */
+                xn = (j > 0) ? x[cidx(g, i, j - 1, k)] : 0.0;
+                s += op->ct[tidx(g, i, j, k)] * (xc - xn);
+                /* +theta face */
+                xn = (j < nt - 1) ? x[cidx(g, i, j + 1, k)] : 0.0;
+                s += op->ct[tidx(g, i, j + 1, k)] * (xc - xn);
+                /* -phi and +phi faces, periodic */
+                int km = (k + np - 1) % np, kp = (k + 1) % np;
+                s += op->cp[cidx(g, i, j, km)] * (xc - x[cidx(g, i, j, km)]);
+                s += op->cp[c] * (xc - x[cidx(g, i, j, kp)]);
+                y[c] = s;
+            }
+}
+
+static double dot(const ora_grid *g, const double *a, const double *b, double *plane) {
+    const int nr = g->nr;
+    const size_t m = (size_t)g->nt * g->np;
+#pragma omp parallel for schedule(static)
+    for (int i = 0; i < nr; i++) {
+        double s = 0.0;
+        for (size_t c = (size_t)i * m; c < (size_t)(i + 1) * m; c++) s += a[c] * b[c];
+        plane[i] = s;
+    }
+    double s = 0.0;
+    for (int i = 0; i < nr; i++) s += plane[i];
+    return s;
+}
+
+double ora_dot(const ora_grid *g, const double *a, const double *b) {
+    double *plane = (double *)malloc(sizeof(double) * g->nr);
+    double s = dot(g, a, b, plane);
+    free(plane);
+    return s;
+}
+
+/* b = V .* rhs */
+void ora_rhs(const ora_op *op, const double *rhs, double *b) {
+    size_t n = ncell(&op->g);
+#pragma omp parallel for schedule(static)
+    for (size_t c = 0; c < n; c++) b[c] = op->V[c] * rhs[c];
+}
+
+/* ------------------------------------------------------------------ PCG
+ * Preconditioned conjugate gradient with M = diag(A) (point Jacobi, "PC1"),
+ * in the order of the classical algorithm (Saad, Iterative Methods for
+ * Sparse Linear Systems, preconditioned CG):
+ *     r = b - A x;  z = M^-1 r;  p = z
+ *     repeat:  q = A p;  alpha = (r,z)/(q,p);  x += alpha p;  r -= alpha q
+ *              stop if ||r|| <= tol ||b||
+ *              z = M^-1 r;  beta = (r,z)_new/(r,z)_old;  p = z + beta p
+ * The stopping test uses the recursively updated residual; the true residual
+ * ||b - A x||/||b|| is reported as well.  x holds x0 on entry if use_x0,
+ * otherwise it is zeroed.  Returns the number of alpha steps taken, or -1 if
+ * (q,p) <= 0 or is not finite.  stats = {rel_res_recursive, rel_res_true}.
+ * If hist is non-null, hist[k] = ||r_k||/||b|| for k = 0..iterations.
+ */
+int ora_pcg(const ora_op *op, const double *b, double *x, double tol, int max_iters,
+            int use_x0, double *stats, double *hist) {
+    const ora_grid *g = &op->g;
+    const size_t n = ncell(g);
+    double *r = (double *)malloc(sizeof(double) * n);
+    double *z = (double *)malloc(sizeof(double) * n);
+    double *p = (double *)malloc(sizeof(double) * n);
+    double *q = (double *)malloc(sizeof(double) * n);
+    double *plane = (double *)malloc(sizeof(double) * g->nr);
+    int it = 0, status = 0;
+
+    if (!use_x0) memset(x, 0, sizeof(double) * n);
+    ora_apply(op, x, q);
+#pragma omp parallel for schedule(static)
+    for (size_t c = 0; c < n; c++) {
+        r[c] = b[c] - q[c];
+        z[c] = r[c] / op->diag[c];
+        p[c] = z[c];
+    }
+    double bnorm = sqrt(dot(g, b, b, plane));
+    if (bnorm == 0.0) bnorm = 1.0;
+    double rz = dot(g, r, z, plane);
+    double rnorm = sqrt(dot(g, r, r, plane));
+    if (hist) hist[0] = rnorm / bnorm;
+
+    while (rnorm > tol * bnorm && it < max_iters) {
+        ora_apply(op, p, q);
+        double pq = dot(g, p, q, plane);
+        if (!(pq > 0.0) || !isfinite(pq)) {
+            status = -1;
+            break;
+        }
+        double alpha = rz / pq;
+#pragma omp parallel for schedule(static)
+        for (size_t c = 0; c < n; c++) {
+            x[c] += alpha * p[c];
+            r[c] -= alpha * q[c];
+        }
+        it++;
+        rnorm = sqrt(dot(g, r, r, plane));
+        if (hist) hist[it] = rnorm / bnorm;
+        if (rnorm <= tol * bnorm) break;
+#pragma omp parallel for schedule(static)
+        for (size_t c = 0; c < n; c++) z[c] = r[c] / op->diag[c];
+        double rz_new = dot(g, r, z, plane);
+        double beta = rz_new / rz;
+        rz = rz_new;
+#pragma omp parallel for schedule(static)
+        for (size_t c = 0; c < n; c++) p[c] = z[c] + beta * p[c];
+    }
+
+    if (stats) {
+        stats[0] = rnorm / bnorm;
+        ora_apply(op, x, q);
+#pragma omp parallel for schedule(static)
+        for (size_t c = 0; c < n; c++) r[c] = b[c] - q[c];
+        stats[1] = sqrt(dot(g, r, r, plane)) / bnorm;
+    }
+    free(r), free(z), free(p), free(q), free(plane);
+    return status < 0 ? status : it;
+}
+
+/* ------------------------------------------------------------------ gradient
+ * For L(x) with x = A(nu)^-1 (V .* rhs) and lam = A^-1 dL/dx (A is symmetric):
+ *     dL/drhs_c = V_c lam_c
+ *     dL/dnu_c  = - sum_f (d c_f / d nu_c) (lam_c - lam_nb)(x_c - x_nb)
+ * because dL = -lam^T (dA) x and an interior face adds c_f (e_c - e_nb)(e_c - e_nb)^T
+ * to A.  d c_f/d nu_c = dt A_f/(2 H_f) on interior faces, dt A_f/H_f on a
+ * Dirichlet wall face (where lam_nb = x_nb = 0), 0 on Neumann walls and poles.
+ */
+void ora_gradient(const ora_op *op, const double *x, const double *lam, double *g_nu,
+                  double *g_rhs) {
+    const ora_grid *g = &op->g;
+    const int nr = g->nr, nt = g->nt, np = g->np;
+    const double dt = op->dt;
+#pragma omp parallel for schedule(static)
+    for (int i = 0; i < nr; i++)
+        for (int j = 0; j < nt; j++)
+            for (int k = 0; k < np; k++) {
+                size_t c = cidx(g, i, j, k);
+                double s = 0.0;
+                size_t f;
+                /* -r face */
+                f = ridx(g, i, j, k);
+                if (i > 0) {
+                    size_t nb = cidx(g, i - 1, j, k);
+                    s += 0.5 * dt * op->Ar[f] / op->Hr[f] * (lam[c] - lam[nb]) * (x[c] - x[nb]);
+                } else if (g->bc_inner == ORA_DIRICHLET) {
+                    s += dt * op->Ar[f] / op->Hr[f] * lam[c] * x[c];
+                }
+                /* +r face */
+                f = ridx(g, i + 1, j, k);
+                if (i < nr - 1) {
+                    size_t nb = cidx(g, i + 1, j, k);
+                    s += 0.5 * dt * op->Ar[f] / op->Hr[f] * (lam[c] - lam[nb]) * (x[c] - x[nb]);
+                } else if (g->bc_outer == ORA_DIRICHLET) {
+                    s += dt * op->Ar[f] / op->Hr[f] * lam[c] * x[c];
+                }
+                /* theta faces (pole faces have zero area) */
+                if (j > 0) {
+                    f = tidx(g, i, j, k);
+                    size_t nb = cidx(g, i, j - 1, k);
+                    s += 0.5 * dt * op->At[f] / op->Ht[f] * (lam[c] - lam[nb]) * (x[c] - x[nb]);
+                }
+                if (j < nt - 1) {
+                    f = tidx(g, i, j + 1, k);
+                    size_t nb = cidx(g, i, j + 1, k);
+                    s += 0.5 * dt * op->At[f] / op->Ht[f] * (lam[c] - lam[nb]) * (x[c] - x[nb]);
+                }
+                /* phi faces */
+                {
+                    int km = (k + np - 1) % np, kp = (k + 1) % np;
+                    size_t fm = cidx(g, i, j, km), nbm = fm;
+                    size_t nbp = cidx(g, i, j, kp);
+                    s += 0.5 * dt * op->Ap[fm] / op->Hp[fm] * (lam[c] - lam[nbm]) * (x[c] - x[nbm]);
+                    s += 0.5 * dt * op->Ap[c] / op->Hp[c] * (lam[c] - lam[nbp]) * (x[c] - x[nbp]);
+                }
+                g_nu[c] = -s;
+                if (g_rhs) g_rhs[c] = op->V[c] * lam[c];
+            }
+}

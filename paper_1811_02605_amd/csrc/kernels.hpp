@@ -1,0 +1,645 @@
+// Device kernels of the implicit viscous solver (gfx950, wave64).
+//
+// Storage of the operator (built once per nu, dt):
+//   w[c]      = sqrt(A_cc)                                 (double)
+//   cr[c]     = -A(c, c+r)     / (w_c w_{c+r})             (0 on the last r plane)
+//   ct[c]     = -A(c, c+theta) / (w_c w_{c+theta})         (0 on the last theta row: pole)
+//   cp[c]     = -A(c, c+phi)   / (w_c w_{c+phi})           (periodic in phi)
+// i.e. the symmetrically scaled operator  A^ = W^-1 A W^-1  with unit diagonal,
+// W = diag(w).  Jacobi-preconditioned CG on A x = b produces, in exact
+// arithmetic, the same iterates as plain CG on A^ x^ = b^ with x = W^-1 x^,
+// b^ = W^-1 b (split preconditioning with M = diag(A) = W^2), so the solver
+// iterates on the scaled system and never stores or reads diag(A)^-1.
+//
+// One PCG iteration is ONE stencil kernel (k_pcg_iter) plus a one-block
+// finalize.  Kernel k, for every cell, forms
+//     r_k = r_{k-1} - alpha_{k-1} q_{k-1}
+//     x_k = x_{k-1} + alpha_{k-1} p_{k-1}
+//     p_k = r_k + beta_k p_{k-1}
+//     q_k = A^ p_k
+// and block partials of (p_k,q_k), (r_k,q_k), (q_k,q_k), (r_k,r_k) and, on
+// check iterations, ||W r_k||^2 = ||b - A x_k||^2.  The finalize sets
+//     alpha_k = (r_k,r_k)/(p_k,q_k)
+//     (r_{k+1},r_{k+1}) = (r_k,r_k) - 2 alpha_k (r_k,q_k) + alpha_k^2 (q_k,q_k)
+//     beta_{k+1} = (r_{k+1},r_{k+1}) / (r_k,r_k)
+// so the next kernel can build p_{k+1} without another global reduction.
+// (r_k,r_k) itself is always the freshly summed value; only one step of
+// the expansion is ever used.  q_k at a cell needs p_k at its six
+// neighbours; p_k at the in-plane neighbours is recomputed from
+// (r, q, p)_{k-1} (one halo row/column around the tile, served from L2),
+// the r-neighbours come from marching along r with a register queue.  r, p, q
+// are double-buffered between iterations (neighbouring tiles still read the
+// old values), x is updated in place (it has no halo).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace mas {
+
+constexpr int kWave = 64;
+constexpr int kNV = 5;        // partial sums per block of the iteration kernel
+constexpr int kRedThreads = 256;
+
+// Device control block of one PCG run (lives in the workspace).
+struct Ctl {
+    double alpha;      // alpha_{k-1}, applied by the next iteration kernel (0: skip)
+    double beta;       // beta_k,      applied by the next iteration kernel (0: p = r)
+    double rr;         // (r_k, r_k) of the last finished iteration (scaled variables)
+    double rw;         // last checked ||W r||^2 (= ||b - A x||^2)
+    double tol2;       // threshold on the checked quantity
+    double inner_rtol2;// inner (refined) mode: relative threshold on (r,r)
+    double pq, rq, qq; // last sums (diagnostics)
+    double sums[8];    // results of k_reduce
+    int32_t flag;      // 0 running, 1 converged, 2 iteration limit, -2 breakdown
+    int32_t iter;      // index of the next iteration kernel
+    int32_t max_iter;  // last admissible iteration index
+    int32_t mode;      // 0: ||W r||^2 <= tol2 on check iterations; 1: (r,r) <= inner_rtol2 (r0,r0)
+    int32_t conv_iter; // iteration index at which flag was set
+    int32_t pad[3];
+};
+
+enum { FLAG_RUN = 0, FLAG_CONV = 1, FLAG_MAXIT = 2, FLAG_BREAK = -2 };
+
+struct Dims {
+    int nr, nt, np;
+    int64_t plane;  // nt*np
+    int64_t n;      // nr*nt*np
+};
+
+// 1-D geometric factors (double, device).  With r_f the radial faces, r_i the
+// cell centres (face midpoints), t_f / t_j the same in theta and dphi = 2 pi/np:
+//   vr[i]  = (r_{i+1}^3 - r_i^3)/3
+//   vt[j]  = (cos t_j - cos t_{j+1}) dphi            V_c = vr[i] vt[j]
+//   gr[i]  = r_{f,i+1}^2 / (r_{i+1} - r_i)           +r face: G = gr[i] vt[j]  (i < nr-1)
+//   gq[i]  = (r_{f,i+1}^2 - r_{f,i}^2) / (2 r_i)
+//   gtt[j] = sin(t_{f,j+1}) dphi / (t_{j+1} - t_j)   +theta face: G = gq[i] gtt[j] (0 at the pole)
+//   gpt[j] = (t_{f,j+1} - t_{f,j}) / (sin(t_j) dphi) +phi face:   G = gq[i] gpt[j]
+//   gw_in  = r_{f,0}^2/(r_0 - r_{f,0}),  gw_out = r_{f,nr}^2/(r_{f,nr} - r_{nr-1})
+//            (Dirichlet walls, times vt[j]; 0 for a Neumann wall)
+struct Geo {
+    const double *vr, *vt, *gr, *gq, *gtt, *gpt;
+    double gw_in, gw_out;
+    double dt;
+    int np_one;  // 1 if np == 1 (the phi face joins a cell to itself: no coupling)
+};
+
+// ---------------------------------------------------------------- reductions
+__device__ inline double wave_sum(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
+    return v;
+}
+
+// Sum NV values over the block in a fixed order; thread 0 writes them to out.
+template <int NV>
+__device__ inline void block_sum_store(double (&v)[NV], double *out, double *lds) {
+    const int tid = threadIdx.x + threadIdx.y * blockDim.x;
+    const int lane = tid & (kWave - 1);
+    const int wv = tid / kWave;
+    const int nw = (blockDim.x * blockDim.y) / kWave;
+#pragma unroll
+    for (int t = 0; t < NV; ++t) v[t] = wave_sum(v[t]);
+    if (lane == 0) {
+#pragma unroll
+        for (int t = 0; t < NV; ++t) lds[wv * NV + t] = v[t];
+    }
+    __syncthreads();
+    if (threadIdx.x == 0 && threadIdx.y == 0) {
+        for (int t = 0; t < NV; ++t) {
+            double s = 0.0;
+            for (int u = 0; u < nw; ++u) s += lds[u * NV + t];
+            out[t] = s;
+        }
+    }
+}
+
+// ---------------------------------------------------------------- iteration kernel
+template <typename T>
+struct IterArgs {
+    const T *r_in, *p_in, *q_in;
+    T *r_out, *p_out, *q_out;
+    T *x;
+    const T *cr, *ct, *cp;
+    const double *w;
+    double *partials;  // [nblk][kNV]
+    const Ctl *ctl;
+    Dims d;
+    int tiles_k, tiles_j, ti;  // phi tiles (64 wide), theta tiles (TJ rows), r planes per block
+    int nblk;
+};
+
+// Bijective block -> tile remap: consecutive hardware block ids go round-robin
+// to the 8 XCDs; give each XCD a contiguous range of tiles so that theta
+// neighbours (tile distance tiles_k) share an L2.
+__device__ inline int xcd_remap(int b, int nblk) {
+    const int q = nblk >> 3, rem = nblk & 7;
+    const int x = b & 7, s = b >> 3;
+    return x * q + (x < rem ? x : rem) + s;
+}
+
+template <typename T, int TJ, bool CHECK>
+__global__ __launch_bounds__(kWave * TJ) void k_pcg_iter(IterArgs<T> a) {
+    const Ctl *ctl = a.ctl;
+    if (ctl->flag != FLAG_RUN) return;
+    const double alpha_d = ctl->alpha, beta_d = ctl->beta;
+    const T alpha = (T)alpha_d, beta = (T)beta_d;
+    const bool use_q = alpha_d != 0.0;
+    const bool use_p = beta_d != 0.0;
+    const bool load_p = use_q || use_p;
+
+    const int nr = a.d.nr, nt = a.d.nt, np = a.d.np;
+    const int64_t plane = a.d.plane;
+
+    const int L = xcd_remap(blockIdx.x, a.nblk);
+    const int kt = L % a.tiles_k;
+    const int jt = (L / a.tiles_k) % a.tiles_j;
+    const int it = L / (a.tiles_k * a.tiles_j);
+
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wv = threadIdx.x / kWave;
+    const int j0 = jt * TJ;
+    const int j = j0 + wv;
+    const int k0 = kt * kWave;
+    const int k = k0 + lane;
+    const int nlane = min(kWave, np - k0);
+    const bool rowok = j < nt;
+    const bool act = rowok && lane < nlane;
+    const int i0 = it * a.ti;
+    const int i1 = min(i0 + a.ti, nr);
+
+    // neighbours of the segment ends (periodic phi)
+    const int kL = (k0 == 0) ? np - 1 : k0 - 1;
+    const int kLast = k0 + nlane - 1;
+    const int kR = (kLast == np - 1) ? 0 : kLast + 1;
+
+    __shared__ T sP[3][TJ + 2][kWave + 2];  // p_k: [slot][row+1][k-k0+1]
+    __shared__ T sCt[3][TJ + 1][kWave];     // ct:  [slot][row+1][k-k0], row 0 = row j0-1
+    __shared__ T sCp[3][TJ][kWave + 1];     // cp:  [slot][row][k-k0+1], index 0 = cp(kL)
+    __shared__ double sRed[TJ * kNV];
+
+    auto newp = [&](int64_t c, T &rn) -> T {
+        T r = a.r_in[c];
+        T po = load_p ? a.p_in[c] : T(0);
+        if (use_q) r -= alpha * a.q_in[c];
+        rn = r;
+        return use_p ? r + beta * po : r;
+    };
+
+    double acc[kNV] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    T pn_m1 = 0, pn_m2 = 0;  // own p_k at planes m-1, m-2
+    T cr_m1 = 0, cr_m2 = 0;  // own cr at planes m-1, m-2
+    T rn_m1 = 0;             // own r_k at plane m-1
+    T ct_m1 = 0, cp_m1 = 0;  // own ct, cp at plane m-1
+    const int64_t colj = (int64_t)j * np + k;
+
+    for (int m = i0 - 1; m <= i1; ++m) {
+        const int slot = (m + 3) % 3;
+        const bool indom = (m >= 0) && (m < nr);
+        const bool own = (m >= i0) && (m < i1);
+        T pn = 0, rn = 0, crm = 0, ctm = 0, cpm = 0;
+        if (indom && act) {
+            const int64_t c = (int64_t)m * plane + colj;
+            T r = a.r_in[c];
+            T po = load_p ? a.p_in[c] : T(0);
+            if (use_q) r -= alpha * a.q_in[c];
+            rn = r;
+            pn = use_p ? r + beta * po : r;
+            crm = a.cr[c];
+            if (own) {
+                ctm = a.ct[c];
+                cpm = a.cp[c];
+                a.r_out[c] = rn;
+                a.p_out[c] = pn;
+                if (use_q) a.x[c] = a.x[c] + alpha * po;
+            }
+        }
+        if (own) {
+            if (lane < nlane) {
+                sP[slot][wv + 1][lane + 1] = pn;
+                sCt[slot][wv + 1][lane] = ctm;
+                sCp[slot][wv][lane + 1] = cpm;
+            }
+            // phi halo of this row
+            if (rowok && lane == 0) {
+                const int64_t c = (int64_t)m * plane + (int64_t)j * np + kL;
+                T rdum;
+                sP[slot][wv + 1][0] = newp(c, rdum);
+                sCp[slot][wv][0] = a.cp[c];
+            }
+            if (rowok && lane == nlane - 1) {
+                const int64_t c = (int64_t)m * plane + (int64_t)j * np + kR;
+                T rdum;
+                sP[slot][wv + 1][nlane + 1] = newp(c, rdum);
+            }
+            // theta halo rows
+            if (wv == 0 && lane < nlane) {
+                T v = 0, cv = 0;
+                if (j0 > 0) {
+                    const int64_t c = (int64_t)m * plane + (int64_t)(j0 - 1) * np + k;
+                    T rdum;
+                    v = newp(c, rdum);
+                    cv = a.ct[c];
+                }
+                sP[slot][0][lane + 1] = v;
+                sCt[slot][0][lane] = cv;
+            }
+            if (wv == TJ - 1 && lane < nlane) {
+                T v = 0;
+                if (j0 + TJ < nt) {
+                    const int64_t c = (int64_t)m * plane + (int64_t)(j0 + TJ) * np + k;
+                    T rdum;
+                    v = newp(c, rdum);
+                }
+                sP[slot][TJ + 1][lane + 1] = v;
+            }
+        }
+        __syncthreads();
+        if (m - 1 >= i0 && act) {
+            const int ps = (m + 2) % 3;  // slot of plane m-1
+            const T s = cr_m1 * pn + cr_m2 * pn_m2
+                      + ct_m1 * sP[ps][wv + 2][lane + 1] + sCt[ps][wv][lane] * sP[ps][wv][lane + 1]
+                      + cp_m1 * sP[ps][wv + 1][lane + 2] + sCp[ps][wv][lane] * sP[ps][wv + 1][lane];
+            const T qv = pn_m1 - s;
+            const int64_t c = (int64_t)(m - 1) * plane + colj;
+            a.q_out[c] = qv;
+            const double pd = (double)pn_m1, qd = (double)qv, rd = (double)rn_m1;
+            acc[0] += pd * qd;
+            acc[1] += rd * qd;
+            acc[2] += qd * qd;
+            acc[3] += rd * rd;
+            if (CHECK) {
+                const double t = a.w[c] * rd;
+                acc[4] += t * t;
+            }
+        }
+        pn_m2 = pn_m1;
+        pn_m1 = pn;
+        cr_m2 = cr_m1;
+        cr_m1 = crm;
+        rn_m1 = rn;
+        ct_m1 = ctm;
+        cp_m1 = cpm;
+    }
+    block_sum_store<kNV>(acc, a.partials + (int64_t)L * kNV, sRed);
+}
+
+// One block: fixed-order sum of the iteration partials, then the scalar
+// recurrences and the stopping tests.
+__global__ __launch_bounds__(kRedThreads) void k_finalize(const double *partials, int nblk,
+                                                         Ctl *ctl, int is_check) {
+    if (ctl->flag != FLAG_RUN) return;
+    __shared__ double sh[kRedThreads * kNV];
+    double v[kNV] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    for (int b = threadIdx.x; b < nblk; b += kRedThreads) {
+#pragma unroll
+        for (int t = 0; t < kNV; ++t) v[t] += partials[(int64_t)b * kNV + t];
+    }
+#pragma unroll
+    for (int t = 0; t < kNV; ++t) sh[threadIdx.x * kNV + t] = v[t];
+    __syncthreads();
+    for (int s = kRedThreads / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) {
+#pragma unroll
+            for (int t = 0; t < kNV; ++t) sh[threadIdx.x * kNV + t] += sh[(threadIdx.x + s) * kNV + t];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x != 0) return;
+    const double PQ = sh[0], RQ = sh[1], QQ = sh[2], RR = sh[3], RW = sh[4];
+    const int k = ctl->iter;
+    ctl->pq = PQ;
+    ctl->rq = RQ;
+    ctl->qq = QQ;
+    bool conv = false;
+    if (ctl->mode == 0) {
+        if (is_check) {
+            ctl->rw = RW;
+            conv = RW <= ctl->tol2;
+        }
+    } else {
+        if (k == 0) ctl->tol2 = ctl->inner_rtol2 * RR;
+        conv = RR <= ctl->tol2;
+    }
+    ctl->rr = RR;
+    if (conv) {
+        ctl->flag = FLAG_CONV;
+        ctl->conv_iter = k;
+        return;
+    }
+    if (k >= ctl->max_iter) {
+        ctl->flag = FLAG_MAXIT;
+        ctl->conv_iter = k;
+        return;
+    }
+    if (!(PQ > 0.0) || !isfinite(PQ) || !isfinite(RR)) {
+        ctl->flag = FLAG_BREAK;
+        ctl->conv_iter = k;
+        return;
+    }
+    const double alpha = RR / PQ;
+    const double rho1 = RR - 2.0 * alpha * RQ + alpha * alpha * QQ;
+    ctl->alpha = alpha;
+    ctl->beta = (rho1 > 0.0 && RR > 0.0) ? rho1 / RR : 0.0;
+    ctl->iter = k + 1;
+}
+
+// Generic fixed-order sum of [nblk][nv] partials into ctl->sums[0:nv].
+__global__ __launch_bounds__(kRedThreads) void k_reduce(const double *partials, int nblk, int nv,
+                                                       Ctl *ctl) {
+    __shared__ double sh[kRedThreads];
+    for (int t = 0; t < nv; ++t) {
+        double v = 0.0;
+        for (int b = threadIdx.x; b < nblk; b += kRedThreads) v += partials[(int64_t)b * nv + t];
+        sh[threadIdx.x] = v;
+        __syncthreads();
+        for (int s = kRedThreads / 2; s > 0; s >>= 1) {
+            if ((int)threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) ctl->sums[t] = sh[0];
+        __syncthreads();
+    }
+}
+
+// Reset the control block for a new PCG run (a kernel, not a memset, so it
+// is safe inside captured graphs as well).
+__global__ void k_ctl_init(Ctl *ctl, int mode, int iter0, int max_iter, double tol2,
+                           double inner_rtol2) {
+    if (threadIdx.x != 0) return;
+    ctl->alpha = 0.0;
+    ctl->beta = 0.0;
+    ctl->rr = 0.0;
+    ctl->rw = 0.0;
+    ctl->tol2 = tol2;
+    ctl->inner_rtol2 = inner_rtol2;
+    ctl->flag = FLAG_RUN;
+    ctl->iter = iter0;
+    ctl->max_iter = max_iter;
+    ctl->mode = mode;
+    ctl->conv_iter = -1;
+}
+
+// ---------------------------------------------------------------- simple stencil tiles
+// Block (64, 4): 64 phi cells x 4 theta rows, looping over kSimpleR r planes.
+constexpr int kSimpleJ = 4;
+constexpr int kSimpleR = 16;
+
+struct SimpleCell {
+    int i, j, k;
+    int64_t c;
+    bool ok;
+};
+
+#define MAS_SIMPLE_LOOP(d, ...)                                                    \
+    {                                                                              \
+        const int k_ = blockIdx.x * kWave + threadIdx.x;                           \
+        const int j_ = blockIdx.y * kSimpleJ + threadIdx.y;                        \
+        const int ib_ = blockIdx.z * kSimpleR;                                     \
+        const int ie_ = min(ib_ + kSimpleR, (d).nr);                               \
+        const bool ok_ = (k_ < (d).np) && (j_ < (d).nt);                           \
+        for (int i_ = ib_; i_ < ie_; ++i_) {                                       \
+            SimpleCell cell{i_, j_, k_, ((int64_t)i_ * (d).nt + j_) * (d).np + k_, \
+                            ok_};                                                  \
+            __VA_ARGS__                                                            \
+        }                                                                          \
+    }
+
+__device__ inline int64_t simple_block_id() {
+    return ((int64_t)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
+}
+
+// Face conductance dt * nu_f * G_f, the single definition used by the build.
+__device__ inline double face_c(double dt, double nua, double nub, double g) {
+    return dt * (0.5 * (nua + nub)) * g;
+}
+
+// Diagonal of A, its square root, and validity of nu.
+__global__ __launch_bounds__(kWave *kSimpleJ) void k_build_diag(const double *nu, Geo geo, Dims d,
+                                                                double *w, int32_t *bad) {
+    int badv = 0;
+    MAS_SIMPLE_LOOP(d, {
+        if (cell.ok) {
+            const int i = cell.i, j = cell.j, k = cell.k;
+            const int64_t c = cell.c;
+            const double nc = nu[c];
+            if (!(nc > 0.0) || !isfinite(nc)) badv = 1;
+            const double vt = geo.vt[j];
+            double s = geo.vr[i] * vt;
+            // r faces
+            if (i > 0) s += face_c(geo.dt, nc, nu[c - d.plane], geo.gr[i - 1] * vt);
+            else s += geo.dt * nc * (geo.gw_in * vt);
+            if (i < d.nr - 1) s += face_c(geo.dt, nc, nu[c + d.plane], geo.gr[i] * vt);
+            else s += geo.dt * nc * (geo.gw_out * vt);
+            // theta faces (zero at the poles)
+            if (j > 0) s += face_c(geo.dt, nc, nu[c - d.np], geo.gq[i] * geo.gtt[j - 1]);
+            if (j < d.nt - 1) s += face_c(geo.dt, nc, nu[c + d.np], geo.gq[i] * geo.gtt[j]);
+            // phi faces (periodic)
+            if (!geo.np_one) {
+                const int km = (k == 0) ? d.np - 1 : k - 1;
+                const int kp = (k == d.np - 1) ? 0 : k + 1;
+                const double gp = geo.gq[i] * geo.gpt[j];
+                s += face_c(geo.dt, nc, nu[c - k + km], gp);
+                s += face_c(geo.dt, nc, nu[c - k + kp], gp);
+            }
+            w[c] = sqrt(s);
+        }
+    })
+    if (badv) atomicOr(bad, 1);
+}
+
+// Scaled couplings to the +r, +theta, +phi neighbours.
+template <bool F32>
+__global__ __launch_bounds__(kWave *kSimpleJ) void k_build_coef(const double *nu, const double *w,
+                                                                Geo geo, Dims d, double *cr,
+                                                                double *ct, double *cp, float *cr32,
+                                                                float *ct32, float *cp32) {
+    MAS_SIMPLE_LOOP(d, {
+        if (cell.ok) {
+            const int i = cell.i, j = cell.j, k = cell.k;
+            const int64_t c = cell.c;
+            const double nc = nu[c], wc = w[c];
+            double vr = 0.0, vth = 0.0, vp = 0.0;
+            if (i < d.nr - 1)
+                vr = face_c(geo.dt, nc, nu[c + d.plane], geo.gr[i] * geo.vt[j]) / (wc * w[c + d.plane]);
+            if (j < d.nt - 1)
+                vth = face_c(geo.dt, nc, nu[c + d.np], geo.gq[i] * geo.gtt[j]) / (wc * w[c + d.np]);
+            if (!geo.np_one) {
+                const int64_t cn = c - k + ((k == d.np - 1) ? 0 : k + 1);
+                vp = face_c(geo.dt, nc, nu[cn], geo.gq[i] * geo.gpt[j]) / (wc * w[cn]);
+            }
+            cr[c] = vr;
+            ct[c] = vth;
+            cp[c] = vp;
+            if (F32) {
+                cr32[c] = (float)vr;
+                ct32[c] = (float)vth;
+                cp32[c] = (float)vp;
+            }
+        }
+    })
+}
+
+// Unscaled entries as the solver uses them: -A(c, nb) = w_c c^ w_nb, A_cc = w_c^2.
+__global__ __launch_bounds__(kWave *kSimpleJ) void k_export(const double *w, const double *cr,
+                                                            const double *ct, const double *cp,
+                                                            Dims d, double *ocr, double *oct,
+                                                            double *ocp, double *odiag) {
+    MAS_SIMPLE_LOOP(d, {
+        if (cell.ok) {
+            const int i = cell.i, j = cell.j, k = cell.k;
+            const int64_t c = cell.c;
+            const double wc = w[c];
+            if (ocr) ocr[c] = (i < d.nr - 1) ? wc * cr[c] * w[c + d.plane] : 0.0;
+            if (oct) oct[c] = (j < d.nt - 1) ? wc * ct[c] * w[c + d.np] : 0.0;
+            if (ocp) ocp[c] = wc * cp[c] * w[c - k + ((k == d.np - 1) ? 0 : k + 1)];
+            if (odiag) odiag[c] = wc * wc;
+        }
+    })
+}
+
+// A^ u at one cell (unit diagonal), u read through the functor.
+template <typename F>
+__device__ inline double scaled_apply(const double *cr, const double *ct, const double *cp, Dims d,
+                                      const SimpleCell &cell, F u) {
+    const int i = cell.i, j = cell.j, k = cell.k;
+    const int64_t c = cell.c;
+    double s = 0.0;
+    if (i < d.nr - 1) s += cr[c] * u(c + d.plane);
+    if (i > 0) s += cr[c - d.plane] * u(c - d.plane);
+    if (j < d.nt - 1) s += ct[c] * u(c + d.np);
+    if (j > 0) s += ct[c - d.np] * u(c - d.np);
+    const int64_t km = c - k + ((k == 0) ? d.np - 1 : k - 1);
+    const int64_t kp = c - k + ((k == d.np - 1) ? 0 : k + 1);
+    s += cp[c] * u(kp) + cp[km] * u(km);
+    return u(c) - s;
+}
+
+// y = A x = W A^ W x.
+__global__ __launch_bounds__(kWave *kSimpleJ) void k_apply(const double *w, const double *cr,
+                                                           const double *ct, const double *cp,
+                                                           Dims d, const double *x, double *y) {
+    MAS_SIMPLE_LOOP(d, {
+        if (cell.ok) {
+            const double v = scaled_apply(cr, ct, cp, d, cell,
+                                          [&](int64_t c) { return w[c] * x[c]; });
+            y[cell.c] = w[cell.c] * v;
+        }
+    })
+}
+
+// r^ = b^ - A^ x^ (double), stored as TOUT; partial ||W r^||^2.
+template <typename TOUT>
+__global__ __launch_bounds__(kWave *kSimpleJ) void k_residual(const double *bhat, const double *xhat,
+                                                              const double *w, const double *cr,
+                                                              const double *ct, const double *cp,
+                                                              Dims d, TOUT *rout,
+                                                              double *partials) {
+    __shared__ double lds[kSimpleJ * 1];
+    double acc[1] = {0.0};
+    MAS_SIMPLE_LOOP(d, {
+        if (cell.ok) {
+            const double r = bhat[cell.c] -
+                             scaled_apply(cr, ct, cp, d, cell, [&](int64_t c) { return xhat[c]; });
+            rout[cell.c] = (TOUT)r;
+            const double t = w[cell.c] * r;
+            acc[0] += t * t;
+        }
+    })
+    block_sum_store<1>(acc, partials + simple_block_id(), lds);
+}
+
+// b^ = V src / w (src = rhs) or src / w (src = adjoint seed), partial ||b||^2;
+// x^ = w x0 (warm start) or 0.
+__global__ __launch_bounds__(kWave *kSimpleJ) void k_setup(const double *src, int src_is_rhs,
+                                                           const double *w, Geo geo, Dims d,
+                                                           double *bhat, double *x, int use_x0,
+                                                           double *partials) {
+    __shared__ double lds[kSimpleJ * 1];
+    double acc[1] = {0.0};
+    MAS_SIMPLE_LOOP(d, {
+        if (cell.ok) {
+            const int64_t c = cell.c;
+            double b = src[c];
+            if (src_is_rhs) b *= geo.vr[cell.i] * geo.vt[cell.j];
+            const double wc = w[c];
+            bhat[c] = b / wc;
+            x[c] = use_x0 ? wc * x[c] : 0.0;
+            acc[0] += b * b;
+        }
+    })
+    block_sum_store<1>(acc, partials + simple_block_id(), lds);
+}
+
+// x = x^ / w, in place.
+__global__ __launch_bounds__(kWave *kSimpleJ) void k_unscale(const double *w, Dims d, double *x) {
+    MAS_SIMPLE_LOOP(d, {
+        if (cell.ok) x[cell.c] = x[cell.c] / w[cell.c];
+    })
+}
+
+// x^ += d^ (refinement update, double += single).
+__global__ __launch_bounds__(kWave *kSimpleJ) void k_refine_add(const float *dh, Dims d, double *x) {
+    MAS_SIMPLE_LOOP(d, {
+        if (cell.ok) x[cell.c] = x[cell.c] + (double)dh[cell.c];
+    })
+}
+
+template <typename T>
+__global__ __launch_bounds__(kWave *kSimpleJ) void k_fill(T *x, Dims d, T v) {
+    MAS_SIMPLE_LOOP(d, {
+        if (cell.ok) x[cell.c] = v;
+    })
+}
+
+// dL/dnu and dL/drhs from the forward solution x and the adjoint lam.
+__global__ __launch_bounds__(kWave *kSimpleJ) void k_gradient(const double *x, const double *lam,
+                                                              Geo geo, Dims d, double *gnu,
+                                                              double *grhs) {
+    MAS_SIMPLE_LOOP(d, {
+        if (cell.ok) {
+            const int i = cell.i, j = cell.j, k = cell.k;
+            const int64_t c = cell.c;
+            const double xc = x[c], lc = lam[c];
+            const double vt = geo.vt[j];
+            double s = 0.0;
+            if (i > 0) {
+                const int64_t n = c - d.plane;
+                s += 0.5 * geo.gr[i - 1] * vt * (lc - lam[n]) * (xc - x[n]);
+            } else {
+                s += geo.gw_in * vt * lc * xc;
+            }
+            if (i < d.nr - 1) {
+                const int64_t n = c + d.plane;
+                s += 0.5 * geo.gr[i] * vt * (lc - lam[n]) * (xc - x[n]);
+            } else {
+                s += geo.gw_out * vt * lc * xc;
+            }
+            if (j > 0) {
+                const int64_t n = c - d.np;
+                s += 0.5 * geo.gq[i] * geo.gtt[j - 1] * (lc - lam[n]) * (xc - x[n]);
+            }
+            if (j < d.nt - 1) {
+                const int64_t n = c + d.np;
+                s += 0.5 * geo.gq[i] * geo.gtt[j] * (lc - lam[n]) * (xc - x[n]);
+            }
+            if (!geo.np_one) {
+                const double gp = 0.5 * geo.gq[i] * geo.gpt[j];
+                const int64_t nm = c - k + ((k == 0) ? d.np - 1 : k - 1);
+                const int64_t np_ = c - k + ((k == d.np - 1) ? 0 : k + 1);
+                s += gp * ((lc - lam[nm]) * (xc - x[nm]) + (lc - lam[np_]) * (xc - x[np_]));
+            }
+            gnu[c] = -geo.dt * s;
+            if (grhs) grhs[c] = geo.vr[i] * vt * lc;
+        }
+    })
+}
+
+// Streaming copy, 16 bytes per lane per step.
+__global__ __launch_bounds__(256) void k_copy16(const double2 *src, double2 *dst, int64_t n16) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n16; t += stride)
+        dst[t] = src[t];
+}
+
+}  // namespace mas

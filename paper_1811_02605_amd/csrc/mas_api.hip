@@ -1,0 +1,763 @@
+// Host side of the implicit viscous solver: argument checking, storage and
+// workspace layout, the 1-D geometry tables, and the PCG / refinement /
+// adjoint drivers that launch the kernels in kernels.hpp.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/mas.h"
+#include "kernels.hpp"
+
+using namespace mas;
+
+// ------------------------------------------------------------------ errors
+static thread_local std::string g_last_error;
+
+static int fail(int status, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return status;
+}
+
+#define HIPCHK(expr)                                                                   \
+    do {                                                                               \
+        hipError_t e_ = (expr);                                                        \
+        if (e_ != hipSuccess)                                                          \
+            return fail(MAS_EHIP, "%s failed: %s", #expr, hipGetErrorString(e_));      \
+    } while (0)
+
+#define LAUNCHCHK()                                                                    \
+    do {                                                                               \
+        hipError_t e_ = hipGetLastError();                                             \
+        if (e_ != hipSuccess)                                                          \
+            return fail(MAS_EHIP, "kernel launch failed: %s", hipGetErrorString(e_)); \
+    } while (0)
+
+// ------------------------------------------------------------------ tile configuration
+// Iteration kernel: 64 phi cells x kTJ theta rows per block, kTI r planes per block.
+static constexpr int kTJ = 8;
+static constexpr int kTI = 32;
+
+static inline int64_t align256(int64_t v) { return (v + 255) & ~int64_t(255); }
+
+struct Shape {
+    int nr, nt, np;
+    int64_t plane, n;
+    Dims dims() const { return Dims{nr, nt, np, plane, n}; }
+    int tiles_k() const { return (np + kWave - 1) / kWave; }
+    int tiles_j() const { return (nt + kTJ - 1) / kTJ; }
+    int tiles_i() const { return (nr + kTI - 1) / kTI; }
+    int64_t nblk_iter() const { return (int64_t)tiles_k() * tiles_j() * tiles_i(); }
+    dim3 simple_grid() const {
+        return dim3((np + kWave - 1) / kWave, (nt + kSimpleJ - 1) / kSimpleJ,
+                    (nr + kSimpleR - 1) / kSimpleR);
+    }
+    int64_t nblk_simple() const {
+        dim3 g = simple_grid();
+        return (int64_t)g.x * g.y * g.z;
+    }
+};
+
+// ------------------------------------------------------------------ operator
+struct mas_op {
+    Shape s;
+    int precision;
+    int bc_inner, bc_outer;
+    double dt;
+    Geo geo;            // device pointers into storage + scalars
+    double *w;
+    double *c64[3];
+    float *c32[3];      // null unless built with MAS_FP32_REFINED
+    hipStream_t build_stream;
+};
+
+struct StorageLayout {
+    int64_t flags, vr, vt, gr, gq, gtt, gpt, w, c64[3], c32[3], total;
+};
+
+static StorageLayout storage_layout(const Shape &s, int precision) {
+    StorageLayout L{};
+    int64_t off = 0;
+    auto take = [&](int64_t bytes) {
+        int64_t o = off;
+        off = align256(off + bytes);
+        return o;
+    };
+    L.flags = take(256);
+    L.vr = take(8 * (int64_t)s.nr);
+    L.vt = take(8 * (int64_t)s.nt);
+    L.gr = take(8 * (int64_t)s.nr);
+    L.gq = take(8 * (int64_t)s.nr);
+    L.gtt = take(8 * (int64_t)s.nt);
+    L.gpt = take(8 * (int64_t)s.nt);
+    L.w = take(8 * s.n);
+    for (int t = 0; t < 3; ++t) L.c64[t] = take(8 * s.n);
+    for (int t = 0; t < 3; ++t) L.c32[t] = (precision == MAS_FP32_REFINED) ? take(4 * s.n) : -1;
+    L.total = off;
+    return L;
+}
+
+static int check_grid(const mas_grid *g, Shape *out) {
+    if (!g) return fail(MAS_EINVAL, "grid is NULL");
+    if (g->nr < 1 || g->nt < 1 || g->np < 1)
+        return fail(MAS_EINVAL, "grid sizes must be >= 1 (got %d x %d x %d)", g->nr, g->nt, g->np);
+    if (!g->r_faces || !g->t_faces) return fail(MAS_EINVAL, "face arrays must not be NULL");
+    const int64_t n = (int64_t)g->nr * g->nt * g->np;
+    if (n > ((int64_t)1 << 40)) return fail(MAS_EINVAL, "grid too large");
+    if ((int64_t)g->nt > 65535LL * kSimpleJ) return fail(MAS_EINVAL, "nt too large");
+    if (!(g->r_faces[0] > 0.0) || !std::isfinite(g->r_faces[0]))
+        return fail(MAS_EINVAL, "r_faces[0] must be positive and finite");
+    for (int i = 0; i < g->nr; ++i)
+        if (!(g->r_faces[i + 1] > g->r_faces[i]) || !std::isfinite(g->r_faces[i + 1]))
+            return fail(MAS_EINVAL, "r_faces must be strictly increasing and finite (index %d)", i + 1);
+    if (g->t_faces[0] != 0.0 || g->t_faces[g->nt] != M_PI)
+        return fail(MAS_EINVAL, "t_faces must run from exactly 0 to exactly pi");
+    for (int j = 0; j < g->nt; ++j)
+        if (!(g->t_faces[j + 1] > g->t_faces[j]))
+            return fail(MAS_EINVAL, "t_faces must be strictly increasing (index %d)", j + 1);
+    for (int b : {g->bc_inner, g->bc_outer})
+        if (b != MAS_BC_DIRICHLET0 && b != MAS_BC_NEUMANN0)
+            return fail(MAS_EINVAL, "unknown boundary condition %d", b);
+    if (out) {
+        out->nr = g->nr;
+        out->nt = g->nt;
+        out->np = g->np;
+        out->plane = (int64_t)g->nt * g->np;
+        out->n = n;
+    }
+    return MAS_OK;
+}
+
+// 1-D geometric factors in double precision (libm), see struct Geo.
+struct HostGeo {
+    std::vector<double> vr, vt, gr, gq, gtt, gpt;
+    double gw_in, gw_out;
+};
+
+static HostGeo host_geometry(const mas_grid *g) {
+    const int nr = g->nr, nt = g->nt, np = g->np;
+    const double *rf = g->r_faces, *tf = g->t_faces;
+    const double dphi = 2.0 * M_PI / np;
+    HostGeo h;
+    h.vr.resize(nr);
+    h.gr.resize(nr);
+    h.gq.resize(nr);
+    h.vt.resize(nt);
+    h.gtt.resize(nt);
+    h.gpt.resize(nt);
+    std::vector<double> rc(nr), tc(nt);
+    for (int i = 0; i < nr; ++i) rc[i] = 0.5 * (rf[i] + rf[i + 1]);
+    for (int j = 0; j < nt; ++j) tc[j] = 0.5 * (tf[j] + tf[j + 1]);
+    for (int i = 0; i < nr; ++i) {
+        const double a = rf[i], b = rf[i + 1];
+        h.vr[i] = (b - a) * (b * b + b * a + a * a) / 3.0;
+        h.gq[i] = (b * b - a * a) / (2.0 * rc[i]);
+        h.gr[i] = (i < nr - 1) ? b * b / (rc[i + 1] - rc[i]) : 0.0;
+    }
+    for (int j = 0; j < nt; ++j) {
+        const double a = tf[j], b = tf[j + 1];
+        // cos a - cos b without cancellation
+        h.vt[j] = 2.0 * std::sin(0.5 * (a + b)) * std::sin(0.5 * (b - a)) * dphi;
+        h.gtt[j] = (j < nt - 1) ? std::sin(b) * dphi / (tc[j + 1] - tc[j]) : 0.0;
+        h.gpt[j] = (b - a) / (std::sin(tc[j]) * dphi);
+    }
+    h.gw_in = (g->bc_inner == MAS_BC_DIRICHLET0) ? rf[0] * rf[0] / (rc[0] - rf[0]) : 0.0;
+    h.gw_out = (g->bc_outer == MAS_BC_DIRICHLET0) ? rf[nr] * rf[nr] / (rf[nr] - rc[nr - 1]) : 0.0;
+    return h;
+}
+
+static hipStream_t as_stream(void *s) { return reinterpret_cast<hipStream_t>(s); }
+
+extern "C" void mas_pcg_default_opts(mas_pcg_opts *o) {
+    if (!o) return;
+    o->rtol = 1e-10;
+    o->max_iters = 100000;
+    o->precision = MAS_FP64;
+    o->inner_rtol = 1e-5;
+    o->max_outer = 20;
+    o->check_every = 8;
+    o->use_x0 = 0;
+    o->max_restarts = 3;
+    o->sample_timing = 0;
+}
+
+extern "C" int64_t mas_op_storage_bytes(const mas_grid *g, int32_t precision) {
+    Shape s;
+    int st = check_grid(g, &s);
+    if (st != MAS_OK) return st;
+    if (precision != MAS_FP64 && precision != MAS_FP32_REFINED)
+        return fail(MAS_EINVAL, "unknown precision %d", precision);
+    return storage_layout(s, precision).total;
+}
+
+extern "C" int mas_op_build(const mas_grid *g, const double *nu, double dt, int32_t precision,
+                            void *storage, int64_t storage_bytes, void *hip_stream,
+                            mas_op **op_out) {
+    g_last_error.clear();
+    if (op_out) *op_out = nullptr;
+    Shape s;
+    int st = check_grid(g, &s);
+    if (st != MAS_OK) return st;
+    if (!nu || !storage || !op_out) return fail(MAS_EINVAL, "nu, storage and op_out must not be NULL");
+    if (precision != MAS_FP64 && precision != MAS_FP32_REFINED)
+        return fail(MAS_EINVAL, "unknown precision %d", precision);
+    if (!(dt >= 0.0) || !std::isfinite(dt)) return fail(MAS_EINVAL, "dt must be finite and >= 0");
+    if (reinterpret_cast<uintptr_t>(storage) & 255)
+        return fail(MAS_EINVAL, "storage must be 256-byte aligned");
+    const StorageLayout L = storage_layout(s, precision);
+    if (storage_bytes < L.total)
+        return fail(MAS_ENOMEM, "storage too small: %lld < %lld bytes", (long long)storage_bytes,
+                    (long long)L.total);
+
+    hipStream_t stream = as_stream(hip_stream);
+    char *base = static_cast<char *>(storage);
+    HostGeo h = host_geometry(g);
+
+    mas_op *op = new (std::nothrow) mas_op();
+    if (!op) return fail(MAS_EINVAL, "out of host memory");
+    op->s = s;
+    op->precision = precision;
+    op->bc_inner = g->bc_inner;
+    op->bc_outer = g->bc_outer;
+    op->dt = dt;
+    double *vr = reinterpret_cast<double *>(base + L.vr);
+    double *vt = reinterpret_cast<double *>(base + L.vt);
+    double *gr = reinterpret_cast<double *>(base + L.gr);
+    double *gq = reinterpret_cast<double *>(base + L.gq);
+    double *gtt = reinterpret_cast<double *>(base + L.gtt);
+    double *gpt = reinterpret_cast<double *>(base + L.gpt);
+    op->geo = Geo{vr, vt, gr, gq, gtt, gpt, h.gw_in, h.gw_out, dt, s.np == 1 ? 1 : 0};
+    op->w = reinterpret_cast<double *>(base + L.w);
+    for (int t = 0; t < 3; ++t) {
+        op->c64[t] = reinterpret_cast<double *>(base + L.c64[t]);
+        op->c32[t] = (L.c32[t] >= 0) ? reinterpret_cast<float *>(base + L.c32[t]) : nullptr;
+    }
+    int32_t *flags = reinterpret_cast<int32_t *>(base + L.flags);
+
+    auto cleanup_fail = [&](int status) {
+        delete op;
+        return status;
+    };
+    struct Up {
+        double *dst;
+        const std::vector<double> *src;
+    } ups[] = {{vr, &h.vr}, {vt, &h.vt}, {gr, &h.gr}, {gq, &h.gq}, {gtt, &h.gtt}, {gpt, &h.gpt}};
+    for (auto &u : ups) {
+        hipError_t e = hipMemcpyAsync(u.dst, u.src->data(), 8 * u.src->size(),
+                                      hipMemcpyHostToDevice, stream);
+        if (e != hipSuccess)
+            return cleanup_fail(fail(MAS_EHIP, "geometry upload failed: %s", hipGetErrorString(e)));
+    }
+    const Dims d = s.dims();
+    const dim3 grid = s.simple_grid(), block(kWave, kSimpleJ);
+    hipLaunchKernelGGL(k_fill<int32_t>, dim3(1, 1, 1), block, 0, stream, flags,
+                       Dims{1, 1, 1, 1, 1}, 0);
+    hipLaunchKernelGGL(k_build_diag, grid, block, 0, stream, nu, op->geo, d, op->w, flags);
+    if (precision == MAS_FP32_REFINED)
+        hipLaunchKernelGGL(k_build_coef<true>, grid, block, 0, stream, nu, op->w, op->geo, d,
+                           op->c64[0], op->c64[1], op->c64[2], op->c32[0], op->c32[1], op->c32[2]);
+    else
+        hipLaunchKernelGGL(k_build_coef<false>, grid, block, 0, stream, nu, op->w, op->geo, d,
+                           op->c64[0], op->c64[1], op->c64[2], nullptr, nullptr, nullptr);
+    {
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess)
+            return cleanup_fail(fail(MAS_EHIP, "build launch failed: %s", hipGetErrorString(e)));
+    }
+    int32_t bad = 0;
+    {
+        hipError_t e = hipMemcpyAsync(&bad, flags, sizeof bad, hipMemcpyDeviceToHost, stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(stream);
+        if (e != hipSuccess)
+            return cleanup_fail(fail(MAS_EHIP, "build failed: %s", hipGetErrorString(e)));
+    }
+    if (bad) return cleanup_fail(fail(MAS_EINVAL, "nu must be positive and finite everywhere"));
+    *op_out = op;
+    return MAS_OK;
+}
+
+extern "C" void mas_op_destroy(mas_op *op) { delete op; }
+
+extern "C" int mas_op_apply(const mas_op *op, const double *x, double *y, void *hip_stream) {
+    if (!op || !x || !y) return fail(MAS_EINVAL, "op, x and y must not be NULL");
+    if (x == y) return fail(MAS_EINVAL, "x and y must be distinct");
+    hipLaunchKernelGGL(k_apply, op->s.simple_grid(), dim3(kWave, kSimpleJ), 0, as_stream(hip_stream),
+                       op->w, op->c64[0], op->c64[1], op->c64[2], op->s.dims(), x, y);
+    LAUNCHCHK();
+    return MAS_OK;
+}
+
+extern "C" int mas_op_export(const mas_op *op, double *cr, double *ct, double *cp, double *diag,
+                             void *hip_stream) {
+    if (!op) return fail(MAS_EINVAL, "op must not be NULL");
+    hipLaunchKernelGGL(k_export, op->s.simple_grid(), dim3(kWave, kSimpleJ), 0,
+                       as_stream(hip_stream), op->w, op->c64[0], op->c64[1], op->c64[2],
+                       op->s.dims(), cr, ct, cp, diag);
+    LAUNCHCHK();
+    return MAS_OK;
+}
+
+// ------------------------------------------------------------------ workspace
+struct WorkLayout {
+    int64_t ctl, partials, bhat, vec[6], dh, total;
+};
+
+static WorkLayout work_layout(const Shape &s, int precision) {
+    WorkLayout L{};
+    int64_t off = 0;
+    auto take = [&](int64_t bytes) {
+        int64_t o = off;
+        off = align256(off + bytes);
+        return o;
+    };
+    const int64_t nparts = std::max(s.nblk_iter() * kNV, s.nblk_simple());
+    L.ctl = take(sizeof(Ctl));
+    L.partials = take(8 * nparts);
+    L.bhat = take(8 * s.n);
+    const int64_t es = (precision == MAS_FP32_REFINED) ? 4 : 8;
+    for (int t = 0; t < 6; ++t) L.vec[t] = take(es * s.n);
+    L.dh = (precision == MAS_FP32_REFINED) ? take(4 * s.n) : -1;
+    L.total = off;
+    return L;
+}
+
+static int check_opts(const mas_op *op, const mas_pcg_opts *o) {
+    if (!(o->rtol >= 0.0)) return fail(MAS_EINVAL, "rtol must be >= 0");
+    if (o->max_iters < 0) return fail(MAS_EINVAL, "max_iters must be >= 0");
+    if (o->check_every < 1) return fail(MAS_EINVAL, "check_every must be >= 1");
+    if (o->precision != MAS_FP64 && o->precision != MAS_FP32_REFINED)
+        return fail(MAS_EINVAL, "unknown precision %d", o->precision);
+    if (o->precision == MAS_FP32_REFINED) {
+        if (!op->c32[0])
+            return fail(MAS_EINVAL, "operator was built without single-precision coefficients");
+        if (!(o->inner_rtol > 0.0 && o->inner_rtol < 1.0))
+            return fail(MAS_EINVAL, "inner_rtol must lie in (0, 1)");
+        if (o->max_outer < 1) return fail(MAS_EINVAL, "max_outer must be >= 1");
+    }
+    if (o->max_restarts < 0) return fail(MAS_EINVAL, "max_restarts must be >= 0");
+    return MAS_OK;
+}
+
+extern "C" int64_t mas_pcg_workspace_bytes(const mas_op *op, const mas_pcg_opts *o) {
+    if (!op) return fail(MAS_EINVAL, "op must not be NULL");
+    mas_pcg_opts def;
+    mas_pcg_default_opts(&def);
+    if (!o) o = &def;
+    return work_layout(op->s, o->precision).total;
+}
+
+// ------------------------------------------------------------------ drivers
+namespace {
+
+struct Pinned {
+    int32_t *p = nullptr;
+    ~Pinned() {
+        if (p) (void)hipHostFree(p);
+    }
+};
+static thread_local Pinned g_pinned;
+
+static int pinned_buffer(int32_t **out) {
+    if (!g_pinned.p) {
+        void *p = nullptr;
+        HIPCHK(hipHostMalloc(&p, 4096, hipHostMallocDefault));
+        g_pinned.p = static_cast<int32_t *>(p);
+    }
+    *out = g_pinned.p;
+    return MAS_OK;
+}
+
+struct Ctx {
+    const mas_op *op;
+    hipStream_t stream;
+    Ctl *ctl;
+    double *partials;
+    double *bhat;
+    bool timing;
+    // event samples of the iteration kernel
+    std::vector<hipEvent_t> ev;
+    std::vector<int> ev_iter;
+    ~Ctx() {
+        for (auto e : ev) (void)hipEventDestroy(e);
+    }
+};
+
+// Host copy of the control block (synchronous).
+static int read_ctl(Ctx &cx, Ctl *h) {
+    HIPCHK(hipMemcpyAsync(h, cx.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, cx.stream));
+    HIPCHK(hipStreamSynchronize(cx.stream));
+    return MAS_OK;
+}
+
+// Sum the simple-kernel partials into ctl->sums[0] and return it.
+static int reduce1(Ctx &cx, double *out) {
+    const int nblk = (int)cx.op->s.nblk_simple();
+    hipLaunchKernelGGL(k_reduce, dim3(1), dim3(kRedThreads), 0, cx.stream, cx.partials, nblk, 1,
+                       cx.ctl);
+    LAUNCHCHK();
+    HIPCHK(hipMemcpyAsync(out, &cx.ctl->sums[0], sizeof(double), hipMemcpyDeviceToHost, cx.stream));
+    HIPCHK(hipStreamSynchronize(cx.stream));
+    return MAS_OK;
+}
+
+// r^ = b^ - A^ x^ in double precision, stored as T into r; returns ||W r^||^2.
+template <typename T>
+static int residual(Ctx &cx, const double *xhat, T *r, double *rw2) {
+    const mas_op *op = cx.op;
+    hipLaunchKernelGGL(k_residual<T>, op->s.simple_grid(), dim3(kWave, kSimpleJ), 0, cx.stream,
+                       cx.bhat, xhat, op->w, op->c64[0], op->c64[1], op->c64[2], op->s.dims(), r,
+                       cx.partials);
+    LAUNCHCHK();
+    return reduce1(cx, rw2);
+}
+
+struct PcgResult {
+    int flag;
+    int last_iter;  // index of the last iteration kernel that did work
+};
+
+// PCG iterations on the scaled system in precision T.  Before the call,
+// r[iter0 % 2] holds r_{iter0} and x holds x_{iter0}.  mode 0 stops on
+// ||W r||^2 <= tol2 (checked every check_every iterations), mode 1 on
+// (r,r) <= inner_rtol2 (r_0,r_0).
+template <typename T>
+static int run_pcg(Ctx &cx, T *const r[2], T *const p[2], T *const q[2], T *x, const T *const c[3],
+                   int mode, int iter0, int max_iter, int check_every, double tol2,
+                   double inner_rtol2, PcgResult *res) {
+    const mas_op *op = cx.op;
+    const Shape &s = op->s;
+    hipStream_t st = cx.stream;
+    hipLaunchKernelGGL(k_ctl_init, dim3(1), dim3(64), 0, st, cx.ctl, mode, iter0, max_iter, tol2,
+                       inner_rtol2);
+    LAUNCHCHK();
+    int32_t *pin = nullptr;
+    int e = pinned_buffer(&pin);
+    if (e != MAS_OK) return e;
+
+    IterArgs<T> a{};
+    a.cr = c[0];
+    a.ct = c[1];
+    a.cp = c[2];
+    a.w = op->w;
+    a.partials = cx.partials;
+    a.ctl = cx.ctl;
+    a.d = s.dims();
+    a.tiles_k = s.tiles_k();
+    a.tiles_j = s.tiles_j();
+    a.ti = kTI;
+    a.nblk = (int)s.nblk_iter();
+    a.x = x;
+    const dim3 grid((unsigned)a.nblk), block(kWave * kTJ);
+
+    // batches of launches; the host polls the device flag one batch behind
+    const int batch = std::max(check_every, 16);
+    hipEvent_t done[2] = {nullptr, nullptr};
+    HIPCHK(hipEventCreateWithFlags(&done[0], hipEventDisableTiming));
+    HIPCHK(hipEventCreateWithFlags(&done[1], hipEventDisableTiming));
+    struct EvGuard {
+        hipEvent_t *e;
+        ~EvGuard() {
+            (void)hipEventDestroy(e[0]);
+            (void)hipEventDestroy(e[1]);
+        }
+    } guard{done};
+
+    int k = iter0;
+    int nb = 0;
+    bool stop = false;
+    while (!stop && k <= max_iter) {
+        const int kend = std::min(max_iter, k + batch - 1);
+        for (; k <= kend; ++k) {
+            const int cur = k & 1, nxt = cur ^ 1;
+            a.r_in = r[cur];
+            a.p_in = p[cur];
+            a.q_in = q[cur];
+            a.r_out = r[nxt];
+            a.p_out = p[nxt];
+            a.q_out = q[nxt];
+            const bool chk = (mode == 0) && ((k % check_every) == 0 || k == max_iter);
+            const bool sample = cx.timing && (k % 16 == 7) && cx.ev.size() < 128;
+            if (sample) {
+                hipEvent_t e0, e1;
+                HIPCHK(hipEventCreate(&e0));
+                HIPCHK(hipEventCreate(&e1));
+                cx.ev.push_back(e0);
+                cx.ev.push_back(e1);
+                cx.ev_iter.push_back(k);
+                HIPCHK(hipEventRecord(e0, st));
+            }
+            if (chk)
+                hipLaunchKernelGGL((k_pcg_iter<T, kTJ, true>), grid, block, 0, st, a);
+            else
+                hipLaunchKernelGGL((k_pcg_iter<T, kTJ, false>), grid, block, 0, st, a);
+            if (sample) HIPCHK(hipEventRecord(cx.ev.back(), st));
+            hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kRedThreads), 0, st, cx.partials, a.nblk,
+                               cx.ctl, chk ? 1 : 0);
+        }
+        LAUNCHCHK();
+        HIPCHK(hipMemcpyAsync(pin + 2 * (nb & 1), &cx.ctl->flag, 2 * sizeof(int32_t),
+                              hipMemcpyDeviceToHost, st));
+        HIPCHK(hipEventRecord(done[nb & 1], st));
+        if (nb > 0) {
+            HIPCHK(hipEventSynchronize(done[(nb - 1) & 1]));
+            if (pin[2 * ((nb - 1) & 1)] != FLAG_RUN) stop = true;
+        }
+        ++nb;
+    }
+    HIPCHK(hipStreamSynchronize(st));
+    Ctl h;
+    e = read_ctl(cx, &h);
+    if (e != MAS_OK) return e;
+    res->flag = h.flag;
+    res->last_iter = (h.flag == FLAG_RUN) ? max_iter : h.conv_iter;
+    return MAS_OK;
+}
+
+static void timing_summary(Ctx &cx, int last_iter, mas_pcg_info *info) {
+    double tot = 0.0;
+    int n = 0;
+    for (size_t t = 0; t < cx.ev_iter.size(); ++t) {
+        if (cx.ev_iter[t] > last_iter) continue;
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, cx.ev[2 * t], cx.ev[2 * t + 1]) == hipSuccess) {
+            tot += ms;
+            ++n;
+        }
+    }
+    if (n > 0) {
+        // running mean over all solves of this call
+        const double prev = info->iter_kernel_us * info->iter_kernel_samples;
+        info->iter_kernel_samples += n;
+        info->iter_kernel_us = (prev + 1000.0 * tot) / info->iter_kernel_samples;
+    }
+    for (auto ev : cx.ev) (void)hipEventDestroy(ev);
+    cx.ev.clear();
+    cx.ev_iter.clear();
+}
+
+static int status_from_flag(int flag) {
+    switch (flag) {
+        case FLAG_CONV: return MAS_OK;
+        case FLAG_BREAK: return MAS_EBREAKDOWN;
+        default: return MAS_ENOTCONV;
+    }
+}
+
+// Solve A x = b with b = V src (src_is_rhs) or b = src; result (unscaled) in x.
+static int solve_core(const mas_op *op, const double *src, int src_is_rhs, double *x,
+                      const mas_pcg_opts *o_in, void *work, int64_t work_bytes, void *hip_stream,
+                      mas_pcg_info *info_out) {
+    const auto t0 = std::chrono::steady_clock::now();
+    mas_pcg_info info{};
+    mas_pcg_opts o;
+    mas_pcg_default_opts(&o);
+    if (o_in) o = *o_in;
+    if (!op || !src || !x || !work)
+        return fail(MAS_EINVAL, "op, right-hand side, solution and work must not be NULL");
+    int st = check_opts(op, &o);
+    if (st != MAS_OK) return st;
+    if (reinterpret_cast<uintptr_t>(work) & 255)
+        return fail(MAS_EINVAL, "work must be 256-byte aligned");
+    const Shape &s = op->s;
+    const WorkLayout L = work_layout(s, o.precision);
+    if (work_bytes < L.total)
+        return fail(MAS_ENOMEM, "workspace too small: %lld < %lld bytes", (long long)work_bytes,
+                    (long long)L.total);
+
+    char *base = static_cast<char *>(work);
+    Ctx cx;
+    cx.op = op;
+    cx.stream = as_stream(hip_stream);
+    cx.ctl = reinterpret_cast<Ctl *>(base + L.ctl);
+    cx.partials = reinterpret_cast<double *>(base + L.partials);
+    cx.bhat = reinterpret_cast<double *>(base + L.bhat);
+    cx.timing = o.sample_timing != 0;
+    const Dims d = s.dims();
+    const dim3 sgrid = s.simple_grid(), sblock(kWave, kSimpleJ);
+
+    // b^ = W^-1 b, x^ = W x0 or 0, ||b||^2
+    hipLaunchKernelGGL(k_setup, sgrid, sblock, 0, cx.stream, src, src_is_rhs, op->w, op->geo, d,
+                       cx.bhat, x, o.use_x0 ? 1 : 0, cx.partials);
+    LAUNCHCHK();
+    double b2 = 0.0;
+    st = reduce1(cx, &b2);
+    if (st != MAS_OK) return st;
+    const double bnorm = std::sqrt(b2);
+    info.bnorm = bnorm;
+    if (!std::isfinite(bnorm)) return fail(MAS_EINVAL, "right-hand side is not finite");
+    const double tol2 = (o.rtol * bnorm) * (o.rtol * bnorm);
+    int status = MAS_OK;
+
+    if (bnorm == 0.0) {
+        hipLaunchKernelGGL(k_fill<double>, sgrid, sblock, 0, cx.stream, x, d, 0.0);
+        LAUNCHCHK();
+        HIPCHK(hipStreamSynchronize(cx.stream));
+        info.status = MAS_OK;
+        info.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+        if (info_out) *info_out = info;
+        return MAS_OK;
+    }
+
+    if (o.precision == MAS_FP64) {
+        double *v[6];
+        for (int t = 0; t < 6; ++t) v[t] = reinterpret_cast<double *>(base + L.vec[t]);
+        double *const r[2] = {v[0], v[1]}, *const p[2] = {v[2], v[3]}, *const q[2] = {v[4], v[5]};
+        const double *const c[3] = {op->c64[0], op->c64[1], op->c64[2]};
+        double rw2 = 0.0;
+        st = residual<double>(cx, x, r[0], &rw2);
+        if (st != MAS_OK) return st;
+        info.rel_resid_true = info.rel_resid_recursive = std::sqrt(rw2) / bnorm;
+        int iter0 = 0;
+        status = MAS_ENOTCONV;
+        if (rw2 <= tol2) status = MAS_OK;
+        while (status != MAS_OK) {
+            if (iter0 > o.max_iters) break;
+            PcgResult pr{};
+            st = run_pcg<double>(cx, r, p, q, x, c, 0, iter0, o.max_iters, o.check_every, tol2, 0.0,
+                                 &pr);
+            if (st != MAS_OK) return st;
+            timing_summary(cx, pr.last_iter, &info);
+            info.iters = pr.last_iter;
+            Ctl h;
+            st = read_ctl(cx, &h);
+            if (st != MAS_OK) return st;
+            info.rel_resid_recursive = std::sqrt(h.rw) / bnorm;
+            if (pr.flag == FLAG_BREAK) {
+                status = MAS_EBREAKDOWN;
+                break;
+            }
+            // true residual of x_k into the buffer the next iteration reads
+            const int nxt = (pr.last_iter + 1) & 1;
+            st = residual<double>(cx, x, r[nxt], &rw2);
+            if (st != MAS_OK) return st;
+            info.rel_resid_true = std::sqrt(rw2) / bnorm;
+            if (rw2 <= tol2) {
+                status = MAS_OK;
+                break;
+            }
+            if (pr.flag != FLAG_CONV || info.restarts >= o.max_restarts) {
+                status = MAS_ENOTCONV;
+                break;
+            }
+            ++info.restarts;
+            iter0 = pr.last_iter + 1;
+        }
+    } else {
+        float *v[6];
+        for (int t = 0; t < 6; ++t) v[t] = reinterpret_cast<float *>(base + L.vec[t]);
+        float *dh = reinterpret_cast<float *>(base + L.dh);
+        float *const r[2] = {v[0], v[1]}, *const p[2] = {v[2], v[3]}, *const q[2] = {v[4], v[5]};
+        const float *const c[3] = {op->c32[0], op->c32[1], op->c32[2]};
+        double rw2 = 0.0;
+        st = residual<float>(cx, x, r[0], &rw2);
+        if (st != MAS_OK) return st;
+        info.rel_resid_true = std::sqrt(rw2) / bnorm;
+        status = (rw2 <= tol2) ? MAS_OK : MAS_ENOTCONV;
+        int used = 0;
+        while (status != MAS_OK && info.outer_iters < o.max_outer && used < o.max_iters) {
+            hipLaunchKernelGGL(k_fill<float>, sgrid, sblock, 0, cx.stream, dh, d, 0.0f);
+            LAUNCHCHK();
+            PcgResult pr{};
+            st = run_pcg<float>(cx, r, p, q, dh, c, 1, 0, o.max_iters - used, 1, 0.0,
+                                o.inner_rtol * o.inner_rtol, &pr);
+            if (st != MAS_OK) return st;
+            timing_summary(cx, pr.last_iter, &info);
+            if (pr.flag == FLAG_BREAK && pr.last_iter == 0) {
+                status = MAS_EBREAKDOWN;
+                break;
+            }
+            used += pr.last_iter;
+            info.outer_iters++;
+            Ctl h;
+            st = read_ctl(cx, &h);
+            if (st != MAS_OK) return st;
+            hipLaunchKernelGGL(k_refine_add, sgrid, sblock, 0, cx.stream, dh, d, x);
+            LAUNCHCHK();
+            st = residual<float>(cx, x, r[0], &rw2);
+            if (st != MAS_OK) return st;
+            info.rel_resid_true = std::sqrt(rw2) / bnorm;
+            status = (rw2 <= tol2) ? MAS_OK : MAS_ENOTCONV;
+            if (pr.flag == FLAG_BREAK && status != MAS_OK) {
+                status = MAS_EBREAKDOWN;
+                break;
+            }
+        }
+        info.iters = used;
+        info.rel_resid_recursive = info.rel_resid_true;
+    }
+
+    hipLaunchKernelGGL(k_unscale, sgrid, sblock, 0, cx.stream, op->w, d, x);
+    LAUNCHCHK();
+    HIPCHK(hipStreamSynchronize(cx.stream));
+    info.status = status;
+    info.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    if (info_out) *info_out = info;
+    if (status == MAS_ENOTCONV)
+        fail(status, "tolerance not reached (relative residual %.3e)", info.rel_resid_true);
+    if (status == MAS_EBREAKDOWN) fail(status, "PCG breakdown: (p, A p) <= 0 or not finite");
+    return status;
+}
+
+}  // namespace
+
+extern "C" int mas_pcg_solve(const mas_op *op, const double *rhs, double *x, const mas_pcg_opts *o,
+                             void *work, int64_t work_bytes, void *hip_stream, mas_pcg_info *info) {
+    g_last_error.clear();
+    return solve_core(op, rhs, 1, x, o, work, work_bytes, hip_stream, info);
+}
+
+extern "C" int mas_pcg_solve_adjoint(const mas_op *op, const double *x, const double *gx,
+                                     double *lambda, double *g_nu, double *g_rhs,
+                                     const mas_pcg_opts *o, void *work, int64_t work_bytes,
+                                     void *hip_stream, mas_pcg_info *info) {
+    g_last_error.clear();
+    if (!op || !x || !gx || !lambda || !g_nu)
+        return fail(MAS_EINVAL, "op, x, gx, lambda and g_nu must not be NULL");
+    int st = solve_core(op, gx, 0, lambda, o, work, work_bytes, hip_stream, info);
+    if (st < 0) return st;
+    hipLaunchKernelGGL(k_gradient, op->s.simple_grid(), dim3(kWave, kSimpleJ), 0,
+                       as_stream(hip_stream), x, lambda, op->geo, op->s.dims(), g_nu, g_rhs);
+    LAUNCHCHK();
+    HIPCHK(hipStreamSynchronize(as_stream(hip_stream)));
+    return st;
+}
+
+extern "C" int mas_probe_copy(const void *src, void *dst, int64_t bytes, void *hip_stream) {
+    if (!src || !dst) return fail(MAS_EINVAL, "src and dst must not be NULL");
+    if (bytes < 0 || (bytes & 15) || (reinterpret_cast<uintptr_t>(src) & 15) ||
+        (reinterpret_cast<uintptr_t>(dst) & 15))
+        return fail(MAS_EINVAL, "copy needs 16-byte aligned pointers and a multiple of 16 bytes");
+    const int64_t n16 = bytes / 16;
+    if (n16 == 0) return MAS_OK;
+    const int64_t blocks = std::min<int64_t>((n16 + 255) / 256, 256 * 64);
+    hipLaunchKernelGGL(k_copy16, dim3((unsigned)blocks), dim3(256), 0, as_stream(hip_stream),
+                       static_cast<const double2 *>(src), static_cast<double2 *>(dst), n16);
+    LAUNCHCHK();
+    return MAS_OK;
+}
+
+extern "C" const char *mas_status_string(int status) {
+    switch (status) {
+        case MAS_OK: return "MAS_OK: converged";
+        case MAS_ENOTCONV: return "MAS_ENOTCONV: tolerance not reached";
+        case MAS_EINVAL: return "MAS_EINVAL: invalid argument";
+        case MAS_EBREAKDOWN: return "MAS_EBREAKDOWN: PCG breakdown";
+        case MAS_EHIP: return "MAS_EHIP: HIP runtime error";
+        case MAS_ENOMEM: return "MAS_ENOMEM: storage or workspace too small";
+        default: return "unknown status";
+    }
+}
+
+extern "C" const char *mas_last_error(void) { return g_last_error.c_str(); }

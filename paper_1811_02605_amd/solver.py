@@ -1,0 +1,223 @@
+"""PyTorch-facing layer over the C ABI.
+
+PyTorch provides device memory (operator storage, workspace, vectors) and
+the current HIP stream; every step of the solve runs in the HIP library.
+Nothing here computes on tensors.
+
+    grid = Grid(r_faces, t_faces, np)
+    op = Operator(grid, nu, dt, precision="fp64")        # mas_op_build
+    x, info = op.solve(rhs)                              # mas_pcg_solve
+    lam, g_nu, g_rhs, info = op.adjoint(x, gx)           # mas_pcg_solve_adjoint
+    x = solve(nu, rhs, grid, dt)                          # differentiable (MasSolve)
+"""
+from __future__ import annotations
+
+import ctypes
+import warnings
+
+import numpy as np
+import torch
+
+from . import _abi as abi
+
+PRECISIONS = {"fp64": abi.MAS_FP64, "fp32_refined": abi.MAS_FP32_REFINED}
+
+
+class Grid:
+    """Radial and colatitude faces (host, float64) and the phi cell count."""
+
+    def __init__(self, r_faces, t_faces, np_, bc_inner=abi.MAS_BC_DIRICHLET0,
+                 bc_outer=abi.MAS_BC_DIRICHLET0):
+        self.r_faces = np.ascontiguousarray(r_faces, dtype=np.float64)
+        self.t_faces = np.ascontiguousarray(t_faces, dtype=np.float64)
+        self.nr = self.r_faces.size - 1
+        self.nt = self.t_faces.size - 1
+        self.np = int(np_)
+        self.bc_inner = int(bc_inner)
+        self.bc_outer = int(bc_outer)
+
+    @property
+    def shape(self):
+        return (self.nr, self.nt, self.np)
+
+    @property
+    def n(self):
+        return self.nr * self.nt * self.np
+
+    def c_struct(self) -> abi.mas_grid:
+        dp = ctypes.POINTER(ctypes.c_double)
+        return abi.mas_grid(self.nr, self.nt, self.np, self.r_faces.ctypes.data_as(dp),
+                            self.t_faces.ctypes.data_as(dp), self.bc_inner, self.bc_outer)
+
+    @classmethod
+    def from_problem(cls, p):
+        return cls(p.r_faces, p.t_faces, p.cfg.np_, p.bc_inner, p.bc_outer)
+
+
+def make_opts(rtol=None, max_iters=None, precision=None, inner_rtol=None, max_outer=None,
+              check_every=None, use_x0=None, max_restarts=None, sample_timing=None):
+    o = abi.default_opts()
+    if isinstance(precision, str):
+        precision = PRECISIONS[precision]
+    for name, v in dict(rtol=rtol, max_iters=max_iters, precision=precision,
+                        inner_rtol=inner_rtol, max_outer=max_outer, check_every=check_every,
+                        use_x0=use_x0, max_restarts=max_restarts,
+                        sample_timing=sample_timing).items():
+        if v is not None:
+            setattr(o, name, type(getattr(o, name))(v))
+    return o
+
+
+def _stream(device) -> int:
+    return torch.cuda.current_stream(device).cuda_stream
+
+
+def _check_vec(t: torch.Tensor, shape, name):
+    if not isinstance(t, torch.Tensor) or t.dtype != torch.float64 or not t.is_cuda:
+        raise TypeError(f"{name} must be a float64 CUDA/HIP tensor")
+    if tuple(t.shape) != tuple(shape) and t.numel() != int(np.prod(shape)):
+        raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {tuple(shape)}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+
+
+def _device_bytes(nbytes: int, device) -> torch.Tensor:
+    buf = torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=device)
+    if buf.data_ptr() % 256:
+        raise RuntimeError("device allocation is not 256-byte aligned")
+    return buf
+
+
+class Operator:
+    """A(nu, dt) built by mas_op_build into torch-owned device storage."""
+
+    def __init__(self, grid: Grid, nu: torch.Tensor, dt: float, precision="fp64"):
+        lib = abi.load()
+        _check_vec(nu, grid.shape, "nu")
+        self.grid = grid
+        self.device = nu.device
+        self.dt = float(dt)
+        self.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+        g = grid.c_struct()
+        nbytes = lib.mas_op_storage_bytes(ctypes.byref(g), self.precision)
+        abi.check(int(nbytes) if nbytes < 0 else 0, "mas_op_storage_bytes")
+        self.storage = _device_bytes(nbytes, self.device)
+        h = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            st = lib.mas_op_build(ctypes.byref(g), nu.data_ptr(), self.dt, self.precision,
+                                  self.storage.data_ptr(), nbytes, _stream(self.device),
+                                  ctypes.byref(h))
+        abi.check(st, "mas_op_build")
+        self._h = h
+        self._work = {}
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            abi.load().mas_op_destroy(h)
+            self._h = None
+
+    @property
+    def handle(self):
+        return self._h
+
+    def apply(self, x: torch.Tensor) -> torch.Tensor:
+        _check_vec(x, self.grid.shape, "x")
+        y = torch.empty_like(x)
+        with torch.cuda.device(self.device):
+            abi.check(abi.load().mas_op_apply(self._h, x.data_ptr(), y.data_ptr(),
+                                              _stream(self.device)), "mas_op_apply")
+        return y
+
+    def export(self):
+        """(cr, ct, cp, diag): couplings to the +r/+theta/+phi neighbours and diag(A)."""
+        outs = [torch.empty(self.grid.shape, dtype=torch.float64, device=self.device)
+                for _ in range(4)]
+        with torch.cuda.device(self.device):
+            abi.check(abi.load().mas_op_export(self._h, *[o.data_ptr() for o in outs],
+                                               _stream(self.device)), "mas_op_export")
+        return tuple(outs)
+
+    def workspace(self, opts) -> tuple[torch.Tensor, int]:
+        nbytes = int(abi.load().mas_pcg_workspace_bytes(self._h, ctypes.byref(opts)))
+        abi.check(nbytes if nbytes < 0 else 0, "mas_pcg_workspace_bytes")
+        buf = self._work.get(opts.precision)
+        if buf is None or buf.numel() < nbytes:
+            buf = _device_bytes(nbytes, self.device)
+            self._work[opts.precision] = buf
+        return buf, nbytes
+
+    def solve(self, rhs: torch.Tensor, opts=None, x0: torch.Tensor | None = None,
+              out: torch.Tensor | None = None, allow_notconv=True):
+        """x = A^-1 (V .* rhs).  Returns (x, info dict)."""
+        _check_vec(rhs, self.grid.shape, "rhs")
+        opts = opts if opts is not None else make_opts()
+        x = out if out is not None else torch.empty_like(rhs)
+        if x0 is not None:
+            x.copy_(x0)
+            opts.use_x0 = 1
+        work, nbytes = self.workspace(opts)
+        info = abi.mas_pcg_info()
+        with torch.cuda.device(self.device):
+            st = abi.load().mas_pcg_solve(self._h, rhs.data_ptr(), x.data_ptr(), ctypes.byref(opts),
+                                          work.data_ptr(), nbytes, _stream(self.device),
+                                          ctypes.byref(info))
+        abi.check(st, "mas_pcg_solve", allow_notconv=allow_notconv)
+        if st == abi.MAS_ENOTCONV:
+            warnings.warn(f"mas_pcg_solve did not converge: {info.as_dict()}")
+        return x, info.as_dict()
+
+    def adjoint(self, x: torch.Tensor, gx: torch.Tensor, opts=None, allow_notconv=True):
+        """(lambda, dL/dnu, dL/drhs, info) for dL/dx = gx at the solution x."""
+        _check_vec(x, self.grid.shape, "x")
+        _check_vec(gx, self.grid.shape, "gx")
+        opts = opts if opts is not None else make_opts()
+        lam = torch.empty_like(x)
+        gnu = torch.empty_like(x)
+        grhs = torch.empty_like(x)
+        work, nbytes = self.workspace(opts)
+        info = abi.mas_pcg_info()
+        with torch.cuda.device(self.device):
+            st = abi.load().mas_pcg_solve_adjoint(
+                self._h, x.data_ptr(), gx.data_ptr(), lam.data_ptr(), gnu.data_ptr(),
+                grhs.data_ptr(), ctypes.byref(opts), work.data_ptr(), nbytes,
+                _stream(self.device), ctypes.byref(info))
+        abi.check(st, "mas_pcg_solve_adjoint", allow_notconv=allow_notconv)
+        return lam, gnu, grhs, info.as_dict()
+
+
+def probe_copy(src: torch.Tensor, dst: torch.Tensor):
+    nbytes = src.numel() * src.element_size()
+    assert dst.numel() * dst.element_size() >= nbytes
+    with torch.cuda.device(src.device):
+        abi.check(abi.load().mas_probe_copy(src.data_ptr(), dst.data_ptr(), nbytes,
+                                            _stream(src.device)), "mas_probe_copy")
+
+
+class MasSolve(torch.autograd.Function):
+    """x = A(nu)^-1 (V .* rhs); backward runs the adjoint solve and the fused
+    dL/dnu, dL/drhs kernel in the HIP library."""
+
+    @staticmethod
+    def forward(ctx, nu, rhs, grid, dt, opts_kw):
+        opts_kw = dict(opts_kw or {})
+        op = Operator(grid, nu.detach().contiguous(), dt,
+                      precision=opts_kw.get("precision", "fp64"))
+        x, info = op.solve(rhs.detach().contiguous(), make_opts(**opts_kw), allow_notconv=False)
+        ctx.op = op
+        ctx.opts_kw = opts_kw
+        ctx.save_for_backward(x)
+        ctx.info = info
+        return x
+
+    @staticmethod
+    def backward(ctx, gx):
+        (x,) = ctx.saved_tensors
+        opts = make_opts(**ctx.opts_kw)
+        _, gnu, grhs, _ = ctx.op.adjoint(x, gx.contiguous(), opts, allow_notconv=False)
+        return gnu, grhs, None, None, None
+
+
+def solve(nu: torch.Tensor, rhs: torch.Tensor, grid: Grid, dt: float, **opts) -> torch.Tensor:
+    """Differentiable implicit viscous step: gradients flow to nu and rhs."""
+    return MasSolve.apply(nu, rhs, grid, dt, opts)

@@ -1,0 +1,230 @@
+"""GPU parity against the FP64 CPU oracle on seeded inputs (small and ragged
+grids spanning several tiles: 64-wide phi segments, 8-row theta tiles and
+32-plane r chunks, with ragged tails in every direction)."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+from gpu_util import (DEV, gpu_operator, oracle_operator, oracle_plus_face_arrays, problem, rel,
+                      to_dev, to_host)
+from oracle import dense
+from paper_1811_02605_amd import _abi as abi
+from paper_1811_02605_amd import solver as S
+
+pytestmark = pytest.mark.gpu
+
+# (nr, nt, np): single tile, ragged phi (70, 129), ragged theta (7, 17), two r
+# chunks (33, 65), degenerate 1-cell directions, the small benchmark grid.
+SHAPES = [(4, 4, 8), (5, 7, 13), (3, 9, 70), (33, 17, 129), (65, 8, 64), (1, 3, 2), (6, 3, 1),
+          (2, 1, 5), (9, 16, 32)]
+BCS = [(0, 0), (1, 0), (1, 1)]
+
+# Elementwise bound for the exported entries: both sides form each conductance
+# with ~10 roundings in a different order, and the scaled storage adds 4 more
+# (c^ = c/(w_a w_b), then w_a c^ w_b): well under 64 ulp.
+EXPORT_RTOL = 64 * 2.0 ** -52
+
+
+@pytest.mark.parametrize("shape", SHAPES + ["c0"])
+@pytest.mark.parametrize("bc", BCS)
+def test_exported_operator_matches_oracle(shape, bc):
+    p = problem(shape, bc)
+    _, op = gpu_operator(p)
+    got = [to_host(t) for t in op.export()]
+    want = oracle_plus_face_arrays(oracle_operator(p))
+    for name, g, w in zip(("cr", "ct", "cp", "diag"), got, want):
+        np.testing.assert_allclose(g, w, rtol=EXPORT_RTOL, atol=0, err_msg=name)
+    # exact zeros: last r plane, pole rows
+    assert np.all(got[0][-1] == 0.0) and np.all(got[1][:, -1] == 0.0)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32_refined"])
+@pytest.mark.parametrize("shape", SHAPES + ["c0"])
+def test_apply_matches_oracle(shape, precision):
+    p = problem(shape, (0, 1))
+    _, op = gpu_operator(p, precision)
+    ora = oracle_operator(p)
+    x = np.random.default_rng(11).standard_normal(p.shape)
+    y = to_host(op.apply(to_dev(x)))
+    assert rel(y, ora.apply(x)) <= 1e-13
+
+
+@pytest.mark.parametrize("shape", SHAPES + ["c0"])
+@pytest.mark.parametrize("bc", [(0, 0), (1, 1)])
+def test_fp64_solve_matches_oracle(shape, bc):
+    p = problem(shape, bc)
+    _, op = gpu_operator(p)
+    ora = oracle_operator(p)
+    x, info = op.solve(to_dev(p.rhs), S.make_opts(rtol=1e-10), allow_notconv=False)
+    x = to_host(x)
+    b = ora.rhs_to_b(p.rhs)
+    res = ora.rel_residual(b, x)
+    assert res <= 1e-10, res
+    assert info["rel_resid_true"] <= 1e-10
+    assert abs(info["rel_resid_true"] - res) <= 1e-3 * res + 1e-15
+    xo, it_o, _, _ = ora.pcg(b, tol=1e-13)
+    err = rel(x, xo)
+    print(f"{shape} bc={bc}: iters gpu {info['iters']} oracle(1e-13) {it_o}; "
+          f"residual {res:.2e}; error vs oracle {err:.2e}")
+    assert err <= 1e-6
+
+
+def test_iteration_count_tracks_oracle_at_small_config():
+    p = problem("c0")
+    _, op = gpu_operator(p)
+    ora = oracle_operator(p)
+    x, info = op.solve(to_dev(p.rhs), S.make_opts(rtol=1e-10, check_every=1), allow_notconv=False)
+    _, it_o, _, _ = ora.pcg(ora.rhs_to_b(p.rhs), tol=1e-10)
+    assert abs(info["iters"] - it_o) <= max(2, 0.03 * it_o), (info["iters"], it_o)
+
+
+@pytest.mark.parametrize("k", [0, 1, 2, 5, 20])
+@pytest.mark.parametrize("shape", [(5, 7, 13), (33, 17, 129), "c0"])
+def test_iterates_match_oracle(shape, k):
+    # the GPU's scaled single-reduction recurrence and the oracle's classical
+    # PCG produce the same iterates in exact arithmetic
+    p = problem(shape)
+    _, op = gpu_operator(p)
+    ora = oracle_operator(p)
+    x, info = op.solve(to_dev(p.rhs), S.make_opts(rtol=0.0, max_iters=k, check_every=1))
+    assert info["status"] == abi.MAS_ENOTCONV and info["iters"] == k
+    xo = ora.pcg(ora.rhs_to_b(p.rhs), tol=0.0, max_iters=k)[0]
+    e = rel(to_host(x), xo)
+    assert e <= 1e-11 * max(1, k), e
+
+
+@pytest.mark.parametrize("shape", [(5, 7, 13), (33, 17, 129), (1, 3, 2), "c0"])
+def test_mixed_precision_reaches_fp64_residual(shape):
+    p = problem(shape)
+    _, op = gpu_operator(p, "fp32_refined")
+    ora = oracle_operator(p)
+    x, info = op.solve(to_dev(p.rhs), S.make_opts(rtol=1e-10, precision="fp32_refined"),
+                       allow_notconv=False)
+    x = to_host(x)
+    b = ora.rhs_to_b(p.rhs)
+    res = ora.rel_residual(b, x)
+    xo = ora.pcg(b, tol=1e-13)[0]
+    print(f"{shape} refined: outer {info['outer_iters']} inner {info['iters']} "
+          f"residual {res:.2e} error vs FP64 oracle {rel(x, xo):.2e}")
+    assert res <= 1e-10 and info["rel_resid_true"] <= 1e-10
+    assert info["outer_iters"] >= 2
+    assert rel(x, xo) <= 1e-6
+
+
+def test_fp64_solve_is_bitwise_deterministic():
+    p = problem((33, 17, 129))
+    _, op = gpu_operator(p)
+    rhs = to_dev(p.rhs)
+    x1, i1 = op.solve(rhs)
+    x2, i2 = op.solve(rhs)
+    assert torch.equal(x1, x2) and i1["iters"] == i2["iters"]
+    _, opm = gpu_operator(p, "fp32_refined")
+    o = S.make_opts(precision="fp32_refined")
+    y1, _ = opm.solve(rhs, o)
+    y2, _ = opm.solve(rhs, o)
+    assert torch.equal(y1, y2)
+
+
+def test_warm_start_from_solution():
+    p = problem((9, 16, 32))
+    _, op = gpu_operator(p)
+    ora = oracle_operator(p)
+    xs = dense.dense_solve(ora, ora.rhs_to_b(p.rhs)) if p.cfg.n <= 600 else \
+        ora.pcg(ora.rhs_to_b(p.rhs), tol=1e-14)[0]
+    x, info = op.solve(to_dev(p.rhs), x0=to_dev(xs))
+    assert info["iters"] == 0 and info["status"] == 0
+    assert rel(to_host(x), xs) <= 1e-13
+    # a rough warm start converges in fewer iterations than a cold one
+    x0 = xs + 1e-4 * np.random.default_rng(0).standard_normal(p.shape)
+    _, iw = op.solve(to_dev(p.rhs), x0=to_dev(x0))
+    _, ic = op.solve(to_dev(p.rhs))
+    assert iw["status"] == 0 and iw["iters"] < ic["iters"]
+
+
+def test_zero_time_step_and_zero_rhs():
+    p = problem((5, 7, 13))
+    _, op = gpu_operator(p, dt=0.0)
+    x, info = op.solve(to_dev(p.rhs))
+    assert info["iters"] <= 1 and rel(to_host(x), p.rhs) <= 1e-14
+    _, op = gpu_operator(p)
+    x, info = op.solve(torch.zeros(p.shape, dtype=torch.float64, device=DEV))
+    assert info["iters"] == 0 and torch.count_nonzero(x) == 0
+
+
+def test_status_codes_on_device():
+    p = problem((5, 7, 13))
+    grid = S.Grid.from_problem(p)
+    nu = p.nu.copy()
+    nu[2, 3, 4] = -1.0
+    with pytest.raises(abi.MasError) as e:
+        S.Operator(grid, to_dev(nu), p.dt)
+    assert e.value.status == abi.MAS_EINVAL
+    nu[2, 3, 4] = np.nan
+    with pytest.raises(abi.MasError):
+        S.Operator(grid, to_dev(nu), p.dt)
+    _, op = gpu_operator(p)
+    with pytest.raises(abi.MasError) as e:  # no single-precision coefficients in an FP64 build
+        op.solve(to_dev(p.rhs), S.make_opts(precision="fp32_refined"))
+    assert e.value.status == abi.MAS_EINVAL
+    x, info = op.solve(to_dev(p.rhs), S.make_opts(max_iters=3))
+    assert info["status"] == abi.MAS_ENOTCONV and info["iters"] == 3
+    with pytest.raises(abi.MasError) as e:
+        op.solve(to_dev(p.rhs), allow_notconv=False, opts=S.make_opts(max_iters=3))
+    assert e.value.status == abi.MAS_ENOTCONV
+    # workspace too small
+    import ctypes
+    o = S.make_opts()
+    work, nbytes = op.workspace(o)
+    info = abi.mas_pcg_info()
+    rhs = to_dev(p.rhs)
+    xx = torch.empty_like(rhs)
+    st = abi.load().mas_pcg_solve(op.handle, rhs.data_ptr(), xx.data_ptr(), ctypes.byref(o),
+                                  work.data_ptr(), nbytes - 256, 0, ctypes.byref(info))
+    assert st == abi.MAS_ENOMEM
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32_refined"])
+def test_adjoint_matches_oracle_gradient(precision):
+    p = problem((16, 16, 32))
+    _, op = gpu_operator(p, precision)
+    ora = oracle_operator(p)
+    o = S.make_opts(precision=precision)
+    x, _ = op.solve(to_dev(p.rhs), o, allow_notconv=False)
+    xt = ora.solve_rhs(p.rhs) * 0.9
+    gx = to_host(x) - xt
+    lam, gnu, grhs, info = op.adjoint(x, to_dev(gx), o, allow_notconv=False)
+    xo = ora.solve_rhs(p.rhs, tol=1e-13)
+    lo = ora.pcg(gx, tol=1e-13)[0]
+    gnu_o, grhs_o = ora.gradient(xo, lo)
+    e_nu, e_rhs = rel(to_host(gnu), gnu_o), rel(to_host(grhs), grhs_o)
+    print(f"adjoint {precision}: dL/dnu rel {e_nu:.2e}, dL/drhs rel {e_rhs:.2e}")
+    assert e_nu <= 1e-6 and e_rhs <= 1e-6
+    # the adjoint solve meets the same tolerance
+    assert ora.rel_residual(gx, to_host(lam)) <= 1e-10
+
+
+def test_autograd_function():
+    p = problem((6, 8, 16))
+    grid = S.Grid.from_problem(p)
+    nu = to_dev(p.nu).requires_grad_(True)
+    rhs = to_dev(p.rhs).requires_grad_(True)
+    x = S.solve(nu, rhs, grid, p.dt, rtol=1e-12)
+    xt = torch.zeros_like(x)
+    loss = 0.5 * ((x - xt) ** 2).sum()
+    loss.backward()
+    ora = oracle_operator(p)
+    xo = ora.solve_rhs(p.rhs, tol=1e-13)
+    lo = ora.pcg(xo, tol=1e-13)[0]
+    gnu_o, grhs_o = ora.gradient(xo, lo)
+    assert rel(to_host(nu.grad), gnu_o) <= 1e-8
+    assert rel(to_host(rhs.grad), grhs_o) <= 1e-8
+
+
+def test_probe_copy():
+    src = torch.arange(1 << 20, dtype=torch.float64, device=DEV)
+    dst = torch.empty_like(src)
+    S.probe_copy(src, dst)
+    torch.cuda.synchronize()
+    assert torch.equal(src, dst)

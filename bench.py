@@ -1,0 +1,200 @@
+"""Benchmark of the implicit viscous PCG solve on one MI355X.
+
+Workload (default): the production-like FP64 solve, a 256 x 320 x 640
+spherical-shell grid (52.4M cells), radial stretching 1.01, a smooth random
+viscosity field with 100x contrast, diffusion number 1000 and a smoothed
+N(0,1) right-hand side, solved to ||b - A x|| <= 1e-10 ||b||.  Inputs are
+seeded and synthetic; they are generated on the host and copied to HBM
+before the timed region.
+
+One step = build the operator from (nu, dt) + one full FP64 PCG solve to the
+tolerance.  `value` is PCG iterations per second of wall time over the K
+timed steps.  Alongside, the same grid and data are solved with the
+single-precision inner PCG inside double-precision refinement and both
+times-to-1e-10 are reported.
+
+The dominant kernel is the fused PCG iteration kernel; its duration is
+sampled with HIP events on the solver's stream (inside the library) and
+converted to algorithmic HBM bytes per second.
+
+    python bench.py [--steps K] [--warmup W] [--gpus 1] [--workload c1]
+                    [--no-cpu-baseline] [--no-refined]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import re
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+# algorithmic bytes per cell of one PCG iteration kernel launch (non-check
+# iterations): reads r, q, p, x, c_r, c_theta, c_phi; writes r, p, x, q
+BYTES_PER_CELL = {"fp64": 11 * 8, "fp32": 11 * 4}
+KERNEL_SRC = os.path.join(ROOT, "paper_1811_02605_amd", "csrc", "kernels.hpp")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "pcg_iter_fp64_c1_traffic.txt")
+
+
+def kernel_hash() -> str:
+    return hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
+
+
+def read_traffic():
+    """HBM bytes per launch of the iteration kernel from the committed PMC
+    summary, if it was taken on the current kernel source; else None."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    txt = open(TRAFFIC_FILE).read()
+    m_hash = re.search(r"kernel_source_sha256_16:\s*([0-9a-f]+)", txt)
+    m_bytes = re.search(r"hbm_bytes_per_launch:\s*([0-9.eE+]+)", txt)
+    if not m_hash or not m_bytes or m_hash.group(1) != kernel_hash():
+        return None
+    return float(m_bytes.group(1))
+
+
+def cpu_baseline(p, iters=12):
+    """The FP64 CPU oracle (unchanged) on the same workload: assemble, then a
+    fixed number of PCG iterations from x0 = 0; iterations per second."""
+    import oracle
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    t0 = time.perf_counter()
+    ora = oracle.Operator(p.r_faces, p.t_faces, p.cfg.np_, p.nu, p.dt)
+    b = ora.rhs_to_b(p.rhs)
+    t1 = time.perf_counter()
+    ora.pcg(b, tol=0.0, max_iters=iters)
+    t2 = time.perf_counter()
+    return {"value": iters / (t2 - t1), "unit": "PCG iters/s", "cores": threads,
+            "kind": "oracle",
+            "sample": f"{p.cfg.name} grid {p.cfg.nr}x{p.cfg.nt}x{p.cfg.np_}: {iters} PCG iterations "
+                      f"from x0=0 timed ({t2 - t1:.1f} s); assembly {t1 - t0:.1f} s not counted"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="c1")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-refined", action="store_true")
+    ap.add_argument("--check-every", type=int, default=8)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
+              "(the multi-GPU r-slab decomposition is a design note, not code).", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_1811_02605_amd import solver as S
+    from paper_1811_02605_amd import workloads as W
+
+    dev = "cuda:0"
+    cfg = W.CONFIGS[args.workload]
+    t_gen = time.perf_counter()
+    p = W.make_problem(cfg)
+    t_gen = time.perf_counter() - t_gen
+    print(f"[bench] inputs {cfg.name} {cfg.shape} generated in {t_gen:.1f} s", file=sys.stderr,
+          flush=True)
+    grid = S.Grid.from_problem(p)
+    nu = torch.from_numpy(p.nu).to(dev)
+    rhs = torch.from_numpy(p.rhs).to(dev)
+    x = torch.empty_like(rhs)
+    torch.cuda.synchronize()
+
+    opts = S.make_opts(rtol=cfg.rtol, precision="fp64", sample_timing=1,
+                       check_every=args.check_every)
+
+    def step():
+        op = S.Operator(grid, nu, p.dt, precision="fp64")
+        _, info = op.solve(rhs, opts, out=x, allow_notconv=False)
+        return info
+
+    for w in range(args.warmup):
+        info = step()
+        print(f"[bench] warmup {w}: {info['iters']} iterations, {info['seconds']:.3f} s",
+              file=sys.stderr, flush=True)
+
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    infos = [step() for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    iters = sum(i["iters"] for i in infos)
+    solve_s = [i["seconds"] for i in infos]
+    kus = [i["iter_kernel_us"] for i in infos if i["iter_kernel_samples"] > 0]
+    kernel_us = float(np.mean(kus)) if kus else None
+    print(f"[bench] {args.steps} steps, {iters} iterations in {elapsed:.3f} s; "
+          f"iteration kernel {kernel_us} us", file=sys.stderr, flush=True)
+
+    n = cfg.n
+    alg_bytes = BYTES_PER_CELL["fp64"] * n
+    achieved = alg_bytes / (kernel_us * 1e-6) / 1e9 if kernel_us else None
+    traffic = read_traffic()
+
+    out = {
+        "metric": "PCG iters/s + HBM GB/s; time-to-1e-10 rel residual, FP64 vs FP32/FP64-refined",
+        "value": iters / elapsed,
+        "unit": "PCG iters/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1000.0 * elapsed / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic (seeded smooth random viscosity, N(0,1) right-hand side)",
+        "config": {"workload": f"{cfg.name}: FP64 Jacobi-PCG to 1e-10, "
+                               f"{cfg.nr}x{cfg.nt}x{cfg.np_} spherical shell "
+                               f"({n} cells), step = operator build + full solve",
+                   "cells": n, "iterations_per_solve": infos[-1]["iters"],
+                   "rel_resid_true": infos[-1]["rel_resid_true"],
+                   "time_to_tol_s_fp64": float(np.median(solve_s))},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": (achieved / HBM_PEAK_GBS) if achieved else None,
+                     "traffic": traffic,
+                     "kernel": "k_pcg_iter<double> (one fused PCG iteration)",
+                     "bytes_per_cell": BYTES_PER_CELL["fp64"],
+                     "kernel_us": kernel_us},
+    }
+
+    if not args.no_refined:
+        # same grid and data, single-precision inner PCG inside FP64 refinement
+        opm = S.Operator(grid, nu, p.dt, precision="fp32_refined")
+        mopts = S.make_opts(rtol=cfg.rtol, precision="fp32_refined", sample_timing=1)
+        xm = torch.empty_like(rhs)
+        opm.solve(rhs, mopts, out=xm, allow_notconv=False)  # warm-up
+        mi = [opm.solve(rhs, mopts, out=xm, allow_notconv=False)[1] for _ in range(3)]
+        t_ref = float(np.median([i["seconds"] for i in mi]))
+        kus32 = [i["iter_kernel_us"] for i in mi if i["iter_kernel_samples"] > 0]
+        k32 = float(np.mean(kus32)) if kus32 else None
+        diff = float(torch.linalg.vector_norm(xm - x) / torch.linalg.vector_norm(x))
+        out["refined"] = {
+            "time_to_tol_s": t_ref,
+            "speedup_vs_fp64": float(np.median(solve_s)) / t_ref,
+            "outer_iters": mi[-1]["outer_iters"], "inner_iters": mi[-1]["iters"],
+            "rel_resid_true": mi[-1]["rel_resid_true"],
+            "rel_diff_vs_fp64_solution": diff,
+            "inner_kernel_us": k32,
+            "inner_kernel_GBs": (BYTES_PER_CELL["fp32"] * n / (k32 * 1e-6) / 1e9) if k32 else None,
+        }
+        print(f"[bench] refined: {t_ref:.3f} s vs fp64 {np.median(solve_s):.3f} s",
+              file=sys.stderr, flush=True)
+
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(p)
+        print(f"[bench] cpu baseline {out['cpu_baseline']}", file=sys.stderr, flush=True)
+
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

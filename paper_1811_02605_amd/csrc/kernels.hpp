@@ -322,6 +322,8 @@ __global__ __launch_bounds__(kRedThreads) void k_finalize(const double *partials
         conv = RR <= ctl->tol2;
     }
     ctl->rr = RR;
+    // an exactly zero scaled residual is an exact solution (W r = 0 as well)
+    if (RR == 0.0) conv = true;
     if (conv) {
         ctl->flag = FLAG_CONV;
         ctl->conv_iter = k;

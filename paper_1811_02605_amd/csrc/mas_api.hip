@@ -634,10 +634,6 @@ static int solve_core(const mas_op *op, const double *src, int src_is_rhs, doubl
             st = read_ctl(cx, &h);
             if (st != MAS_OK) return st;
             info.rel_resid_recursive = std::sqrt(h.rw) / bnorm;
-            if (pr.flag == FLAG_BREAK) {
-                status = MAS_EBREAKDOWN;
-                break;
-            }
             // true residual of x_k into the buffer the next iteration reads
             const int nxt = (pr.last_iter + 1) & 1;
             st = residual<double>(cx, x, r[nxt], &rw2);
@@ -645,6 +641,10 @@ static int solve_core(const mas_op *op, const double *src, int src_is_rhs, doubl
             info.rel_resid_true = std::sqrt(rw2) / bnorm;
             if (rw2 <= tol2) {
                 status = MAS_OK;
+                break;
+            }
+            if (pr.flag == FLAG_BREAK) {
+                status = MAS_EBREAKDOWN;
                 break;
             }
             if (pr.flag != FLAG_CONV || info.restarts >= o.max_restarts) {

@@ -216,17 +216,25 @@ def viscosity(cfg: Config, r_faces, t_faces) -> np.ndarray:
 def jacobi_smooth(u: np.ndarray, weight: float = 2.0 / 3.0) -> np.ndarray:
     """u + w (mean of index-space neighbours - u); phi periodic, missing
     r/theta neighbours left out of the mean."""
-    s = np.roll(u, 1, axis=2) + np.roll(u, -1, axis=2)
-    cnt = np.full(u.shape, 2.0)
+    nr, nt, _ = u.shape
+    # phi neighbours k-1 and k+1 (periodic), summed in that order
+    s = np.empty_like(u)
+    s[:, :, 1:] = u[:, :, :-1]
+    s[:, :, 0] = u[:, :, -1]
+    s[:, :, :-1] += u[:, :, 1:]
+    s[:, :, -1] += u[:, :, 0]
     s[1:] += u[:-1]
     s[:-1] += u[1:]
-    cnt[1:] += 1.0
-    cnt[:-1] += 1.0
     s[:, 1:] += u[:, :-1]
     s[:, :-1] += u[:, 1:]
-    cnt[:, 1:] += 1.0
-    cnt[:, :-1] += 1.0
-    return u + weight * (s / cnt - u)
+    ir, it = np.arange(nr), np.arange(nt)
+    cr = 2.0 + (ir > 0).astype(np.float64) + (ir < nr - 1).astype(np.float64)
+    ct = (it > 0).astype(np.float64) + (it < nt - 1).astype(np.float64)
+    s /= (cr[:, None] + ct[None, :])[:, :, None]
+    s -= u
+    s *= weight
+    s += u
+    return s
 
 
 def right_hand_side(cfg: Config) -> np.ndarray:

@@ -63,7 +63,7 @@ def test_fp64_solve_matches_oracle(shape, bc):
     res = ora.rel_residual(b, x)
     assert res <= 1e-10, res
     assert info["rel_resid_true"] <= 1e-10
-    assert abs(info["rel_resid_true"] - res) <= 1e-3 * res + 1e-15
+    assert abs(info["rel_resid_true"] - res) <= 1e-3 * res + 1e-13
     xo, it_o, _, _ = ora.pcg(b, tol=1e-13)
     err = rel(x, xo)
     print(f"{shape} bc={bc}: iters gpu {info['iters']} oracle(1e-13) {it_o}; "

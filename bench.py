@@ -189,6 +189,22 @@ def main():
         print(f"[bench] refined: {t_ref:.3f} s vs fp64 {np.median(solve_s):.3f} s",
               file=sys.stderr, flush=True)
 
+    # practical HBM ceiling: a plain streaming copy of 2 GiB (read + write)
+    src = torch.empty(1 << 28, dtype=torch.float64, device=dev).fill_(1.0)
+    dst = torch.empty_like(src)
+    S.probe_copy(src, dst)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(10):
+        S.probe_copy(src, dst)
+    e1.record()
+    torch.cuda.synchronize()
+    copy_gbs = 10 * 2 * src.numel() * 8 / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    out["roofline"]["copy_probe_GBs"] = copy_gbs
+    out["roofline"]["frac_of_copy"] = (achieved / copy_gbs) if achieved else None
+    del src, dst
+    print(f"[bench] copy probe {copy_gbs:.0f} GB/s", file=sys.stderr, flush=True)
+
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(p)
         print(f"[bench] cpu baseline {out['cpu_baseline']}", file=sys.stderr, flush=True)

@@ -125,7 +125,7 @@ struct IterArgs {
     double *partials;  // [nblk][kNV]
     const Ctl *ctl;
     Dims d;
-    int tiles_k, tiles_j, ti;  // phi tiles (64 wide), theta tiles (TJ rows), r planes per block
+    int tiles_i, tiles_k, tiles_j, ti;  // r chunks, phi segments, theta tiles; r planes per chunk
     int nblk;
 };
 
@@ -138,149 +138,220 @@ __device__ inline int xcd_remap(int b, int nblk) {
     return x * q + (x < rem ? x : rem) + s;
 }
 
-template <typename T, int TJ, bool CHECK>
-__global__ __launch_bounds__(kWave * TJ) void k_pcg_iter(IterArgs<T> a) {
+// Vector of V consecutive phi cells (16-byte accesses for V = 16/sizeof(T)).
+template <typename T, int V>
+struct VecT {
+    T v[V];
+};
+
+template <typename T, int V>
+__device__ inline VecT<T, V> ldv(const T *__restrict__ p, int64_t c) {
+    VecT<T, V> r;
+    if constexpr (V == 1) {
+        r.v[0] = p[c];
+    } else {
+        typedef T raw_t __attribute__((ext_vector_type(V)));
+        const raw_t t = *reinterpret_cast<const raw_t *>(p + c);
+#pragma unroll
+        for (int e = 0; e < V; ++e) r.v[e] = t[e];
+    }
+    return r;
+}
+
+template <typename T, int V>
+__device__ inline void stv(T *__restrict__ p, int64_t c, const VecT<T, V> &x) {
+    if constexpr (V == 1) {
+        p[c] = x.v[0];
+    } else {
+        typedef T raw_t __attribute__((ext_vector_type(V)));
+        raw_t t;
+#pragma unroll
+        for (int e = 0; e < V; ++e) t[e] = x.v[e];
+        *reinterpret_cast<raw_t *>(p + c) = t;
+    }
+}
+
+__device__ inline double shfl_up1(double v) { return __shfl_up(v, 1, kWave); }
+__device__ inline float shfl_up1(float v) { return __shfl_up(v, 1, kWave); }
+__device__ inline double shfl_dn1(double v) { return __shfl_down(v, 1, kWave); }
+__device__ inline float shfl_dn1(float v) { return __shfl_down(v, 1, kWave); }
+
+// Each wave owns one theta row j and a segment of SEG = 64 V phi cells and
+// marches through the r planes of its chunk on its own: no LDS, no barrier.
+// p_k at the in-plane neighbours is recomputed from (r, q, p)_{k-1}: rows
+// j-1 and j+1 are loaded directly (they are the own rows of the neighbouring
+// waves, so these loads hit L1/L2), the phi neighbours come from lane shuffles
+// and the two segment-edge cells from two extra lanes' loads.  Chunks march
+// up (even chunk index) or down (odd) so that the halo plane a chunk reads
+// is the plane its neighbour chunk reads at the same time.
+// Per plane step m, the in-plane part of q_k(m) plus the term of the r
+// neighbour already visited is summed into S(m); q_k(m) is completed one
+// step later, when p_k of the next plane is known.
+template <typename T, int WPB, int V, bool CHECK>
+__global__ __launch_bounds__(kWave *WPB) void k_pcg_iter(IterArgs<T> a) {
+    constexpr int SEG = kWave * V;
+    using VT = VecT<T, V>;
+
     const Ctl *ctl = a.ctl;
     if (ctl->flag != FLAG_RUN) return;
-    const double alpha_d = ctl->alpha, beta_d = ctl->beta;
-    const T alpha = (T)alpha_d, beta = (T)beta_d;
-    const bool use_q = alpha_d != 0.0;
-    const bool use_p = beta_d != 0.0;
-    const bool load_p = use_q || use_p;
+    const T alpha = (T)ctl->alpha, beta = (T)ctl->beta;
 
     const int nr = a.d.nr, nt = a.d.nt, np = a.d.np;
     const int64_t plane = a.d.plane;
 
     const int L = xcd_remap(blockIdx.x, a.nblk);
-    const int kt = L % a.tiles_k;
-    const int jt = (L / a.tiles_k) % a.tiles_j;
-    const int it = L / (a.tiles_k * a.tiles_j);
+    const int it = L % a.tiles_i;  // r chunks fastest
+    const int kt = (L / a.tiles_i) % a.tiles_k;
+    const int jt = L / (a.tiles_i * a.tiles_k);
 
     const int lane = threadIdx.x & (kWave - 1);
     const int wv = threadIdx.x / kWave;
-    const int j0 = jt * TJ;
-    const int j = j0 + wv;
-    const int k0 = kt * kWave;
-    const int k = k0 + lane;
-    const int nlane = min(kWave, np - k0);
+    const int j = jt * WPB + wv;
+    const int k0 = kt * SEG;
+    const int nseg = min(SEG, np - k0);  // a multiple of V
+    const int nvl = nseg / V;            // lanes holding cells
     const bool rowok = j < nt;
-    const bool act = rowok && lane < nlane;
+    const bool act = rowok && lane < nvl;
     const int i0 = it * a.ti;
     const int i1 = min(i0 + a.ti, nr);
+    const bool up = (it & 1) == 0;
 
-    // neighbours of the segment ends (periodic phi)
-    const int kL = (k0 == 0) ? np - 1 : k0 - 1;
-    const int kLast = k0 + nlane - 1;
-    const int kR = (kLast == np - 1) ? 0 : kLast + 1;
-
-    __shared__ T sP[3][TJ + 2][kWave + 2];  // p_k: [slot][row+1][k-k0+1]
-    __shared__ T sCt[3][TJ + 1][kWave];     // ct:  [slot][row+1][k-k0], row 0 = row j0-1
-    __shared__ T sCp[3][TJ][kWave + 1];     // cp:  [slot][row][k-k0+1], index 0 = cp(kL)
-    __shared__ double sRed[TJ * kNV];
-
-    auto newp = [&](int64_t c, T &rn) -> T {
-        T r = a.r_in[c];
-        T po = load_p ? a.p_in[c] : T(0);
-        if (use_q) r -= alpha * a.q_in[c];
-        rn = r;
-        return use_p ? r + beta * po : r;
-    };
+    // own cells; inactive lanes read cell 0 of the plane and discard it
+    const int64_t col = act ? (int64_t)j * np + k0 + lane * V : 0;
+    const bool hasU = act && j > 0, hasD = act && j < nt - 1;
+    const int64_t colU = hasU ? col - np : 0;
+    const int64_t colD = hasD ? col + np : 0;
+    // segment edges: lane 0 needs the cell left of k0, lane nvl-1 the cell
+    // right of the segment end (periodic in phi)
+    const bool eL = rowok && lane == 0;
+    const bool eR = rowok && lane == nvl - 1;
+    const int64_t colL = eL ? (int64_t)j * np + ((k0 == 0) ? np - 1 : k0 - 1) : 0;
+    const int64_t colR = eR ? (int64_t)j * np + ((k0 + nseg == np) ? 0 : k0 + nseg) : 0;
 
     double acc[kNV] = {0.0, 0.0, 0.0, 0.0, 0.0};
-    T pn_m1 = 0, pn_m2 = 0;  // own p_k at planes m-1, m-2
-    T cr_m1 = 0, cr_m2 = 0;  // own cr at planes m-1, m-2
-    T rn_m1 = 0;             // own r_k at plane m-1
-    T ct_m1 = 0, cp_m1 = 0;  // own ct, cp at plane m-1
-    const int64_t colj = (int64_t)j * np + k;
+    VT pn1{}, rn1{}, S1{}, cr1{};
+    VecT<double, V> w1{};
+    int64_t base1 = 0;
 
-    for (int m = i0 - 1; m <= i1; ++m) {
-        const int slot = (m + 3) % 3;
+    const int nsteps = i1 - i0 + 2;
+    for (int s = 0; s < nsteps; ++s) {
+        const int m = up ? i0 - 1 + s : i1 - s;
         const bool indom = (m >= 0) && (m < nr);
         const bool own = (m >= i0) && (m < i1);
-        T pn = 0, rn = 0, crm = 0, ctm = 0, cpm = 0;
-        if (indom && act) {
-            const int64_t c = (int64_t)m * plane + colj;
-            T r = a.r_in[c];
-            T po = load_p ? a.p_in[c] : T(0);
-            if (use_q) r -= alpha * a.q_in[c];
-            rn = r;
-            pn = use_p ? r + beta * po : r;
-            crm = a.cr[c];
+        const int64_t base = (int64_t)(indom ? m : 0) * plane;
+        // ---- loads of plane m, all issued before any use
+        VT r{}, q{}, p{}, cr{}, x{}, ct{}, cp{};
+        VT rU{}, qU{}, pU{}, ctU{}, rD{}, qD{}, pD{};
+        VecT<double, V> w{};
+        T lr = 0, lq = 0, lp = 0, lcp = 0, rr_ = 0, rq_ = 0, rp_ = 0;
+        if (indom) {
+            r = ldv<T, V>(a.r_in, base + col);
+            q = ldv<T, V>(a.q_in, base + col);
+            p = ldv<T, V>(a.p_in, base + col);
+            if (m < i1) cr = ldv<T, V>(a.cr, base + col);
             if (own) {
-                ctm = a.ct[c];
-                cpm = a.cp[c];
-                a.r_out[c] = rn;
-                a.p_out[c] = pn;
-                if (use_q) a.x[c] = a.x[c] + alpha * po;
+                x = ldv<T, V>(a.x, base + col);
+                ct = ldv<T, V>(a.ct, base + col);
+                cp = ldv<T, V>(a.cp, base + col);
+                rU = ldv<T, V>(a.r_in, base + colU);
+                qU = ldv<T, V>(a.q_in, base + colU);
+                pU = ldv<T, V>(a.p_in, base + colU);
+                ctU = ldv<T, V>(a.ct, base + colU);
+                rD = ldv<T, V>(a.r_in, base + colD);
+                qD = ldv<T, V>(a.q_in, base + colD);
+                pD = ldv<T, V>(a.p_in, base + colD);
+                if (CHECK) w = ldv<double, V>(a.w, base + col);
+                if (eL) {
+                    lr = a.r_in[base + colL];
+                    lq = a.q_in[base + colL];
+                    lp = a.p_in[base + colL];
+                    lcp = a.cp[base + colL];
+                }
+                if (eR) {
+                    rr_ = a.r_in[base + colR];
+                    rq_ = a.q_in[base + colR];
+                    rp_ = a.p_in[base + colR];
+                }
             }
         }
+        // ---- r_k, p_k, x_k of plane m (every load is consumed before any store)
+        VT rn, pn, xn;
+#pragma unroll
+        for (int e = 0; e < V; ++e) {
+            rn.v[e] = r.v[e] - alpha * q.v[e];
+            pn.v[e] = rn.v[e] + beta * p.v[e];
+            xn.v[e] = x.v[e] + alpha * p.v[e];
+        }
+        if (!(indom && act)) {
+            pn = VT{};
+            cr = VT{};
+        }
+        // face between the previous plane and this one
+        const VT cf = up ? cr1 : cr;
+        // ---- in-plane part of q_k(m) plus the visited r neighbour
+        VT S{};
         if (own) {
-            if (lane < nlane) {
-                sP[slot][wv + 1][lane + 1] = pn;
-                sCt[slot][wv + 1][lane] = ctm;
-                sCp[slot][wv][lane + 1] = cpm;
+            VT pU_, pD_;
+#pragma unroll
+            for (int e = 0; e < V; ++e) {
+                pU_.v[e] = hasU ? (rU.v[e] - alpha * qU.v[e]) + beta * pU.v[e] : T(0);
+                pD_.v[e] = hasD ? (rD.v[e] - alpha * qD.v[e]) + beta * pD.v[e] : T(0);
+                if (!hasU) ctU.v[e] = T(0);
             }
-            // phi halo of this row
-            if (rowok && lane == 0) {
-                const int64_t c = (int64_t)m * plane + (int64_t)j * np + kL;
-                T rdum;
-                sP[slot][wv + 1][0] = newp(c, rdum);
-                sCp[slot][wv][0] = a.cp[c];
+            const T pl_edge = (lr - alpha * lq) + beta * lp;
+            const T pr_edge = (rr_ - alpha * rq_) + beta * rp_;
+            T left0 = shfl_up1(pn.v[V - 1]);
+            T right0 = shfl_dn1(pn.v[0]);
+            T cpl0 = shfl_up1(cp.v[V - 1]);
+            if (lane == 0) {
+                left0 = pl_edge;
+                cpl0 = lcp;
             }
-            if (rowok && lane == nlane - 1) {
-                const int64_t c = (int64_t)m * plane + (int64_t)j * np + kR;
-                T rdum;
-                sP[slot][wv + 1][nlane + 1] = newp(c, rdum);
-            }
-            // theta halo rows
-            if (wv == 0 && lane < nlane) {
-                T v = 0, cv = 0;
-                if (j0 > 0) {
-                    const int64_t c = (int64_t)m * plane + (int64_t)(j0 - 1) * np + k;
-                    T rdum;
-                    v = newp(c, rdum);
-                    cv = a.ct[c];
-                }
-                sP[slot][0][lane + 1] = v;
-                sCt[slot][0][lane] = cv;
-            }
-            if (wv == TJ - 1 && lane < nlane) {
-                T v = 0;
-                if (j0 + TJ < nt) {
-                    const int64_t c = (int64_t)m * plane + (int64_t)(j0 + TJ) * np + k;
-                    T rdum;
-                    v = newp(c, rdum);
-                }
-                sP[slot][TJ + 1][lane + 1] = v;
+            if (lane == nvl - 1) right0 = pr_edge;
+#pragma unroll
+            for (int e = 0; e < V; ++e) {
+                const T left = (e > 0) ? pn.v[e - 1] : left0;
+                const T right = (e < V - 1) ? pn.v[e + 1] : right0;
+                const T cpl = (e > 0) ? cp.v[e - 1] : cpl0;
+                S.v[e] = ct.v[e] * pD_.v[e] + ctU.v[e] * pU_.v[e] + cp.v[e] * right + cpl * left +
+                         cf.v[e] * pn1.v[e];
             }
         }
-        __syncthreads();
-        if (m - 1 >= i0 && act) {
-            const int ps = (m + 2) % 3;  // slot of plane m-1
-            const T s = cr_m1 * pn + cr_m2 * pn_m2
-                      + ct_m1 * sP[ps][wv + 2][lane + 1] + sCt[ps][wv][lane] * sP[ps][wv][lane + 1]
-                      + cp_m1 * sP[ps][wv + 1][lane + 2] + sCp[ps][wv][lane] * sP[ps][wv + 1][lane];
-            const T qv = pn_m1 - s;
-            const int64_t c = (int64_t)(m - 1) * plane + colj;
-            a.q_out[c] = qv;
-            const double pd = (double)pn_m1, qd = (double)qv, rd = (double)rn_m1;
-            acc[0] += pd * qd;
-            acc[1] += rd * qd;
-            acc[2] += qd * qd;
-            acc[3] += rd * rd;
-            if (CHECK) {
-                const double t = a.w[c] * rd;
-                acc[4] += t * t;
+        // ---- complete q_k of the previous plane
+        const int mp = up ? m - 1 : m + 1;
+        const bool qdo = mp >= i0 && mp < i1 && act;
+        VT qv{};
+        if (qdo) {
+#pragma unroll
+            for (int e = 0; e < V; ++e) qv.v[e] = pn1.v[e] - (S1.v[e] + cf.v[e] * pn.v[e]);
+#pragma unroll
+            for (int e = 0; e < V; ++e) {
+                const double pd = (double)pn1.v[e], qd = (double)qv.v[e], rd = (double)rn1.v[e];
+                acc[0] += pd * qd;
+                acc[1] += rd * qd;
+                acc[2] += qd * qd;
+                acc[3] += rd * rd;
+                if (CHECK) {
+                    const double t = w1.v[e] * rd;
+                    acc[4] += t * t;
+                }
             }
         }
-        pn_m2 = pn_m1;
-        pn_m1 = pn;
-        cr_m2 = cr_m1;
-        cr_m1 = crm;
-        rn_m1 = rn;
-        ct_m1 = ctm;
-        cp_m1 = cpm;
+        // ---- stores
+        if (own && act) {
+            stv<T, V>(a.r_out, base + col, rn);
+            stv<T, V>(a.p_out, base + col, pn);
+            stv<T, V>(a.x, base + col, xn);
+        }
+        if (qdo) stv<T, V>(a.q_out, base1 + col, qv);
+        pn1 = pn;
+        rn1 = rn;
+        S1 = S;
+        cr1 = cr;
+        if (CHECK) w1 = w;
+        base1 = base;
     }
+    __shared__ double sRed[WPB * kNV];
     block_sum_store<kNV>(acc, a.partials + (int64_t)L * kNV, sRed);
 }
 
@@ -637,11 +708,26 @@ __global__ __launch_bounds__(kWave *kSimpleJ) void k_gradient(const double *x, c
     })
 }
 
-// Streaming copy, 16 bytes per lane per step.
-__global__ __launch_bounds__(256) void k_copy16(const double2 *src, double2 *dst, int64_t n16) {
+// Streaming copy, 16 bytes per lane per access; each thread keeps kCopyU
+// loads in flight before storing them.
+constexpr int kCopyU = 8;
+__global__ __launch_bounds__(256) void k_copy16(const double2 *__restrict__ src,
+                                                double2 *__restrict__ dst, int64_t n16) {
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n16; t += stride)
-        dst[t] = src[t];
+    for (int64_t t0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t0 < n16;
+         t0 += stride * kCopyU) {
+        double2 v[kCopyU];
+#pragma unroll
+        for (int u = 0; u < kCopyU; ++u) {
+            const int64_t t = t0 + u * stride;
+            if (t < n16) v[u] = src[t];
+        }
+#pragma unroll
+        for (int u = 0; u < kCopyU; ++u) {
+            const int64_t t = t0 + u * stride;
+            if (t < n16) dst[t] = v[u];
+        }
+    }
 }
 
 }  // namespace mas

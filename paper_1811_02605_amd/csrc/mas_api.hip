@@ -46,9 +46,23 @@ static int fail(int status, const char *fmt, ...) {
     } while (0)
 
 // ------------------------------------------------------------------ tile configuration
-// Iteration kernel: 64 phi cells x kTJ theta rows per block, kTI r planes per block.
-static constexpr int kTJ = 8;
-static constexpr int kTI = 32;
+// Iteration kernel: (64 V) phi cells x kTJ theta rows (one wave each) per
+// block, kTI r planes per block; V = 16 bytes / element size when np is a
+// multiple of it, else 1.
+#ifndef MAS_TJ
+#define MAS_TJ 4
+#endif
+#ifndef MAS_TI
+#define MAS_TI 16
+#endif
+static constexpr int kTJ = MAS_TJ;
+static constexpr int kTI = MAS_TI;
+
+template <typename T>
+static inline int vec_width(int np) {
+    constexpr int v = 16 / (int)sizeof(T);
+    return (np % v == 0) ? v : 1;
+}
 
 static inline int64_t align256(int64_t v) { return (v + 255) & ~int64_t(255); }
 
@@ -56,10 +70,10 @@ struct Shape {
     int nr, nt, np;
     int64_t plane, n;
     Dims dims() const { return Dims{nr, nt, np, plane, n}; }
-    int tiles_k() const { return (np + kWave - 1) / kWave; }
+    int tiles_k(int v) const { return (np + kWave * v - 1) / (kWave * v); }
     int tiles_j() const { return (nt + kTJ - 1) / kTJ; }
     int tiles_i() const { return (nr + kTI - 1) / kTI; }
-    int64_t nblk_iter() const { return (int64_t)tiles_k() * tiles_j() * tiles_i(); }
+    int64_t nblk_iter(int v) const { return (int64_t)tiles_k(v) * tiles_j() * tiles_i(); }
     dim3 simple_grid() const {
         return dim3((np + kWave - 1) / kWave, (nt + kSimpleJ - 1) / kSimpleJ,
                     (nr + kSimpleR - 1) / kSimpleR);
@@ -322,7 +336,7 @@ static WorkLayout work_layout(const Shape &s, int precision) {
         off = align256(off + bytes);
         return o;
     };
-    const int64_t nparts = std::max(s.nblk_iter() * kNV, s.nblk_simple());
+    const int64_t nparts = std::max(s.nblk_iter(1) * kNV, s.nblk_simple());
     L.ctl = take(sizeof(Ctl));
     L.partials = take(8 * nparts);
     L.bhat = take(8 * s.n);
@@ -454,10 +468,12 @@ static int run_pcg(Ctx &cx, T *const r[2], T *const p[2], T *const q[2], T *x, c
     a.partials = cx.partials;
     a.ctl = cx.ctl;
     a.d = s.dims();
-    a.tiles_k = s.tiles_k();
+    const int V = vec_width<T>(s.np);
+    a.tiles_i = s.tiles_i();
+    a.tiles_k = s.tiles_k(V);
     a.tiles_j = s.tiles_j();
     a.ti = kTI;
-    a.nblk = (int)s.nblk_iter();
+    a.nblk = (int)s.nblk_iter(V);
     a.x = x;
     const dim3 grid((unsigned)a.nblk), block(kWave * kTJ);
 
@@ -482,8 +498,10 @@ static int run_pcg(Ctx &cx, T *const r[2], T *const p[2], T *const q[2], T *x, c
         for (; k <= kend; ++k) {
             const int cur = k & 1, nxt = cur ^ 1;
             a.r_in = r[cur];
-            a.p_in = p[cur];
-            a.q_in = q[cur];
+            // the first kernel of a run has alpha = beta = 0: point q and p at
+            // r (finite values) so that every load stays unconditional
+            a.p_in = (k == iter0) ? r[cur] : p[cur];
+            a.q_in = (k == iter0) ? r[cur] : q[cur];
             a.r_out = r[nxt];
             a.p_out = p[nxt];
             a.q_out = q[nxt];
@@ -498,10 +516,18 @@ static int run_pcg(Ctx &cx, T *const r[2], T *const p[2], T *const q[2], T *x, c
                 cx.ev_iter.push_back(k);
                 HIPCHK(hipEventRecord(e0, st));
             }
-            if (chk)
-                hipLaunchKernelGGL((k_pcg_iter<T, kTJ, true>), grid, block, 0, st, a);
-            else
-                hipLaunchKernelGGL((k_pcg_iter<T, kTJ, false>), grid, block, 0, st, a);
+            constexpr int VW = 16 / (int)sizeof(T);
+            if (V == VW) {
+                if (chk)
+                    hipLaunchKernelGGL((k_pcg_iter<T, kTJ, VW, true>), grid, block, 0, st, a);
+                else
+                    hipLaunchKernelGGL((k_pcg_iter<T, kTJ, VW, false>), grid, block, 0, st, a);
+            } else {
+                if (chk)
+                    hipLaunchKernelGGL((k_pcg_iter<T, kTJ, 1, true>), grid, block, 0, st, a);
+                else
+                    hipLaunchKernelGGL((k_pcg_iter<T, kTJ, 1, false>), grid, block, 0, st, a);
+            }
             if (sample) HIPCHK(hipEventRecord(cx.ev.back(), st));
             hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kRedThreads), 0, st, cx.partials, a.nblk,
                                cx.ctl, chk ? 1 : 0);
@@ -741,7 +767,7 @@ extern "C" int mas_probe_copy(const void *src, void *dst, int64_t bytes, void *h
         return fail(MAS_EINVAL, "copy needs 16-byte aligned pointers and a multiple of 16 bytes");
     const int64_t n16 = bytes / 16;
     if (n16 == 0) return MAS_OK;
-    const int64_t blocks = std::min<int64_t>((n16 + 255) / 256, 256 * 64);
+    const int64_t blocks = std::min<int64_t>((n16 + 256 * kCopyU - 1) / (256 * kCopyU), 256 * 16);
     hipLaunchKernelGGL(k_copy16, dim3((unsigned)blocks), dim3(256), 0, as_stream(hip_stream),
                        static_cast<const double2 *>(src), static_cast<double2 *>(dst), n16);
     LAUNCHCHK();

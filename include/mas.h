@@ -64,6 +64,16 @@ enum { MAS_BC_DIRICHLET0 = 0, MAS_BC_NEUMANN0 = 1 };
  *   product are accumulated in double precision. */
 enum { MAS_FP64 = 0, MAS_FP32_REFINED = 1 };
 
+/* Refinement strategy of MAS_FP32_REFINED.  Both replace the single-precision
+ * residual by the double-precision one, r = b - A x, whenever the inner
+ * residual has dropped by inner_rtol (or far enough to meet rtol):
+ *   MAS_REFINE_RESTART: classical iterative refinement; every inner solve
+ *     starts a new conjugate-gradient run from the replaced residual.
+ *   MAS_REFINE_RELIABLE: residual replacement; the inner run folds its
+ *     pending step into x and continues from its current search direction,
+ *     so the Krylov information is not thrown away at each refinement step. */
+enum { MAS_REFINE_RESTART = 0, MAS_REFINE_RELIABLE = 1 };
+
 typedef struct {
     int32_t nr, nt, np;       /* cells in r, theta, phi (each >= 1)                   */
     const double *r_faces;    /* host, nr+1, strictly increasing, r_faces[0] > 0       */
@@ -79,19 +89,21 @@ typedef struct {
     double rtol;          /* stop when ||b - A x||_2 <= rtol ||b||_2               (1e-10) */
     int32_t max_iters;    /* PCG iterations (refined: total inner iterations)     (100000) */
     int32_t precision;    /* MAS_FP64 | MAS_FP32_REFINED                            (FP64) */
-    double inner_rtol;    /* refined: inner stop on the preconditioned residual     (1e-5) */
-    int32_t max_outer;    /* refined: refinement steps                                (20) */
+    double inner_rtol;    /* refined: drop of the inner (preconditioned) residual
+                             between two double-precision residuals            (1e-5) */
+    int32_t max_outer;    /* refined: double-precision residual replacements          (20) */
     int32_t check_every;  /* FP64: iterations between residual-norm checks (>= 1)      (8) */
     int32_t use_x0;       /* nonzero: x (or lambda) holds the initial guess            (0) */
     int32_t max_restarts; /* FP64: restarts from the true residual if the recursive
                              residual converged but the true one did not               (3) */
     int32_t sample_timing;/* nonzero: time a sample of PCG iteration kernels with HIP
                              events (reported in mas_pcg_info)                          (0) */
+    int32_t refine;       /* refined: MAS_REFINE_RESTART | MAS_REFINE_RELIABLE   (RELIABLE) */
 } mas_pcg_opts;
 
 typedef struct {
     int32_t status;              /* the call's return value                                  */
-    int32_t iters;               /* PCG iterations (refined: total inner iterations)         */
+    int32_t iters;               /* PCG iterations (refined: inner iteration kernels run)    */
     int32_t outer_iters;         /* refined: refinement steps taken; FP64: 0                  */
     int32_t restarts;            /* FP64: restarts taken                                      */
     double rel_resid_true;       /* ||b - A x||_2/||b||_2 at exit, double precision           */

@@ -48,13 +48,13 @@ struct Ctl {
     double rr;         // (r_k, r_k) of the last finished iteration (scaled variables)
     double rw;         // last checked ||W r||^2 (= ||b - A x||^2)
     double tol2;       // threshold on the checked quantity
-    double inner_rtol2;// inner (refined) mode: relative threshold on (r,r)
+    double rr_next;    // (r_{k+1}, r_{k+1}) predicted by the recurrence at the last finalize
     double pq, rq, qq; // last sums (diagnostics)
     double sums[8];    // results of k_reduce
     int32_t flag;      // 0 running, 1 converged, 2 iteration limit, -2 breakdown
     int32_t iter;      // index of the next iteration kernel
     int32_t max_iter;  // last admissible iteration index
-    int32_t mode;      // 0: ||W r||^2 <= tol2 on check iterations; 1: (r,r) <= inner_rtol2 (r0,r0)
+    int32_t mode;      // 0: ||W r||^2 <= tol2 on check iterations; 1: (r,r) <= tol2 every iteration
     int32_t conv_iter; // iteration index at which flag was set
     int32_t pad[3];
 };
@@ -389,12 +389,20 @@ __global__ __launch_bounds__(kRedThreads) void k_finalize(const double *partials
             conv = RW <= ctl->tol2;
         }
     } else {
-        if (k == 0) ctl->tol2 = ctl->inner_rtol2 * RR;
         conv = RR <= ctl->tol2;
     }
     ctl->rr = RR;
     // an exactly zero scaled residual is an exact solution (W r = 0 as well)
     if (RR == 0.0) conv = true;
+    // alpha_k and the predicted (r_{k+1}, r_{k+1}) are recorded even when
+    // stopping: a refinement step that keeps the search direction folds the
+    // pending alpha_k p_k into the solution and compares the replaced
+    // residual with the prediction
+    {
+        const double al = (PQ > 0.0 && isfinite(PQ)) ? RR / PQ : 0.0;
+        ctl->alpha = al;
+        ctl->rr_next = RR - 2.0 * al * RQ + al * al * QQ;
+    }
     if (conv) {
         ctl->flag = FLAG_CONV;
         ctl->conv_iter = k;
@@ -438,14 +446,13 @@ __global__ __launch_bounds__(kRedThreads) void k_reduce(const double *partials, 
 // Reset the control block for a new PCG run (a kernel, not a memset, so it
 // is safe inside captured graphs as well).
 __global__ void k_ctl_init(Ctl *ctl, int mode, int iter0, int max_iter, double tol2,
-                           double inner_rtol2) {
+                           double beta0) {
     if (threadIdx.x != 0) return;
     ctl->alpha = 0.0;
-    ctl->beta = 0.0;
+    ctl->beta = beta0;
     ctl->rr = 0.0;
     ctl->rw = 0.0;
     ctl->tol2 = tol2;
-    ctl->inner_rtol2 = inner_rtol2;
     ctl->flag = FLAG_RUN;
     ctl->iter = iter0;
     ctl->max_iter = max_iter;
@@ -601,15 +608,15 @@ __global__ __launch_bounds__(kWave *kSimpleJ) void k_apply(const double *w, cons
     })
 }
 
-// r^ = b^ - A^ x^ (double), stored as TOUT; partial ||W r^||^2.
+// r^ = b^ - A^ x^ (double), stored as TOUT; partials ||W r^||^2 and ||r^||^2.
 template <typename TOUT>
 __global__ __launch_bounds__(kWave *kSimpleJ) void k_residual(const double *bhat, const double *xhat,
                                                               const double *w, const double *cr,
                                                               const double *ct, const double *cp,
                                                               Dims d, TOUT *rout,
                                                               double *partials) {
-    __shared__ double lds[kSimpleJ * 1];
-    double acc[1] = {0.0};
+    __shared__ double lds[kSimpleJ * 2];
+    double acc[2] = {0.0, 0.0};
     MAS_SIMPLE_LOOP(d, {
         if (cell.ok) {
             const double r = bhat[cell.c] -
@@ -617,9 +624,10 @@ __global__ __launch_bounds__(kWave *kSimpleJ) void k_residual(const double *bhat
             rout[cell.c] = (TOUT)r;
             const double t = w[cell.c] * r;
             acc[0] += t * t;
+            acc[1] += r * r;
         }
     })
-    block_sum_store<1>(acc, partials + simple_block_id(), lds);
+    block_sum_store<2>(acc, partials + 2 * simple_block_id(), lds);
 }
 
 // b^ = V src / w (src = rhs) or src / w (src = adjoint seed), partial ||b||^2;
@@ -651,10 +659,17 @@ __global__ __launch_bounds__(kWave *kSimpleJ) void k_unscale(const double *w, Di
     })
 }
 
-// x^ += d^ (refinement update, double += single).
-__global__ __launch_bounds__(kWave *kSimpleJ) void k_refine_add(const float *dh, Dims d, double *x) {
+// Refinement update x^ += d^ + alpha p (double accumulation of the single-
+// precision correction and of the pending step, alpha read from the control
+// block; alpha = 0 for a restarted inner solve), then d^ = 0.
+__global__ __launch_bounds__(kWave *kSimpleJ) void k_refine_fold(float *dh, const float *p,
+                                                                 const Ctl *ctl, Dims d, double *x) {
+    const double alpha = ctl->alpha;
     MAS_SIMPLE_LOOP(d, {
-        if (cell.ok) x[cell.c] = x[cell.c] + (double)dh[cell.c];
+        if (cell.ok) {
+            x[cell.c] = x[cell.c] + ((double)dh[cell.c] + alpha * (double)p[cell.c]);
+            dh[cell.c] = 0.0f;
+        }
     })
 }
 
@@ -708,24 +723,25 @@ __global__ __launch_bounds__(kWave *kSimpleJ) void k_gradient(const double *x, c
     })
 }
 
-// Streaming copy, 16 bytes per lane per access; each thread keeps kCopyU
-// loads in flight before storing them.
-constexpr int kCopyU = 8;
+// Streaming copy: each block copies one contiguous chunk of kCopyChunk
+// 16-byte elements, each thread keeping kCopyU loads in flight.
+constexpr int kCopyU = 4;
+constexpr int64_t kCopyChunk = 16384;
 __global__ __launch_bounds__(256) void k_copy16(const double2 *__restrict__ src,
                                                 double2 *__restrict__ dst, int64_t n16) {
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t t0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t0 < n16;
-         t0 += stride * kCopyU) {
+    const int64_t beg = (int64_t)blockIdx.x * kCopyChunk;
+    const int64_t end = min(beg + kCopyChunk, n16);
+    for (int64_t t0 = beg + threadIdx.x; t0 < end; t0 += 256 * kCopyU) {
         double2 v[kCopyU];
 #pragma unroll
         for (int u = 0; u < kCopyU; ++u) {
-            const int64_t t = t0 + u * stride;
-            if (t < n16) v[u] = src[t];
+            const int64_t t = t0 + u * 256;
+            if (t < end) v[u] = src[t];
         }
 #pragma unroll
         for (int u = 0; u < kCopyU; ++u) {
-            const int64_t t = t0 + u * stride;
-            if (t < n16) dst[t] = v[u];
+            const int64_t t = t0 + u * 256;
+            if (t < end) dst[t] = v[u];
         }
     }
 }

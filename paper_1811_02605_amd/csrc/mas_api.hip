@@ -205,6 +205,7 @@ extern "C" void mas_pcg_default_opts(mas_pcg_opts *o) {
     o->use_x0 = 0;
     o->max_restarts = 3;
     o->sample_timing = 0;
+    o->refine = MAS_REFINE_RELIABLE;
 }
 
 extern "C" int64_t mas_op_storage_bytes(const mas_grid *g, int32_t precision) {
@@ -359,6 +360,8 @@ static int check_opts(const mas_op *op, const mas_pcg_opts *o) {
         if (!(o->inner_rtol > 0.0 && o->inner_rtol < 1.0))
             return fail(MAS_EINVAL, "inner_rtol must lie in (0, 1)");
         if (o->max_outer < 1) return fail(MAS_EINVAL, "max_outer must be >= 1");
+        if (o->refine != MAS_REFINE_RESTART && o->refine != MAS_REFINE_RELIABLE)
+            return fail(MAS_EINVAL, "unknown refinement strategy %d", o->refine);
     }
     if (o->max_restarts < 0) return fail(MAS_EINVAL, "max_restarts must be >= 0");
     return MAS_OK;
@@ -415,26 +418,33 @@ static int read_ctl(Ctx &cx, Ctl *h) {
     return MAS_OK;
 }
 
-// Sum the simple-kernel partials into ctl->sums[0] and return it.
-static int reduce1(Ctx &cx, double *out) {
+// Sum nv values of the simple-kernel partials into ctl->sums[0:nv] and
+// copy them to the host (synchronous).
+static int reduce_n(Ctx &cx, int nv, double *out) {
     const int nblk = (int)cx.op->s.nblk_simple();
-    hipLaunchKernelGGL(k_reduce, dim3(1), dim3(kRedThreads), 0, cx.stream, cx.partials, nblk, 1,
+    hipLaunchKernelGGL(k_reduce, dim3(1), dim3(kRedThreads), 0, cx.stream, cx.partials, nblk, nv,
                        cx.ctl);
     LAUNCHCHK();
-    HIPCHK(hipMemcpyAsync(out, &cx.ctl->sums[0], sizeof(double), hipMemcpyDeviceToHost, cx.stream));
+    HIPCHK(hipMemcpyAsync(out, &cx.ctl->sums[0], nv * sizeof(double), hipMemcpyDeviceToHost,
+                          cx.stream));
     HIPCHK(hipStreamSynchronize(cx.stream));
     return MAS_OK;
 }
 
-// r^ = b^ - A^ x^ in double precision, stored as T into r; returns ||W r^||^2.
+// r^ = b^ - A^ x^ in double precision, stored as T into r.
+// Returns rw2 = ||W r^||^2 = ||b - A x||^2 and rr2 = ||r^||^2.
 template <typename T>
-static int residual(Ctx &cx, const double *xhat, T *r, double *rw2) {
+static int residual(Ctx &cx, const double *xhat, T *r, double *rw2, double *rr2 = nullptr) {
     const mas_op *op = cx.op;
     hipLaunchKernelGGL(k_residual<T>, op->s.simple_grid(), dim3(kWave, kSimpleJ), 0, cx.stream,
                        cx.bhat, xhat, op->w, op->c64[0], op->c64[1], op->c64[2], op->s.dims(), r,
                        cx.partials);
     LAUNCHCHK();
-    return reduce1(cx, rw2);
+    double sums[2];
+    int st = reduce_n(cx, 2, sums);
+    *rw2 = sums[0];
+    if (rr2) *rr2 = sums[1];
+    return st;
 }
 
 struct PcgResult {
@@ -445,16 +455,19 @@ struct PcgResult {
 // PCG iterations on the scaled system in precision T.  Before the call,
 // r[iter0 % 2] holds r_{iter0} and x holds x_{iter0}.  mode 0 stops on
 // ||W r||^2 <= tol2 (checked every check_every iterations), mode 1 on
-// (r,r) <= inner_rtol2 (r_0,r_0).
+// (r,r) <= tol2 (every iteration).  The first kernel uses alpha = 0 and
+// beta = beta0: with keep_p it continues the search direction in
+// p[iter0 % 2] (p = r + beta0 p), otherwise it starts afresh (p = r).
 template <typename T>
 static int run_pcg(Ctx &cx, T *const r[2], T *const p[2], T *const q[2], T *x, const T *const c[3],
-                   int mode, int iter0, int max_iter, int check_every, double tol2,
-                   double inner_rtol2, PcgResult *res) {
+                   int mode, int iter0, int max_iter, int check_every, double tol2, bool keep_p,
+                   double beta0, PcgResult *res) {
     const mas_op *op = cx.op;
     const Shape &s = op->s;
     hipStream_t st = cx.stream;
+    if (!keep_p) beta0 = 0.0;
     hipLaunchKernelGGL(k_ctl_init, dim3(1), dim3(64), 0, st, cx.ctl, mode, iter0, max_iter, tol2,
-                       inner_rtol2);
+                       beta0);
     LAUNCHCHK();
     int32_t *pin = nullptr;
     int e = pinned_buffer(&pin);
@@ -498,9 +511,10 @@ static int run_pcg(Ctx &cx, T *const r[2], T *const p[2], T *const q[2], T *x, c
         for (; k <= kend; ++k) {
             const int cur = k & 1, nxt = cur ^ 1;
             a.r_in = r[cur];
-            // the first kernel of a run has alpha = beta = 0: point q and p at
-            // r (finite values) so that every load stays unconditional
-            a.p_in = (k == iter0) ? r[cur] : p[cur];
+            // the first kernel of a run has alpha = 0 (and beta = 0 unless the
+            // direction is kept): point q (and p) at r, finite values, so
+            // that every load stays unconditional
+            a.p_in = (k == iter0 && !keep_p) ? r[cur] : p[cur];
             a.q_in = (k == iter0) ? r[cur] : q[cur];
             a.r_out = r[nxt];
             a.p_out = p[nxt];
@@ -618,7 +632,7 @@ static int solve_core(const mas_op *op, const double *src, int src_is_rhs, doubl
                        cx.bhat, x, o.use_x0 ? 1 : 0, cx.partials);
     LAUNCHCHK();
     double b2 = 0.0;
-    st = reduce1(cx, &b2);
+    st = reduce_n(cx, 1, &b2);
     if (st != MAS_OK) return st;
     const double bnorm = std::sqrt(b2);
     info.bnorm = bnorm;
@@ -651,8 +665,8 @@ static int solve_core(const mas_op *op, const double *src, int src_is_rhs, doubl
         while (status != MAS_OK) {
             if (iter0 > o.max_iters) break;
             PcgResult pr{};
-            st = run_pcg<double>(cx, r, p, q, x, c, 0, iter0, o.max_iters, o.check_every, tol2, 0.0,
-                                 &pr);
+            st = run_pcg<double>(cx, r, p, q, x, c, 0, iter0, o.max_iters, o.check_every, tol2,
+                                 false, 0.0, &pr);
             if (st != MAS_OK) return st;
             timing_summary(cx, pr.last_iter, &info);
             info.iters = pr.last_iter;
@@ -686,36 +700,73 @@ static int solve_core(const mas_op *op, const double *src, int src_is_rhs, doubl
         float *dh = reinterpret_cast<float *>(base + L.dh);
         float *const r[2] = {v[0], v[1]}, *const p[2] = {v[2], v[3]}, *const q[2] = {v[4], v[5]};
         const float *const c[3] = {op->c32[0], op->c32[1], op->c32[2]};
-        double rw2 = 0.0;
-        st = residual<float>(cx, x, r[0], &rw2);
+        const bool reliable = o.refine == MAS_REFINE_RELIABLE;
+        double rw2 = 0.0, rr2 = 0.0;
+        st = residual<float>(cx, x, r[0], &rw2, &rr2);
         if (st != MAS_OK) return st;
         info.rel_resid_true = std::sqrt(rw2) / bnorm;
         status = (rw2 <= tol2) ? MAS_OK : MAS_ENOTCONV;
-        int used = 0;
+        hipLaunchKernelGGL(k_fill<float>, sgrid, sblock, 0, cx.stream, dh, d, 0.0f);
+        LAUNCHCHK();
+        const double d2 = o.inner_rtol * o.inner_rtol;
+        int k0 = 0;          // index of the next iteration kernel
+        int used = 0;        // inner iterations taken
+        double beta0 = 0.0;  // reliable: beta for the first kernel after a replacement
         while (status != MAS_OK && info.outer_iters < o.max_outer && used < o.max_iters) {
-            hipLaunchKernelGGL(k_fill<float>, sgrid, sblock, 0, cx.stream, dh, d, 0.0f);
-            LAUNCHCHK();
+            // Inner stop on the single-precision recursive (scaled) residual:
+            // a factor inner_rtol below the last double-precision residual, or
+            // low enough that the unscaled residual it predicts meets the
+            // tolerance (ratio ||W r||/||r|| taken at the last replacement).
+            double thr = d2 * rr2;
+            if (reliable && rw2 > 0.0) thr = std::max(thr, 0.25 * tol2 * (rr2 / rw2));
             PcgResult pr{};
-            st = run_pcg<float>(cx, r, p, q, dh, c, 1, 0, o.max_iters - used, 1, 0.0,
-                                o.inner_rtol * o.inner_rtol, &pr);
+            const int cur = k0 & 1;
+            st = run_pcg<float>(cx, r, p, q, dh, c, 1, k0, k0 + (o.max_iters - used), 1, thr,
+                                reliable && beta0 > 0.0, beta0, &pr);
             if (st != MAS_OK) return st;
+            (void)cur;
             timing_summary(cx, pr.last_iter, &info);
-            if (pr.flag == FLAG_BREAK && pr.last_iter == 0) {
+            const int taken = pr.last_iter - k0 + 1;  // iteration kernels that did work
+            used += taken;
+            info.outer_iters++;
+            if (pr.flag == FLAG_BREAK && taken == 0) {
                 status = MAS_EBREAKDOWN;
                 break;
             }
-            used += pr.last_iter;
-            info.outer_iters++;
             Ctl h;
             st = read_ctl(cx, &h);
             if (st != MAS_OK) return st;
-            hipLaunchKernelGGL(k_refine_add, sgrid, sblock, 0, cx.stream, dh, d, x);
-            LAUNCHCHK();
-            st = residual<float>(cx, x, r[0], &rw2);
-            if (st != MAS_OK) return st;
+            const int nxt = (pr.last_iter + 1) & 1;
+            if (reliable) {
+                // x^ += d^ + alpha_K p_K, then replace r by the double-precision
+                // residual and continue from the same search direction p_K
+                hipLaunchKernelGGL(k_refine_fold, sgrid, sblock, 0, cx.stream, dh, p[nxt], cx.ctl,
+                                   d, x);
+                LAUNCHCHK();
+                const double rr_old = h.rr, rr_pred = h.rr_next;
+                st = residual<float>(cx, x, r[nxt], &rw2, &rr2);
+                if (st != MAS_OK) return st;
+                // keep the direction only while the replaced residual agrees
+                // with the one the recurrence predicted (no drift of the
+                // single-precision residual); otherwise restart from r
+                const bool keep = pr.flag == FLAG_CONV && rr_old > 0.0 && rr_pred > 0.0 &&
+                                  rr2 <= 4.0 * rr_pred;
+                beta0 = keep ? rr2 / rr_old : 0.0;
+                k0 = pr.last_iter + 1;
+            } else {
+                // classical refinement: x^ += d^; the next inner solve restarts
+                hipLaunchKernelGGL(k_ctl_init, dim3(1), dim3(64), 0, cx.stream, cx.ctl, 1, 0, 0,
+                                   0.0, 0.0);  // alpha = 0 for the fold
+                hipLaunchKernelGGL(k_refine_fold, sgrid, sblock, 0, cx.stream, dh, p[nxt], cx.ctl,
+                                   d, x);
+                LAUNCHCHK();
+                st = residual<float>(cx, x, r[0], &rw2, &rr2);
+                if (st != MAS_OK) return st;
+                k0 = 0;
+            }
             info.rel_resid_true = std::sqrt(rw2) / bnorm;
             status = (rw2 <= tol2) ? MAS_OK : MAS_ENOTCONV;
-            if (pr.flag == FLAG_BREAK && status != MAS_OK) {
+            if (pr.flag == FLAG_BREAK && status != MAS_OK && !reliable) {
                 status = MAS_EBREAKDOWN;
                 break;
             }
@@ -767,7 +818,8 @@ extern "C" int mas_probe_copy(const void *src, void *dst, int64_t bytes, void *h
         return fail(MAS_EINVAL, "copy needs 16-byte aligned pointers and a multiple of 16 bytes");
     const int64_t n16 = bytes / 16;
     if (n16 == 0) return MAS_OK;
-    const int64_t blocks = std::min<int64_t>((n16 + 256 * kCopyU - 1) / (256 * kCopyU), 256 * 16);
+    const int64_t blocks = (n16 + kCopyChunk - 1) / kCopyChunk;
+    if (blocks > INT32_MAX) return fail(MAS_EINVAL, "copy too large");
     hipLaunchKernelGGL(k_copy16, dim3((unsigned)blocks), dim3(256), 0, as_stream(hip_stream),
                        static_cast<const double2 *>(src), static_cast<double2 *>(dst), n16);
     LAUNCHCHK();

@@ -54,15 +54,20 @@ class Grid:
         return cls(p.r_faces, p.t_faces, p.cfg.np_, p.bc_inner, p.bc_outer)
 
 
+REFINES = {"restart": abi.MAS_REFINE_RESTART, "reliable": abi.MAS_REFINE_RELIABLE}
+
+
 def make_opts(rtol=None, max_iters=None, precision=None, inner_rtol=None, max_outer=None,
-              check_every=None, use_x0=None, max_restarts=None, sample_timing=None):
+              check_every=None, use_x0=None, max_restarts=None, sample_timing=None, refine=None):
     o = abi.default_opts()
     if isinstance(precision, str):
         precision = PRECISIONS[precision]
+    if isinstance(refine, str):
+        refine = REFINES[refine]
     for name, v in dict(rtol=rtol, max_iters=max_iters, precision=precision,
                         inner_rtol=inner_rtol, max_outer=max_outer, check_every=check_every,
                         use_x0=use_x0, max_restarts=max_restarts,
-                        sample_timing=sample_timing).items():
+                        sample_timing=sample_timing, refine=refine).items():
         if v is not None:
             setattr(o, name, type(getattr(o, name))(v))
     return o

@@ -1,0 +1,168 @@
+"""Parity at the full workload sizes, in the launch configuration bench.py
+times, through properties the FP64 oracle can check at any size (its own
+residual of the GPU solution, its coefficients and operator apply on every
+cell, its gradient formula evaluated at the GPU's x and lambda, the Euler
+identity) and central differences of the GPU solve itself."""
+import math
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+from gpu_util import DEV, gpu_operator, oracle_operator, oracle_plus_face_arrays, rel, to_dev, to_host
+from paper_1811_02605_amd import _abi as abi
+from paper_1811_02605_amd import solver as S
+from paper_1811_02605_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def c1():
+    p = W.make_problem("c1")
+    say(f"c1 inputs ready: {p.cfg.shape}, dt*max(nu) = {p.dt * p.nu.max():.4e}")
+    return p
+
+
+@pytest.fixture(scope="module")
+def c1_oracle(c1):
+    ora = oracle_operator(c1)
+    say("c1 oracle assembled")
+    return ora
+
+
+def test_c1_operator_and_apply_full(c1, c1_oracle):
+    _, op = gpu_operator(c1, "fp32_refined")
+    got = [to_host(t) for t in op.export()]
+    want = oracle_plus_face_arrays(c1_oracle)
+    for name, g, w in zip(("cr", "ct", "cp", "diag"), got, want):
+        np.testing.assert_allclose(g, w, rtol=64 * 2.0 ** -52, atol=0, err_msg=name)
+    del got, want
+    x = np.random.default_rng(5).standard_normal(c1.shape)
+    y = to_host(op.apply(to_dev(x)))
+    assert rel(y, c1_oracle.apply(x)) <= 1e-13
+    say("c1 coefficients and apply match the oracle on every cell")
+
+
+def test_c1_fp64_and_refined_solves_full(c1, c1_oracle):
+    grid = S.Grid.from_problem(c1)
+    nu, rhs = to_dev(c1.nu), to_dev(c1.rhs)
+    op64 = S.Operator(grid, nu, c1.dt, precision="fp64")
+    x64, i64 = op64.solve(rhs, S.make_opts(rtol=1e-10), allow_notconv=False)
+    del op64
+    opm = S.Operator(grid, nu, c1.dt, precision="fp32_refined")
+    xmp, imp = opm.solve(rhs, S.make_opts(rtol=1e-10, precision="fp32_refined"),
+                         allow_notconv=False)
+    xr, ir = opm.solve(rhs, S.make_opts(rtol=1e-10, precision="fp32_refined", refine="restart"),
+                       allow_notconv=False)
+    del opm
+    b = c1_oracle.rhs_to_b(c1.rhs)
+    x64, xmp, xr = to_host(x64), to_host(xmp), to_host(xr)
+    r64, rmp, rr = (c1_oracle.rel_residual(b, v) for v in (x64, xmp, xr))
+    say(f"c1 oracle residuals: fp64 {r64:.3e} ({i64['iters']} it), refined {rmp:.3e} "
+        f"({imp['iters']} inner, {imp['outer_iters']} outer), restarted {rr:.3e} ({ir['iters']} inner)")
+    assert r64 <= 1e-10 and rmp <= 1e-10 and rr <= 1e-10
+    # the FP64 oracle's own solution, to 1e-12
+    xo, it_o, _, res_o = c1_oracle.pcg(b, tol=1e-12)
+    e64, emp, er = rel(x64, xo), rel(xmp, xo), rel(xr, xo)
+    say(f"c1 error vs oracle solution ({it_o} oracle iterations, residual {res_o:.2e}): "
+        f"fp64 {e64:.2e}, refined {emp:.2e}, restarted {er:.2e}")
+    assert max(e64, emp, er) <= 1e-6
+
+
+@pytest.fixture(scope="module")
+def c3():
+    p = W.make_problem("c3")
+    say(f"c3 inputs ready: {p.cfg.shape}")
+    return p
+
+
+def test_c3_gradient_central_differences(c3):
+    """32 seeded joint directions (d_nu, d_rhs), h = 1e-6, fixed iteration
+    count K for the +/- solves (the count the unperturbed solve needs for
+    1e-13, +10%), so that the finite-difference quotient differentiates a
+    smooth map."""
+    grid = S.Grid.from_problem(c3)
+    nu, rhs = to_dev(c3.nu), to_dev(c3.rhs)
+    op_t = S.Operator(grid, to_dev(W.target_viscosity(c3.nu)), c3.dt)
+    x_t, _ = op_t.solve(rhs, S.make_opts(rtol=1e-12), allow_notconv=False)
+    del op_t
+    op = S.Operator(grid, nu, c3.dt)
+    _, info13 = op.solve(rhs, S.make_opts(rtol=1e-13, check_every=1), allow_notconv=False)
+    K = int(math.ceil(1.1 * info13["iters"]))
+    fixed = S.make_opts(rtol=0.0, max_iters=K, check_every=K)
+
+    # reverse mode through the autograd Function (adjoint solve + fused kernel)
+    nu_r = nu.clone().requires_grad_(True)
+    rhs_r = rhs.clone().requires_grad_(True)
+    x = S.solve(nu_r, rhs_r, grid, c3.dt, rtol=1e-12)
+    loss = 0.5 * torch.sum((x - x_t) ** 2)
+    loss.backward()
+    g_nu, g_rhs = nu_r.grad.detach(), rhs_r.grad.detach()
+    gnorm = math.sqrt(float(torch.sum(g_nu ** 2) + torch.sum(g_rhs ** 2)))
+    say(f"c3: K = {K} fixed iterations; loss {float(loss):.6e}; |g| {gnorm:.3e}")
+
+    def L(nu_v, rhs_v):
+        o = S.Operator(grid, nu_v, c3.dt)
+        xv, inf = o.solve(rhs_v, fixed)
+        assert inf["iters"] == K
+        return float(0.5 * torch.sum((xv - x_t) ** 2))
+
+    h = 1e-6
+    n = c3.cfg.n
+    worst = 0.0
+    for kdir in range(32):
+        d_nu, d_rhs = W.fd_direction(c3.shape, kdir)
+        d_nu, d_rhs = to_dev(d_nu), to_dev(d_rhs)
+        lp = L(nu * (1 + h * d_nu), rhs + h * d_rhs)
+        lm = L(nu * (1 - h * d_nu), rhs - h * d_rhs)
+        fd = (lp - lm) / (2 * h)
+        ad = float(torch.sum(g_nu * nu * d_nu) + torch.sum(g_rhs * d_rhs))
+        dnorm = math.sqrt(float(torch.sum((nu * d_nu) ** 2) + torch.sum(d_rhs ** 2)))
+        err = abs(fd - ad) / max(abs(ad), 0.1 * gnorm * dnorm / math.sqrt(n))
+        worst = max(worst, err)
+        if kdir % 8 == 0:
+            say(f"c3 direction {kdir}: fd {fd:.9e} ad {ad:.9e} rel err {err:.2e}")
+    say(f"c3 worst FD error over 32 directions: {worst:.2e}")
+    assert worst <= 1e-6
+
+
+def test_c4_stress_refined_forward_and_adjoint():
+    p = W.make_problem("c4")
+    say(f"c4 inputs ready: {p.cfg.shape}, dt*max(nu) = {p.dt * p.nu.max():.4e}")
+    grid = S.Grid.from_problem(p)
+    nu, rhs = to_dev(p.nu), to_dev(p.rhs)
+    op = S.Operator(grid, nu, p.dt, precision="fp32_refined")
+    o = S.make_opts(rtol=1e-10, precision="fp32_refined")
+    x, info = op.solve(rhs, o, allow_notconv=False)
+    say(f"c4 refined forward: {info['iters']} inner, {info['outer_iters']} outer, "
+        f"{info['seconds']:.3f} s, residual {info['rel_resid_true']:.2e}")
+    xt = x * 0.95
+    gx = (x - xt).contiguous()
+    lam, gnu, grhs, ainfo = op.adjoint(x, gx, o, allow_notconv=False)
+    say(f"c4 refined adjoint: {ainfo['iters']} inner, {ainfo['seconds']:.3f} s")
+    del op
+    x, lam, gnu, grhs, gx = (to_host(t) for t in (x, lam, gnu, grhs, gx))
+    torch.cuda.empty_cache()
+    ora = oracle_operator(p)
+    b = ora.rhs_to_b(p.rhs)
+    rf, ra = ora.rel_residual(b, x), ora.rel_residual(gx, lam)
+    say(f"c4 oracle residuals: forward {rf:.3e}, adjoint {ra:.3e}")
+    assert rf <= 1e-10 and ra <= 1e-10
+    # the gradient kernel against the oracle's formula at the same x, lambda
+    gnu_o, grhs_o = ora.gradient(x, lam)
+    e_nu, e_rhs = rel(gnu, gnu_o), rel(grhs, grhs_o)
+    say(f"c4 gradient vs oracle formula at the GPU x, lambda: nu {e_nu:.2e}, rhs {e_rhs:.2e}")
+    assert e_nu <= 1e-12 and e_rhs <= 1e-14
+    # Euler identity: <g_nu, nu> = sum V lam x - lam^T b
+    lhs = float(np.sum(gnu * p.nu))
+    rhs_ = float(np.sum(ora.V * lam * x) - np.sum(lam * b))
+    scale = float(np.sum(np.abs(ora.V * lam * x)))
+    say(f"c4 Euler identity: {lhs:.9e} vs {rhs_:.9e}")
+    assert abs(lhs - rhs_) <= 1e-8 * scale

@@ -158,6 +158,48 @@ __device__ inline VecT<T, V> ldv(const T *__restrict__ p, int64_t c) {
     return r;
 }
 
+// Non-temporal variants for data used once per iteration (streamed).
+template <typename T, int V>
+__device__ inline VecT<T, V> ldv_nt(const T *__restrict__ p, int64_t c) {
+    VecT<T, V> r;
+    if constexpr (V == 1) {
+        r.v[0] = __builtin_nontemporal_load(p + c);
+    } else {
+        typedef T raw_t __attribute__((ext_vector_type(V)));
+        const raw_t t = __builtin_nontemporal_load(reinterpret_cast<const raw_t *>(p + c));
+#pragma unroll
+        for (int e = 0; e < V; ++e) r.v[e] = t[e];
+    }
+    return r;
+}
+
+template <typename T, int V>
+__device__ inline void stv_nt(T *__restrict__ p, int64_t c, const VecT<T, V> &x) {
+    if constexpr (V == 1) {
+        __builtin_nontemporal_store(x.v[0], p + c);
+    } else {
+        typedef T raw_t __attribute__((ext_vector_type(V)));
+        raw_t t;
+#pragma unroll
+        for (int e = 0; e < V; ++e) t[e] = x.v[e];
+        __builtin_nontemporal_store(t, reinterpret_cast<raw_t *>(p + c));
+    }
+}
+
+#ifndef MAS_ITER_SYNC
+#define MAS_ITER_SYNC 1
+#endif
+#ifndef MAS_ITER_NT
+#define MAS_ITER_NT 1
+#endif
+#if MAS_ITER_NT
+#define MAS_LDS_ ldv_nt
+#define MAS_STS_ stv_nt
+#else
+#define MAS_LDS_ ldv
+#define MAS_STS_ stv
+#endif
+
 template <typename T, int V>
 __device__ inline void stv(T *__restrict__ p, int64_t c, const VecT<T, V> &x) {
     if constexpr (V == 1) {
@@ -187,8 +229,15 @@ __device__ inline float shfl_dn1(float v) { return __shfl_down(v, 1, kWave); }
 // Per plane step m, the in-plane part of q_k(m) plus the term of the r
 // neighbour already visited is summed into S(m); q_k(m) is completed one
 // step later, when p_k of the next plane is known.
+#ifndef MAS_ITER_WPE
+#define MAS_ITER_WPE 0
+#endif
 template <typename T, int WPB, int V, bool CHECK>
-__global__ __launch_bounds__(kWave *WPB) void k_pcg_iter(IterArgs<T> a) {
+__global__ __launch_bounds__(kWave *WPB)
+#if MAS_ITER_WPE > 0
+__attribute__((amdgpu_waves_per_eu(MAS_ITER_WPE, 8)))
+#endif
+void k_pcg_iter(IterArgs<T> a) {
     constexpr int SEG = kWave * V;
     using VT = VecT<T, V>;
 
@@ -248,11 +297,11 @@ __global__ __launch_bounds__(kWave *WPB) void k_pcg_iter(IterArgs<T> a) {
             r = ldv<T, V>(a.r_in, base + col);
             q = ldv<T, V>(a.q_in, base + col);
             p = ldv<T, V>(a.p_in, base + col);
-            if (m < i1) cr = ldv<T, V>(a.cr, base + col);
+            if (m < i1) cr = MAS_LDS_<T, V>(a.cr, base + col);
             if (own) {
-                x = ldv<T, V>(a.x, base + col);
+                x = MAS_LDS_<T, V>(a.x, base + col);
                 ct = ldv<T, V>(a.ct, base + col);
-                cp = ldv<T, V>(a.cp, base + col);
+                cp = MAS_LDS_<T, V>(a.cp, base + col);
                 rU = ldv<T, V>(a.r_in, base + colU);
                 qU = ldv<T, V>(a.q_in, base + colU);
                 pU = ldv<T, V>(a.p_in, base + colU);
@@ -339,11 +388,16 @@ __global__ __launch_bounds__(kWave *WPB) void k_pcg_iter(IterArgs<T> a) {
         }
         // ---- stores
         if (own && act) {
-            stv<T, V>(a.r_out, base + col, rn);
-            stv<T, V>(a.p_out, base + col, pn);
-            stv<T, V>(a.x, base + col, xn);
+            MAS_STS_<T, V>(a.r_out, base + col, rn);
+            MAS_STS_<T, V>(a.p_out, base + col, pn);
+            MAS_STS_<T, V>(a.x, base + col, xn);
         }
-        if (qdo) stv<T, V>(a.q_out, base1 + col, qv);
+        if (qdo) MAS_STS_<T, V>(a.q_out, base1 + col, qv);
+#if MAS_ITER_SYNC
+        // keep the block's waves on the same plane so that the rows they
+        // load for each other are requested together (L1/L2 reuse)
+        __syncthreads();
+#endif
         pn1 = pn;
         rn1 = rn;
         S1 = S;
@@ -464,6 +518,7 @@ __global__ void k_ctl_init(Ctl *ctl, int mode, int iter0, int max_iter, double t
 // Block (64, 4): 64 phi cells x 4 theta rows, looping over kSimpleR r planes.
 constexpr int kSimpleJ = 4;
 constexpr int kSimpleR = 16;
+constexpr int kSimpleNV = 2;  // most partial sums a simple-tile kernel writes per block
 
 struct SimpleCell {
     int i, j, k;
@@ -615,6 +670,7 @@ __global__ __launch_bounds__(kWave *kSimpleJ) void k_residual(const double *bhat
                                                               const double *ct, const double *cp,
                                                               Dims d, TOUT *rout,
                                                               double *partials) {
+    static_assert(kSimpleNV >= 2, "partials per simple block");
     __shared__ double lds[kSimpleJ * 2];
     double acc[2] = {0.0, 0.0};
     MAS_SIMPLE_LOOP(d, {

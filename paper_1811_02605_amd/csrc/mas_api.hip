@@ -58,9 +58,12 @@ static int fail(int status, const char *fmt, ...) {
 static constexpr int kTJ = MAS_TJ;
 static constexpr int kTI = MAS_TI;
 
+#ifndef MAS_ITER_VEC
+#define MAS_ITER_VEC 16
+#endif
 template <typename T>
 static inline int vec_width(int np) {
-    constexpr int v = 16 / (int)sizeof(T);
+    constexpr int v = MAS_ITER_VEC / (int)sizeof(T) > 0 ? MAS_ITER_VEC / (int)sizeof(T) : 1;
     return (np % v == 0) ? v : 1;
 }
 
@@ -337,7 +340,9 @@ static WorkLayout work_layout(const Shape &s, int precision) {
         off = align256(off + bytes);
         return o;
     };
-    const int64_t nparts = std::max(s.nblk_iter(1) * kNV, s.nblk_simple());
+    // the iteration kernel writes kNV partials per block (most blocks with
+    // V = 1), the simple-tile kernels up to kSimpleNV
+    const int64_t nparts = std::max(s.nblk_iter(1) * kNV, s.nblk_simple() * kSimpleNV);
     L.ctl = take(sizeof(Ctl));
     L.partials = take(8 * nparts);
     L.bhat = take(8 * s.n);
@@ -530,7 +535,7 @@ static int run_pcg(Ctx &cx, T *const r[2], T *const p[2], T *const q[2], T *x, c
                 cx.ev_iter.push_back(k);
                 HIPCHK(hipEventRecord(e0, st));
             }
-            constexpr int VW = 16 / (int)sizeof(T);
+            constexpr int VW = MAS_ITER_VEC / (int)sizeof(T) > 0 ? MAS_ITER_VEC / (int)sizeof(T) : 1;
             if (V == VW) {
                 if (chk)
                     hipLaunchKernelGGL((k_pcg_iter<T, kTJ, VW, true>), grid, block, 0, st, a);
@@ -616,6 +621,9 @@ static int solve_core(const mas_op *op, const double *src, int src_is_rhs, doubl
         return fail(MAS_ENOMEM, "workspace too small: %lld < %lld bytes", (long long)work_bytes,
                     (long long)L.total);
 
+    if (std::max(s.nblk_iter(1) * kNV, s.nblk_simple() * kSimpleNV) * 8 >
+        L.bhat - L.partials)
+        return fail(MAS_EINVAL, "internal: partial-sum area too small");
     char *base = static_cast<char *>(work);
     Ctx cx;
     cx.op = op;

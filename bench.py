@@ -58,21 +58,24 @@ def read_traffic():
     return float(m_bytes.group(1))
 
 
-def cpu_baseline(p, iters=12):
-    """The FP64 CPU oracle (unchanged) on the same workload: assemble, then a
-    fixed number of PCG iterations from x0 = 0; iterations per second."""
+def cpu_baseline(p, max_iters=400):
+    """The FP64 CPU oracle, as it stands, on the same workload: assemble, then
+    its Jacobi-PCG from x0 = 0 to the same 1e-10 tolerance (bounded at
+    max_iters iterations); PCG iterations per second of its solve."""
     import oracle
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     t0 = time.perf_counter()
     ora = oracle.Operator(p.r_faces, p.t_faces, p.cfg.np_, p.nu, p.dt)
     b = ora.rhs_to_b(p.rhs)
     t1 = time.perf_counter()
-    ora.pcg(b, tol=0.0, max_iters=iters)
+    _, iters, rel_rec, rel_true = ora.pcg(b, tol=p.cfg.rtol, max_iters=max_iters)
     t2 = time.perf_counter()
     return {"value": iters / (t2 - t1), "unit": "PCG iters/s", "cores": threads,
             "kind": "oracle",
-            "sample": f"{p.cfg.name} grid {p.cfg.nr}x{p.cfg.nt}x{p.cfg.np_}: {iters} PCG iterations "
-                      f"from x0=0 timed ({t2 - t1:.1f} s); assembly {t1 - t0:.1f} s not counted"}
+            "sample": f"{p.cfg.name} grid {p.cfg.nr}x{p.cfg.nt}x{p.cfg.np_}: oracle PCG from x0=0 "
+                      f"to rel. residual {rel_true:.2e} in {iters} iterations, {t2 - t1:.1f} s "
+                      f"(time to solution); assembly {t1 - t0:.1f} s not counted",
+            "time_to_tol_s": t2 - t1}
 
 
 def main():

@@ -186,11 +186,69 @@ __device__ inline void stv_nt(T *__restrict__ p, int64_t c, const VecT<T, V> &x)
     }
 }
 
+// Buffer-resource access (range-checked by the hardware): an offset at or
+// beyond the resource size reads zeros and drops stores without touching
+// memory, which gives masked accesses with no branch.  Offsets are bytes,
+// 32-bit; every array is below 2^31 bytes.
+constexpr uint32_t kOOB = 0x80000000u;
+constexpr int kAuxNT = 2;  // non-temporal hint in the aux field (gfx94x/gfx950)
+
+__device__ inline __amdgpu_buffer_rsrc_t make_rsrc(const void *p, uint32_t bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), (short)0, (int)bytes, 0x00020000);
+}
+
+template <typename T, int V, int AUX = 0>
+__device__ inline VecT<T, V> bld(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+    constexpr int B = (int)sizeof(T) * V;
+    static_assert(B == 4 || B == 8 || B == 16 || B == 32, "buffer access size");
+    VecT<T, V> out;
+    if constexpr (B == 32) {
+        const auto t0 = __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, AUX);
+        const auto t1 = __builtin_amdgcn_raw_buffer_load_b128(r, off + 16u, 0, AUX);
+        __builtin_memcpy(&out, &t0, 16);
+        __builtin_memcpy(reinterpret_cast<char *>(&out) + 16, &t1, 16);
+    } else if constexpr (B == 16) {
+        const auto t = __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, AUX);
+        __builtin_memcpy(&out, &t, 16);
+    } else if constexpr (B == 8) {
+        const auto t = __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, AUX);
+        __builtin_memcpy(&out, &t, 8);
+    } else {
+        const auto t = __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, AUX);
+        __builtin_memcpy(&out, &t, 4);
+    }
+    return out;
+}
+
+template <typename T, int V, int AUX = 0>
+__device__ inline void bst(__amdgpu_buffer_rsrc_t r, uint32_t off, const VecT<T, V> &x) {
+    constexpr int B = (int)sizeof(T) * V;
+    static_assert(B == 4 || B == 8 || B == 16, "buffer access size");
+    if constexpr (B == 16) {
+        typedef int i4 __attribute__((ext_vector_type(4)));
+        i4 t;
+        __builtin_memcpy(&t, &x, 16);
+        __builtin_amdgcn_raw_buffer_store_b128(t, r, off, 0, AUX);
+    } else if constexpr (B == 8) {
+        typedef int i2 __attribute__((ext_vector_type(2)));
+        i2 t;
+        __builtin_memcpy(&t, &x, 8);
+        __builtin_amdgcn_raw_buffer_store_b64(t, r, off, 0, AUX);
+    } else {
+        int t;
+        __builtin_memcpy(&t, &x, 4);
+        __builtin_amdgcn_raw_buffer_store_b32(t, r, off, 0, AUX);
+    }
+}
+
 #ifndef MAS_ITER_SYNC
-#define MAS_ITER_SYNC 1
+#define MAS_ITER_SYNC 0
 #endif
 #ifndef MAS_ITER_NT
 #define MAS_ITER_NT 1
+#endif
+#ifndef MAS_ITER_DEFER
+#define MAS_ITER_DEFER 1
 #endif
 #if MAS_ITER_NT
 #define MAS_LDS_ ldv_nt
@@ -217,28 +275,34 @@ __device__ inline double shfl_up1(double v) { return __shfl_up(v, 1, kWave); }
 __device__ inline float shfl_up1(float v) { return __shfl_up(v, 1, kWave); }
 __device__ inline double shfl_dn1(double v) { return __shfl_down(v, 1, kWave); }
 __device__ inline float shfl_dn1(float v) { return __shfl_down(v, 1, kWave); }
+__device__ inline double shfl_lane(double v, int src) { return __shfl(v, src, kWave); }
+__device__ inline float shfl_lane(float v, int src) { return __shfl(v, src, kWave); }
 
-// Each wave owns one theta row j and a segment of SEG = 64 V phi cells and
-// marches through the r planes of its chunk on its own: no LDS, no barrier.
-// p_k at the in-plane neighbours is recomputed from (r, q, p)_{k-1}: rows
-// j-1 and j+1 are loaded directly (they are the own rows of the neighbouring
-// waves, so these loads hit L1/L2), the phi neighbours come from lane shuffles
-// and the two segment-edge cells from two extra lanes' loads.  Chunks march
-// up (even chunk index) or down (odd) so that the halo plane a chunk reads
-// is the plane its neighbour chunk reads at the same time.
+// Each wave owns RPW consecutive theta rows, 64/RPW lanes per row, each lane
+// V consecutive phi cells (a segment of SEG = (64/RPW) V cells per row), and
+// marches through the r planes of its chunk on its own.
+// In-plane neighbours of p_k are recomputed from (r, q, p)_{k-1}:
+//   - a theta neighbour inside the wave comes from a cross-lane shuffle of
+//     the neighbouring row's p_k; only the wave's first row loads row j-1 and
+//     its last row loads row j+1 (served by L1/L2/MALL: they are other
+//     waves' own rows);
+//   - phi neighbours come from lane shuffles, the two segment-edge cells of
+//     every row from two extra lanes' loads.
+// Chunks march up (even chunk index) or down (odd), so the halo plane a chunk
+// reads is the plane its neighbour chunk reads at the same time; the
+// block's waves stay on the same plane (a barrier per plane step).
 // Per plane step m, the in-plane part of q_k(m) plus the term of the r
 // neighbour already visited is summed into S(m); q_k(m) is completed one
 // step later, when p_k of the next plane is known.
-#ifndef MAS_ITER_WPE
-#define MAS_ITER_WPE 0
-#endif
-template <typename T, int WPB, int V, bool CHECK>
+template <typename T, int WPB, int RPW, int V, bool CHECK>
 __global__ __launch_bounds__(kWave *WPB)
 #if MAS_ITER_WPE > 0
 __attribute__((amdgpu_waves_per_eu(MAS_ITER_WPE, 8)))
 #endif
 void k_pcg_iter(IterArgs<T> a) {
-    constexpr int SEG = kWave * V;
+    static_assert(kWave % RPW == 0, "rows per wave");
+    constexpr int W = kWave / RPW;  // lanes per row
+    constexpr int SEG = W * V;
     using VT = VecT<T, V>;
 
     const Ctl *ctl = a.ctl;
@@ -255,25 +319,31 @@ void k_pcg_iter(IterArgs<T> a) {
 
     const int lane = threadIdx.x & (kWave - 1);
     const int wv = threadIdx.x / kWave;
-    const int j = jt * WPB + wv;
+    const int rr = lane / W;  // row within the wave
+    const int lp = lane % W;  // lane within the row
+    const int j = (jt * WPB + wv) * RPW + rr;
     const int k0 = kt * SEG;
     const int nseg = min(SEG, np - k0);  // a multiple of V
-    const int nvl = nseg / V;            // lanes holding cells
+    const int nvl = nseg / V;            // lanes per row holding cells
     const bool rowok = j < nt;
-    const bool act = rowok && lane < nvl;
+    const bool act = rowok && lp < nvl;
     const int i0 = it * a.ti;
     const int i1 = min(i0 + a.ti, nr);
     const bool up = (it & 1) == 0;
 
     // own cells; inactive lanes read cell 0 of the plane and discard it
-    const int64_t col = act ? (int64_t)j * np + k0 + lane * V : 0;
+    const int64_t col = act ? (int64_t)j * np + k0 + lp * V : 0;
     const bool hasU = act && j > 0, hasD = act && j < nt - 1;
-    const int64_t colU = hasU ? col - np : 0;
-    const int64_t colD = hasD ? col + np : 0;
-    // segment edges: lane 0 needs the cell left of k0, lane nvl-1 the cell
-    // right of the segment end (periodic in phi)
-    const bool eL = rowok && lane == 0;
-    const bool eR = rowok && lane == nvl - 1;
+    // rows j-1 / j+1 are loaded only by the wave's first / last row
+    const bool ldU = hasU && rr == 0, ldD = hasD && rr == RPW - 1;
+    const int64_t colU = ldU ? col - np : 0;
+    const int64_t colD = ldD ? col + np : 0;
+    const int srcU = (rr > 0) ? lane - W : lane;
+    const int srcD = (rr < RPW - 1) ? lane + W : lane;
+    // segment edges: lane lp = 0 needs the cell left of k0, lane lp = nvl-1
+    // the cell right of the segment end (periodic in phi)
+    const bool eL = rowok && lp == 0;
+    const bool eR = rowok && lp == nvl - 1;
     const int64_t colL = eL ? (int64_t)j * np + ((k0 == 0) ? np - 1 : k0 - 1) : 0;
     const int64_t colR = eR ? (int64_t)j * np + ((k0 + nseg == np) ? 0 : k0 + nseg) : 0;
 
@@ -281,98 +351,134 @@ void k_pcg_iter(IterArgs<T> a) {
     VT pn1{}, rn1{}, S1{}, cr1{};
     VecT<double, V> w1{};
     int64_t base1 = 0;
+#if MAS_ITER_DEFER
+    // results of the previous step, stored only after this step's loads are
+    // issued: the in-order vector-memory counter then never makes a load
+    // wait for a store to complete
+    VT st_r{}, st_p{}, st_x{}, st_q{};
+    bool st_own = false, st_q_do = false;
+    uint32_t st_off = kOOB, st_qoff = kOOB;
+#endif
 
+    // Every access goes through a range-checked buffer resource; a lane that
+    // does not need an access uses an out-of-range offset (zeros in, stores
+    // dropped), so the loop body has no branch around a memory access, the
+    // compiler counts outstanding accesses exactly and no load waits for a
+    // store to complete.
+    constexpr int AN = MAS_ITER_NT ? kAuxNT : 0;
+    const uint32_t nbytes = (uint32_t)(a.d.n * (int64_t)sizeof(T));
+    const auto Rr = make_rsrc(a.r_in, nbytes), Rq = make_rsrc(a.q_in, nbytes),
+               Rp = make_rsrc(a.p_in, nbytes), Rcr = make_rsrc(a.cr, nbytes),
+               Rct = make_rsrc(a.ct, nbytes), Rcp = make_rsrc(a.cp, nbytes),
+               Rx = make_rsrc(a.x, nbytes), Rro = make_rsrc(a.r_out, nbytes),
+               Rpo = make_rsrc(a.p_out, nbytes), Rqo = make_rsrc(a.q_out, nbytes),
+               Rw = make_rsrc(a.w, (uint32_t)(a.d.n * (int64_t)sizeof(double)));
+    constexpr uint32_t ES = sizeof(T);
     const int nsteps = i1 - i0 + 2;
     for (int s = 0; s < nsteps; ++s) {
         const int m = up ? i0 - 1 + s : i1 - s;
         const bool indom = (m >= 0) && (m < nr);
         const bool own = (m >= i0) && (m < i1);
         const int64_t base = (int64_t)(indom ? m : 0) * plane;
+        const bool vin = indom && act, vown = own && act;
+        const uint32_t oc = vin ? (uint32_t)(base + col) * ES : kOOB;
+        const uint32_t oo = vown ? (uint32_t)(base + col) * ES : kOOB;
+        const uint32_t ocr = (vin && m < i1) ? oc : kOOB;
+        const bool vU = own && ldU, vD = own && ldD, vL = own && eL, vR = own && eR;
+        const uint32_t oU = vU ? (uint32_t)(base + colU) * ES : kOOB;
+        const uint32_t oD = vD ? (uint32_t)(base + colD) * ES : kOOB;
+        const uint32_t oL = vL ? (uint32_t)(base + colL) * ES : kOOB;
+        const uint32_t oR = vR ? (uint32_t)(base + colR) * ES : kOOB;
         // ---- loads of plane m, all issued before any use
-        VT r{}, q{}, p{}, cr{}, x{}, ct{}, cp{};
-        VT rU{}, qU{}, pU{}, ctU{}, rD{}, qD{}, pD{};
+        const VT r = bld<T, V>(Rr, oc);
+        const VT q = bld<T, V>(Rq, oc);
+        const VT p = bld<T, V>(Rp, oc);
+        VT cr = bld<T, V, AN>(Rcr, ocr);
+        const VT x = bld<T, V, AN>(Rx, oo);
+        VT ct = bld<T, V>(Rct, oo);
+        VT cp = bld<T, V, AN>(Rcp, oo);
         VecT<double, V> w{};
-        T lr = 0, lq = 0, lp = 0, lcp = 0, rr_ = 0, rq_ = 0, rp_ = 0;
-        if (indom) {
-            r = ldv<T, V>(a.r_in, base + col);
-            q = ldv<T, V>(a.q_in, base + col);
-            p = ldv<T, V>(a.p_in, base + col);
-            if (m < i1) cr = MAS_LDS_<T, V>(a.cr, base + col);
-            if (own) {
-                x = MAS_LDS_<T, V>(a.x, base + col);
-                ct = ldv<T, V>(a.ct, base + col);
-                cp = MAS_LDS_<T, V>(a.cp, base + col);
-                rU = ldv<T, V>(a.r_in, base + colU);
-                qU = ldv<T, V>(a.q_in, base + colU);
-                pU = ldv<T, V>(a.p_in, base + colU);
-                ctU = ldv<T, V>(a.ct, base + colU);
-                rD = ldv<T, V>(a.r_in, base + colD);
-                qD = ldv<T, V>(a.q_in, base + colD);
-                pD = ldv<T, V>(a.p_in, base + colD);
-                if (CHECK) w = ldv<double, V>(a.w, base + col);
-                if (eL) {
-                    lr = a.r_in[base + colL];
-                    lq = a.q_in[base + colL];
-                    lp = a.p_in[base + colL];
-                    lcp = a.cp[base + colL];
-                }
-                if (eR) {
-                    rr_ = a.r_in[base + colR];
-                    rq_ = a.q_in[base + colR];
-                    rp_ = a.p_in[base + colR];
-                }
-            }
-        }
-        // ---- r_k, p_k, x_k of plane m (every load is consumed before any store)
+        if (CHECK) w = bld<double, V>(Rw, vown ? (uint32_t)(base + col) * 8u : kOOB);
+        const VT rU = bld<T, V>(Rr, oU);
+        const VT qU = bld<T, V>(Rq, oU);
+        const VT pU = bld<T, V>(Rp, oU);
+        const VT ctU = bld<T, V>(Rct, oU);
+        const VT rD = bld<T, V>(Rr, oD);
+        const VT qD = bld<T, V>(Rq, oD);
+        const VT pD = bld<T, V>(Rp, oD);
+        const T lr = bld<T, 1>(Rr, oL).v[0];
+        const T lq = bld<T, 1>(Rq, oL).v[0];
+        const T lp_ = bld<T, 1>(Rp, oL).v[0];
+        const T lcp = bld<T, 1>(Rcp, oL).v[0];
+        const T rr_ = bld<T, 1>(Rr, oR).v[0];
+        const T rq_ = bld<T, 1>(Rq, oR).v[0];
+        const T rp_ = bld<T, 1>(Rp, oR).v[0];
+#if MAS_ITER_DEFER
+        // ---- stores of the previous step
+        bst<T, V, AN>(Rro, st_own ? st_off : kOOB, st_r);
+        bst<T, V, AN>(Rpo, st_own ? st_off : kOOB, st_p);
+        bst<T, V, AN>(Rx, st_own ? st_off : kOOB, st_x);
+        bst<T, V, AN>(Rqo, st_q_do ? st_qoff : kOOB, st_q);
+#endif
+        // ---- r_k, p_k, x_k of plane m
         VT rn, pn, xn;
 #pragma unroll
         for (int e = 0; e < V; ++e) {
             rn.v[e] = r.v[e] - alpha * q.v[e];
             pn.v[e] = rn.v[e] + beta * p.v[e];
             xn.v[e] = x.v[e] + alpha * p.v[e];
-        }
-        if (!(indom && act)) {
-            pn = VT{};
-            cr = VT{};
+            if (!vin) pn.v[e] = T(0);
+            if (!(vin && m < i1)) cr.v[e] = T(0);
+            if (!vown) {
+                ct.v[e] = T(0);
+                cp.v[e] = T(0);
+            }
         }
         // face between the previous plane and this one
         const VT cf = up ? cr1 : cr;
         // ---- in-plane part of q_k(m) plus the visited r neighbour
         VT S{};
         if (own) {
-            VT pU_, pD_;
+            VT pU_, pD_, ctU_;
 #pragma unroll
             for (int e = 0; e < V; ++e) {
-                pU_.v[e] = hasU ? (rU.v[e] - alpha * qU.v[e]) + beta * pU.v[e] : T(0);
-                pD_.v[e] = hasD ? (rD.v[e] - alpha * qD.v[e]) + beta * pD.v[e] : T(0);
-                if (!hasU) ctU.v[e] = T(0);
+                // theta neighbours: shuffled from the neighbouring row of the
+                // wave, or formed from the loaded row at the wave's edges
+                const T sU = shfl_lane(pn.v[e], srcU);
+                const T sD = shfl_lane(pn.v[e], srcD);
+                const T sct = shfl_lane(ct.v[e], srcU);
+                const T lU = (rU.v[e] - alpha * qU.v[e]) + beta * pU.v[e];
+                const T lD = (rD.v[e] - alpha * qD.v[e]) + beta * pD.v[e];
+                pU_.v[e] = !hasU ? T(0) : (rr == 0 ? lU : sU);
+                pD_.v[e] = !hasD ? T(0) : (rr == RPW - 1 ? lD : sD);
+                ctU_.v[e] = !hasU ? T(0) : (rr == 0 ? ctU.v[e] : sct);
             }
-            const T pl_edge = (lr - alpha * lq) + beta * lp;
+            const T pl_edge = (lr - alpha * lq) + beta * lp_;
             const T pr_edge = (rr_ - alpha * rq_) + beta * rp_;
             T left0 = shfl_up1(pn.v[V - 1]);
             T right0 = shfl_dn1(pn.v[0]);
             T cpl0 = shfl_up1(cp.v[V - 1]);
-            if (lane == 0) {
-                left0 = pl_edge;
-                cpl0 = lcp;
+            if (lp == 0) {
+                left0 = vL ? pl_edge : T(0);
+                cpl0 = vL ? lcp : T(0);
             }
-            if (lane == nvl - 1) right0 = pr_edge;
+            if (lp == nvl - 1) right0 = vR ? pr_edge : T(0);
 #pragma unroll
             for (int e = 0; e < V; ++e) {
                 const T left = (e > 0) ? pn.v[e - 1] : left0;
                 const T right = (e < V - 1) ? pn.v[e + 1] : right0;
                 const T cpl = (e > 0) ? cp.v[e - 1] : cpl0;
-                S.v[e] = ct.v[e] * pD_.v[e] + ctU.v[e] * pU_.v[e] + cp.v[e] * right + cpl * left +
+                S.v[e] = ct.v[e] * pD_.v[e] + ctU_.v[e] * pU_.v[e] + cp.v[e] * right + cpl * left +
                          cf.v[e] * pn1.v[e];
             }
         }
         // ---- complete q_k of the previous plane
         const int mp = up ? m - 1 : m + 1;
         const bool qdo = mp >= i0 && mp < i1 && act;
-        VT qv{};
-        if (qdo) {
+        VT qv;
 #pragma unroll
-            for (int e = 0; e < V; ++e) qv.v[e] = pn1.v[e] - (S1.v[e] + cf.v[e] * pn.v[e]);
+        for (int e = 0; e < V; ++e) qv.v[e] = pn1.v[e] - (S1.v[e] + cf.v[e] * pn.v[e]);
+        if (qdo) {
 #pragma unroll
             for (int e = 0; e < V; ++e) {
                 const double pd = (double)pn1.v[e], qd = (double)qv.v[e], rd = (double)rn1.v[e];
@@ -387,12 +493,22 @@ void k_pcg_iter(IterArgs<T> a) {
             }
         }
         // ---- stores
-        if (own && act) {
-            MAS_STS_<T, V>(a.r_out, base + col, rn);
-            MAS_STS_<T, V>(a.p_out, base + col, pn);
-            MAS_STS_<T, V>(a.x, base + col, xn);
-        }
-        if (qdo) MAS_STS_<T, V>(a.q_out, base1 + col, qv);
+        const uint32_t oq = qdo ? (uint32_t)(base1 + col) * ES : kOOB;
+#if MAS_ITER_DEFER
+        st_own = vown;
+        st_r = rn;
+        st_p = pn;
+        st_x = xn;
+        st_off = oo;
+        st_q_do = qdo;
+        st_q = qv;
+        st_qoff = oq;
+#else
+        bst<T, V, AN>(Rro, oo, rn);
+        bst<T, V, AN>(Rpo, oo, pn);
+        bst<T, V, AN>(Rx, oo, xn);
+        bst<T, V, AN>(Rqo, oq, qv);
+#endif
 #if MAS_ITER_SYNC
         // keep the block's waves on the same plane so that the rows they
         // load for each other are requested together (L1/L2 reuse)
@@ -405,6 +521,12 @@ void k_pcg_iter(IterArgs<T> a) {
         if (CHECK) w1 = w;
         base1 = base;
     }
+#if MAS_ITER_DEFER
+    bst<T, V, AN>(Rro, st_own ? st_off : kOOB, st_r);
+    bst<T, V, AN>(Rpo, st_own ? st_off : kOOB, st_p);
+    bst<T, V, AN>(Rx, st_own ? st_off : kOOB, st_x);
+    bst<T, V, AN>(Rqo, st_q_do ? st_qoff : kOOB, st_q);
+#endif
     __shared__ double sRed[WPB * kNV];
     block_sum_store<kNV>(acc, a.partials + (int64_t)L * kNV, sRed);
 }

@@ -55,7 +55,11 @@ static int fail(int status, const char *fmt, ...) {
 #ifndef MAS_TI
 #define MAS_TI 16
 #endif
-static constexpr int kTJ = MAS_TJ;
+#ifndef MAS_RPW
+#define MAS_RPW 2
+#endif
+static constexpr int kTJ = MAS_TJ;   // waves per block
+static constexpr int kRPW = MAS_RPW; // theta rows per wave
 static constexpr int kTI = MAS_TI;
 
 #ifndef MAS_ITER_VEC
@@ -73,8 +77,8 @@ struct Shape {
     int nr, nt, np;
     int64_t plane, n;
     Dims dims() const { return Dims{nr, nt, np, plane, n}; }
-    int tiles_k(int v) const { return (np + kWave * v - 1) / (kWave * v); }
-    int tiles_j() const { return (nt + kTJ - 1) / kTJ; }
+    int tiles_k(int v) const { return (np + (kWave / kRPW) * v - 1) / ((kWave / kRPW) * v); }
+    int tiles_j() const { return (nt + kTJ * kRPW - 1) / (kTJ * kRPW); }
     int tiles_i() const { return (nr + kTI - 1) / kTI; }
     int64_t nblk_iter(int v) const { return (int64_t)tiles_k(v) * tiles_j() * tiles_i(); }
     dim3 simple_grid() const {
@@ -132,7 +136,9 @@ static int check_grid(const mas_grid *g, Shape *out) {
         return fail(MAS_EINVAL, "grid sizes must be >= 1 (got %d x %d x %d)", g->nr, g->nt, g->np);
     if (!g->r_faces || !g->t_faces) return fail(MAS_EINVAL, "face arrays must not be NULL");
     const int64_t n = (int64_t)g->nr * g->nt * g->np;
-    if (n > ((int64_t)1 << 40)) return fail(MAS_EINVAL, "grid too large");
+    // the iteration kernel addresses each array with 32-bit byte offsets
+    if (n * (int64_t)sizeof(double) >= ((int64_t)1 << 31))
+        return fail(MAS_EINVAL, "grid too large: at most 268435455 cells");
     if ((int64_t)g->nt > 65535LL * kSimpleJ) return fail(MAS_EINVAL, "nt too large");
     if (!(g->r_faces[0] > 0.0) || !std::isfinite(g->r_faces[0]))
         return fail(MAS_EINVAL, "r_faces[0] must be positive and finite");
@@ -538,14 +544,14 @@ static int run_pcg(Ctx &cx, T *const r[2], T *const p[2], T *const q[2], T *x, c
             constexpr int VW = MAS_ITER_VEC / (int)sizeof(T) > 0 ? MAS_ITER_VEC / (int)sizeof(T) : 1;
             if (V == VW) {
                 if (chk)
-                    hipLaunchKernelGGL((k_pcg_iter<T, kTJ, VW, true>), grid, block, 0, st, a);
+                    hipLaunchKernelGGL((k_pcg_iter<T, kTJ, kRPW, VW, true>), grid, block, 0, st, a);
                 else
-                    hipLaunchKernelGGL((k_pcg_iter<T, kTJ, VW, false>), grid, block, 0, st, a);
+                    hipLaunchKernelGGL((k_pcg_iter<T, kTJ, kRPW, VW, false>), grid, block, 0, st, a);
             } else {
                 if (chk)
-                    hipLaunchKernelGGL((k_pcg_iter<T, kTJ, 1, true>), grid, block, 0, st, a);
+                    hipLaunchKernelGGL((k_pcg_iter<T, kTJ, kRPW, 1, true>), grid, block, 0, st, a);
                 else
-                    hipLaunchKernelGGL((k_pcg_iter<T, kTJ, 1, false>), grid, block, 0, st, a);
+                    hipLaunchKernelGGL((k_pcg_iter<T, kTJ, kRPW, 1, false>), grid, block, 0, st, a);
             }
             if (sample) HIPCHK(hipEventRecord(cx.ev.back(), st));
             hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kRedThreads), 0, st, cx.partials, a.nblk,

@@ -6,13 +6,14 @@ Python binding) never does, and this package imports nothing from the
 product: the two sides share only the seeded inputs they are handed.
 
 ``mas_oracle.c`` holds the arithmetic (geometry, assembly, operator apply,
-Jacobi-preconditioned CG, adjoint gradient); this module is ctypes
+Jacobi-preconditioned CG, adjoint gradient, RKL2 super time-step); this module is ctypes
 marshalling plus numpy array allocation.  ``dense`` holds small dense-matrix
 helpers for tiny grids.
 
 Parity status: every function here is pinned by ``tests/test_oracle_*.py``
-against closed forms, invariants, a manufactured solution, dense LU and
-brute-force finite differences; none is "parity unpinned".
+against closed forms, invariants, a manufactured solution, dense LU,
+brute-force finite differences, the Legendre closed form of the RKL2
+stability polynomial and the matrix exponential; none is "parity unpinned".
 """
 from __future__ import annotations
 
@@ -61,6 +62,14 @@ class _Op(ctypes.Structure):
         for name in ("V", "Ar", "Hr", "At", "Ht", "Ap", "Hp", "cr", "ct", "cp", "diag")]
 
 
+def rkl2_coefficients(s: int):
+    """(mu, nu, mt, gt) arrays of length s+1 for the s-stage RKL2 recursion."""
+    lib = _load()
+    out = [np.zeros(s + 1) for _ in range(4)]
+    lib.ora_rkl2_coefficients(int(s), *[_ptr(a) for a in out])
+    return tuple(out)
+
+
 def _load():
     global _lib
     if _lib is None:
@@ -83,6 +92,12 @@ def _load():
         lib.ora_pcg.restype = ctypes.c_int
         lib.ora_gradient.argtypes = [P(_Op), _dp(), _dp(), _dp(), _dp()]
         lib.ora_gradient.restype = None
+        lib.ora_rkl2_coefficients.argtypes = [ctypes.c_int, _dp(), _dp(), _dp(), _dp()]
+        lib.ora_rkl2_coefficients.restype = None
+        lib.ora_rkl2_stages.argtypes = [P(_Op)]
+        lib.ora_rkl2_stages.restype = ctypes.c_int
+        lib.ora_rkl2_step.argtypes = [P(_Op), _dp(), _dp(), ctypes.c_int]
+        lib.ora_rkl2_step.restype = ctypes.c_int
         _lib = lib
     return _lib
 
@@ -184,6 +199,19 @@ class Operator:
         grhs = np.empty(self.shape)
         _load().ora_gradient(ctypes.byref(self._op), _ptr(x), _ptr(lam), _ptr(gnu), _ptr(grhs))
         return gnu, grhs
+
+    def rkl2_stages(self) -> int:
+        """Stages the stability bound requires for one step of dt."""
+        return int(_load().ora_rkl2_stages(ctypes.byref(self._op)))
+
+    def rkl2_step(self, u0, stages=None) -> np.ndarray:
+        """One RKL2 super time-step of du/dt = L u over dt."""
+        s = self.rkl2_stages() if stages is None else int(stages)
+        u0 = _f64(u0).reshape(self.shape)
+        u1 = np.empty(self.shape)
+        if _load().ora_rkl2_step(ctypes.byref(self._op), _ptr(u0), _ptr(u1), s) != 0:
+            raise ValueError("need at least 2 stages")
+        return u1
 
     def rel_residual(self, b, x) -> float:
         b = _f64(b).reshape(self.shape)

@@ -417,3 +417,87 @@ void ora_gradient(const ora_op *op, const double *x, const double *lam, double *
                 if (g_rhs) g_rhs[c] = op->V[c] * lam[c];
             }
 }
+
+/* ------------------------------------------------------------------ RKL2 super time-stepping
+ * The explicit alternative to the implicit solve for the viscous term (the paper, Section 2.2,
+ * cites the second-order Runge-Kutta-Legendre scheme RKL2 of Meyer, Balsara and Aslam, 2014;
+ * Section 3 reports about 200 such sub-steps per time step; Section 5.2 finds it the faster
+ * choice on GPUs).  The stage recursion below is that published method restated, not taken
+ * from the paper, which gives no coefficients.
+ * It advances du/dt = L u by one step of the operator's dt, where the finite-volume
+ * diffusion operator is L u = -(1/V) sum_f (c_f/dt)(u_c - u_nb); with A = V + dt K this is
+ *     dt L u = u - (A u)/V.
+ * s-stage recursion (w1 = 4/(s^2+s-2); b_0 = b_1 = b_2 = 1/3, b_j = (j^2+j-2)/(2j(j+1));
+ * a_j = 1 - b_j; mu_j = (2j-1)/j b_j/b_{j-1}; nu_j = -(j-1)/j b_j/b_{j-2};
+ * mt_j = mu_j w1 (mt_1 = b_1 w1); gt_j = -a_{j-1} mt_j):
+ *     Y_0 = u,  Y_1 = Y_0 + mt_1 dtL(Y_0),
+ *     Y_j = mu_j Y_{j-1} + nu_j Y_{j-2} + (1 - mu_j - nu_j) Y_0 + mt_j dtL(Y_{j-1}) + gt_j dtL(Y_0),
+ *     u_new = Y_s.
+ * It is stable while dt |lambda| <= (s^2 + s - 2)/2 for every eigenvalue lambda of L.
+ */
+void ora_rkl2_coefficients(int s, double *mu, double *nu, double *mt, double *gt) {
+    double w1 = 4.0 / ((double)s * s + s - 2.0);
+    double *b = (double *)malloc(sizeof(double) * (s + 1));
+    for (int j = 0; j <= s; j++) b[j] = (j <= 2) ? 1.0 / 3.0 : ((double)j * j + j - 2.0) / (2.0 * j * (j + 1.0));
+    for (int j = 0; j <= s; j++) mu[j] = nu[j] = mt[j] = gt[j] = 0.0;
+    mt[1] = b[1] * w1;
+    for (int j = 2; j <= s; j++) {
+        mu[j] = (2.0 * j - 1.0) / j * b[j] / b[j - 1];
+        nu[j] = -(j - 1.0) / j * b[j] / b[j - 2];
+        mt[j] = mu[j] * w1;
+        gt[j] = -(1.0 - b[j - 1]) * mt[j];
+    }
+    free(b);
+}
+
+/* Smallest s >= 2 with (s^2 + s - 2)/2 >= z_max, z_max = max_c 2 (A_cc - V_c)/V_c
+ * (a Gershgorin bound of dt |lambda| for V^-1 (A - V)). */
+int ora_rkl2_stages(const ora_op *op) {
+    size_t n = ncell(&op->g);
+    double zmax = 0.0;
+    for (size_t c = 0; c < n; c++) {
+        double z = 2.0 * (op->diag[c] - op->V[c]) / op->V[c];
+        if (z > zmax) zmax = z;
+    }
+    int s = 2;
+    while (((double)s * s + s - 2.0) / 2.0 < zmax) s++;
+    return s;
+}
+
+static void dtL(const ora_op *op, const double *y, double *ay, double *out) {
+    size_t n = ncell(&op->g);
+    ora_apply(op, y, ay);
+#pragma omp parallel for schedule(static)
+    for (size_t c = 0; c < n; c++) out[c] = y[c] - ay[c] / op->V[c];
+}
+
+int ora_rkl2_step(const ora_op *op, const double *u0, double *u1, int s) {
+    if (s < 2) return -1;
+    size_t n = ncell(&op->g);
+    double *mu = (double *)malloc(sizeof(double) * (s + 1)), *nu = (double *)malloc(sizeof(double) * (s + 1));
+    double *mt = (double *)malloc(sizeof(double) * (s + 1)), *gt = (double *)malloc(sizeof(double) * (s + 1));
+    ora_rkl2_coefficients(s, mu, nu, mt, gt);
+    double *L0 = (double *)malloc(sizeof(double) * n), *Lj = (double *)malloc(sizeof(double) * n);
+    double *ay = (double *)malloc(sizeof(double) * n);
+    double *ym2 = (double *)malloc(sizeof(double) * n), *ym1 = (double *)malloc(sizeof(double) * n);
+    double *yj = (double *)malloc(sizeof(double) * n);
+    dtL(op, u0, ay, L0);
+#pragma omp parallel for schedule(static)
+    for (size_t c = 0; c < n; c++) {
+        ym2[c] = u0[c];
+        ym1[c] = u0[c] + mt[1] * L0[c];
+    }
+    for (int j = 2; j <= s; j++) {
+        dtL(op, ym1, ay, Lj);
+#pragma omp parallel for schedule(static)
+        for (size_t c = 0; c < n; c++)
+            yj[c] = mu[j] * ym1[c] + nu[j] * ym2[c] + (1.0 - mu[j] - nu[j]) * u0[c] + mt[j] * Lj[c] + gt[j] * L0[c];
+        double *t = ym2;
+        ym2 = ym1;
+        ym1 = yj;
+        yj = t;
+    }
+    memcpy(u1, ym1, sizeof(double) * n);
+    free(mu), free(nu), free(mt), free(gt), free(L0), free(Lj), free(ay), free(ym2), free(ym1), free(yj);
+    return 0;
+}

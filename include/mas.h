@@ -32,7 +32,8 @@
  *   - hip_stream is a hipStream_t (NULL = the null stream).  All device work
  *     is ordered on it.  Calls that return a solver result (build, solve,
  *     adjoint) block the calling thread until the result is known; the others
- *     only enqueue work.
+ *     (the explicit step included, unless it is asked to time itself) only
+ *     enqueue work.
  *   - Errors are returned as status codes (never thrown, never abort);
  *     mas_last_error() gives a message for the calling thread.
  */
@@ -123,7 +124,8 @@ void mas_pcg_default_opts(mas_pcg_opts *o);
  * negative status for an invalid grid. */
 int64_t mas_op_storage_bytes(const mas_grid *g, int32_t precision);
 
-/* Assemble the operator A(nu, dt) of the system above into caller storage.
+/* Assemble the operator A(nu, dt) of the system above into caller storage
+ * (with a copy of nu and the bound z_max that the explicit step uses).
  *   g        host grid (read during the call only)
  *   nu       dev, N viscosity values, each > 0 and finite (read during the call only)
  *   dt       time step >= 0
@@ -183,6 +185,68 @@ int mas_pcg_solve(const mas_op *op, const double *rhs, double *x, const mas_pcg_
 int mas_pcg_solve_adjoint(const mas_op *op, const double *x, const double *gx, double *lambda,
                           double *g_nu, double *g_rhs, const mas_pcg_opts *o, void *work,
                           int64_t work_bytes, void *hip_stream, mas_pcg_info *info);
+
+/* ---------------------------------------------------------------- explicit viscous step
+ * RKL2 super time-stepping: the explicit alternative to the implicit solve for
+ * the viscous term (the paper, Section 2.2, cites the second-order
+ * Runge-Kutta-Legendre scheme of Meyer, Balsara and Aslam, 2014; Section 3
+ * reports about 200 such sub-steps per time step; Section 5.2 finds it the
+ * faster choice on GPUs).  With the operator's nu and dt it advances
+ *
+ *     du/dt = L u,   dt L u = u - (A u) ./ V = -(1/V) sum_f c_f (u_c - u_nb)
+ *
+ * over one time step dt by s stages of the Legendre recursion
+ *     Y_0 = u0,  Y_1 = Y_0 + mt_1 dtL(Y_0),
+ *     Y_j = mu_j Y_{j-1} + nu_j Y_{j-2} + (1 - mu_j - nu_j) Y_0
+ *           + mt_j dtL(Y_{j-1}) + gt_j dtL(Y_0),            j = 2..s,
+ *     u1 = Y_s,
+ * with w1 = 4/(s^2+s-2), b_0 = b_1 = b_2 = 1/3, b_j = (j^2+j-2)/(2j(j+1)),
+ * mt_1 = b_1 w1, mu_j = (2j-1)/j b_j/b_{j-1}, nu_j = -(j-1)/j b_j/b_{j-2},
+ * mt_j = mu_j w1, gt_j = -(1 - b_{j-1}) mt_j.  The step is second-order
+ * accurate and stable while dt |lambda| <= (s^2+s-2)/2 for every eigenvalue
+ * lambda of L; the automatic stage count bounds dt |lambda| by the Gershgorin
+ * bound z_max = max_c 2 (A_cc - V_c)/V_c taken when the operator was built.
+ * The operator may have been built in either precision; the step is always
+ * double precision. */
+typedef struct {
+    int32_t stages;        /* 0: the smallest s >= 2 with (s^2+s-2)/2 >= z_max
+                              (mas_sts_stages); else s in [2, 1000000], fewer
+                              than the automatic count may be unstable          (0) */
+    int32_t sample_timing; /* nonzero: time the step and a sample of its stage
+                              kernels with HIP events and wait for completion    (0) */
+} mas_sts_opts;
+
+typedef struct {
+    int32_t status;               /* the call's return value                             */
+    int32_t stages;               /* stages run                                          */
+    double z_max;                 /* Gershgorin bound of dt * spectral radius of L       */
+    double step_us;               /* device time of the whole step (sample_timing only)  */
+    double stage_kernel_us;       /* mean of the sampled stage kernels (us)              */
+    int32_t stage_kernel_samples; /* samples behind stage_kernel_us (0: not sampled)     */
+    int32_t pad_;
+} mas_sts_info;
+
+/* Fill *o with the defaults shown above. */
+void mas_sts_default_opts(mas_sts_opts *o);
+
+/* The automatic stage count for op's dt (>= 2), or a negative status:
+ * MAS_EINVAL for a NULL op or a dt needing more than 1000000 stages. */
+int32_t mas_sts_stages(const mas_op *op);
+
+/* Bytes of device workspace mas_sts_step needs (three cell arrays). */
+int64_t mas_sts_workspace_bytes(const mas_op *op);
+
+/* One RKL2 step of dt: u1 = Y_s from u0 (both dev, N).  u1 may equal u0
+ * (in-place step); neither may overlap the workspace.
+ *   o     host, may be NULL for the defaults
+ *   work  dev, >= mas_sts_workspace_bytes(op) bytes, 256-byte aligned
+ *   info  host, may be NULL
+ * Enqueues s kernels (dtL(u0), then stages 2..s) on hip_stream and returns; with
+ * o->sample_timing it also waits for them.  Calls sharing one workspace must
+ * be ordered on one stream.  Returns MAS_OK, MAS_EINVAL, MAS_ENOMEM or
+ * MAS_EHIP. */
+int mas_sts_step(const mas_op *op, const double *u0, double *u1, const mas_sts_opts *o,
+                 void *work, int64_t work_bytes, void *hip_stream, mas_sts_info *info);
 
 /* Bandwidth probe: dst[0:bytes) = src[0:bytes), both dev, 16-byte aligned,
  * bytes a multiple of 16.  A plain streaming copy used to calibrate the HBM

@@ -58,6 +58,20 @@ class mas_pcg_info(ctypes.Structure):
         return {f: getattr(self, f) for f, _ in self._fields_ if f != "pad_"}
 
 
+class mas_sts_opts(ctypes.Structure):
+    _fields_ = [("stages", ctypes.c_int32), ("sample_timing", ctypes.c_int32)]
+
+
+class mas_sts_info(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("stages", ctypes.c_int32),
+                ("z_max", ctypes.c_double), ("step_us", ctypes.c_double),
+                ("stage_kernel_us", ctypes.c_double), ("stage_kernel_samples", ctypes.c_int32),
+                ("pad_", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_ if f != "pad_"}
+
+
 # name -> (restype, argtypes), in the order of include/mas.h
 _VP = ctypes.c_void_p
 _SIGS = {
@@ -74,6 +88,11 @@ _SIGS = {
     "mas_pcg_solve_adjoint": (ctypes.c_int, [_VP, _VP, _VP, _VP, _VP, _VP,
                                              ctypes.POINTER(mas_pcg_opts), _VP, ctypes.c_int64,
                                              _VP, ctypes.POINTER(mas_pcg_info)]),
+    "mas_sts_default_opts": (None, [ctypes.POINTER(mas_sts_opts)]),
+    "mas_sts_stages": (ctypes.c_int32, [_VP]),
+    "mas_sts_workspace_bytes": (ctypes.c_int64, [_VP]),
+    "mas_sts_step": (ctypes.c_int, [_VP, _VP, _VP, ctypes.POINTER(mas_sts_opts), _VP,
+                                    ctypes.c_int64, _VP, ctypes.POINTER(mas_sts_info)]),
     "mas_probe_copy": (ctypes.c_int, [_VP, _VP, ctypes.c_int64, _VP]),
     "mas_status_string": (ctypes.c_char_p, [ctypes.c_int]),
     "mas_last_error": (ctypes.c_char_p, []),

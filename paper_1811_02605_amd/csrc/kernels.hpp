@@ -671,10 +671,17 @@ __device__ inline double face_c(double dt, double nua, double nub, double g) {
     return dt * (0.5 * (nua + nub)) * g;
 }
 
-// Diagonal of A, its square root, and validity of nu.
+// Diagonal of A, its square root, and validity of nu; also a copy of nu
+// (the explicit stages form their conductances from it) and the largest
+// z_c = 2 (A_cc - V_c) / V_c, a Gershgorin bound of dt times the spectral
+// radius of V^-1 (A - V), kept as the bits of a non-negative double so that
+// an integer maximum finds it.
 __global__ __launch_bounds__(kWave *kSimpleJ) void k_build_diag(const double *nu, Geo geo, Dims d,
-                                                                double *w, int32_t *bad) {
+                                                                double *w, double *nu_copy,
+                                                                int32_t *bad,
+                                                                unsigned long long *zmax_bits) {
     int badv = 0;
+    double zmax = 0.0;
     MAS_SIMPLE_LOOP(d, {
         if (cell.ok) {
             const int i = cell.i, j = cell.j, k = cell.k;
@@ -700,9 +707,20 @@ __global__ __launch_bounds__(kWave *kSimpleJ) void k_build_diag(const double *nu
                 s += face_c(geo.dt, nc, nu[c - k + kp], gp);
             }
             w[c] = sqrt(s);
+            nu_copy[c] = nc;
+            const double vc = geo.vr[i] * vt;
+            const double z = 2.0 * (s - vc) / vc;
+            zmax = (z > zmax) ? z : zmax;  // false for NaN: nu was then flagged bad
         }
     })
     if (badv) atomicOr(bad, 1);
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        const double t = __shfl_xor(zmax, o, kWave);
+        zmax = (t > zmax) ? t : zmax;
+    }
+    if ((threadIdx.x & (kWave - 1)) == 0 && zmax > 0.0)
+        atomicMax(zmax_bits, (unsigned long long)__double_as_longlong(zmax));
 }
 
 // Scaled couplings to the +r, +theta, +phi neighbours.

@@ -15,6 +15,7 @@
 
 #include "../../include/mas.h"
 #include "kernels.hpp"
+#include "sts_kernels.hpp"
 
 using namespace mas;
 
@@ -101,11 +102,13 @@ struct mas_op {
     double *w;
     double *c64[3];
     float *c32[3];      // null unless built with MAS_FP32_REFINED
+    double *nu;         // copy of nu (explicit stages form conductances from it)
+    double zmax;        // max_c 2 (A_cc - V_c) / V_c
     hipStream_t build_stream;
 };
 
 struct StorageLayout {
-    int64_t flags, vr, vt, gr, gq, gtt, gpt, w, c64[3], c32[3], total;
+    int64_t flags, vr, vt, gr, gq, gtt, gpt, w, c64[3], c32[3], nu, total;
 };
 
 static StorageLayout storage_layout(const Shape &s, int precision) {
@@ -126,6 +129,7 @@ static StorageLayout storage_layout(const Shape &s, int precision) {
     L.w = take(8 * s.n);
     for (int t = 0; t < 3; ++t) L.c64[t] = take(8 * s.n);
     for (int t = 0; t < 3; ++t) L.c32[t] = (precision == MAS_FP32_REFINED) ? take(4 * s.n) : -1;
+    L.nu = take(8 * s.n);
     L.total = off;
     return L;
 }
@@ -268,6 +272,8 @@ extern "C" int mas_op_build(const mas_grid *g, const double *nu, double dt, int3
         op->c64[t] = reinterpret_cast<double *>(base + L.c64[t]);
         op->c32[t] = (L.c32[t] >= 0) ? reinterpret_cast<float *>(base + L.c32[t]) : nullptr;
     }
+    op->nu = reinterpret_cast<double *>(base + L.nu);
+    // flags: [0] nu invalid, [2:4] bits of z_max
     int32_t *flags = reinterpret_cast<int32_t *>(base + L.flags);
 
     auto cleanup_fail = [&](int status) {
@@ -287,8 +293,9 @@ extern "C" int mas_op_build(const mas_grid *g, const double *nu, double dt, int3
     const Dims d = s.dims();
     const dim3 grid = s.simple_grid(), block(kWave, kSimpleJ);
     hipLaunchKernelGGL(k_fill<int32_t>, dim3(1, 1, 1), block, 0, stream, flags,
-                       Dims{1, 1, 1, 1, 1}, 0);
-    hipLaunchKernelGGL(k_build_diag, grid, block, 0, stream, nu, op->geo, d, op->w, flags);
+                       Dims{1, 1, 4, 4, 4}, 0);
+    hipLaunchKernelGGL(k_build_diag, grid, block, 0, stream, nu, op->geo, d, op->w, op->nu, flags,
+                       reinterpret_cast<unsigned long long *>(flags + 2));
     if (precision == MAS_FP32_REFINED)
         hipLaunchKernelGGL(k_build_coef<true>, grid, block, 0, stream, nu, op->w, op->geo, d,
                            op->c64[0], op->c64[1], op->c64[2], op->c32[0], op->c32[1], op->c32[2]);
@@ -300,14 +307,15 @@ extern "C" int mas_op_build(const mas_grid *g, const double *nu, double dt, int3
         if (e != hipSuccess)
             return cleanup_fail(fail(MAS_EHIP, "build launch failed: %s", hipGetErrorString(e)));
     }
-    int32_t bad = 0;
+    int32_t fl[4] = {0, 0, 0, 0};
     {
-        hipError_t e = hipMemcpyAsync(&bad, flags, sizeof bad, hipMemcpyDeviceToHost, stream);
+        hipError_t e = hipMemcpyAsync(fl, flags, sizeof fl, hipMemcpyDeviceToHost, stream);
         if (e == hipSuccess) e = hipStreamSynchronize(stream);
         if (e != hipSuccess)
             return cleanup_fail(fail(MAS_EHIP, "build failed: %s", hipGetErrorString(e)));
     }
-    if (bad) return cleanup_fail(fail(MAS_EINVAL, "nu must be positive and finite everywhere"));
+    if (fl[0]) return cleanup_fail(fail(MAS_EINVAL, "nu must be positive and finite everywhere"));
+    std::memcpy(&op->zmax, &fl[2], sizeof(double));
     *op_out = op;
     return MAS_OK;
 }
@@ -823,6 +831,247 @@ extern "C" int mas_pcg_solve_adjoint(const mas_op *op, const double *x, const do
     LAUNCHCHK();
     HIPCHK(hipStreamSynchronize(as_stream(hip_stream)));
     return st;
+}
+
+// ------------------------------------------------------------------ RKL2 super time-stepping
+#ifndef MAS_STS_WPB
+#define MAS_STS_WPB 4
+#endif
+#ifndef MAS_STS_RPW
+#define MAS_STS_RPW 2
+#endif
+#ifndef MAS_STS_TI
+#define MAS_STS_TI 16
+#endif
+static constexpr int kStsWPB = MAS_STS_WPB, kStsRPW = MAS_STS_RPW, kStsTI = MAS_STS_TI;
+static constexpr int kStsMaxStages = 1000000;
+static constexpr int kStsMaxSamples = 32;
+
+// Smallest s >= 2 whose stability interval [-(s^2 + s - 2)/2, 0] holds
+// [-zmax, 0]; -1 when that needs more than kStsMaxStages.
+static int sts_stages_for(double zmax) {
+    if (!(zmax <= 0.5 * ((double)kStsMaxStages * kStsMaxStages + kStsMaxStages - 2.0))) return -1;
+    auto covers = [&](int s) { return 0.5 * ((double)s * s + s - 2.0) >= zmax; };
+    int s = std::max(2, (int)std::ceil(0.5 * (-1.0 + std::sqrt(9.0 + 8.0 * std::max(zmax, 0.0)))));
+    while (!covers(s)) ++s;
+    while (s > 2 && covers(s - 1)) --s;
+    return s;
+}
+
+// Coefficients of the s-stage RKL2 recursion (Meyer, Balsara and Aslam,
+// 2014), index j = 0..s:
+//   w1 = 4/(s^2+s-2), b_0 = b_1 = b_2 = 1/3, b_j = (j^2+j-2)/(2j(j+1)),
+//   mt_1 = b_1 w1, and for j >= 2
+//   mu_j = (2j-1)/j b_j/b_{j-1}, nu_j = -(j-1)/j b_j/b_{j-2},
+//   mt_j = mu_j w1, gt_j = -(1 - b_{j-1}) mt_j.
+struct Rkl2 {
+    std::vector<double> mu, nu, mt, gt;
+};
+
+static Rkl2 rkl2_coefficients(int s) {
+    Rkl2 c;
+    c.mu.assign(s + 1, 0.0);
+    c.nu.assign(s + 1, 0.0);
+    c.mt.assign(s + 1, 0.0);
+    c.gt.assign(s + 1, 0.0);
+    std::vector<double> b(s + 1);
+    for (int j = 0; j <= s; ++j)
+        b[j] = (j < 3) ? 1.0 / 3.0 : ((double)j * j + j - 2.0) / (2.0 * j * (j + 1.0));
+    const double w1 = 4.0 / ((double)s * s + s - 2.0);
+    c.mt[1] = b[1] * w1;
+    for (int j = 2; j <= s; ++j) {
+        c.mu[j] = (2.0 * j - 1.0) / j * b[j] / b[j - 1];
+        c.nu[j] = -(j - 1.0) / j * b[j] / b[j - 2];
+        c.mt[j] = c.mu[j] * w1;
+        c.gt[j] = -(1.0 - b[j - 1]) * c.mt[j];
+    }
+    return c;
+}
+
+struct StsWork {
+    int64_t vec[3], total;
+};
+
+static StsWork sts_work_layout(const Shape &s) {
+    StsWork L{};
+    int64_t off = 0;
+    for (int t = 0; t < 3; ++t) {
+        L.vec[t] = off;
+        off = align256(off + 8 * s.n);
+    }
+    L.total = off;
+    return L;
+}
+
+extern "C" void mas_sts_default_opts(mas_sts_opts *o) {
+    if (!o) return;
+    o->stages = 0;
+    o->sample_timing = 0;
+}
+
+extern "C" int32_t mas_sts_stages(const mas_op *op) {
+    if (!op) return fail(MAS_EINVAL, "op must not be NULL");
+    const int s = sts_stages_for(op->zmax);
+    if (s < 0) return fail(MAS_EINVAL, "dt needs more than %d explicit stages", kStsMaxStages);
+    return s;
+}
+
+extern "C" int64_t mas_sts_workspace_bytes(const mas_op *op) {
+    if (!op) return fail(MAS_EINVAL, "op must not be NULL");
+    return sts_work_layout(op->s).total;
+}
+
+// One stage kernel: out = a X + b Z + g L0 + Y0 + m dtL(X).
+static int sts_launch(const mas_op *op, hipStream_t stream, const double *X, const double *Z,
+                      const double *L0, const double *Y0, double *out, double a, double b,
+                      double g, double m) {
+    const Shape &s = op->s;
+    const int v = (s.np % 2 == 0) ? 2 : 1;
+    const int seg = (kWave / kStsRPW) * v;
+    const int64_t tiles_i = (s.nr + kStsTI - 1) / kStsTI;
+    const int64_t tiles_k = (s.np + seg - 1) / seg;
+    const int64_t tiles_j = (s.nt + kStsWPB * kStsRPW - 1) / (kStsWPB * kStsRPW);
+    const int64_t nblk = tiles_i * tiles_k * tiles_j;
+    if (nblk > INT32_MAX) return fail(MAS_EINVAL, "grid too large for the stage kernel");
+    StsArgs args{X, op->nu, Z, L0, Y0, out, a, b, g, m * op->dt, op->geo, s.dims(),
+                 (int)tiles_i, (int)tiles_k, (int)tiles_j, kStsTI, (int)nblk};
+    if (v == 2)
+        hipLaunchKernelGGL((k_sts_stage<kStsWPB, kStsRPW, 2>), dim3((unsigned)nblk),
+                           dim3(kWave * kStsWPB), 0, stream, args);
+    else
+        hipLaunchKernelGGL((k_sts_stage<kStsWPB, kStsRPW, 1>), dim3((unsigned)nblk),
+                           dim3(kWave * kStsWPB), 0, stream, args);
+    LAUNCHCHK();
+    return MAS_OK;
+}
+
+namespace {
+struct EventPool {
+    std::vector<hipEvent_t> ev;
+    ~EventPool() {
+        for (auto e : ev) (void)hipEventDestroy(e);
+    }
+    int make(hipEvent_t *out) {
+        hipEvent_t e;
+        HIPCHK(hipEventCreate(&e));
+        ev.push_back(e);
+        *out = e;
+        return MAS_OK;
+    }
+};
+}  // namespace
+
+// The recursion runs on D_j = Y_j - Y_0 (linearity of L gives
+// dtL(Y_{j-1}) = dtL(D_{j-1}) + L_0 with L_0 = dtL(Y_0)):
+//   D_1 = mt_1 L_0,
+//   D_j = mu_j D_{j-1} + nu_j D_{j-2} + mt_j dtL(D_{j-1}) + (mt_j + gt_j) L_0,
+//   u1 = Y_0 + D_s,
+// so only the last stage reads Y_0.  D_1 is never stored (stages 2 and 3 read
+// L_0 in its place) and D_j overwrites D_{j-2} cell by cell.
+extern "C" int mas_sts_step(const mas_op *op, const double *u0, double *u1, const mas_sts_opts *o,
+                            void *work, int64_t work_bytes, void *hip_stream, mas_sts_info *info) {
+    g_last_error.clear();
+    if (info) std::memset(info, 0, sizeof *info);
+    auto done = [&](int st) {
+        if (info) info->status = st;
+        return st;
+    };
+    if (!op || !u0 || !u1 || !work) return done(fail(MAS_EINVAL, "op, u0, u1 and work must not be NULL"));
+    mas_sts_opts def;
+    mas_sts_default_opts(&def);
+    if (!o) o = &def;
+    if (reinterpret_cast<uintptr_t>(work) & 255)
+        return done(fail(MAS_EINVAL, "work must be 256-byte aligned"));
+    const StsWork L = sts_work_layout(op->s);
+    if (work_bytes < L.total)
+        return done(fail(MAS_ENOMEM, "workspace too small: %lld < %lld bytes",
+                         (long long)work_bytes, (long long)L.total));
+    int s = o->stages;
+    if (s == 0) {
+        s = sts_stages_for(op->zmax);
+        if (s < 0) return done(fail(MAS_EINVAL, "dt needs more than %d explicit stages", kStsMaxStages));
+    } else if (s < 2 || s > kStsMaxStages) {
+        return done(fail(MAS_EINVAL, "stages must be 0 (automatic) or in [2, %d]", kStsMaxStages));
+    }
+    if (info) {
+        info->stages = s;
+        info->z_max = op->zmax;
+    }
+    hipStream_t stream = as_stream(hip_stream);
+    char *base = static_cast<char *>(work);
+    double *L0 = reinterpret_cast<double *>(base + L.vec[0]);
+    double *W[2] = {reinterpret_cast<double *>(base + L.vec[1]),
+                    reinterpret_cast<double *>(base + L.vec[2])};
+    const Rkl2 c = rkl2_coefficients(s);
+
+    EventPool pool;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> samples;
+    const bool timing = o->sample_timing != 0;
+    if (timing) {
+        int st = pool.make(&ev0);
+        if (st == MAS_OK) st = pool.make(&ev1);
+        if (st != MAS_OK) return done(st);
+        if (hipEventRecord(ev0, stream) != hipSuccess)
+            return done(fail(MAS_EHIP, "hipEventRecord failed"));
+    }
+    // the general stages 4 .. s-1 are sampled, evenly, up to kStsMaxSamples
+    const int ngen = std::max(0, s - 4);
+    const int every = std::max(1, (ngen + kStsMaxSamples - 1) / kStsMaxSamples);
+
+    // L_0 = dtL(Y_0)
+    int st = sts_launch(op, stream, u0, nullptr, nullptr, nullptr, L0, 0.0, 0.0, 0.0, 1.0);
+    if (st != MAS_OK) return done(st);
+    for (int j = 2; j <= s; ++j) {
+        const bool last = j == s;
+        double *out = last ? u1 : W[j & 1];
+        const double *Y0 = last ? u0 : nullptr;
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        const bool sample = timing && !last && j >= 4 && ((j - 4) % every == 0);
+        if (sample) {
+            if ((st = pool.make(&e0)) != MAS_OK || (st = pool.make(&e1)) != MAS_OK) return done(st);
+            if (hipEventRecord(e0, stream) != hipSuccess)
+                return done(fail(MAS_EHIP, "hipEventRecord failed"));
+        }
+        if (j == 2) {
+            // D_2 = (mu_2 mt_1 + mt_2 + gt_2) L_0 + mt_2 mt_1 dtL(L_0)
+            st = sts_launch(op, stream, L0, nullptr, nullptr, Y0, out,
+                            c.mu[2] * c.mt[1] + c.mt[2] + c.gt[2], 0.0, 0.0, c.mt[2] * c.mt[1]);
+        } else if (j == 3) {
+            // D_3 = mu_3 D_2 + mt_3 dtL(D_2) + (nu_3 mt_1 + mt_3 + gt_3) L_0
+            st = sts_launch(op, stream, W[0], nullptr, L0, Y0, out, c.mu[3], 0.0,
+                            c.nu[3] * c.mt[1] + c.mt[3] + c.gt[3], c.mt[3]);
+        } else {
+            st = sts_launch(op, stream, W[(j - 1) & 1], W[j & 1], L0, Y0, out, c.mu[j], c.nu[j],
+                            c.mt[j] + c.gt[j], c.mt[j]);
+        }
+        if (st != MAS_OK) return done(st);
+        if (sample) {
+            if (hipEventRecord(e1, stream) != hipSuccess)
+                return done(fail(MAS_EHIP, "hipEventRecord failed"));
+            samples.emplace_back(e0, e1);
+        }
+    }
+    if (timing) {
+        if (hipEventRecord(ev1, stream) != hipSuccess || hipEventSynchronize(ev1) != hipSuccess)
+            return done(fail(MAS_EHIP, "stage timing failed"));
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, ev0, ev1) != hipSuccess)
+            return done(fail(MAS_EHIP, "hipEventElapsedTime failed"));
+        double sum = 0.0;
+        for (auto &pr : samples) {
+            float t = 0.f;
+            if (hipEventElapsedTime(&t, pr.first, pr.second) != hipSuccess)
+                return done(fail(MAS_EHIP, "hipEventElapsedTime failed"));
+            sum += t;
+        }
+        if (info) {
+            info->step_us = 1e3 * ms;
+            info->stage_kernel_samples = (int32_t)samples.size();
+            info->stage_kernel_us = samples.empty() ? 0.0 : 1e3 * sum / samples.size();
+        }
+    }
+    return done(MAS_OK);
 }
 
 extern "C" int mas_probe_copy(const void *src, void *dst, int64_t bytes, void *hip_stream) {

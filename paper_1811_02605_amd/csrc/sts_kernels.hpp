@@ -1,0 +1,176 @@
+// RKL2 super time-stepping stage kernel: the explicit alternative to the
+// implicit viscous solve (the paper, Section 2.2, which cites the second-order
+// Runge-Kutta-Legendre scheme of Meyer, Balsara and Aslam, 2014; Section 4.1
+// counts it among the vectorizable stencil algorithms; Section 5.2 finds it
+// the faster choice on GPUs).
+//
+// One kernel per stage.  With dtL(u) = -(dt / V) * sum_f G_f nu_f (u_c - u_nb)
+// (interior faces nu_f = (nu_c + nu_nb)/2, Dirichlet walls nu_f = nu_c with
+// u_nb = 0), the kernel writes
+//
+//     out = a X + b Z + g L0 + Y0 + m dtL(X)
+//
+// for cell arrays X (read with its 6 neighbours), Z, L0, Y0 (cell only; any of
+// the three may be absent, read as zero).  The face conductances are formed
+// on the fly from nu and the separable 1-D geometry tables (the r factor of a
+// face times its theta factor), so a stage streams X, nu, Z and L0 and writes
+// out: 5 words per cell instead of the 9 an assembled-coefficient stencil
+// would stream.
+//
+// Work layout as in the PCG iteration kernel: each wave owns RPW theta rows
+// of one phi segment (64/RPW lanes per row, V cells per lane) and marches
+// through the r planes of its chunk, holding X and nu of the planes m-1, m,
+// m+1 in registers; theta neighbours inside the wave come from lane
+// shuffles, the wave's outer rows are loaded, phi neighbours come from lane
+// shuffles with the two segment-edge cells loaded.  Chunks alternate their
+// march direction so that the halo plane two chunks share is read at the same
+// time by both.
+#pragma once
+
+#include "kernels.hpp"
+
+namespace mas {
+
+struct StsArgs {
+    const double *X, *nu, *Z, *L0, *Y0;  // Z, L0, Y0 may be null
+    double *out;                          // may alias Z or Y0 (same cell read first)
+    double a, b, g, mdt;                  // mdt = m * dt
+    Geo geo;
+    Dims d;
+    int tiles_i, tiles_k, tiles_j, ti, nblk;
+};
+
+template <int WPB, int RPW, int V>
+__global__ __launch_bounds__(kWave *WPB) void k_sts_stage(StsArgs a) {
+    static_assert(kWave % RPW == 0, "rows per wave");
+    constexpr int W = kWave / RPW;  // lanes per row
+    constexpr int SEG = W * V;
+    using VD = VecT<double, V>;
+
+    const int nr = a.d.nr, nt = a.d.nt, np = a.d.np;
+    const int64_t plane = a.d.plane;
+
+    const int L = xcd_remap(blockIdx.x, a.nblk);
+    const int it = L % a.tiles_i;
+    const int kt = (L / a.tiles_i) % a.tiles_k;
+    const int jt = L / (a.tiles_i * a.tiles_k);
+
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wv = threadIdx.x / kWave;
+    const int rr = lane / W;
+    const int lp = lane % W;
+    const int j = (jt * WPB + wv) * RPW + rr;
+    const int k0 = kt * SEG;
+    const int nseg = min(SEG, np - k0);  // a multiple of V
+    const int nvl = nseg / V;
+    const bool rowok = j < nt;
+    const bool act = rowok && lp < nvl;
+    const int i0 = it * a.ti;
+    const int i1 = min(i0 + a.ti, nr);
+    const bool up = (it & 1) == 0;
+    const int dir = up ? 1 : -1;
+    const int first = up ? i0 : i1 - 1;
+
+    const int64_t col = act ? (int64_t)j * np + k0 + lp * V : 0;
+    const bool ldU = act && j > 0 && rr == 0;
+    const bool ldD = act && j < nt - 1 && rr == RPW - 1;
+    const int srcU = (rr > 0) ? lane - W : lane;
+    const int srcD = (rr < RPW - 1) ? lane + W : lane;
+    const bool eL = act && lp == 0;
+    const bool eR = act && lp == nvl - 1;
+    const int64_t colL = (int64_t)j * np + ((k0 == 0) ? np - 1 : k0 - 1);
+    const int64_t colR = (int64_t)j * np + ((k0 + nseg == np) ? 0 : k0 + nseg);
+
+    // per-row geometry: half the theta-face factors (the 1/2 of the face mean)
+    const int jj = rowok ? j : 0;
+    const double vt = a.geo.vt[jj];
+    const double hU = (rowok && j > 0) ? 0.5 * a.geo.gtt[j - 1] : 0.0;
+    const double hD = rowok ? 0.5 * a.geo.gtt[jj] : 0.0;  // zero on the last row
+    const double hP = (rowok && !a.geo.np_one) ? 0.5 * a.geo.gpt[jj] : 0.0;
+
+    constexpr uint32_t ES = sizeof(double);
+    const uint32_t nbytes = (uint32_t)(a.d.n * (int64_t)ES);
+    const auto RX = make_rsrc(a.X, nbytes), RN = make_rsrc(a.nu, nbytes),
+               RZ = make_rsrc(a.Z, a.Z ? nbytes : 0u), RL = make_rsrc(a.L0, a.L0 ? nbytes : 0u),
+               RY = make_rsrc(a.Y0, a.Y0 ? nbytes : 0u), RO = make_rsrc(a.out, nbytes);
+
+    auto own_off = [&](int m) -> uint32_t {
+        return (act && m >= 0 && m < nr) ? (uint32_t)((int64_t)m * plane + col) * ES : kOOB;
+    };
+    // planes m - dir (behind) and m (current) of the first step
+    VD Xb = bld<double, V>(RX, own_off(first - dir));
+    VD Nb = bld<double, V>(RN, own_off(first - dir));
+    VD Xc = bld<double, V>(RX, own_off(first));
+    VD Nc = bld<double, V>(RN, own_off(first));
+
+    VD st{};
+    uint32_t st_off = kOOB;
+    const int nsteps = i1 - i0;
+    for (int s = 0; s < nsteps; ++s) {
+        const int m = first + s * dir;
+        const int64_t base = (int64_t)m * plane;
+        const uint32_t oo = act ? (uint32_t)(base + col) * ES : kOOB;
+        const uint32_t oU = ldU ? (uint32_t)(base + col - np) * ES : kOOB;
+        const uint32_t oD = ldD ? (uint32_t)(base + col + np) * ES : kOOB;
+        const uint32_t oL = eL ? (uint32_t)(base + colL) * ES : kOOB;
+        const uint32_t oR = eR ? (uint32_t)(base + colR) * ES : kOOB;
+        // ---- loads: plane m + dir (ahead) and the rest of plane m
+        const VD Xa = bld<double, V>(RX, own_off(m + dir));
+        const VD Na = bld<double, V>(RN, own_off(m + dir));
+        const VD XU = bld<double, V>(RX, oU);
+        const VD NU = bld<double, V>(RN, oU);
+        const VD XD = bld<double, V>(RX, oD);
+        const VD ND = bld<double, V>(RN, oD);
+        const double XL = bld<double, 1>(RX, oL).v[0];
+        const double NL = bld<double, 1>(RN, oL).v[0];
+        const double XR = bld<double, 1>(RX, oR).v[0];
+        const double NR = bld<double, 1>(RN, oR).v[0];
+        const VD Zv = bld<double, V, kAuxNT>(RZ, oo);
+        const VD Lv = bld<double, V, kAuxNT>(RL, oo);
+        const VD Yv = bld<double, V, kAuxNT>(RY, oo);
+        // ---- store of the previous step (issued after this step's loads)
+        bst<double, V, kAuxNT>(RO, st_off, st);
+
+        // ---- plane factors
+        const double gq = a.geo.gq[m];
+        const double hRp = 0.5 * a.geo.gr[m] * vt;                    // face m | m+1 (0 at m = nr-1)
+        const double hRm = (m > 0) ? 0.5 * a.geo.gr[m - 1] * vt : 0.0;  // face m-1 | m
+        const double gw = ((m == 0) ? a.geo.gw_in : 0.0) * vt + ((m == nr - 1) ? a.geo.gw_out : 0.0) * vt;
+        const double scale = a.mdt / (a.geo.vr[m] * vt);
+        const double tU = gq * hU, tD = gq * hD, tP = gq * hP;
+        const VD &Xp = up ? Xa : Xb, &Xm = up ? Xb : Xa;  // planes m+1, m-1
+        const VD &Np = up ? Na : Nb, &Nm = up ? Nb : Na;
+
+        const double xl0 = shfl_up1(Xc.v[V - 1]), nl0 = shfl_up1(Nc.v[V - 1]);
+        const double xr0 = shfl_dn1(Xc.v[0]), nr0 = shfl_dn1(Nc.v[0]);
+        VD o;
+#pragma unroll
+        for (int e = 0; e < V; ++e) {
+            const double xc = Xc.v[e], nc = Nc.v[e];
+            const double sxu = shfl_lane(xc, srcU), snu = shfl_lane(nc, srcU);
+            const double sxd = shfl_lane(xc, srcD), snd = shfl_lane(nc, srcD);
+            const double xu = (rr == 0) ? XU.v[e] : sxu, nu_u = (rr == 0) ? NU.v[e] : snu;
+            const double xd = (rr == RPW - 1) ? XD.v[e] : sxd, nu_d = (rr == RPW - 1) ? ND.v[e] : snd;
+            const double xl = (e > 0) ? Xc.v[e - 1] : ((lp == 0) ? XL : xl0);
+            const double nl = (e > 0) ? Nc.v[e - 1] : ((lp == 0) ? NL : nl0);
+            const double xr = (e < V - 1) ? Xc.v[e + 1] : ((lp == nvl - 1) ? XR : xr0);
+            const double nrr = (e < V - 1) ? Nc.v[e + 1] : ((lp == nvl - 1) ? NR : nr0);
+            double f = hRp * (nc + Np.v[e]) * (xc - Xp.v[e]);
+            f += hRm * (nc + Nm.v[e]) * (xc - Xm.v[e]);
+            f += gw * nc * xc;
+            f += tU * (nc + nu_u) * (xc - xu);
+            f += tD * (nc + nu_d) * (xc - xd);
+            f += tP * ((nc + nl) * (xc - xl) + (nc + nrr) * (xc - xr));
+            o.v[e] = ((a.a * xc + a.b * Zv.v[e]) + a.g * Lv.v[e] + Yv.v[e]) - scale * f;
+        }
+        st = o;
+        st_off = oo;
+        Xb = Xc;
+        Nb = Nc;
+        Xc = Xa;
+        Nc = Na;
+    }
+    bst<double, V, kAuxNT>(RO, st_off, st);
+}
+
+}  // namespace mas

@@ -8,6 +8,7 @@ Nothing here computes on tensors.
     op = Operator(grid, nu, dt, precision="fp64")        # mas_op_build
     x, info = op.solve(rhs)                              # mas_pcg_solve
     lam, g_nu, g_rhs, info = op.adjoint(x, gx)           # mas_pcg_solve_adjoint
+    u1, info = op.sts_step(u0)                           # mas_sts_step (explicit RKL2)
     x = solve(nu, rhs, grid, dt)                          # differentiable (MasSolve)
 """
 from __future__ import annotations
@@ -189,6 +190,37 @@ class Operator:
                 _stream(self.device), ctypes.byref(info))
         abi.check(st, "mas_pcg_solve_adjoint", allow_notconv=allow_notconv)
         return lam, gnu, grhs, info.as_dict()
+
+    def sts_stages(self) -> int:
+        """Automatic RKL2 stage count for this operator's dt."""
+        s = int(abi.load().mas_sts_stages(self._h))
+        abi.check(s if s < 0 else 0, "mas_sts_stages")
+        return s
+
+    def sts_step(self, u0: torch.Tensor, stages: int = 0, out: torch.Tensor | None = None,
+                 sample_timing: bool = False):
+        """One RKL2 super time-step of du/dt = L u over dt.  Returns (u1, info).
+        out may be u0 itself (in-place step)."""
+        _check_vec(u0, self.grid.shape, "u0")
+        u1 = out if out is not None else torch.empty_like(u0)
+        _check_vec(u1, self.grid.shape, "out")
+        lib = abi.load()
+        nbytes = int(lib.mas_sts_workspace_bytes(self._h))
+        abi.check(nbytes if nbytes < 0 else 0, "mas_sts_workspace_bytes")
+        buf = self._work.get("sts")
+        if buf is None or buf.numel() < nbytes:
+            buf = _device_bytes(nbytes, self.device)
+            self._work["sts"] = buf
+        o = abi.mas_sts_opts()
+        lib.mas_sts_default_opts(ctypes.byref(o))
+        o.stages = int(stages)
+        o.sample_timing = int(bool(sample_timing))
+        info = abi.mas_sts_info()
+        with torch.cuda.device(self.device):
+            st = lib.mas_sts_step(self._h, u0.data_ptr(), u1.data_ptr(), ctypes.byref(o),
+                                  buf.data_ptr(), nbytes, _stream(self.device), ctypes.byref(info))
+        abi.check(st, "mas_sts_step")
+        return u1, info.as_dict()
 
 
 def probe_copy(src: torch.Tensor, dst: torch.Tensor):

@@ -47,7 +47,8 @@ def test_storage_bytes_scale_with_grid_and_precision():
     n = 32 * 32 * 64
     b64 = lib.mas_op_storage_bytes(ctypes.byref(g), abi.MAS_FP64)
     b32 = lib.mas_op_storage_bytes(ctypes.byref(g), abi.MAS_FP32_REFINED)
-    assert 32 * n <= b64 < 32 * n + 64 * 1024
+    # w, three couplings and the copy of nu
+    assert 40 * n <= b64 < 40 * n + 64 * 1024
     assert b32 - b64 >= 12 * n
 
 
@@ -104,6 +105,19 @@ def test_null_operator_and_bad_copy_are_rejected():
     assert lib.mas_probe_copy(8, 32, 16, None) == abi.MAS_EINVAL
     assert lib.mas_probe_copy(None, 32, 16, None) == abi.MAS_EINVAL
     assert lib.mas_op_destroy(None) is None
+
+
+def test_sts_defaults_and_null_operator():
+    lib = abi.load()
+    o = abi.mas_sts_opts(7, 7)
+    lib.mas_sts_default_opts(ctypes.byref(o))
+    assert o.stages == 0 and o.sample_timing == 0
+    info = abi.mas_sts_info()
+    assert lib.mas_sts_stages(None) == abi.MAS_EINVAL
+    assert lib.mas_sts_workspace_bytes(None) == abi.MAS_EINVAL
+    assert lib.mas_sts_step(None, 8, 8, ctypes.byref(o), 256, 1 << 20, None,
+                            ctypes.byref(info)) == abi.MAS_EINVAL
+    assert info.status == abi.MAS_EINVAL
 
 
 def test_status_strings():

@@ -76,6 +76,24 @@ def test_c1_fp64_and_refined_solves_full(c1, c1_oracle):
     assert max(e64, emp, er) <= 1e-6
 
 
+def test_c1_sts_step_full(c1, c1_oracle):
+    """One RKL2 step at the full size, in the launch configuration the
+    benchmark times, against the oracle's step on every cell."""
+    _, op = gpu_operator(c1)
+    u0 = c1.rhs
+    u1, info = op.sts_step(to_dev(u0), sample_timing=True)
+    s = info["stages"]
+    assert s == c1_oracle.rkl2_stages()
+    say(f"c1 RKL2: {s} stages, z_max {info['z_max']:.4g}, step {info['step_us'] / 1e3:.2f} ms, "
+        f"stage kernel {info['stage_kernel_us']:.1f} us")
+    got = to_host(u1)
+    del op, u1
+    want = c1_oracle.rkl2_step(u0, stages=s)
+    err = float(np.abs(got - want).max() / np.abs(u0).max())
+    say(f"c1 RKL2 max error vs oracle: {err:.2e} (of max|u0|)")
+    assert err <= 1e-12
+
+
 @pytest.fixture(scope="module")
 def c3():
     p = W.make_problem("c3")

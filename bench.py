@@ -11,14 +11,15 @@ One step = build the operator from (nu, dt) + one full FP64 PCG solve to the
 tolerance.  `value` is PCG iterations per second of wall time over the K
 timed steps.  Alongside, the same grid and data are solved with the
 single-precision inner PCG inside double-precision refinement and both
-times-to-1e-10 are reported.
+times-to-1e-10 are reported, and one explicit RKL2 super time-step of the
+same dt (the paper's faster GPU choice for the viscous term) is timed.
 
 The dominant kernel is the fused PCG iteration kernel; its duration is
 sampled with HIP events on the solver's stream (inside the library) and
 converted to algorithmic HBM bytes per second.
 
     python bench.py [--steps K] [--warmup W] [--gpus 1] [--workload c1]
-                    [--no-cpu-baseline] [--no-refined]
+                    [--no-cpu-baseline] [--no-refined] [--no-sts]
 """
 from __future__ import annotations
 
@@ -41,23 +42,31 @@ ALG_BYTES_PER_CELL = {"fp64": 14 * 8, "fp32": 14 * 4}
 # What this library's single-kernel iteration has to move per cell (reads r,
 # q, p, x, c_r, c_theta, c_phi; writes r, p, x, q): 11 words.
 KERNEL_BYTES_PER_CELL = {"fp64": 11 * 8, "fp32": 11 * 4}
-KERNEL_SRC = os.path.join(ROOT, "paper_1811_02605_amd", "csrc", "kernels.hpp")
+# One RKL2 stage kernel per cell: reads D_{j-1}, nu, D_{j-2}, L_0, writes D_j.
+STS_BYTES_PER_CELL = 5 * 8
+CSRC = os.path.join(ROOT, "paper_1811_02605_amd", "csrc")
+KERNEL_SRC = os.path.join(CSRC, "kernels.hpp")
+STS_KERNEL_SRC = os.path.join(CSRC, "sts_kernels.hpp")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "pcg_iter_fp64_c1_traffic.txt")
+STS_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "sts_stage_c1_traffic.txt")
 
 
-def kernel_hash() -> str:
-    return hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
+def kernel_hash(*paths) -> str:
+    h = hashlib.sha256()
+    for path in paths or (KERNEL_SRC,):
+        h.update(open(path, "rb").read())
+    return h.hexdigest()[:16]
 
 
-def read_traffic():
-    """HBM bytes per launch of the iteration kernel from the committed PMC
-    summary, if it was taken on the current kernel source; else None."""
-    if not os.path.exists(TRAFFIC_FILE):
+def read_traffic(path=TRAFFIC_FILE, srcs=(KERNEL_SRC,)):
+    """HBM bytes per launch of a kernel from its committed PMC summary, if the
+    summary was taken on the current kernel source; else None."""
+    if not os.path.exists(path):
         return None
-    txt = open(TRAFFIC_FILE).read()
+    txt = open(path).read()
     m_hash = re.search(r"kernel_source_sha256_16:\s*([0-9a-f]+)", txt)
     m_bytes = re.search(r"hbm_bytes_per_launch:\s*([0-9.eE+]+)", txt)
-    if not m_hash or not m_bytes or m_hash.group(1) != kernel_hash():
+    if not m_hash or not m_bytes or m_hash.group(1) != kernel_hash(*srcs):
         return None
     return float(m_bytes.group(1))
 
@@ -82,6 +91,43 @@ def cpu_baseline(p, max_iters=400):
             "time_to_tol_s": t2 - t1}
 
 
+def bench_sts(S, grid, nu, rhs, p, t_pcg, steps):
+    """The explicit alternative for the same viscous step: one RKL2 super
+    time-step of the same dt on the same grid and viscosity (u0 = the smooth
+    right-hand-side field), timed with events on the library's stream."""
+    import numpy as np
+    import torch
+
+    op = S.Operator(grid, nu, p.dt, precision="fp64")
+    u = rhs.clone()
+    _, info = op.sts_step(u, sample_timing=True)  # warm-up, stage-kernel sample
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        op.sts_step(u, out=u)
+    e1.record()
+    torch.cuda.synchronize()
+    step_s = e0.elapsed_time(e1) * 1e-3 / steps
+    k_us = info["stage_kernel_us"] if info["stage_kernel_samples"] > 0 else None
+    gbs = STS_BYTES_PER_CELL * grid.n / (k_us * 1e-6) / 1e9 if k_us else None
+    print(f"[bench] RKL2: {info['stages']} stages, {1e3 * step_s:.2f} ms per step, stage kernel "
+          f"{k_us} us", file=sys.stderr, flush=True)
+    return {
+        "what": "one RKL2 super time-step of the same dt, nu and grid (explicit alternative to "
+                "the implicit solve)",
+        "stages": info["stages"], "z_max": info["z_max"],
+        "step_ms": 1e3 * step_s,
+        "speedup_vs_fp64_pcg_solve": t_pcg / step_s,
+        "roofline": {"bound": "hbm", "kernel": "k_sts_stage (one RKL2 stage)",
+                     "alg_bytes_per_cell": STS_BYTES_PER_CELL, "kernel_us": k_us,
+                     "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": (gbs / HBM_PEAK_GBS) if gbs else None,
+                     "samples": info["stage_kernel_samples"],
+                     "traffic": read_traffic(STS_TRAFFIC_FILE, (STS_KERNEL_SRC, KERNEL_SRC))},
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -90,6 +136,7 @@ def main():
     ap.add_argument("--workload", default="c1")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-refined", action="store_true")
+    ap.add_argument("--no-sts", action="store_true")
     ap.add_argument("--check-every", type=int, default=8)
     args = ap.parse_args()
     if args.gpus != 1:
@@ -207,6 +254,9 @@ def main():
         }
         print(f"[bench] refined: {t_ref:.3f} s vs fp64 {np.median(solve_s):.3f} s",
               file=sys.stderr, flush=True)
+
+    if not args.no_sts:
+        out["sts"] = bench_sts(S, grid, nu, rhs, p, float(np.median(solve_s)), args.steps)
 
     # practical HBM ceiling: a plain streaming copy of 2 GiB (read + write)
     src = torch.empty(1 << 28, dtype=torch.float64, device=dev).fill_(1.0)

@@ -138,6 +138,28 @@ __device__ inline int xcd_remap(int b, int nblk) {
     return x * q + (x < rem ? x : rem) + s;
 }
 
+// Tile coordinates (r chunk it, phi segment kt, theta tile jt) of logical
+// block L.  Consecutive L run on one XCD at the same time (xcd_remap), so the
+// fastest index decides which neighbour tiles share that XCD's L2 while they
+// run: order 0 puts r chunks fastest, 1 theta tiles then r chunks, 2 theta
+// tiles then phi segments.
+template <int ORDER>
+__device__ inline void tile_coords(int L, int ti, int tk, int tj, int &it, int &kt, int &jt) {
+    if constexpr (ORDER == 1) {
+        jt = L % tj;
+        it = (L / tj) % ti;
+        kt = L / (tj * ti);
+    } else if constexpr (ORDER == 2) {
+        jt = L % tj;
+        kt = (L / tj) % tk;
+        it = L / (tj * tk);
+    } else {
+        it = L % ti;
+        kt = (L / ti) % tk;
+        jt = L / (ti * tk);
+    }
+}
+
 // Vector of V consecutive phi cells (16-byte accesses for V = 16/sizeof(T)).
 template <typename T, int V>
 struct VecT {
@@ -241,6 +263,9 @@ __device__ inline void bst(__amdgpu_buffer_rsrc_t r, uint32_t off, const VecT<T,
     }
 }
 
+#ifndef MAS_ITER_ORDER
+#define MAS_ITER_ORDER 2
+#endif
 #ifndef MAS_ITER_SYNC
 #define MAS_ITER_SYNC 0
 #endif
@@ -313,9 +338,8 @@ void k_pcg_iter(IterArgs<T> a) {
     const int64_t plane = a.d.plane;
 
     const int L = xcd_remap(blockIdx.x, a.nblk);
-    const int it = L % a.tiles_i;  // r chunks fastest
-    const int kt = (L / a.tiles_i) % a.tiles_k;
-    const int jt = L / (a.tiles_i * a.tiles_k);
+    int it, kt, jt;
+    tile_coords<MAS_ITER_ORDER>(L, a.tiles_i, a.tiles_k, a.tiles_j, it, kt, jt);
 
     const int lane = threadIdx.x & (kWave - 1);
     const int wv = threadIdx.x / kWave;

@@ -31,6 +31,22 @@
 
 namespace mas {
 
+// Cache hints (buffer aux field) per stream: X and nu are re-read as
+// neighbours, Z, L0, Y0 and out are touched once per stage.
+#ifndef MAS_STS_AUX_XN
+#define MAS_STS_AUX_XN 0
+#endif
+#ifndef MAS_STS_AUX_ZL
+#define MAS_STS_AUX_ZL kAuxNT
+#endif
+#ifndef MAS_STS_AUX_ST
+#define MAS_STS_AUX_ST kAuxNT
+#endif
+
+#ifndef MAS_STS_ORDER
+#define MAS_STS_ORDER 0
+#endif
+
 struct StsArgs {
     const double *X, *nu, *Z, *L0, *Y0;  // Z, L0, Y0 may be null
     double *out;                          // may alias Z or Y0 (same cell read first)
@@ -51,9 +67,8 @@ __global__ __launch_bounds__(kWave *WPB) void k_sts_stage(StsArgs a) {
     const int64_t plane = a.d.plane;
 
     const int L = xcd_remap(blockIdx.x, a.nblk);
-    const int it = L % a.tiles_i;
-    const int kt = (L / a.tiles_i) % a.tiles_k;
-    const int jt = L / (a.tiles_i * a.tiles_k);
+    int it, kt, jt;
+    tile_coords<MAS_STS_ORDER>(L, a.tiles_i, a.tiles_k, a.tiles_j, it, kt, jt);
 
     const int lane = threadIdx.x & (kWave - 1);
     const int wv = threadIdx.x / kWave;
@@ -98,10 +113,10 @@ __global__ __launch_bounds__(kWave *WPB) void k_sts_stage(StsArgs a) {
         return (act && m >= 0 && m < nr) ? (uint32_t)((int64_t)m * plane + col) * ES : kOOB;
     };
     // planes m - dir (behind) and m (current) of the first step
-    VD Xb = bld<double, V>(RX, own_off(first - dir));
-    VD Nb = bld<double, V>(RN, own_off(first - dir));
-    VD Xc = bld<double, V>(RX, own_off(first));
-    VD Nc = bld<double, V>(RN, own_off(first));
+    VD Xb = bld<double, V, MAS_STS_AUX_XN>(RX, own_off(first - dir));
+    VD Nb = bld<double, V, MAS_STS_AUX_XN>(RN, own_off(first - dir));
+    VD Xc = bld<double, V, MAS_STS_AUX_XN>(RX, own_off(first));
+    VD Nc = bld<double, V, MAS_STS_AUX_XN>(RN, own_off(first));
 
     VD st{};
     uint32_t st_off = kOOB;
@@ -115,21 +130,21 @@ __global__ __launch_bounds__(kWave *WPB) void k_sts_stage(StsArgs a) {
         const uint32_t oL = eL ? (uint32_t)(base + colL) * ES : kOOB;
         const uint32_t oR = eR ? (uint32_t)(base + colR) * ES : kOOB;
         // ---- loads: plane m + dir (ahead) and the rest of plane m
-        const VD Xa = bld<double, V>(RX, own_off(m + dir));
-        const VD Na = bld<double, V>(RN, own_off(m + dir));
-        const VD XU = bld<double, V>(RX, oU);
-        const VD NU = bld<double, V>(RN, oU);
-        const VD XD = bld<double, V>(RX, oD);
-        const VD ND = bld<double, V>(RN, oD);
+        const VD Xa = bld<double, V, MAS_STS_AUX_XN>(RX, own_off(m + dir));
+        const VD Na = bld<double, V, MAS_STS_AUX_XN>(RN, own_off(m + dir));
+        const VD XU = bld<double, V, MAS_STS_AUX_XN>(RX, oU);
+        const VD NU = bld<double, V, MAS_STS_AUX_XN>(RN, oU);
+        const VD XD = bld<double, V, MAS_STS_AUX_XN>(RX, oD);
+        const VD ND = bld<double, V, MAS_STS_AUX_XN>(RN, oD);
         const double XL = bld<double, 1>(RX, oL).v[0];
         const double NL = bld<double, 1>(RN, oL).v[0];
         const double XR = bld<double, 1>(RX, oR).v[0];
         const double NR = bld<double, 1>(RN, oR).v[0];
-        const VD Zv = bld<double, V, kAuxNT>(RZ, oo);
-        const VD Lv = bld<double, V, kAuxNT>(RL, oo);
-        const VD Yv = bld<double, V, kAuxNT>(RY, oo);
+        const VD Zv = bld<double, V, MAS_STS_AUX_ZL>(RZ, oo);
+        const VD Lv = bld<double, V, MAS_STS_AUX_ZL>(RL, oo);
+        const VD Yv = bld<double, V, MAS_STS_AUX_ZL>(RY, oo);
         // ---- store of the previous step (issued after this step's loads)
-        bst<double, V, kAuxNT>(RO, st_off, st);
+        bst<double, V, MAS_STS_AUX_ST>(RO, st_off, st);
 
         // ---- plane factors
         const double gq = a.geo.gq[m];
@@ -170,7 +185,7 @@ __global__ __launch_bounds__(kWave *WPB) void k_sts_stage(StsArgs a) {
         Xc = Xa;
         Nc = Na;
     }
-    bst<double, V, kAuxNT>(RO, st_off, st);
+    bst<double, V, MAS_STS_AUX_ST>(RO, st_off, st);
 }
 
 }  // namespace mas

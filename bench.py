@@ -11,15 +11,16 @@ One step = build the operator from (nu, dt) + one full FP64 PCG solve to the
 tolerance.  `value` is PCG iterations per second of wall time over the K
 timed steps.  Alongside, the same grid and data are solved with the
 single-precision inner PCG inside double-precision refinement and both
-times-to-1e-10 are reported, and one explicit RKL2 super time-step of the
-same dt (the paper's faster GPU choice for the viscous term) is timed.
+times-to-1e-10 are reported; three components under the same operator are
+solved together; and one explicit RKL2 super time-step of the same dt (the
+paper's faster GPU choice for the viscous term) is timed.
 
 The dominant kernel is the fused PCG iteration kernel; its duration is
 sampled with HIP events on the solver's stream (inside the library) and
 converted to algorithmic HBM bytes per second.
 
     python bench.py [--steps K] [--warmup W] [--gpus 1] [--workload c1]
-                    [--no-cpu-baseline] [--no-refined] [--no-sts]
+                    [--no-cpu-baseline] [--no-refined] [--no-sts] [--no-multi]
 """
 from __future__ import annotations
 
@@ -91,6 +92,42 @@ def cpu_baseline(p, max_iters=400):
             "time_to_tol_s": t2 - t1}
 
 
+# One iteration kernel with m right-hand sides: the couplings (3 words) once,
+# 8 words per right-hand side.
+def multi_bytes_per_cell(m, word=8):
+    return (3 + 8 * m) * word
+
+
+def bench_multi(S, W, grid, nu, p, t_pcg, k_single_us, m=3):
+    """The three components of a vector field under the same operator, solved
+    together (one iteration kernel carries all three) to the same tolerance."""
+    import numpy as np
+    import torch
+
+    op = S.Operator(grid, nu, p.dt, precision="fp64")
+    B = torch.from_numpy(W.component_rhs(p.cfg, m)).to(nu.device)
+    X = torch.empty_like(B)
+    o = S.make_opts(rtol=p.cfg.rtol, sample_timing=1)
+    op.solve_multi(B, o, out=X, allow_notconv=False)  # warm-up
+    runs = [op.solve_multi(B, o, out=X, allow_notconv=False)[1] for _ in range(2)]
+    t = float(np.median([r[0]["seconds"] for r in runs]))
+    k_us = runs[-1][0]["iter_kernel_us"] or None
+    gbs = multi_bytes_per_cell(m) * grid.n / (k_us * 1e-6) / 1e9 if k_us else None
+    print(f"[bench] {m} components: {t:.3f} s, kernel {k_us} us", file=sys.stderr, flush=True)
+    return {
+        "what": f"{m} right-hand sides (components) under the same operator, one FP64 solve to "
+                "1e-10 each, one iteration kernel carrying all of them",
+        "rhs": m, "iters": [r["iters"] for r in runs[-1]],
+        "time_to_tol_s": t, "time_per_rhs_s": t / m,
+        "speedup_vs_separate_solves": m * t_pcg / t,
+        "kernel_us": k_us, "kernel_us_per_rhs": (k_us / m) if k_us else None,
+        "kernel_speedup_per_rhs_vs_single": (m * k_single_us / k_us) if k_us else None,
+        "bytes_per_cell": multi_bytes_per_cell(m),
+        "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+        "frac": (gbs / HBM_PEAK_GBS) if gbs else None,
+    }
+
+
 def bench_sts(S, grid, nu, rhs, p, t_pcg, steps):
     """The explicit alternative for the same viscous step: one RKL2 super
     time-step of the same dt on the same grid and viscosity (u0 = the smooth
@@ -137,6 +174,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-refined", action="store_true")
     ap.add_argument("--no-sts", action="store_true")
+    ap.add_argument("--no-multi", action="store_true")
     ap.add_argument("--check-every", type=int, default=8)
     args = ap.parse_args()
     if args.gpus != 1:
@@ -254,6 +292,10 @@ def main():
         }
         print(f"[bench] refined: {t_ref:.3f} s vs fp64 {np.median(solve_s):.3f} s",
               file=sys.stderr, flush=True)
+
+    if not args.no_multi:
+        out["multi"] = bench_multi(S, W, grid, nu, p, float(np.median(solve_s)), kernel_us)
+        torch.cuda.empty_cache()
 
     if not args.no_sts:
         out["sts"] = bench_sts(S, grid, nu, rhs, p, float(np.median(solve_s)), args.steps)

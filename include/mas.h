@@ -248,6 +248,39 @@ int64_t mas_sts_workspace_bytes(const mas_op *op);
 int mas_sts_step(const mas_op *op, const double *u0, double *u1, const mas_sts_opts *o,
                  void *work, int64_t work_bytes, void *hip_stream, mas_sts_info *info);
 
+/* ---------------------------------------------------------------- several right-hand sides
+ * The paper's viscous operator acts on the three components of v (Eq. (1)),
+ * and its semi-implicit solve has the same form (Section 2.2).  With the
+ * components treated as scalar fields under one operator (the couplings the
+ * vector Laplacian adds on curvilinear grids left out), the component solves
+ * share A: one iteration kernel reads the operator's couplings once per cell
+ * for all of them.  Each right-hand side keeps its own CG scalars, stopping
+ * test and restarts, so the result equals nrhs separate FP64 solves up to
+ * rounding (the iterations are the same; the dot products are summed in a
+ * different blocking). */
+
+/* Bytes of device workspace mas_pcg_solve_multi needs for nrhs right-hand
+ * sides (1 <= nrhs <= 4).  Negative status on error. */
+int64_t mas_pcg_multi_workspace_bytes(const mas_op *op, int32_t nrhs);
+
+/* Solve A x_h = V .* rhs_h, h = 0..nrhs-1, by Jacobi PCG in double precision.
+ *   nrhs  1..4
+ *   rhs   dev, nrhs*N, right-hand side h at rhs + h*N
+ *   x     dev, nrhs*N, same layout: initial guesses on entry if o->use_x0,
+ *         solutions on exit
+ *   o     host, may be NULL; o->precision must be MAS_FP64; rtol, max_iters,
+ *         check_every, max_restarts and sample_timing apply to every
+ *         right-hand side
+ *   work  dev, >= mas_pcg_multi_workspace_bytes(op, nrhs), 256-byte aligned
+ *   info  host array of nrhs entries, may be NULL; entry h describes
+ *         right-hand side h (iter_kernel_us is the shared kernel's time)
+ * Returns MAS_OK when every right-hand side converged, else MAS_EBREAKDOWN or
+ * MAS_ENOTCONV if any did not (see info[h].status), or MAS_EINVAL, MAS_ENOMEM,
+ * MAS_EHIP.  Blocks until the solves have finished. */
+int mas_pcg_solve_multi(const mas_op *op, int32_t nrhs, const double *rhs, double *x,
+                        const mas_pcg_opts *o, void *work, int64_t work_bytes, void *hip_stream,
+                        mas_pcg_info *info);
+
 /* Bandwidth probe: dst[0:bytes) = src[0:bytes), both dev, 16-byte aligned,
  * bytes a multiple of 16.  A plain streaming copy used to calibrate the HBM
  * byte counters.  Enqueues only. */

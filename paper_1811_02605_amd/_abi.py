@@ -88,6 +88,10 @@ _SIGS = {
     "mas_pcg_solve_adjoint": (ctypes.c_int, [_VP, _VP, _VP, _VP, _VP, _VP,
                                              ctypes.POINTER(mas_pcg_opts), _VP, ctypes.c_int64,
                                              _VP, ctypes.POINTER(mas_pcg_info)]),
+    "mas_pcg_multi_workspace_bytes": (ctypes.c_int64, [_VP, ctypes.c_int32]),
+    "mas_pcg_solve_multi": (ctypes.c_int, [_VP, ctypes.c_int32, _VP, _VP,
+                                           ctypes.POINTER(mas_pcg_opts), _VP, ctypes.c_int64, _VP,
+                                           ctypes.POINTER(mas_pcg_info)]),
     "mas_sts_default_opts": (None, [ctypes.POINTER(mas_sts_opts)]),
     "mas_sts_stages": (ctypes.c_int32, [_VP]),
     "mas_sts_workspace_bytes": (ctypes.c_int64, [_VP]),

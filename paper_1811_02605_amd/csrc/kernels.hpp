@@ -115,15 +115,20 @@ __device__ inline void block_sum_store(double (&v)[NV], double *out, double *lds
 }
 
 // ---------------------------------------------------------------- iteration kernel
+// Right-hand sides one iteration kernel can carry (they share the operator).
+constexpr int kMaxRhs = 4;
+
 template <typename T>
 struct IterArgs {
-    const T *r_in, *p_in, *q_in;
-    T *r_out, *p_out, *q_out;
-    T *x;
+    // per right-hand side
+    const T *r_in[kMaxRhs], *p_in[kMaxRhs], *q_in[kMaxRhs];
+    T *r_out[kMaxRhs], *p_out[kMaxRhs], *q_out[kMaxRhs];
+    T *x[kMaxRhs];
+    // shared
     const T *cr, *ct, *cp;
     const double *w;
-    double *partials;  // [nblk][kNV]
-    const Ctl *ctl;
+    double *partials;  // [nblk][NR][kNV]
+    const Ctl *ctl;    // [NR]
     Dims d;
     int tiles_i, tiles_k, tiles_j, ti;  // r chunks, phi segments, theta tiles; r planes per chunk
     int nblk;
@@ -314,25 +319,39 @@ __device__ inline float shfl_lane(float v, int src) { return __shfl(v, src, kWav
 //   - phi neighbours come from lane shuffles, the two segment-edge cells of
 //     every row from two extra lanes' loads.
 // Chunks march up (even chunk index) or down (odd), so the halo plane a chunk
-// reads is the plane its neighbour chunk reads at the same time; the
-// block's waves stay on the same plane (a barrier per plane step).
+// reads is the plane its neighbour chunk reads at the same time.
 // Per plane step m, the in-plane part of q_k(m) plus the term of the r
 // neighbour already visited is summed into S(m); q_k(m) is completed one
 // step later, when p_k of the next plane is known.
-template <typename T, int WPB, int RPW, int V, bool CHECK>
+// NR right-hand sides share one pass: the couplings (and w) are loaded once
+// per cell, each right-hand side keeps its own vectors, scalars and partial
+// sums.  A right-hand side whose run has stopped gets zero-length buffer
+// resources: its loads return zeros and its stores are dropped, so it moves
+// no bytes.
+template <typename T, int NR, int WPB, int RPW, int V, bool CHECK>
 __global__ __launch_bounds__(kWave *WPB)
 #if MAS_ITER_WPE > 0
 __attribute__((amdgpu_waves_per_eu(MAS_ITER_WPE, 8)))
 #endif
 void k_pcg_iter(IterArgs<T> a) {
     static_assert(kWave % RPW == 0, "rows per wave");
+    static_assert(NR >= 1 && NR <= kMaxRhs, "right-hand sides");
     constexpr int W = kWave / RPW;  // lanes per row
     constexpr int SEG = W * V;
     using VT = VecT<T, V>;
 
-    const Ctl *ctl = a.ctl;
-    if (ctl->flag != FLAG_RUN) return;
-    const T alpha = (T)ctl->alpha, beta = (T)ctl->beta;
+    bool run[NR];
+    T alpha[NR], beta[NR];
+    bool any = false;
+#pragma unroll
+    for (int c = 0; c < NR; ++c) {
+        const Ctl *ctl = a.ctl + c;
+        run[c] = ctl->flag == FLAG_RUN;
+        any = any || run[c];
+        alpha[c] = (T)ctl->alpha;
+        beta[c] = (T)ctl->beta;
+    }
+    if (!any) return;
 
     const int nr = a.d.nr, nt = a.d.nt, np = a.d.np;
     const int64_t plane = a.d.plane;
@@ -371,15 +390,19 @@ void k_pcg_iter(IterArgs<T> a) {
     const int64_t colL = eL ? (int64_t)j * np + ((k0 == 0) ? np - 1 : k0 - 1) : 0;
     const int64_t colR = eR ? (int64_t)j * np + ((k0 + nseg == np) ? 0 : k0 + nseg) : 0;
 
-    double acc[kNV] = {0.0, 0.0, 0.0, 0.0, 0.0};
-    VT pn1{}, rn1{}, S1{}, cr1{};
+    double acc[NR * kNV];
+#pragma unroll
+    for (int t = 0; t < NR * kNV; ++t) acc[t] = 0.0;
+    VT pn1[NR], rn1[NR], S1[NR], cr1{};
+#pragma unroll
+    for (int c = 0; c < NR; ++c) pn1[c] = rn1[c] = S1[c] = VT{};
     VecT<double, V> w1{};
     int64_t base1 = 0;
 #if MAS_ITER_DEFER
     // results of the previous step, stored only after this step's loads are
     // issued: the in-order vector-memory counter then never makes a load
     // wait for a store to complete
-    VT st_r{}, st_p{}, st_x{}, st_q{};
+    VT st_r[NR], st_p[NR], st_x[NR], st_q[NR];
     bool st_own = false, st_q_do = false;
     uint32_t st_off = kOOB, st_qoff = kOOB;
 #endif
@@ -391,11 +414,20 @@ void k_pcg_iter(IterArgs<T> a) {
     // store to complete.
     constexpr int AN = MAS_ITER_NT ? kAuxNT : 0;
     const uint32_t nbytes = (uint32_t)(a.d.n * (int64_t)sizeof(T));
-    const auto Rr = make_rsrc(a.r_in, nbytes), Rq = make_rsrc(a.q_in, nbytes),
-               Rp = make_rsrc(a.p_in, nbytes), Rcr = make_rsrc(a.cr, nbytes),
-               Rct = make_rsrc(a.ct, nbytes), Rcp = make_rsrc(a.cp, nbytes),
-               Rx = make_rsrc(a.x, nbytes), Rro = make_rsrc(a.r_out, nbytes),
-               Rpo = make_rsrc(a.p_out, nbytes), Rqo = make_rsrc(a.q_out, nbytes),
+    __amdgpu_buffer_rsrc_t Rr[NR], Rq[NR], Rp[NR], Rx[NR], Rro[NR], Rpo[NR], Rqo[NR];
+#pragma unroll
+    for (int c = 0; c < NR; ++c) {
+        const uint32_t nb = run[c] ? nbytes : 0u;
+        Rr[c] = make_rsrc(a.r_in[c], nb);
+        Rq[c] = make_rsrc(a.q_in[c], nb);
+        Rp[c] = make_rsrc(a.p_in[c], nb);
+        Rx[c] = make_rsrc(a.x[c], nb);
+        Rro[c] = make_rsrc(a.r_out[c], nb);
+        Rpo[c] = make_rsrc(a.p_out[c], nb);
+        Rqo[c] = make_rsrc(a.q_out[c], nb);
+    }
+    const auto Rcr = make_rsrc(a.cr, nbytes), Rct = make_rsrc(a.ct, nbytes),
+               Rcp = make_rsrc(a.cp, nbytes),
                Rw = make_rsrc(a.w, (uint32_t)(a.d.n * (int64_t)sizeof(double)));
     constexpr uint32_t ES = sizeof(T);
     const int nsteps = i1 - i0 + 2;
@@ -414,44 +446,56 @@ void k_pcg_iter(IterArgs<T> a) {
         const uint32_t oL = vL ? (uint32_t)(base + colL) * ES : kOOB;
         const uint32_t oR = vR ? (uint32_t)(base + colR) * ES : kOOB;
         // ---- loads of plane m, all issued before any use
-        const VT r = bld<T, V>(Rr, oc);
-        const VT q = bld<T, V>(Rq, oc);
-        const VT p = bld<T, V>(Rp, oc);
+        VT r[NR], q[NR], p[NR], x[NR], rU[NR], qU[NR], pU[NR], rD[NR], qD[NR], pD[NR];
+        T lr[NR], lq[NR], lp_[NR], rr_[NR], rq_[NR], rp_[NR];
+#pragma unroll
+        for (int c = 0; c < NR; ++c) {
+            r[c] = bld<T, V>(Rr[c], oc);
+            q[c] = bld<T, V>(Rq[c], oc);
+            p[c] = bld<T, V>(Rp[c], oc);
+        }
         VT cr = bld<T, V, AN>(Rcr, ocr);
-        const VT x = bld<T, V, AN>(Rx, oo);
+#pragma unroll
+        for (int c = 0; c < NR; ++c) x[c] = bld<T, V, AN>(Rx[c], oo);
         VT ct = bld<T, V>(Rct, oo);
         VT cp = bld<T, V, AN>(Rcp, oo);
         VecT<double, V> w{};
         if (CHECK) w = bld<double, V>(Rw, vown ? (uint32_t)(base + col) * 8u : kOOB);
-        const VT rU = bld<T, V>(Rr, oU);
-        const VT qU = bld<T, V>(Rq, oU);
-        const VT pU = bld<T, V>(Rp, oU);
+#pragma unroll
+        for (int c = 0; c < NR; ++c) {
+            rU[c] = bld<T, V>(Rr[c], oU);
+            qU[c] = bld<T, V>(Rq[c], oU);
+            pU[c] = bld<T, V>(Rp[c], oU);
+        }
         const VT ctU = bld<T, V>(Rct, oU);
-        const VT rD = bld<T, V>(Rr, oD);
-        const VT qD = bld<T, V>(Rq, oD);
-        const VT pD = bld<T, V>(Rp, oD);
-        const T lr = bld<T, 1>(Rr, oL).v[0];
-        const T lq = bld<T, 1>(Rq, oL).v[0];
-        const T lp_ = bld<T, 1>(Rp, oL).v[0];
+#pragma unroll
+        for (int c = 0; c < NR; ++c) {
+            rD[c] = bld<T, V>(Rr[c], oD);
+            qD[c] = bld<T, V>(Rq[c], oD);
+            pD[c] = bld<T, V>(Rp[c], oD);
+            lr[c] = bld<T, 1>(Rr[c], oL).v[0];
+            lq[c] = bld<T, 1>(Rq[c], oL).v[0];
+            lp_[c] = bld<T, 1>(Rp[c], oL).v[0];
+        }
         const T lcp = bld<T, 1>(Rcp, oL).v[0];
-        const T rr_ = bld<T, 1>(Rr, oR).v[0];
-        const T rq_ = bld<T, 1>(Rq, oR).v[0];
-        const T rp_ = bld<T, 1>(Rp, oR).v[0];
+#pragma unroll
+        for (int c = 0; c < NR; ++c) {
+            rr_[c] = bld<T, 1>(Rr[c], oR).v[0];
+            rq_[c] = bld<T, 1>(Rq[c], oR).v[0];
+            rp_[c] = bld<T, 1>(Rp[c], oR).v[0];
+        }
 #if MAS_ITER_DEFER
         // ---- stores of the previous step
-        bst<T, V, AN>(Rro, st_own ? st_off : kOOB, st_r);
-        bst<T, V, AN>(Rpo, st_own ? st_off : kOOB, st_p);
-        bst<T, V, AN>(Rx, st_own ? st_off : kOOB, st_x);
-        bst<T, V, AN>(Rqo, st_q_do ? st_qoff : kOOB, st_q);
+#pragma unroll
+        for (int c = 0; c < NR; ++c) {
+            bst<T, V, AN>(Rro[c], st_own ? st_off : kOOB, st_r[c]);
+            bst<T, V, AN>(Rpo[c], st_own ? st_off : kOOB, st_p[c]);
+            bst<T, V, AN>(Rx[c], st_own ? st_off : kOOB, st_x[c]);
+            bst<T, V, AN>(Rqo[c], st_q_do ? st_qoff : kOOB, st_q[c]);
+        }
 #endif
-        // ---- r_k, p_k, x_k of plane m
-        VT rn, pn, xn;
 #pragma unroll
         for (int e = 0; e < V; ++e) {
-            rn.v[e] = r.v[e] - alpha * q.v[e];
-            pn.v[e] = rn.v[e] + beta * p.v[e];
-            xn.v[e] = x.v[e] + alpha * p.v[e];
-            if (!vin) pn.v[e] = T(0);
             if (!(vin && m < i1)) cr.v[e] = T(0);
             if (!vown) {
                 ct.v[e] = T(0);
@@ -460,111 +504,133 @@ void k_pcg_iter(IterArgs<T> a) {
         }
         // face between the previous plane and this one
         const VT cf = up ? cr1 : cr;
-        // ---- in-plane part of q_k(m) plus the visited r neighbour
-        VT S{};
-        if (own) {
-            VT pU_, pD_, ctU_;
-#pragma unroll
-            for (int e = 0; e < V; ++e) {
-                // theta neighbours: shuffled from the neighbouring row of the
-                // wave, or formed from the loaded row at the wave's edges
-                const T sU = shfl_lane(pn.v[e], srcU);
-                const T sD = shfl_lane(pn.v[e], srcD);
-                const T sct = shfl_lane(ct.v[e], srcU);
-                const T lU = (rU.v[e] - alpha * qU.v[e]) + beta * pU.v[e];
-                const T lD = (rD.v[e] - alpha * qD.v[e]) + beta * pD.v[e];
-                pU_.v[e] = !hasU ? T(0) : (rr == 0 ? lU : sU);
-                pD_.v[e] = !hasD ? T(0) : (rr == RPW - 1 ? lD : sD);
-                ctU_.v[e] = !hasU ? T(0) : (rr == 0 ? ctU.v[e] : sct);
-            }
-            const T pl_edge = (lr - alpha * lq) + beta * lp_;
-            const T pr_edge = (rr_ - alpha * rq_) + beta * rp_;
-            T left0 = shfl_up1(pn.v[V - 1]);
-            T right0 = shfl_dn1(pn.v[0]);
-            T cpl0 = shfl_up1(cp.v[V - 1]);
-            if (lp == 0) {
-                left0 = vL ? pl_edge : T(0);
-                cpl0 = vL ? lcp : T(0);
-            }
-            if (lp == nvl - 1) right0 = vR ? pr_edge : T(0);
-#pragma unroll
-            for (int e = 0; e < V; ++e) {
-                const T left = (e > 0) ? pn.v[e - 1] : left0;
-                const T right = (e < V - 1) ? pn.v[e + 1] : right0;
-                const T cpl = (e > 0) ? cp.v[e - 1] : cpl0;
-                S.v[e] = ct.v[e] * pD_.v[e] + ctU_.v[e] * pU_.v[e] + cp.v[e] * right + cpl * left +
-                         cf.v[e] * pn1.v[e];
-            }
-        }
-        // ---- complete q_k of the previous plane
         const int mp = up ? m - 1 : m + 1;
         const bool qdo = mp >= i0 && mp < i1 && act;
-        VT qv;
+        const uint32_t oq = qdo ? (uint32_t)(base1 + col) * ES : kOOB;
 #pragma unroll
-        for (int e = 0; e < V; ++e) qv.v[e] = pn1.v[e] - (S1.v[e] + cf.v[e] * pn.v[e]);
-        if (qdo) {
+        for (int c = 0; c < NR; ++c) {
+            // ---- r_k, p_k, x_k of plane m
+            VT rn, pn, xn;
 #pragma unroll
             for (int e = 0; e < V; ++e) {
-                const double pd = (double)pn1.v[e], qd = (double)qv.v[e], rd = (double)rn1.v[e];
-                acc[0] += pd * qd;
-                acc[1] += rd * qd;
-                acc[2] += qd * qd;
-                acc[3] += rd * rd;
-                if (CHECK) {
-                    const double t = w1.v[e] * rd;
-                    acc[4] += t * t;
+                rn.v[e] = r[c].v[e] - alpha[c] * q[c].v[e];
+                pn.v[e] = rn.v[e] + beta[c] * p[c].v[e];
+                xn.v[e] = x[c].v[e] + alpha[c] * p[c].v[e];
+                if (!vin) pn.v[e] = T(0);
+            }
+            // ---- in-plane part of q_k(m) plus the visited r neighbour
+            VT S{};
+            if (own) {
+                VT pU_, pD_, ctU_;
+#pragma unroll
+                for (int e = 0; e < V; ++e) {
+                    // theta neighbours: shuffled from the neighbouring row of
+                    // the wave, or formed from the loaded row at its edges
+                    const T sU = shfl_lane(pn.v[e], srcU);
+                    const T sD = shfl_lane(pn.v[e], srcD);
+                    const T sct = shfl_lane(ct.v[e], srcU);
+                    const T lU = (rU[c].v[e] - alpha[c] * qU[c].v[e]) + beta[c] * pU[c].v[e];
+                    const T lD = (rD[c].v[e] - alpha[c] * qD[c].v[e]) + beta[c] * pD[c].v[e];
+                    pU_.v[e] = !hasU ? T(0) : (rr == 0 ? lU : sU);
+                    pD_.v[e] = !hasD ? T(0) : (rr == RPW - 1 ? lD : sD);
+                    ctU_.v[e] = !hasU ? T(0) : (rr == 0 ? ctU.v[e] : sct);
+                }
+                const T pl_edge = (lr[c] - alpha[c] * lq[c]) + beta[c] * lp_[c];
+                const T pr_edge = (rr_[c] - alpha[c] * rq_[c]) + beta[c] * rp_[c];
+                T left0 = shfl_up1(pn.v[V - 1]);
+                T right0 = shfl_dn1(pn.v[0]);
+                T cpl0 = shfl_up1(cp.v[V - 1]);
+                if (lp == 0) {
+                    left0 = vL ? pl_edge : T(0);
+                    cpl0 = vL ? lcp : T(0);
+                }
+                if (lp == nvl - 1) right0 = vR ? pr_edge : T(0);
+#pragma unroll
+                for (int e = 0; e < V; ++e) {
+                    const T left = (e > 0) ? pn.v[e - 1] : left0;
+                    const T right = (e < V - 1) ? pn.v[e + 1] : right0;
+                    const T cpl = (e > 0) ? cp.v[e - 1] : cpl0;
+                    S.v[e] = ct.v[e] * pD_.v[e] + ctU_.v[e] * pU_.v[e] + cp.v[e] * right +
+                             cpl * left + cf.v[e] * pn1[c].v[e];
                 }
             }
+            // ---- complete q_k of the previous plane
+            VT qv;
+#pragma unroll
+            for (int e = 0; e < V; ++e) qv.v[e] = pn1[c].v[e] - (S1[c].v[e] + cf.v[e] * pn.v[e]);
+            if (qdo) {
+#pragma unroll
+                for (int e = 0; e < V; ++e) {
+                    const double pd = (double)pn1[c].v[e], qd = (double)qv.v[e],
+                                 rd = (double)rn1[c].v[e];
+                    acc[c * kNV + 0] += pd * qd;
+                    acc[c * kNV + 1] += rd * qd;
+                    acc[c * kNV + 2] += qd * qd;
+                    acc[c * kNV + 3] += rd * rd;
+                    if (CHECK) {
+                        const double t = w1.v[e] * rd;
+                        acc[c * kNV + 4] += t * t;
+                    }
+                }
+            }
+            // ---- stores
+#if MAS_ITER_DEFER
+            st_r[c] = rn;
+            st_p[c] = pn;
+            st_x[c] = xn;
+            st_q[c] = qv;
+#else
+            bst<T, V, AN>(Rro[c], oo, rn);
+            bst<T, V, AN>(Rpo[c], oo, pn);
+            bst<T, V, AN>(Rx[c], oo, xn);
+            bst<T, V, AN>(Rqo[c], oq, qv);
+#endif
+            pn1[c] = pn;
+            rn1[c] = rn;
+            S1[c] = S;
         }
-        // ---- stores
-        const uint32_t oq = qdo ? (uint32_t)(base1 + col) * ES : kOOB;
 #if MAS_ITER_DEFER
         st_own = vown;
-        st_r = rn;
-        st_p = pn;
-        st_x = xn;
         st_off = oo;
         st_q_do = qdo;
-        st_q = qv;
         st_qoff = oq;
-#else
-        bst<T, V, AN>(Rro, oo, rn);
-        bst<T, V, AN>(Rpo, oo, pn);
-        bst<T, V, AN>(Rx, oo, xn);
-        bst<T, V, AN>(Rqo, oq, qv);
 #endif
 #if MAS_ITER_SYNC
         // keep the block's waves on the same plane so that the rows they
         // load for each other are requested together (L1/L2 reuse)
         __syncthreads();
 #endif
-        pn1 = pn;
-        rn1 = rn;
-        S1 = S;
         cr1 = cr;
         if (CHECK) w1 = w;
         base1 = base;
     }
 #if MAS_ITER_DEFER
-    bst<T, V, AN>(Rro, st_own ? st_off : kOOB, st_r);
-    bst<T, V, AN>(Rpo, st_own ? st_off : kOOB, st_p);
-    bst<T, V, AN>(Rx, st_own ? st_off : kOOB, st_x);
-    bst<T, V, AN>(Rqo, st_q_do ? st_qoff : kOOB, st_q);
+#pragma unroll
+    for (int c = 0; c < NR; ++c) {
+        bst<T, V, AN>(Rro[c], st_own ? st_off : kOOB, st_r[c]);
+        bst<T, V, AN>(Rpo[c], st_own ? st_off : kOOB, st_p[c]);
+        bst<T, V, AN>(Rx[c], st_own ? st_off : kOOB, st_x[c]);
+        bst<T, V, AN>(Rqo[c], st_q_do ? st_qoff : kOOB, st_q[c]);
+    }
 #endif
-    __shared__ double sRed[WPB * kNV];
-    block_sum_store<kNV>(acc, a.partials + (int64_t)L * kNV, sRed);
+    __shared__ double sRed[WPB * NR * kNV];
+    block_sum_store<NR * kNV>(acc, a.partials + (int64_t)L * NR * kNV, sRed);
 }
 
 // One block: fixed-order sum of the iteration partials, then the scalar
 // recurrences and the stopping tests.
+// With several right-hand sides, block c of the launch finalizes right-hand
+// side c (partials [nblk][nrhs][kNV], control blocks ctl[0:nrhs]).
 __global__ __launch_bounds__(kRedThreads) void k_finalize(const double *partials, int nblk,
-                                                         Ctl *ctl, int is_check) {
+                                                         Ctl *ctl_all, int is_check) {
+    const int c = blockIdx.x, nrhs = gridDim.x;
+    Ctl *ctl = ctl_all + c;
     if (ctl->flag != FLAG_RUN) return;
     __shared__ double sh[kRedThreads * kNV];
     double v[kNV] = {0.0, 0.0, 0.0, 0.0, 0.0};
     for (int b = threadIdx.x; b < nblk; b += kRedThreads) {
 #pragma unroll
-        for (int t = 0; t < kNV; ++t) v[t] += partials[(int64_t)b * kNV + t];
+        for (int t = 0; t < kNV; ++t) v[t] += partials[((int64_t)b * nrhs + c) * kNV + t];
     }
 #pragma unroll
     for (int t = 0; t < kNV; ++t) sh[threadIdx.x * kNV + t] = v[t];
@@ -645,15 +711,17 @@ __global__ __launch_bounds__(kRedThreads) void k_reduce(const double *partials, 
 
 // Reset the control block for a new PCG run (a kernel, not a memset, so it
 // is safe inside captured graphs as well).
+// flag0 = FLAG_RUN starts the run; another flag leaves this control block
+// (one right-hand side of several) stopped from the start.
 __global__ void k_ctl_init(Ctl *ctl, int mode, int iter0, int max_iter, double tol2,
-                           double beta0) {
+                           double beta0, int flag0) {
     if (threadIdx.x != 0) return;
     ctl->alpha = 0.0;
     ctl->beta = beta0;
     ctl->rr = 0.0;
     ctl->rw = 0.0;
     ctl->tol2 = tol2;
-    ctl->flag = FLAG_RUN;
+    ctl->flag = flag0;
     ctl->iter = iter0;
     ctl->max_iter = max_iter;
     ctl->mode = mode;

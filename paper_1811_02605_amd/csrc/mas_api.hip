@@ -343,10 +343,12 @@ extern "C" int mas_op_export(const mas_op *op, double *cr, double *ct, double *c
 
 // ------------------------------------------------------------------ workspace
 struct WorkLayout {
-    int64_t ctl, partials, bhat, vec[6], dh, total;
+    int64_t ctl, partials, bhat[kMaxRhs], vec[kMaxRhs][6], dh, total;
 };
 
-static WorkLayout work_layout(const Shape &s, int precision) {
+// nrhs right-hand sides: control blocks and the iteration partials for all of
+// them, then b^ and the six PCG vectors of each.
+static WorkLayout work_layout(const Shape &s, int precision, int nrhs = 1) {
     WorkLayout L{};
     int64_t off = 0;
     auto take = [&](int64_t bytes) {
@@ -354,14 +356,20 @@ static WorkLayout work_layout(const Shape &s, int precision) {
         off = align256(off + bytes);
         return o;
     };
-    // the iteration kernel writes kNV partials per block (most blocks with
-    // V = 1), the simple-tile kernels up to kSimpleNV
-    const int64_t nparts = std::max(s.nblk_iter(1) * kNV, s.nblk_simple() * kSimpleNV);
-    L.ctl = take(sizeof(Ctl));
+    // the iteration kernel writes nrhs * kNV partials per block (most blocks
+    // with V = 1), the simple-tile kernels up to kSimpleNV
+    const int64_t nparts = std::max(s.nblk_iter(1) * kNV * nrhs, s.nblk_simple() * kSimpleNV);
+    L.ctl = take(sizeof(Ctl) * nrhs);
     L.partials = take(8 * nparts);
-    L.bhat = take(8 * s.n);
     const int64_t es = (precision == MAS_FP32_REFINED) ? 4 : 8;
-    for (int t = 0; t < 6; ++t) L.vec[t] = take(es * s.n);
+    for (int c = 0; c < kMaxRhs; ++c) {
+        L.bhat[c] = -1;
+        for (int t = 0; t < 6; ++t) L.vec[c][t] = -1;
+    }
+    for (int c = 0; c < nrhs; ++c) {
+        L.bhat[c] = take(8 * s.n);
+        for (int t = 0; t < 6; ++t) L.vec[c][t] = take(es * s.n);
+    }
     L.dh = (precision == MAS_FP32_REFINED) ? take(4 * s.n) : -1;
     L.total = off;
     return L;
@@ -394,6 +402,12 @@ extern "C" int64_t mas_pcg_workspace_bytes(const mas_op *op, const mas_pcg_opts 
     return work_layout(op->s, o->precision).total;
 }
 
+extern "C" int64_t mas_pcg_multi_workspace_bytes(const mas_op *op, int32_t nrhs) {
+    if (!op) return fail(MAS_EINVAL, "op must not be NULL");
+    if (nrhs < 1 || nrhs > kMaxRhs) return fail(MAS_EINVAL, "nrhs must lie in [1, %d]", kMaxRhs);
+    return work_layout(op->s, MAS_FP64, nrhs).total;
+}
+
 // ------------------------------------------------------------------ drivers
 namespace {
 
@@ -418,9 +432,8 @@ static int pinned_buffer(int32_t **out) {
 struct Ctx {
     const mas_op *op;
     hipStream_t stream;
-    Ctl *ctl;
+    Ctl *ctl;  // [nrhs]; ctl[0] also receives k_reduce sums
     double *partials;
-    double *bhat;
     bool timing;
     // event samples of the iteration kernel
     std::vector<hipEvent_t> ev;
@@ -430,9 +443,9 @@ struct Ctx {
     }
 };
 
-// Host copy of the control block (synchronous).
-static int read_ctl(Ctx &cx, Ctl *h) {
-    HIPCHK(hipMemcpyAsync(h, cx.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, cx.stream));
+// Host copy of control block c (synchronous).
+static int read_ctl(Ctx &cx, Ctl *h, int c = 0) {
+    HIPCHK(hipMemcpyAsync(h, cx.ctl + c, sizeof(Ctl), hipMemcpyDeviceToHost, cx.stream));
     HIPCHK(hipStreamSynchronize(cx.stream));
     return MAS_OK;
 }
@@ -453,10 +466,11 @@ static int reduce_n(Ctx &cx, int nv, double *out) {
 // r^ = b^ - A^ x^ in double precision, stored as T into r.
 // Returns rw2 = ||W r^||^2 = ||b - A x||^2 and rr2 = ||r^||^2.
 template <typename T>
-static int residual(Ctx &cx, const double *xhat, T *r, double *rw2, double *rr2 = nullptr) {
+static int residual(Ctx &cx, const double *bhat, const double *xhat, T *r, double *rw2,
+                    double *rr2 = nullptr) {
     const mas_op *op = cx.op;
     hipLaunchKernelGGL(k_residual<T>, op->s.simple_grid(), dim3(kWave, kSimpleJ), 0, cx.stream,
-                       cx.bhat, xhat, op->w, op->c64[0], op->c64[1], op->c64[2], op->s.dims(), r,
+                       bhat, xhat, op->w, op->c64[0], op->c64[1], op->c64[2], op->s.dims(), r,
                        cx.partials);
     LAUNCHCHK();
     double sums[2];
@@ -466,27 +480,43 @@ static int residual(Ctx &cx, const double *xhat, T *r, double *rw2, double *rr2 
     return st;
 }
 
-struct PcgResult {
-    int flag;
-    int last_iter;  // index of the last iteration kernel that did work
+// The vectors of the right-hand sides one PCG run carries, and which of them
+// run (the others stay stopped and move no bytes).
+template <typename T>
+struct RhsSet {
+    int n = 0;
+    T *r[kMaxRhs][2], *p[kMaxRhs][2], *q[kMaxRhs][2];
+    T *x[kMaxRhs];
+    double tol2[kMaxRhs];
+    int max_iter[kMaxRhs];  // last admissible iteration index of each
+    bool active[kMaxRhs];
 };
 
-// PCG iterations on the scaled system in precision T.  Before the call,
-// r[iter0 % 2] holds r_{iter0} and x holds x_{iter0}.  mode 0 stops on
-// ||W r||^2 <= tol2 (checked every check_every iterations), mode 1 on
-// (r,r) <= tol2 (every iteration).  The first kernel uses alpha = 0 and
-// beta = beta0: with keep_p it continues the search direction in
-// p[iter0 % 2] (p = r + beta0 p), otherwise it starts afresh (p = r).
-template <typename T>
-static int run_pcg(Ctx &cx, T *const r[2], T *const p[2], T *const q[2], T *x, const T *const c[3],
-                   int mode, int iter0, int max_iter, int check_every, double tol2, bool keep_p,
-                   double beta0, PcgResult *res) {
+struct PcgResult {
+    int flag[kMaxRhs];
+    int last_iter[kMaxRhs];  // index of the last iteration kernel that did work
+};
+
+// PCG iterations on the scaled system in precision T for NR right-hand sides
+// sharing the operator.  Before the call, r[c][iter0 % 2] holds r_{iter0} and
+// x[c] holds x_{iter0}.  mode 0 stops on ||W r||^2 <= tol2 (checked every
+// check_every iterations), mode 1 on (r,r) <= tol2 (every iteration).  The
+// first kernel uses alpha = 0 and beta = beta0: with keep_p it continues the
+// search direction in p[iter0 % 2] (p = r + beta0 p), otherwise it starts
+// afresh (p = r).
+template <typename T, int NR>
+static int run_pcg(Ctx &cx, const RhsSet<T> &v, const T *const c[3], int mode, int iter0,
+                   int check_every, bool keep_p, double beta0, PcgResult *res) {
     const mas_op *op = cx.op;
     const Shape &s = op->s;
     hipStream_t st = cx.stream;
     if (!keep_p) beta0 = 0.0;
-    hipLaunchKernelGGL(k_ctl_init, dim3(1), dim3(64), 0, st, cx.ctl, mode, iter0, max_iter, tol2,
-                       beta0);
+    int max_iter = iter0;
+    for (int h = 0; h < NR; ++h) {
+        hipLaunchKernelGGL(k_ctl_init, dim3(1), dim3(64), 0, st, cx.ctl + h, mode, iter0,
+                           v.max_iter[h], v.tol2[h], beta0, v.active[h] ? FLAG_RUN : FLAG_CONV);
+        if (v.active[h]) max_iter = std::max(max_iter, v.max_iter[h]);
+    }
     LAUNCHCHK();
     int32_t *pin = nullptr;
     int e = pinned_buffer(&pin);
@@ -506,10 +536,10 @@ static int run_pcg(Ctx &cx, T *const r[2], T *const p[2], T *const q[2], T *x, c
     a.tiles_j = s.tiles_j();
     a.ti = kTI;
     a.nblk = (int)s.nblk_iter(V);
-    a.x = x;
+    for (int h = 0; h < NR; ++h) a.x[h] = v.x[h];
     const dim3 grid((unsigned)a.nblk), block(kWave * kTJ);
 
-    // batches of launches; the host polls the device flag one batch behind
+    // batches of launches; the host polls the device flags one batch behind
     const int batch = std::max(check_every, 16);
     hipEvent_t done[2] = {nullptr, nullptr};
     HIPCHK(hipEventCreateWithFlags(&done[0], hipEventDisableTiming));
@@ -529,15 +559,17 @@ static int run_pcg(Ctx &cx, T *const r[2], T *const p[2], T *const q[2], T *x, c
         const int kend = std::min(max_iter, k + batch - 1);
         for (; k <= kend; ++k) {
             const int cur = k & 1, nxt = cur ^ 1;
-            a.r_in = r[cur];
-            // the first kernel of a run has alpha = 0 (and beta = 0 unless the
-            // direction is kept): point q (and p) at r, finite values, so
-            // that every load stays unconditional
-            a.p_in = (k == iter0 && !keep_p) ? r[cur] : p[cur];
-            a.q_in = (k == iter0) ? r[cur] : q[cur];
-            a.r_out = r[nxt];
-            a.p_out = p[nxt];
-            a.q_out = q[nxt];
+            for (int h = 0; h < NR; ++h) {
+                a.r_in[h] = v.r[h][cur];
+                // the first kernel of a run has alpha = 0 (and beta = 0 unless
+                // the direction is kept): point q (and p) at r, finite
+                // values, so that every load stays unconditional
+                a.p_in[h] = (k == iter0 && !keep_p) ? v.r[h][cur] : v.p[h][cur];
+                a.q_in[h] = (k == iter0) ? v.r[h][cur] : v.q[h][cur];
+                a.r_out[h] = v.r[h][nxt];
+                a.p_out[h] = v.p[h][nxt];
+                a.q_out[h] = v.q[h][nxt];
+            }
             const bool chk = (mode == 0) && ((k % check_every) == 0 || k == max_iter);
             const bool sample = cx.timing && (k % 16 == 7) && cx.ev.size() < 128;
             if (sample) {
@@ -552,35 +584,42 @@ static int run_pcg(Ctx &cx, T *const r[2], T *const p[2], T *const q[2], T *x, c
             constexpr int VW = MAS_ITER_VEC / (int)sizeof(T) > 0 ? MAS_ITER_VEC / (int)sizeof(T) : 1;
             if (V == VW) {
                 if (chk)
-                    hipLaunchKernelGGL((k_pcg_iter<T, kTJ, kRPW, VW, true>), grid, block, 0, st, a);
+                    hipLaunchKernelGGL((k_pcg_iter<T, NR, kTJ, kRPW, VW, true>), grid, block, 0, st, a);
                 else
-                    hipLaunchKernelGGL((k_pcg_iter<T, kTJ, kRPW, VW, false>), grid, block, 0, st, a);
+                    hipLaunchKernelGGL((k_pcg_iter<T, NR, kTJ, kRPW, VW, false>), grid, block, 0, st, a);
             } else {
                 if (chk)
-                    hipLaunchKernelGGL((k_pcg_iter<T, kTJ, kRPW, 1, true>), grid, block, 0, st, a);
+                    hipLaunchKernelGGL((k_pcg_iter<T, NR, kTJ, kRPW, 1, true>), grid, block, 0, st, a);
                 else
-                    hipLaunchKernelGGL((k_pcg_iter<T, kTJ, kRPW, 1, false>), grid, block, 0, st, a);
+                    hipLaunchKernelGGL((k_pcg_iter<T, NR, kTJ, kRPW, 1, false>), grid, block, 0, st, a);
             }
             if (sample) HIPCHK(hipEventRecord(cx.ev.back(), st));
-            hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kRedThreads), 0, st, cx.partials, a.nblk,
+            hipLaunchKernelGGL(k_finalize, dim3(NR), dim3(kRedThreads), 0, st, cx.partials, a.nblk,
                                cx.ctl, chk ? 1 : 0);
         }
         LAUNCHCHK();
-        HIPCHK(hipMemcpyAsync(pin + 2 * (nb & 1), &cx.ctl->flag, 2 * sizeof(int32_t),
-                              hipMemcpyDeviceToHost, st));
+        int32_t *slot = pin + 2 * kMaxRhs * (nb & 1);
+        for (int h = 0; h < NR; ++h)
+            HIPCHK(hipMemcpyAsync(slot + 2 * h, &cx.ctl[h].flag, 2 * sizeof(int32_t),
+                                  hipMemcpyDeviceToHost, st));
         HIPCHK(hipEventRecord(done[nb & 1], st));
         if (nb > 0) {
             HIPCHK(hipEventSynchronize(done[(nb - 1) & 1]));
-            if (pin[2 * ((nb - 1) & 1)] != FLAG_RUN) stop = true;
+            const int32_t *prev = pin + 2 * kMaxRhs * ((nb - 1) & 1);
+            bool any = false;
+            for (int h = 0; h < NR; ++h) any = any || prev[2 * h] == FLAG_RUN;
+            if (!any) stop = true;
         }
         ++nb;
     }
     HIPCHK(hipStreamSynchronize(st));
-    Ctl h;
-    e = read_ctl(cx, &h);
-    if (e != MAS_OK) return e;
-    res->flag = h.flag;
-    res->last_iter = (h.flag == FLAG_RUN) ? max_iter : h.conv_iter;
+    for (int h = 0; h < NR; ++h) {
+        Ctl hc;
+        e = read_ctl(cx, &hc, h);
+        if (e != MAS_OK) return e;
+        res->flag[h] = hc.flag;
+        res->last_iter[h] = (hc.flag == FLAG_RUN) ? v.max_iter[h] : hc.conv_iter;
+    }
     return MAS_OK;
 }
 
@@ -636,7 +675,7 @@ static int solve_core(const mas_op *op, const double *src, int src_is_rhs, doubl
                     (long long)L.total);
 
     if (std::max(s.nblk_iter(1) * kNV, s.nblk_simple() * kSimpleNV) * 8 >
-        L.bhat - L.partials)
+        L.bhat[0] - L.partials)
         return fail(MAS_EINVAL, "internal: partial-sum area too small");
     char *base = static_cast<char *>(work);
     Ctx cx;
@@ -644,14 +683,14 @@ static int solve_core(const mas_op *op, const double *src, int src_is_rhs, doubl
     cx.stream = as_stream(hip_stream);
     cx.ctl = reinterpret_cast<Ctl *>(base + L.ctl);
     cx.partials = reinterpret_cast<double *>(base + L.partials);
-    cx.bhat = reinterpret_cast<double *>(base + L.bhat);
+    double *bhat = reinterpret_cast<double *>(base + L.bhat[0]);
     cx.timing = o.sample_timing != 0;
     const Dims d = s.dims();
     const dim3 sgrid = s.simple_grid(), sblock(kWave, kSimpleJ);
 
     // b^ = W^-1 b, x^ = W x0 or 0, ||b||^2
     hipLaunchKernelGGL(k_setup, sgrid, sblock, 0, cx.stream, src, src_is_rhs, op->w, op->geo, d,
-                       cx.bhat, x, o.use_x0 ? 1 : 0, cx.partials);
+                       bhat, x, o.use_x0 ? 1 : 0, cx.partials);
     LAUNCHCHK();
     double b2 = 0.0;
     st = reduce_n(cx, 1, &b2);
@@ -673,12 +712,20 @@ static int solve_core(const mas_op *op, const double *src, int src_is_rhs, doubl
     }
 
     if (o.precision == MAS_FP64) {
-        double *v[6];
-        for (int t = 0; t < 6; ++t) v[t] = reinterpret_cast<double *>(base + L.vec[t]);
-        double *const r[2] = {v[0], v[1]}, *const p[2] = {v[2], v[3]}, *const q[2] = {v[4], v[5]};
+        RhsSet<double> v;
+        v.n = 1;
+        for (int t = 0; t < 2; ++t) {
+            v.r[0][t] = reinterpret_cast<double *>(base + L.vec[0][t]);
+            v.p[0][t] = reinterpret_cast<double *>(base + L.vec[0][2 + t]);
+            v.q[0][t] = reinterpret_cast<double *>(base + L.vec[0][4 + t]);
+        }
+        v.x[0] = x;
+        v.tol2[0] = tol2;
+        v.max_iter[0] = o.max_iters;
+        v.active[0] = true;
         const double *const c[3] = {op->c64[0], op->c64[1], op->c64[2]};
         double rw2 = 0.0;
-        st = residual<double>(cx, x, r[0], &rw2);
+        st = residual<double>(cx, bhat, x, v.r[0][0], &rw2);
         if (st != MAS_OK) return st;
         info.rel_resid_true = info.rel_resid_recursive = std::sqrt(rw2) / bnorm;
         int iter0 = 0;
@@ -687,44 +734,51 @@ static int solve_core(const mas_op *op, const double *src, int src_is_rhs, doubl
         while (status != MAS_OK) {
             if (iter0 > o.max_iters) break;
             PcgResult pr{};
-            st = run_pcg<double>(cx, r, p, q, x, c, 0, iter0, o.max_iters, o.check_every, tol2,
-                                 false, 0.0, &pr);
+            st = run_pcg<double, 1>(cx, v, c, 0, iter0, o.check_every, false, 0.0, &pr);
             if (st != MAS_OK) return st;
-            timing_summary(cx, pr.last_iter, &info);
-            info.iters = pr.last_iter;
+            timing_summary(cx, pr.last_iter[0], &info);
+            info.iters = pr.last_iter[0];
             Ctl h;
             st = read_ctl(cx, &h);
             if (st != MAS_OK) return st;
             info.rel_resid_recursive = std::sqrt(h.rw) / bnorm;
             // true residual of x_k into the buffer the next iteration reads
-            const int nxt = (pr.last_iter + 1) & 1;
-            st = residual<double>(cx, x, r[nxt], &rw2);
+            const int nxt = (pr.last_iter[0] + 1) & 1;
+            st = residual<double>(cx, bhat, x, v.r[0][nxt], &rw2);
             if (st != MAS_OK) return st;
             info.rel_resid_true = std::sqrt(rw2) / bnorm;
             if (rw2 <= tol2) {
                 status = MAS_OK;
                 break;
             }
-            if (pr.flag == FLAG_BREAK) {
+            if (pr.flag[0] == FLAG_BREAK) {
                 status = MAS_EBREAKDOWN;
                 break;
             }
-            if (pr.flag != FLAG_CONV || info.restarts >= o.max_restarts) {
+            if (pr.flag[0] != FLAG_CONV || info.restarts >= o.max_restarts) {
                 status = MAS_ENOTCONV;
                 break;
             }
             ++info.restarts;
-            iter0 = pr.last_iter + 1;
+            iter0 = pr.last_iter[0] + 1;
         }
     } else {
-        float *v[6];
-        for (int t = 0; t < 6; ++t) v[t] = reinterpret_cast<float *>(base + L.vec[t]);
+        RhsSet<float> v;
+        v.n = 1;
+        for (int t = 0; t < 2; ++t) {
+            v.r[0][t] = reinterpret_cast<float *>(base + L.vec[0][t]);
+            v.p[0][t] = reinterpret_cast<float *>(base + L.vec[0][2 + t]);
+            v.q[0][t] = reinterpret_cast<float *>(base + L.vec[0][4 + t]);
+        }
         float *dh = reinterpret_cast<float *>(base + L.dh);
-        float *const r[2] = {v[0], v[1]}, *const p[2] = {v[2], v[3]}, *const q[2] = {v[4], v[5]};
+        v.x[0] = dh;
+        v.active[0] = true;
+        float *const *r = v.r[0];
+        float *const *p = v.p[0];
         const float *const c[3] = {op->c32[0], op->c32[1], op->c32[2]};
         const bool reliable = o.refine == MAS_REFINE_RELIABLE;
         double rw2 = 0.0, rr2 = 0.0;
-        st = residual<float>(cx, x, r[0], &rw2, &rr2);
+        st = residual<float>(cx, bhat, x, r[0], &rw2, &rr2);
         if (st != MAS_OK) return st;
         info.rel_resid_true = std::sqrt(rw2) / bnorm;
         status = (rw2 <= tol2) ? MAS_OK : MAS_ENOTCONV;
@@ -741,24 +795,23 @@ static int solve_core(const mas_op *op, const double *src, int src_is_rhs, doubl
             // tolerance (ratio ||W r||/||r|| taken at the last replacement).
             double thr = d2 * rr2;
             if (reliable && rw2 > 0.0) thr = std::max(thr, 0.25 * tol2 * (rr2 / rw2));
+            v.tol2[0] = thr;
+            v.max_iter[0] = k0 + (o.max_iters - used);
             PcgResult pr{};
-            const int cur = k0 & 1;
-            st = run_pcg<float>(cx, r, p, q, dh, c, 1, k0, k0 + (o.max_iters - used), 1, thr,
-                                reliable && beta0 > 0.0, beta0, &pr);
+            st = run_pcg<float, 1>(cx, v, c, 1, k0, 1, reliable && beta0 > 0.0, beta0, &pr);
             if (st != MAS_OK) return st;
-            (void)cur;
-            timing_summary(cx, pr.last_iter, &info);
-            const int taken = pr.last_iter - k0 + 1;  // iteration kernels that did work
+            timing_summary(cx, pr.last_iter[0], &info);
+            const int taken = pr.last_iter[0] - k0 + 1;  // iteration kernels that did work
             used += taken;
             info.outer_iters++;
-            if (pr.flag == FLAG_BREAK && taken == 0) {
+            if (pr.flag[0] == FLAG_BREAK && taken == 0) {
                 status = MAS_EBREAKDOWN;
                 break;
             }
             Ctl h;
             st = read_ctl(cx, &h);
             if (st != MAS_OK) return st;
-            const int nxt = (pr.last_iter + 1) & 1;
+            const int nxt = (pr.last_iter[0] + 1) & 1;
             if (reliable) {
                 // x^ += d^ + alpha_K p_K, then replace r by the double-precision
                 // residual and continue from the same search direction p_K
@@ -766,29 +819,29 @@ static int solve_core(const mas_op *op, const double *src, int src_is_rhs, doubl
                                    d, x);
                 LAUNCHCHK();
                 const double rr_old = h.rr, rr_pred = h.rr_next;
-                st = residual<float>(cx, x, r[nxt], &rw2, &rr2);
+                st = residual<float>(cx, bhat, x, r[nxt], &rw2, &rr2);
                 if (st != MAS_OK) return st;
                 // keep the direction only while the replaced residual agrees
                 // with the one the recurrence predicted (no drift of the
                 // single-precision residual); otherwise restart from r
-                const bool keep = pr.flag == FLAG_CONV && rr_old > 0.0 && rr_pred > 0.0 &&
+                const bool keep = pr.flag[0] == FLAG_CONV && rr_old > 0.0 && rr_pred > 0.0 &&
                                   rr2 <= 4.0 * rr_pred;
                 beta0 = keep ? rr2 / rr_old : 0.0;
-                k0 = pr.last_iter + 1;
+                k0 = pr.last_iter[0] + 1;
             } else {
                 // classical refinement: x^ += d^; the next inner solve restarts
                 hipLaunchKernelGGL(k_ctl_init, dim3(1), dim3(64), 0, cx.stream, cx.ctl, 1, 0, 0,
-                                   0.0, 0.0);  // alpha = 0 for the fold
+                                   0.0, 0.0, (int)FLAG_RUN);  // alpha = 0 for the fold
                 hipLaunchKernelGGL(k_refine_fold, sgrid, sblock, 0, cx.stream, dh, p[nxt], cx.ctl,
                                    d, x);
                 LAUNCHCHK();
-                st = residual<float>(cx, x, r[0], &rw2, &rr2);
+                st = residual<float>(cx, bhat, x, r[0], &rw2, &rr2);
                 if (st != MAS_OK) return st;
                 k0 = 0;
             }
             info.rel_resid_true = std::sqrt(rw2) / bnorm;
             status = (rw2 <= tol2) ? MAS_OK : MAS_ENOTCONV;
-            if (pr.flag == FLAG_BREAK && status != MAS_OK && !reliable) {
+            if (pr.flag[0] == FLAG_BREAK && status != MAS_OK && !reliable) {
                 status = MAS_EBREAKDOWN;
                 break;
             }
@@ -809,12 +862,183 @@ static int solve_core(const mas_op *op, const double *src, int src_is_rhs, doubl
     return status;
 }
 
+// nrhs right-hand sides (contiguous, right-hand side h at rhs + h N) solved
+// together in double precision: one iteration kernel carries all of them and
+// each keeps its own CG scalars, stopping test and restarts.
+template <int NR>
+static int solve_multi_core(const mas_op *op, const double *rhs, double *x, const mas_pcg_opts &o,
+                            char *base, const WorkLayout &L, hipStream_t stream,
+                            mas_pcg_info *info) {
+    const auto t0 = std::chrono::steady_clock::now();
+    const Shape &s = op->s;
+    const int64_t n = s.n;
+    Ctx cx;
+    cx.op = op;
+    cx.stream = stream;
+    cx.ctl = reinterpret_cast<Ctl *>(base + L.ctl);
+    cx.partials = reinterpret_cast<double *>(base + L.partials);
+    cx.timing = o.sample_timing != 0;
+    const Dims d = s.dims();
+    const dim3 sgrid = s.simple_grid(), sblock(kWave, kSimpleJ);
+    const double *const c[3] = {op->c64[0], op->c64[1], op->c64[2]};
+
+    RhsSet<double> v;
+    v.n = NR;
+    double *bhat[NR];
+    double bnorm[NR], rw2[NR];
+    bool done[NR];
+    int kernels[NR];  // iteration kernels that did work for each right-hand side
+    for (int h = 0; h < NR; ++h) {
+        info[h] = mas_pcg_info{};
+        bhat[h] = reinterpret_cast<double *>(base + L.bhat[h]);
+        for (int t = 0; t < 2; ++t) {
+            v.r[h][t] = reinterpret_cast<double *>(base + L.vec[h][t]);
+            v.p[h][t] = reinterpret_cast<double *>(base + L.vec[h][2 + t]);
+            v.q[h][t] = reinterpret_cast<double *>(base + L.vec[h][4 + t]);
+        }
+        v.x[h] = x + h * n;
+        kernels[h] = 0;
+        // b^ = W^-1 V rhs, x^ = W x0 or 0, ||b||^2
+        hipLaunchKernelGGL(k_setup, sgrid, sblock, 0, stream, rhs + h * n, 1, op->w, op->geo, d,
+                           bhat[h], v.x[h], o.use_x0 ? 1 : 0, cx.partials);
+        LAUNCHCHK();
+        double b2 = 0.0;
+        int st = reduce_n(cx, 1, &b2);
+        if (st != MAS_OK) return st;
+        bnorm[h] = std::sqrt(b2);
+        info[h].bnorm = bnorm[h];
+        if (!std::isfinite(bnorm[h]))
+            return fail(MAS_EINVAL, "right-hand side %d is not finite", h);
+        v.tol2[h] = (o.rtol * bnorm[h]) * (o.rtol * bnorm[h]);
+        done[h] = false;
+        info[h].status = MAS_ENOTCONV;
+        if (bnorm[h] == 0.0) {
+            hipLaunchKernelGGL(k_fill<double>, sgrid, sblock, 0, stream, v.x[h], d, 0.0);
+            LAUNCHCHK();
+            done[h] = true;
+            info[h].status = MAS_OK;
+            continue;
+        }
+        st = residual<double>(cx, bhat[h], v.x[h], v.r[h][0], &rw2[h]);
+        if (st != MAS_OK) return st;
+        info[h].rel_resid_true = info[h].rel_resid_recursive = std::sqrt(rw2[h]) / bnorm[h];
+        if (rw2[h] <= v.tol2[h]) {
+            done[h] = true;
+            info[h].status = MAS_OK;
+        }
+    }
+    int iter0 = 0;
+    int restarts = 0;
+    for (;;) {
+        bool any = false;
+        // as in the single solve, at most max_iters + 1 iteration kernels
+        // (the first of a run only forms q = A p) and iters = kernels - 1
+        for (int h = 0; h < NR; ++h) {
+            v.active[h] = !done[h] && kernels[h] <= o.max_iters;
+            v.max_iter[h] = iter0 + (o.max_iters - kernels[h]);
+            any = any || v.active[h];
+        }
+        if (!any) break;
+        PcgResult pr{};
+        int st = run_pcg<double, NR>(cx, v, c, 0, iter0, o.check_every, false, 0.0, &pr);
+        if (st != MAS_OK) return st;
+        int last = iter0;
+        for (int h = 0; h < NR; ++h)
+            if (v.active[h]) last = std::max(last, pr.last_iter[h]);
+        for (int h = 0; h < NR; ++h) {
+            if (!v.active[h]) continue;
+            kernels[h] += pr.last_iter[h] - iter0 + 1;
+            info[h].iters = kernels[h] - 1;
+            Ctl hc;
+            st = read_ctl(cx, &hc, h);
+            if (st != MAS_OK) return st;
+            info[h].rel_resid_recursive = std::sqrt(hc.rw) / bnorm[h];
+            // true residual of x_k into the buffer the next run starts from
+            st = residual<double>(cx, bhat[h], v.x[h], v.r[h][(last + 1) & 1], &rw2[h]);
+            if (st != MAS_OK) return st;
+            info[h].rel_resid_true = std::sqrt(rw2[h]) / bnorm[h];
+            if (rw2[h] <= v.tol2[h]) {
+                done[h] = true;
+                info[h].status = MAS_OK;
+            } else if (pr.flag[h] == FLAG_BREAK) {
+                done[h] = true;
+                info[h].status = MAS_EBREAKDOWN;
+            } else if (pr.flag[h] != FLAG_CONV || restarts >= o.max_restarts) {
+                done[h] = true;
+                info[h].status = MAS_ENOTCONV;
+            } else {
+                info[h].restarts++;
+            }
+        }
+        // the sampled iteration kernels carried every right-hand side
+        mas_pcg_info tinfo{};
+        timing_summary(cx, last, &tinfo);
+        for (int h = 0; h < NR; ++h) {
+            const double prev = info[h].iter_kernel_us * info[h].iter_kernel_samples;
+            info[h].iter_kernel_samples += tinfo.iter_kernel_samples;
+            if (info[h].iter_kernel_samples > 0)
+                info[h].iter_kernel_us =
+                    (prev + tinfo.iter_kernel_us * tinfo.iter_kernel_samples) /
+                    info[h].iter_kernel_samples;
+        }
+        ++restarts;
+        iter0 = last + 1;
+    }
+    int status = MAS_OK;
+    for (int h = 0; h < NR; ++h) {
+        hipLaunchKernelGGL(k_unscale, sgrid, sblock, 0, stream, op->w, d, v.x[h]);
+        LAUNCHCHK();
+        if (info[h].status == MAS_EBREAKDOWN) status = MAS_EBREAKDOWN;
+        else if (info[h].status == MAS_ENOTCONV && status == MAS_OK) status = MAS_ENOTCONV;
+    }
+    HIPCHK(hipStreamSynchronize(stream));
+    const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    for (int h = 0; h < NR; ++h) info[h].seconds = secs;
+    return status;
+}
+
 }  // namespace
 
 extern "C" int mas_pcg_solve(const mas_op *op, const double *rhs, double *x, const mas_pcg_opts *o,
                              void *work, int64_t work_bytes, void *hip_stream, mas_pcg_info *info) {
     g_last_error.clear();
     return solve_core(op, rhs, 1, x, o, work, work_bytes, hip_stream, info);
+}
+
+extern "C" int mas_pcg_solve_multi(const mas_op *op, int32_t nrhs, const double *rhs, double *x,
+                                   const mas_pcg_opts *o_in, void *work, int64_t work_bytes,
+                                   void *hip_stream, mas_pcg_info *info) {
+    g_last_error.clear();
+    if (!op || !rhs || !x || !work)
+        return fail(MAS_EINVAL, "op, rhs, x and work must not be NULL");
+    if (nrhs < 1 || nrhs > kMaxRhs) return fail(MAS_EINVAL, "nrhs must lie in [1, %d]", kMaxRhs);
+    mas_pcg_opts o;
+    mas_pcg_default_opts(&o);
+    if (o_in) o = *o_in;
+    if (o.precision != MAS_FP64)
+        return fail(MAS_EINVAL, "solves of several right-hand sides are double precision only");
+    int st = check_opts(op, &o);
+    if (st != MAS_OK) return st;
+    if (reinterpret_cast<uintptr_t>(work) & 255)
+        return fail(MAS_EINVAL, "work must be 256-byte aligned");
+    const WorkLayout L = work_layout(op->s, MAS_FP64, nrhs);
+    if (work_bytes < L.total)
+        return fail(MAS_ENOMEM, "workspace too small: %lld < %lld bytes", (long long)work_bytes,
+                    (long long)L.total);
+    mas_pcg_info local[kMaxRhs];
+    char *base = static_cast<char *>(work);
+    hipStream_t stream = as_stream(hip_stream);
+    switch (nrhs) {
+        case 1: st = solve_multi_core<1>(op, rhs, x, o, base, L, stream, local); break;
+        case 2: st = solve_multi_core<2>(op, rhs, x, o, base, L, stream, local); break;
+        case 3: st = solve_multi_core<3>(op, rhs, x, o, base, L, stream, local); break;
+        default: st = solve_multi_core<4>(op, rhs, x, o, base, L, stream, local); break;
+    }
+    if (info)
+        for (int h = 0; h < nrhs; ++h) info[h] = local[h];
+    if (st == MAS_ENOTCONV) fail(st, "tolerance not reached for at least one right-hand side");
+    if (st == MAS_EBREAKDOWN) fail(st, "PCG breakdown in at least one right-hand side");
+    return st;
 }
 
 extern "C" int mas_pcg_solve_adjoint(const mas_op *op, const double *x, const double *gx,

@@ -9,6 +9,7 @@ Nothing here computes on tensors.
     x, info = op.solve(rhs)                              # mas_pcg_solve
     lam, g_nu, g_rhs, info = op.adjoint(x, gx)           # mas_pcg_solve_adjoint
     u1, info = op.sts_step(u0)                           # mas_sts_step (explicit RKL2)
+    X, infos = op.solve_multi(RHS)                       # mas_pcg_solve_multi (RHS: (m, nr, nt, np))
     x = solve(nu, rhs, grid, dt)                          # differentiable (MasSolve)
 """
 from __future__ import annotations
@@ -172,6 +173,36 @@ class Operator:
         if st == abi.MAS_ENOTCONV:
             warnings.warn(f"mas_pcg_solve did not converge: {info.as_dict()}")
         return x, info.as_dict()
+
+    def solve_multi(self, rhs: torch.Tensor, opts=None, x0: torch.Tensor | None = None,
+                    out: torch.Tensor | None = None, allow_notconv=True):
+        """X[h] = A^-1 (V .* rhs[h]) for the m = rhs.shape[0] right-hand sides
+        (1..4) in one double-precision solve.  Returns (X, [info dict per h])."""
+        m = int(rhs.shape[0])
+        shape = (m,) + tuple(self.grid.shape)
+        _check_vec(rhs, shape, "rhs")
+        opts = opts if opts is not None else make_opts()
+        x = out if out is not None else torch.empty_like(rhs)
+        _check_vec(x, shape, "out")
+        if x0 is not None:
+            x.copy_(x0)
+            opts.use_x0 = 1
+        lib = abi.load()
+        nbytes = int(lib.mas_pcg_multi_workspace_bytes(self._h, m))
+        abi.check(nbytes if nbytes < 0 else 0, "mas_pcg_multi_workspace_bytes")
+        key = ("multi", m)
+        buf = self._work.get(key)
+        if buf is None or buf.numel() < nbytes:
+            buf = _device_bytes(nbytes, self.device)
+            self._work[key] = buf
+        infos = (abi.mas_pcg_info * m)()
+        with torch.cuda.device(self.device):
+            st = lib.mas_pcg_solve_multi(self._h, m, rhs.data_ptr(), x.data_ptr(), ctypes.byref(opts),
+                                         buf.data_ptr(), nbytes, _stream(self.device), infos)
+        abi.check(st, "mas_pcg_solve_multi", allow_notconv=allow_notconv)
+        if st == abi.MAS_ENOTCONV:
+            warnings.warn("mas_pcg_solve_multi: a right-hand side did not converge")
+        return x, [i.as_dict() for i in infos]
 
     def adjoint(self, x: torch.Tensor, gx: torch.Tensor, opts=None, allow_notconv=True):
         """(lambda, dL/dnu, dL/drhs, info) for dL/dx = gx at the solution x."""

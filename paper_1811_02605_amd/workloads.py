@@ -245,6 +245,19 @@ def right_hand_side(cfg: Config) -> np.ndarray:
     return rhs
 
 
+def component_rhs(cfg: Config, m: int) -> np.ndarray:
+    """m right-hand sides (the components of a vector field), shape (m, nr, nt, np):
+    component 0 is right_hand_side(cfg); component h >= 1 uses the same recipe
+    with seed 500 + 10 seed_index + h."""
+    out = np.empty((m,) + cfg.shape)
+    out[0] = right_hand_side(cfg)
+    for h in range(1, m):
+        rng = np.random.default_rng(500 + 10 * cfg.seed_index + h)
+        u = rng.standard_normal(cfg.n).reshape(cfg.shape)
+        out[h] = jacobi_smooth(u) if cfg.smooth_rhs else u
+    return out
+
+
 def target_viscosity(nu: np.ndarray, seed: int = 303, rel: float = 0.05) -> np.ndarray:
     """nu * (1 + rel xi), xi ~ N(0,1) clipped to [-4, 4]."""
     rng = np.random.default_rng(seed)

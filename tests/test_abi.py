@@ -107,6 +107,15 @@ def test_null_operator_and_bad_copy_are_rejected():
     assert lib.mas_op_destroy(None) is None
 
 
+def test_multi_rhs_argument_checks():
+    lib = abi.load()
+    o = abi.default_opts()
+    infos = (abi.mas_pcg_info * 4)()
+    assert lib.mas_pcg_multi_workspace_bytes(None, 3) == abi.MAS_EINVAL
+    assert lib.mas_pcg_solve_multi(None, 3, 8, 8, ctypes.byref(o), 256, 1 << 20, None,
+                                   infos) == abi.MAS_EINVAL
+
+
 def test_sts_defaults_and_null_operator():
     lib = abi.load()
     o = abi.mas_sts_opts(7, 7)

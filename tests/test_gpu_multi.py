@@ -1,0 +1,122 @@
+"""GPU parity of the solve with several right-hand sides (mas_pcg_solve_multi):
+each component against the FP64 oracle (its residual of the GPU solution and
+the error against its own tight solution), against the single-right-hand-side
+solve of the same component, independent stopping of the components, and the
+error paths."""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+from gpu_util import DEV, gpu_operator, oracle_operator, problem, rel, to_dev, to_host
+from paper_1811_02605_amd import _abi as abi
+from paper_1811_02605_amd import solver as S
+from paper_1811_02605_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+SHAPES = [(4, 4, 8), (5, 7, 13), (3, 9, 70), (33, 17, 129), (65, 8, 64), (1, 3, 2), (6, 3, 1),
+          (9, 16, 32)]
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _rhs(p, m):
+    return W.component_rhs(p.cfg, m)
+
+
+@pytest.mark.parametrize("m", [2, 3, 4])
+@pytest.mark.parametrize("shape", SHAPES + ["c0"])
+def test_components_match_oracle(shape, m):
+    p = problem(shape, (0, 1))
+    _, op = gpu_operator(p)
+    ora = oracle_operator(p)
+    B = _rhs(p, m)
+    X, infos = op.solve_multi(to_dev(B), S.make_opts(rtol=1e-10), allow_notconv=False)
+    X = to_host(X)
+    for h in range(m):
+        b = ora.rhs_to_b(B[h])
+        res = ora.rel_residual(b, X[h])
+        assert infos[h]["status"] == abi.MAS_OK and res <= 1e-10, (h, res, infos[h])
+        xo = ora.pcg(b, tol=1e-13)[0]
+        assert rel(X[h], xo) <= 1e-6
+
+
+@pytest.mark.parametrize("m", [1, 3])
+@pytest.mark.parametrize("shape", [(33, 17, 129), (9, 16, 32), "c0"])
+def test_components_match_single_solves(shape, m):
+    """The per-component iterations are those of the single solve: same
+    iteration counts, solutions equal to rounding."""
+    p = problem(shape, (0, 0))
+    _, op = gpu_operator(p)
+    B = _rhs(p, m)
+    X, infos = op.solve_multi(to_dev(B), S.make_opts(rtol=1e-10), allow_notconv=False)
+    for h in range(m):
+        x1, i1 = op.solve(to_dev(B[h]), S.make_opts(rtol=1e-10), allow_notconv=False)
+        assert infos[h]["iters"] == i1["iters"], (h, infos[h], i1)
+        assert rel(to_host(X[h]), to_host(x1)) <= 1e-13
+        say(f"{shape} m={m} h={h}: {i1['iters']} iterations, bitwise equal: "
+            f"{bool(torch.equal(X[h], x1))}")
+
+
+def test_independent_stopping():
+    """A zero component, a component already solved (warm start) and two hard
+    ones of very different scale: each stops on its own test, the finished
+    ones are left untouched."""
+    p = problem((33, 17, 129), (0, 0))
+    _, op = gpu_operator(p)
+    ora = oracle_operator(p)
+    B = _rhs(p, 4)
+    B[0] = 0.0
+    B[3] *= 1e-9
+    x_sol, _ = op.solve(to_dev(B[2]), S.make_opts(rtol=1e-12), allow_notconv=False)
+    X0 = np.zeros_like(B)
+    X0[2] = to_host(x_sol)
+    X, infos = op.solve_multi(to_dev(B), S.make_opts(rtol=1e-10), x0=to_dev(X0),
+                              allow_notconv=False)
+    X = to_host(X)
+    assert np.all(X[0] == 0.0) and infos[0]["iters"] == 0 and infos[0]["status"] == abi.MAS_OK
+    # the warm start is scaled by w and back: equal to rounding
+    assert infos[2]["iters"] == 0 and rel(X[2], X0[2]) <= 1e-15
+    for h in (1, 3):
+        assert infos[h]["iters"] > 0
+        assert ora.rel_residual(ora.rhs_to_b(B[h]), X[h]) <= 1e-10
+
+
+def test_deterministic_and_timing():
+    p = problem("c0", (0, 0))
+    _, op = gpu_operator(p)
+    B = to_dev(_rhs(p, 3))
+    a, ia = op.solve_multi(B, S.make_opts(sample_timing=1))
+    b, _ = op.solve_multi(B)
+    assert torch.equal(a, b)
+    assert all(i["iter_kernel_samples"] > 0 and i["iter_kernel_us"] > 0 for i in ia)
+
+
+def test_error_paths():
+    p = problem((9, 16, 32), (0, 0))
+    _, op = gpu_operator(p, "fp32_refined")
+    B = to_dev(_rhs(p, 3))
+    with pytest.raises(abi.MasError, match="double precision"):
+        op.solve_multi(B, S.make_opts(precision="fp32_refined"))
+    lib = abi.load()
+    assert lib.mas_pcg_multi_workspace_bytes(op.handle, 5) == abi.MAS_EINVAL
+    assert lib.mas_pcg_multi_workspace_bytes(op.handle, 0) == abi.MAS_EINVAL
+    need = int(lib.mas_pcg_multi_workspace_bytes(op.handle, 3))
+    one = int(lib.mas_pcg_multi_workspace_bytes(op.handle, 1))
+    assert need > 2.9 * (one - 4096)
+    x = torch.empty_like(B)
+    st = lib.mas_pcg_solve_multi(op.handle, 3, B.data_ptr(), x.data_ptr(), None, x.data_ptr(),
+                                 need - 256, None, None)
+    assert st == abi.MAS_ENOMEM
+    st = lib.mas_pcg_solve_multi(op.handle, 5, B.data_ptr(), x.data_ptr(), None, x.data_ptr(),
+                                 need, None, None)
+    assert st == abi.MAS_EINVAL
+    # too few iterations: ENOTCONV with the last iterates, per-component status
+    _, op64 = gpu_operator(p)
+    X, infos = op64.solve_multi(B, S.make_opts(max_iters=3, max_restarts=0))
+    assert all(i["status"] == abi.MAS_ENOTCONV for i in infos)

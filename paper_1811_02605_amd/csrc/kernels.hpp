@@ -280,6 +280,9 @@ __device__ inline void bst(__amdgpu_buffer_rsrc_t r, uint32_t off, const VecT<T,
 #ifndef MAS_ITER_DEFER
 #define MAS_ITER_DEFER 1
 #endif
+#ifndef MAS_ITER_DEFER_MAX_NR
+#define MAS_ITER_DEFER_MAX_NR 1
+#endif
 #if MAS_ITER_NT
 #define MAS_LDS_ ldv_nt
 #define MAS_STS_ stv_nt
@@ -374,8 +377,21 @@ void k_pcg_iter(IterArgs<T> a) {
     const int i1 = min(i0 + a.ti, nr);
     const bool up = (it & 1) == 0;
 
-    // own cells; inactive lanes read cell 0 of the plane and discard it
-    const int64_t col = act ? (int64_t)j * np + k0 + lp * V : 0;
+    // phi neighbours of the segment (periodic): the cell left of k0 and the
+    // cell right of the segment end
+    const int64_t colL = (int64_t)j * np + ((k0 == 0) ? np - 1 : k0 - 1);
+    const int64_t colR = (int64_t)j * np + ((k0 + nseg == np) ? 0 : k0 + nseg);
+    // In a short segment the first lane past its end stands in for the cell
+    // right of it: it loads that cell's r, q, p as if they were its own, and
+    // the last active lane receives p_k there through the phi shuffle.  In a
+    // full segment the row's last lane loads that cell in the same
+    // instruction as lane 0 loads the cell left of the segment.
+    const bool pseudoR = rowok && nvl < W && lp == nvl;
+    const bool eL = rowok && lp == 0;
+    const bool eR = rowok && nvl == W && lp == W - 1;
+
+    // own cells; inactive lanes read nothing (out-of-range offsets)
+    const int64_t col = act ? (int64_t)j * np + k0 + lp * V : (pseudoR ? colR : 0);
     const bool hasU = act && j > 0, hasD = act && j < nt - 1;
     // rows j-1 / j+1 are loaded only by the wave's first / last row
     const bool ldU = hasU && rr == 0, ldD = hasD && rr == RPW - 1;
@@ -383,12 +399,6 @@ void k_pcg_iter(IterArgs<T> a) {
     const int64_t colD = ldD ? col + np : 0;
     const int srcU = (rr > 0) ? lane - W : lane;
     const int srcD = (rr < RPW - 1) ? lane + W : lane;
-    // segment edges: lane lp = 0 needs the cell left of k0, lane lp = nvl-1
-    // the cell right of the segment end (periodic in phi)
-    const bool eL = rowok && lp == 0;
-    const bool eR = rowok && lp == nvl - 1;
-    const int64_t colL = eL ? (int64_t)j * np + ((k0 == 0) ? np - 1 : k0 - 1) : 0;
-    const int64_t colR = eR ? (int64_t)j * np + ((k0 + nseg == np) ? 0 : k0 + nseg) : 0;
 
     double acc[NR * kNV];
 #pragma unroll
@@ -398,14 +408,13 @@ void k_pcg_iter(IterArgs<T> a) {
     for (int c = 0; c < NR; ++c) pn1[c] = rn1[c] = S1[c] = VT{};
     VecT<double, V> w1{};
     int64_t base1 = 0;
-#if MAS_ITER_DEFER
     // results of the previous step, stored only after this step's loads are
     // issued: the in-order vector-memory counter then never makes a load
-    // wait for a store to complete
+    // wait for a store to complete (costs 4 V registers per right-hand side)
+    constexpr bool kDefer = MAS_ITER_DEFER && NR <= MAS_ITER_DEFER_MAX_NR;
     VT st_r[NR], st_p[NR], st_x[NR], st_q[NR];
     bool st_own = false, st_q_do = false;
     uint32_t st_off = kOOB, st_qoff = kOOB;
-#endif
 
     // Every access goes through a range-checked buffer resource; a lane that
     // does not need an access uses an out-of-range offset (zeros in, stores
@@ -436,7 +445,7 @@ void k_pcg_iter(IterArgs<T> a) {
         const bool indom = (m >= 0) && (m < nr);
         const bool own = (m >= i0) && (m < i1);
         const int64_t base = (int64_t)(indom ? m : 0) * plane;
-        const bool vin = indom && act, vown = own && act;
+        const bool vin = indom && (act || pseudoR), vown = own && act;
         const uint32_t oc = vin ? (uint32_t)(base + col) * ES : kOOB;
         const uint32_t oo = vown ? (uint32_t)(base + col) * ES : kOOB;
         const uint32_t ocr = (vin && m < i1) ? oc : kOOB;
@@ -444,10 +453,16 @@ void k_pcg_iter(IterArgs<T> a) {
         const uint32_t oU = vU ? (uint32_t)(base + colU) * ES : kOOB;
         const uint32_t oD = vD ? (uint32_t)(base + colD) * ES : kOOB;
         const uint32_t oL = vL ? (uint32_t)(base + colL) * ES : kOOB;
-        const uint32_t oR = vR ? (uint32_t)(base + colR) * ES : kOOB;
+        const uint32_t oLR = vL ? oL : (vR ? (uint32_t)(base + colR) * ES : kOOB);
         // ---- loads of plane m, all issued before any use
-        VT r[NR], q[NR], p[NR], x[NR], rU[NR], qU[NR], pU[NR], rD[NR], qD[NR], pD[NR];
-        T lr[NR], lq[NR], lp_[NR], rr_[NR], rq_[NR], rp_[NR];
+        // With RPW >= 2 a lane needs row j-1 (first row of the wave) or row
+        // j+1 (last row), never both: one set of edge-row registers (E)
+        // serves both; with RPW = 1 the D set holds row j+1.
+        constexpr bool kSplitUD = RPW == 1;
+        constexpr int ND = kSplitUD ? NR : 1;
+        const uint32_t oE = kSplitUD ? oU : (vU ? oU : oD);
+        VT r[NR], q[NR], p[NR], x[NR], rE[NR], qE[NR], pE[NR], rD[ND], qD[ND], pD[ND];
+        T lr[NR], lq[NR], lp_[NR];
 #pragma unroll
         for (int c = 0; c < NR; ++c) {
             r[c] = bld<T, V>(Rr[c], oc);
@@ -463,37 +478,33 @@ void k_pcg_iter(IterArgs<T> a) {
         if (CHECK) w = bld<double, V>(Rw, vown ? (uint32_t)(base + col) * 8u : kOOB);
 #pragma unroll
         for (int c = 0; c < NR; ++c) {
-            rU[c] = bld<T, V>(Rr[c], oU);
-            qU[c] = bld<T, V>(Rq[c], oU);
-            pU[c] = bld<T, V>(Rp[c], oU);
+            rE[c] = bld<T, V>(Rr[c], oE);
+            qE[c] = bld<T, V>(Rq[c], oE);
+            pE[c] = bld<T, V>(Rp[c], oE);
         }
         const VT ctU = bld<T, V>(Rct, oU);
 #pragma unroll
         for (int c = 0; c < NR; ++c) {
-            rD[c] = bld<T, V>(Rr[c], oD);
-            qD[c] = bld<T, V>(Rq[c], oD);
-            pD[c] = bld<T, V>(Rp[c], oD);
-            lr[c] = bld<T, 1>(Rr[c], oL).v[0];
-            lq[c] = bld<T, 1>(Rq[c], oL).v[0];
-            lp_[c] = bld<T, 1>(Rp[c], oL).v[0];
+            if constexpr (kSplitUD) {
+                rD[c] = bld<T, V>(Rr[c], oD);
+                qD[c] = bld<T, V>(Rq[c], oD);
+                pD[c] = bld<T, V>(Rp[c], oD);
+            }
+            lr[c] = bld<T, 1>(Rr[c], oLR).v[0];
+            lq[c] = bld<T, 1>(Rq[c], oLR).v[0];
+            lp_[c] = bld<T, 1>(Rp[c], oLR).v[0];
         }
         const T lcp = bld<T, 1>(Rcp, oL).v[0];
-#pragma unroll
-        for (int c = 0; c < NR; ++c) {
-            rr_[c] = bld<T, 1>(Rr[c], oR).v[0];
-            rq_[c] = bld<T, 1>(Rq[c], oR).v[0];
-            rp_[c] = bld<T, 1>(Rp[c], oR).v[0];
-        }
-#if MAS_ITER_DEFER
         // ---- stores of the previous step
+        if constexpr (kDefer) {
 #pragma unroll
-        for (int c = 0; c < NR; ++c) {
-            bst<T, V, AN>(Rro[c], st_own ? st_off : kOOB, st_r[c]);
-            bst<T, V, AN>(Rpo[c], st_own ? st_off : kOOB, st_p[c]);
-            bst<T, V, AN>(Rx[c], st_own ? st_off : kOOB, st_x[c]);
-            bst<T, V, AN>(Rqo[c], st_q_do ? st_qoff : kOOB, st_q[c]);
+            for (int c = 0; c < NR; ++c) {
+                bst<T, V, AN>(Rro[c], st_own ? st_off : kOOB, st_r[c]);
+                bst<T, V, AN>(Rpo[c], st_own ? st_off : kOOB, st_p[c]);
+                bst<T, V, AN>(Rx[c], st_own ? st_off : kOOB, st_x[c]);
+                bst<T, V, AN>(Rqo[c], st_q_do ? st_qoff : kOOB, st_q[c]);
+            }
         }
-#endif
 #pragma unroll
         for (int e = 0; e < V; ++e) {
             if (!(vin && m < i1)) cr.v[e] = T(0);
@@ -529,22 +540,25 @@ void k_pcg_iter(IterArgs<T> a) {
                     const T sU = shfl_lane(pn.v[e], srcU);
                     const T sD = shfl_lane(pn.v[e], srcD);
                     const T sct = shfl_lane(ct.v[e], srcU);
-                    const T lU = (rU[c].v[e] - alpha[c] * qU[c].v[e]) + beta[c] * pU[c].v[e];
-                    const T lD = (rD[c].v[e] - alpha[c] * qD[c].v[e]) + beta[c] * pD[c].v[e];
+                    const T lU = (rE[c].v[e] - alpha[c] * qE[c].v[e]) + beta[c] * pE[c].v[e];
+                    T lD = lU;
+                    if constexpr (kSplitUD)
+                        lD = (rD[c].v[e] - alpha[c] * qD[c].v[e]) + beta[c] * pD[c].v[e];
                     pU_.v[e] = !hasU ? T(0) : (rr == 0 ? lU : sU);
                     pD_.v[e] = !hasD ? T(0) : (rr == RPW - 1 ? lD : sD);
                     ctU_.v[e] = !hasU ? T(0) : (rr == 0 ? ctU.v[e] : sct);
                 }
-                const T pl_edge = (lr[c] - alpha[c] * lq[c]) + beta[c] * lp_[c];
-                const T pr_edge = (rr_[c] - alpha[c] * rq_[c]) + beta[c] * rp_[c];
+                // p_k at the loaded edge cell (left for lane 0, right for
+                // the last lane of a full segment)
+                const T e_edge = (lr[c] - alpha[c] * lq[c]) + beta[c] * lp_[c];
                 T left0 = shfl_up1(pn.v[V - 1]);
                 T right0 = shfl_dn1(pn.v[0]);
                 T cpl0 = shfl_up1(cp.v[V - 1]);
                 if (lp == 0) {
-                    left0 = vL ? pl_edge : T(0);
+                    left0 = vL ? e_edge : T(0);
                     cpl0 = vL ? lcp : T(0);
                 }
-                if (lp == nvl - 1) right0 = vR ? pr_edge : T(0);
+                if (eR) right0 = vR ? e_edge : T(0);
 #pragma unroll
                 for (int e = 0; e < V; ++e) {
                     const T left = (e > 0) ? pn.v[e - 1] : left0;
@@ -574,27 +588,25 @@ void k_pcg_iter(IterArgs<T> a) {
                 }
             }
             // ---- stores
-#if MAS_ITER_DEFER
-            st_r[c] = rn;
-            st_p[c] = pn;
-            st_x[c] = xn;
-            st_q[c] = qv;
-#else
-            bst<T, V, AN>(Rro[c], oo, rn);
-            bst<T, V, AN>(Rpo[c], oo, pn);
-            bst<T, V, AN>(Rx[c], oo, xn);
-            bst<T, V, AN>(Rqo[c], oq, qv);
-#endif
+            if constexpr (kDefer) {
+                st_r[c] = rn;
+                st_p[c] = pn;
+                st_x[c] = xn;
+                st_q[c] = qv;
+            } else {
+                bst<T, V, AN>(Rro[c], oo, rn);
+                bst<T, V, AN>(Rpo[c], oo, pn);
+                bst<T, V, AN>(Rx[c], oo, xn);
+                bst<T, V, AN>(Rqo[c], oq, qv);
+            }
             pn1[c] = pn;
             rn1[c] = rn;
             S1[c] = S;
         }
-#if MAS_ITER_DEFER
         st_own = vown;
         st_off = oo;
         st_q_do = qdo;
         st_qoff = oq;
-#endif
 #if MAS_ITER_SYNC
         // keep the block's waves on the same plane so that the rows they
         // load for each other are requested together (L1/L2 reuse)
@@ -604,15 +616,15 @@ void k_pcg_iter(IterArgs<T> a) {
         if (CHECK) w1 = w;
         base1 = base;
     }
-#if MAS_ITER_DEFER
+    if constexpr (kDefer) {
 #pragma unroll
-    for (int c = 0; c < NR; ++c) {
-        bst<T, V, AN>(Rro[c], st_own ? st_off : kOOB, st_r[c]);
-        bst<T, V, AN>(Rpo[c], st_own ? st_off : kOOB, st_p[c]);
-        bst<T, V, AN>(Rx[c], st_own ? st_off : kOOB, st_x[c]);
-        bst<T, V, AN>(Rqo[c], st_q_do ? st_qoff : kOOB, st_q[c]);
+        for (int c = 0; c < NR; ++c) {
+            bst<T, V, AN>(Rro[c], st_own ? st_off : kOOB, st_r[c]);
+            bst<T, V, AN>(Rpo[c], st_own ? st_off : kOOB, st_p[c]);
+            bst<T, V, AN>(Rx[c], st_own ? st_off : kOOB, st_x[c]);
+            bst<T, V, AN>(Rqo[c], st_q_do ? st_qoff : kOOB, st_q[c]);
+        }
     }
-#endif
     __shared__ double sRed[WPB * NR * kNV];
     block_sum_store<NR * kNV>(acc, a.partials + (int64_t)L * NR * kNV, sRed);
 }

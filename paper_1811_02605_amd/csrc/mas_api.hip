@@ -11,6 +11,7 @@
 #include <cstring>
 #include <new>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "../../include/mas.h"
@@ -71,6 +72,10 @@ static inline int vec_width(int np) {
     constexpr int v = MAS_ITER_VEC / (int)sizeof(T) > 0 ? MAS_ITER_VEC / (int)sizeof(T) : 1;
     return (np % v == 0) ? v : 1;
 }
+
+#ifndef MAS_MULTI_VEC
+#define MAS_MULTI_VEC 1
+#endif
 
 static inline int64_t align256(int64_t v) { return (v + 255) & ~int64_t(255); }
 
@@ -530,7 +535,8 @@ static int run_pcg(Ctx &cx, const RhsSet<T> &v, const T *const c[3], int mode, i
     a.partials = cx.partials;
     a.ctl = cx.ctl;
     a.d = s.dims();
-    const int V = vec_width<T>(s.np);
+    // several right-hand sides: V = 1 unless MAS_MULTI_VEC (register pressure)
+    const int V = (NR > 1 && !MAS_MULTI_VEC) ? 1 : vec_width<T>(s.np);
     a.tiles_i = s.tiles_i();
     a.tiles_k = s.tiles_k(V);
     a.tiles_j = s.tiles_j();
@@ -1159,12 +1165,26 @@ static int sts_launch(const mas_op *op, hipStream_t stream, const double *X, con
     if (nblk > INT32_MAX) return fail(MAS_EINVAL, "grid too large for the stage kernel");
     StsArgs args{X, op->nu, Z, L0, Y0, out, a, b, g, m * op->dt, op->geo, s.dims(),
                  (int)tiles_i, (int)tiles_k, (int)tiles_j, kStsTI, (int)nblk};
+    const int in = (Z ? kStsZ : 0) | (L0 ? kStsL0 : 0) | (Y0 ? kStsY0 : 0);
+    const dim3 grid((unsigned)nblk), block(kWave * kStsWPB);
+    auto go = [&](auto vtag) {
+        constexpr int VV = decltype(vtag)::value;
+        switch (in) {
+            case 0: hipLaunchKernelGGL((k_sts_stage<kStsWPB, kStsRPW, VV, 0>), grid, block, 0, stream, args); break;
+            case kStsY0: hipLaunchKernelGGL((k_sts_stage<kStsWPB, kStsRPW, VV, kStsY0>), grid, block, 0, stream, args); break;
+            case kStsL0: hipLaunchKernelGGL((k_sts_stage<kStsWPB, kStsRPW, VV, kStsL0>), grid, block, 0, stream, args); break;
+            case kStsL0 | kStsY0: hipLaunchKernelGGL((k_sts_stage<kStsWPB, kStsRPW, VV, kStsL0 | kStsY0>), grid, block, 0, stream, args); break;
+            case kStsZ | kStsL0: hipLaunchKernelGGL((k_sts_stage<kStsWPB, kStsRPW, VV, kStsZ | kStsL0>), grid, block, 0, stream, args); break;
+            default: hipLaunchKernelGGL((k_sts_stage<kStsWPB, kStsRPW, VV, kStsZ | kStsL0 | kStsY0>), grid, block, 0, stream, args); break;
+        }
+    };
+    if (in != 0 && in != kStsY0 && in != kStsL0 && in != (kStsL0 | kStsY0) &&
+        in != (kStsZ | kStsL0) && in != (kStsZ | kStsL0 | kStsY0))
+        return fail(MAS_EINVAL, "internal: unsupported stage inputs %d", in);
     if (v == 2)
-        hipLaunchKernelGGL((k_sts_stage<kStsWPB, kStsRPW, 2>), dim3((unsigned)nblk),
-                           dim3(kWave * kStsWPB), 0, stream, args);
+        go(std::integral_constant<int, 2>{});
     else
-        hipLaunchKernelGGL((k_sts_stage<kStsWPB, kStsRPW, 1>), dim3((unsigned)nblk),
-                           dim3(kWave * kStsWPB), 0, stream, args);
+        go(std::integral_constant<int, 1>{});
     LAUNCHCHK();
     return MAS_OK;
 }

@@ -48,7 +48,7 @@ namespace mas {
 #endif
 
 struct StsArgs {
-    const double *X, *nu, *Z, *L0, *Y0;  // Z, L0, Y0 may be null
+    const double *X, *nu, *Z, *L0, *Y0;  // Z, L0, Y0: read only when the kernel's IN mask says so
     double *out;                          // may alias Z or Y0 (same cell read first)
     double a, b, g, mdt;                  // mdt = m * dt
     Geo geo;
@@ -56,11 +56,15 @@ struct StsArgs {
     int tiles_i, tiles_k, tiles_j, ti, nblk;
 };
 
-template <int WPB, int RPW, int V>
+// Inputs a stage reads besides X and nu (template mask).
+constexpr int kStsZ = 1, kStsL0 = 2, kStsY0 = 4;
+
+template <int WPB, int RPW, int V, int IN>
 __global__ __launch_bounds__(kWave *WPB) void k_sts_stage(StsArgs a) {
     static_assert(kWave % RPW == 0, "rows per wave");
     constexpr int W = kWave / RPW;  // lanes per row
     constexpr int SEG = W * V;
+    constexpr bool HZ = IN & kStsZ, HL = IN & kStsL0, HY = IN & kStsY0;
     using VD = VecT<double, V>;
 
     const int nr = a.d.nr, nt = a.d.nt, np = a.d.np;
@@ -86,15 +90,25 @@ __global__ __launch_bounds__(kWave *WPB) void k_sts_stage(StsArgs a) {
     const int dir = up ? 1 : -1;
     const int first = up ? i0 : i1 - 1;
 
-    const int64_t col = act ? (int64_t)j * np + k0 + lp * V : 0;
+    // phi neighbours of the segment (periodic).  In a short segment the first
+    // lane past its end loads the cell right of it as if it were its own
+    // (the last active lane takes it through the phi shuffle); in a full
+    // segment the row's last lane loads it in the same instruction as lane 0
+    // loads the cell left of the segment.
+    const int64_t colL = (int64_t)j * np + ((k0 == 0) ? np - 1 : k0 - 1);
+    const int64_t colR = (int64_t)j * np + ((k0 + nseg == np) ? 0 : k0 + nseg);
+    const bool pseudoR = rowok && nvl < W && lp == nvl;
+    const bool eL = act && lp == 0;
+    const bool eR = act && nvl == W && lp == W - 1;
+    const int64_t col = act ? (int64_t)j * np + k0 + lp * V : (pseudoR ? colR : 0);
+    const bool ldo = act || pseudoR;
+    // theta neighbours: with RPW >= 2 the wave's first row loads row j-1 and
+    // its last row row j+1 (one set of registers, never both in one lane);
+    // the rows in between come from lane shuffles
     const bool ldU = act && j > 0 && rr == 0;
     const bool ldD = act && j < nt - 1 && rr == RPW - 1;
     const int srcU = (rr > 0) ? lane - W : lane;
     const int srcD = (rr < RPW - 1) ? lane + W : lane;
-    const bool eL = act && lp == 0;
-    const bool eR = act && lp == nvl - 1;
-    const int64_t colL = (int64_t)j * np + ((k0 == 0) ? np - 1 : k0 - 1);
-    const int64_t colR = (int64_t)j * np + ((k0 + nseg == np) ? 0 : k0 + nseg);
 
     // per-row geometry: half the theta-face factors (the 1/2 of the face mean)
     const int jj = rowok ? j : 0;
@@ -106,11 +120,11 @@ __global__ __launch_bounds__(kWave *WPB) void k_sts_stage(StsArgs a) {
     constexpr uint32_t ES = sizeof(double);
     const uint32_t nbytes = (uint32_t)(a.d.n * (int64_t)ES);
     const auto RX = make_rsrc(a.X, nbytes), RN = make_rsrc(a.nu, nbytes),
-               RZ = make_rsrc(a.Z, a.Z ? nbytes : 0u), RL = make_rsrc(a.L0, a.L0 ? nbytes : 0u),
-               RY = make_rsrc(a.Y0, a.Y0 ? nbytes : 0u), RO = make_rsrc(a.out, nbytes);
+               RZ = make_rsrc(a.Z, HZ ? nbytes : 0u), RL = make_rsrc(a.L0, HL ? nbytes : 0u),
+               RY = make_rsrc(a.Y0, HY ? nbytes : 0u), RO = make_rsrc(a.out, nbytes);
 
     auto own_off = [&](int m) -> uint32_t {
-        return (act && m >= 0 && m < nr) ? (uint32_t)((int64_t)m * plane + col) * ES : kOOB;
+        return (ldo && m >= 0 && m < nr) ? (uint32_t)((int64_t)m * plane + col) * ES : kOOB;
     };
     // planes m - dir (behind) and m (current) of the first step
     VD Xb = bld<double, V, MAS_STS_AUX_XN>(RX, own_off(first - dir));
@@ -125,24 +139,28 @@ __global__ __launch_bounds__(kWave *WPB) void k_sts_stage(StsArgs a) {
         const int m = first + s * dir;
         const int64_t base = (int64_t)m * plane;
         const uint32_t oo = act ? (uint32_t)(base + col) * ES : kOOB;
-        const uint32_t oU = ldU ? (uint32_t)(base + col - np) * ES : kOOB;
+        const uint32_t oE = ldU ? (uint32_t)(base + col - np) * ES
+                                : (ldD ? (uint32_t)(base + col + np) * ES : kOOB);
         const uint32_t oD = ldD ? (uint32_t)(base + col + np) * ES : kOOB;
-        const uint32_t oL = eL ? (uint32_t)(base + colL) * ES : kOOB;
-        const uint32_t oR = eR ? (uint32_t)(base + colR) * ES : kOOB;
+        const uint32_t oLR = eL ? (uint32_t)(base + colL) * ES
+                                : (eR ? (uint32_t)(base + colR) * ES : kOOB);
         // ---- loads: plane m + dir (ahead) and the rest of plane m
         const VD Xa = bld<double, V, MAS_STS_AUX_XN>(RX, own_off(m + dir));
         const VD Na = bld<double, V, MAS_STS_AUX_XN>(RN, own_off(m + dir));
-        const VD XU = bld<double, V, MAS_STS_AUX_XN>(RX, oU);
-        const VD NU = bld<double, V, MAS_STS_AUX_XN>(RN, oU);
-        const VD XD = bld<double, V, MAS_STS_AUX_XN>(RX, oD);
-        const VD ND = bld<double, V, MAS_STS_AUX_XN>(RN, oD);
-        const double XL = bld<double, 1>(RX, oL).v[0];
-        const double NL = bld<double, 1>(RN, oL).v[0];
-        const double XR = bld<double, 1>(RX, oR).v[0];
-        const double NR = bld<double, 1>(RN, oR).v[0];
-        const VD Zv = bld<double, V, MAS_STS_AUX_ZL>(RZ, oo);
-        const VD Lv = bld<double, V, MAS_STS_AUX_ZL>(RL, oo);
-        const VD Yv = bld<double, V, MAS_STS_AUX_ZL>(RY, oo);
+        // RPW = 1: E holds row j-1, D row j+1; RPW >= 2: E holds whichever the lane needs
+        const VD XE = bld<double, V, MAS_STS_AUX_XN>(RX, RPW == 1 ? (ldU ? oE : kOOB) : oE);
+        const VD NE = bld<double, V, MAS_STS_AUX_XN>(RN, RPW == 1 ? (ldU ? oE : kOOB) : oE);
+        VD XD{}, ND{};
+        if constexpr (RPW == 1) {
+            XD = bld<double, V, MAS_STS_AUX_XN>(RX, oD);
+            ND = bld<double, V, MAS_STS_AUX_XN>(RN, oD);
+        }
+        const double XS = bld<double, 1>(RX, oLR).v[0];
+        const double NS = bld<double, 1>(RN, oLR).v[0];
+        VD Zv{}, Lv{}, Yv{};
+        if constexpr (HZ) Zv = bld<double, V, MAS_STS_AUX_ZL>(RZ, oo);
+        if constexpr (HL) Lv = bld<double, V, MAS_STS_AUX_ZL>(RL, oo);
+        if constexpr (HY) Yv = bld<double, V, MAS_STS_AUX_ZL>(RY, oo);
         // ---- store of the previous step (issued after this step's loads)
         bst<double, V, MAS_STS_AUX_ST>(RO, st_off, st);
 
@@ -164,12 +182,19 @@ __global__ __launch_bounds__(kWave *WPB) void k_sts_stage(StsArgs a) {
             const double xc = Xc.v[e], nc = Nc.v[e];
             const double sxu = shfl_lane(xc, srcU), snu = shfl_lane(nc, srcU);
             const double sxd = shfl_lane(xc, srcD), snd = shfl_lane(nc, srcD);
-            const double xu = (rr == 0) ? XU.v[e] : sxu, nu_u = (rr == 0) ? NU.v[e] : snu;
-            const double xd = (rr == RPW - 1) ? XD.v[e] : sxd, nu_d = (rr == RPW - 1) ? ND.v[e] : snd;
-            const double xl = (e > 0) ? Xc.v[e - 1] : ((lp == 0) ? XL : xl0);
-            const double nl = (e > 0) ? Nc.v[e - 1] : ((lp == 0) ? NL : nl0);
-            const double xr = (e < V - 1) ? Xc.v[e + 1] : ((lp == nvl - 1) ? XR : xr0);
-            const double nrr = (e < V - 1) ? Nc.v[e + 1] : ((lp == nvl - 1) ? NR : nr0);
+            const double xu = (rr == 0) ? XE.v[e] : sxu, nu_u = (rr == 0) ? NE.v[e] : snu;
+            double xd, nu_d;
+            if constexpr (RPW == 1) {
+                xd = XD.v[e];
+                nu_d = ND.v[e];
+            } else {
+                xd = (rr == RPW - 1) ? XE.v[e] : sxd;
+                nu_d = (rr == RPW - 1) ? NE.v[e] : snd;
+            }
+            const double xl = (e > 0) ? Xc.v[e - 1] : ((lp == 0) ? XS : xl0);
+            const double nl = (e > 0) ? Nc.v[e - 1] : ((lp == 0) ? NS : nl0);
+            const double xr = (e < V - 1) ? Xc.v[e + 1] : (eR ? XS : xr0);
+            const double nrr = (e < V - 1) ? Nc.v[e + 1] : (eR ? NS : nr0);
             double f = hRp * (nc + Np.v[e]) * (xc - Xp.v[e]);
             f += hRm * (nc + Nm.v[e]) * (xc - Xm.v[e]);
             f += gw * nc * xc;

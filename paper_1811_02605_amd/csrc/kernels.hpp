@@ -124,6 +124,11 @@ struct IterArgs {
     const T *r_in[kMaxRhs], *p_in[kMaxRhs], *q_in[kMaxRhs];
     T *r_out[kMaxRhs], *p_out[kMaxRhs], *q_out[kMaxRhs];
     T *x[kMaxRhs];
+    // Segment-edge records [r, p, cp, q] (see k_pcg_iter): written by every
+    // iteration kernel into halo_out, read from halo_in by the next one.
+    T *halo_out[kMaxRhs];
+    const T *halo_in[kMaxRhs];
+    uint32_t halo_bytes;  // bytes of one record buffer; 0: no records
     // shared
     const T *cr, *ct, *cp;
     const double *w;
@@ -147,10 +152,19 @@ __device__ inline int xcd_remap(int b, int nblk) {
 // block L.  Consecutive L run on one XCD at the same time (xcd_remap), so the
 // fastest index decides which neighbour tiles share that XCD's L2 while they
 // run: order 0 puts r chunks fastest, 1 theta tiles then r chunks, 2 theta
-// tiles then phi segments.
+// tiles then phi segments, 3 phi segments then theta tiles, 4 phi segments
+// then r chunks.
 template <int ORDER>
 __device__ inline void tile_coords(int L, int ti, int tk, int tj, int &it, int &kt, int &jt) {
-    if constexpr (ORDER == 1) {
+    if constexpr (ORDER == 3) {
+        kt = L % tk;
+        jt = (L / tk) % tj;
+        it = L / (tk * tj);
+    } else if constexpr (ORDER == 4) {
+        kt = L % tk;
+        it = (L / tk) % ti;
+        jt = L / (tk * ti);
+    } else if constexpr (ORDER == 1) {
         jt = L % tj;
         it = (L / tj) % ti;
         kt = L / (tj * ti);
@@ -250,8 +264,15 @@ __device__ inline VecT<T, V> bld(__amdgpu_buffer_rsrc_t r, uint32_t off) {
 template <typename T, int V, int AUX = 0>
 __device__ inline void bst(__amdgpu_buffer_rsrc_t r, uint32_t off, const VecT<T, V> &x) {
     constexpr int B = (int)sizeof(T) * V;
-    static_assert(B == 4 || B == 8 || B == 16, "buffer access size");
-    if constexpr (B == 16) {
+    static_assert(B == 4 || B == 8 || B == 16 || B == 32, "buffer access size");
+    if constexpr (B == 32) {
+        typedef int i4 __attribute__((ext_vector_type(4)));
+        i4 t0, t1;
+        __builtin_memcpy(&t0, &x, 16);
+        __builtin_memcpy(&t1, reinterpret_cast<const char *>(&x) + 16, 16);
+        __builtin_amdgcn_raw_buffer_store_b128(t0, r, off, 0, AUX);
+        __builtin_amdgcn_raw_buffer_store_b128(t1, r, off + 16u, 0, AUX);
+    } else if constexpr (B == 16) {
         typedef int i4 __attribute__((ext_vector_type(4)));
         i4 t;
         __builtin_memcpy(&t, &x, 16);
@@ -269,7 +290,7 @@ __device__ inline void bst(__amdgpu_buffer_rsrc_t r, uint32_t off, const VecT<T,
 }
 
 #ifndef MAS_ITER_ORDER
-#define MAS_ITER_ORDER 2
+#define MAS_ITER_ORDER 3
 #endif
 #ifndef MAS_ITER_SYNC
 #define MAS_ITER_SYNC 0
@@ -311,6 +332,40 @@ __device__ inline float shfl_dn1(float v) { return __shfl_down(v, 1, kWave); }
 __device__ inline double shfl_lane(double v, int src) { return __shfl(v, src, kWave); }
 __device__ inline float shfl_lane(float v, int src) { return __shfl(v, src, kWave); }
 
+// Cross-lane moves that stay in the vector ALU (no LDS crossbar, no lgkm
+// wait), gfx950:
+//   other_half: the value of lane (l + 32) mod 64 (v_permlane32_swap; its
+//     first result gives lanes 32-63 the lower half's values, its second
+//     gives lanes 0-31 the upper half's);
+//   lane_prev / lane_next: the value of lane l-1 / l+1 (DPP wave_shr:1 /
+//     wave_shl:1); lane 0 / lane 63 get 0 and their callers never use it.
+__device__ inline uint32_t other_half_u32(uint32_t v) {
+    const auto pr = __builtin_amdgcn_permlane32_swap(v, v, false, false);
+    return (threadIdx.x & 32) ? pr[0] : pr[1];
+}
+__device__ inline uint32_t lane_prev_u32(uint32_t v) {
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x138, 0xf, 0xf, false);
+}
+__device__ inline uint32_t lane_next_u32(uint32_t v) {
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x130, 0xf, 0xf, false);
+}
+template <uint32_t (*F)(uint32_t)>
+__device__ inline double lanes64(double v) {
+    const uint64_t b = __builtin_bit_cast(uint64_t, v);
+    const uint64_t lo = F((uint32_t)b), hi = F((uint32_t)(b >> 32));
+    return __builtin_bit_cast(double, lo | (hi << 32));
+}
+template <uint32_t (*F)(uint32_t)>
+__device__ inline float lanes32(float v) {
+    return __builtin_bit_cast(float, F(__builtin_bit_cast(uint32_t, v)));
+}
+__device__ inline double other_half(double v) { return lanes64<other_half_u32>(v); }
+__device__ inline float other_half(float v) { return lanes32<other_half_u32>(v); }
+__device__ inline double lane_prev(double v) { return lanes64<lane_prev_u32>(v); }
+__device__ inline float lane_prev(float v) { return lanes32<lane_prev_u32>(v); }
+__device__ inline double lane_next(double v) { return lanes64<lane_next_u32>(v); }
+__device__ inline float lane_next(float v) { return lanes32<lane_next_u32>(v); }
+
 // Each wave owns RPW consecutive theta rows, 64/RPW lanes per row, each lane
 // V consecutive phi cells (a segment of SEG = (64/RPW) V cells per row), and
 // marches through the r planes of its chunk on its own.
@@ -331,7 +386,16 @@ __device__ inline float shfl_lane(float v, int src) { return __shfl(v, src, kWav
 // sums.  A right-hand side whose run has stopped gets zero-length buffer
 // resources: its loads return zeros and its stores are dropped, so it moves
 // no bytes.
-template <typename T, int NR, int WPB, int RPW, int V, bool CHECK>
+// Segment edges: a phi neighbour outside the segment sits in another tile's
+// cache line, and fetching a whole line for one value per row is what costs
+// bytes.  So every kernel also writes, per (plane, row, segment), a record
+// [r_k, p_k, cp, q_k] for its first cell (side 0) and its last cell (side 1)
+// into a small side buffer; with HALO the next kernel takes its neighbours'
+// p_k and the coupling across the left edge from those records, which pack
+// the edges of a whole row into a few lines.  Without HALO (the first kernel
+// of a run, whose input no kernel wrote records for) the edge cells are
+// loaded directly.  HALO needs every segment to span at least two lanes.
+template <typename T, int NR, int WPB, int RPW, int V, bool CHECK, bool HALO>
 __global__ __launch_bounds__(kWave *WPB)
 #if MAS_ITER_WPE > 0
 __attribute__((amdgpu_waves_per_eu(MAS_ITER_WPE, 8)))
@@ -386,9 +450,17 @@ void k_pcg_iter(IterArgs<T> a) {
     // the last active lane receives p_k there through the phi shuffle.  In a
     // full segment the row's last lane loads that cell in the same
     // instruction as lane 0 loads the cell left of the segment.
-    const bool pseudoR = rowok && nvl < W && lp == nvl;
+    const bool pseudoR = !HALO && rowok && nvl < W && lp == nvl;
     const bool eL = rowok && lp == 0;
     const bool eR = rowok && nvl == W && lp == W - 1;
+    // edge records: lane 0 owns side 0, lane nvl-1 side 1 (distinct with HALO)
+    const int tk = a.tiles_k;
+    const int ktL = (kt == 0) ? tk - 1 : kt - 1, ktR = (kt == tk - 1) ? 0 : kt + 1;
+    const bool wside0 = act && lp == 0, wside1 = act && lp == nvl - 1 && nvl > 1;
+    const bool wrec = wside0 || wside1;
+    auto rec_off = [&](int mm, int kk, int side) -> uint32_t {
+        return (uint32_t)(((((int64_t)mm * nt + j) * tk + kk) * 2 + side) * 4 * (int64_t)sizeof(T));
+    };
 
     // own cells; inactive lanes read nothing (out-of-range offsets)
     const int64_t col = act ? (int64_t)j * np + k0 + lp * V : (pseudoR ? colR : 0);
@@ -413,8 +485,11 @@ void k_pcg_iter(IterArgs<T> a) {
     // wait for a store to complete (costs 4 V registers per right-hand side)
     constexpr bool kDefer = MAS_ITER_DEFER && NR <= MAS_ITER_DEFER_MAX_NR;
     VT st_r[NR], st_p[NR], st_x[NR], st_q[NR];
+    VecT<T, 4> st_h[NR];  // edge record [r, p, cp, q] of the previous plane
     bool st_own = false, st_q_do = false;
-    uint32_t st_off = kOOB, st_qoff = kOOB;
+    uint32_t st_off = kOOB, st_qoff = kOOB, st_hoff = kOOB;
+    T cpw1 = T(0);  // the recording lane's coupling at the previous plane
+    int m1 = 0;     // the previous plane
 
     // Every access goes through a range-checked buffer resource; a lane that
     // does not need an access uses an out-of-range offset (zeros in, stores
@@ -435,6 +510,12 @@ void k_pcg_iter(IterArgs<T> a) {
         Rpo[c] = make_rsrc(a.p_out[c], nb);
         Rqo[c] = make_rsrc(a.q_out[c], nb);
     }
+    __amdgpu_buffer_rsrc_t Rhi[NR], Rho[NR];
+#pragma unroll
+    for (int c = 0; c < NR; ++c) {
+        Rhi[c] = make_rsrc(a.halo_in[c], (HALO && run[c]) ? a.halo_bytes : 0u);
+        Rho[c] = make_rsrc(a.halo_out[c], run[c] ? a.halo_bytes : 0u);
+    }
     const auto Rcr = make_rsrc(a.cr, nbytes), Rct = make_rsrc(a.ct, nbytes),
                Rcp = make_rsrc(a.cp, nbytes),
                Rw = make_rsrc(a.w, (uint32_t)(a.d.n * (int64_t)sizeof(double)));
@@ -452,8 +533,13 @@ void k_pcg_iter(IterArgs<T> a) {
         const bool vU = own && ldU, vD = own && ldD, vL = own && eL, vR = own && eR;
         const uint32_t oU = vU ? (uint32_t)(base + colU) * ES : kOOB;
         const uint32_t oD = vD ? (uint32_t)(base + colD) * ES : kOOB;
-        const uint32_t oL = vL ? (uint32_t)(base + colL) * ES : kOOB;
-        const uint32_t oLR = vL ? oL : (vR ? (uint32_t)(base + colR) * ES : kOOB);
+        const uint32_t oL = (!HALO && vL) ? (uint32_t)(base + colL) * ES : kOOB;
+        const uint32_t oLR = HALO ? kOOB : (vL ? oL : (vR ? (uint32_t)(base + colR) * ES : kOOB));
+        // records: lane 0 reads side 1 of the left segment, lane nvl-1 side 0
+        // of the right segment
+        const uint32_t oRec = !HALO ? kOOB
+                                    : ((own && wside0) ? rec_off(m, ktL, 1)
+                                                       : ((own && act && lp == nvl - 1) ? rec_off(m, ktR, 0) : kOOB));
         // ---- loads of plane m, all issued before any use
         // With RPW >= 2 a lane needs row j-1 (first row of the wave) or row
         // j+1 (last row), never both: one set of edge-row registers (E)
@@ -463,6 +549,7 @@ void k_pcg_iter(IterArgs<T> a) {
         const uint32_t oE = kSplitUD ? oU : (vU ? oU : oD);
         VT r[NR], q[NR], p[NR], x[NR], rE[NR], qE[NR], pE[NR], rD[ND], qD[ND], pD[ND];
         T lr[NR], lq[NR], lp_[NR];
+        VecT<T, 4> hrec[NR];
 #pragma unroll
         for (int c = 0; c < NR; ++c) {
             r[c] = bld<T, V>(Rr[c], oc);
@@ -490,11 +577,18 @@ void k_pcg_iter(IterArgs<T> a) {
                 qD[c] = bld<T, V>(Rq[c], oD);
                 pD[c] = bld<T, V>(Rp[c], oD);
             }
-            lr[c] = bld<T, 1>(Rr[c], oLR).v[0];
-            lq[c] = bld<T, 1>(Rq[c], oLR).v[0];
-            lp_[c] = bld<T, 1>(Rp[c], oLR).v[0];
+            if constexpr (HALO) {
+                hrec[c] = bld<T, 4>(Rhi[c], oRec);
+                lr[c] = hrec[c].v[0];
+                lp_[c] = hrec[c].v[1];
+                lq[c] = hrec[c].v[3];
+            } else {
+                lr[c] = bld<T, 1>(Rr[c], oLR).v[0];
+                lq[c] = bld<T, 1>(Rq[c], oLR).v[0];
+                lp_[c] = bld<T, 1>(Rp[c], oLR).v[0];
+            }
         }
-        const T lcp = bld<T, 1>(Rcp, oL).v[0];
+        const T lcp = HALO ? T(0) : bld<T, 1>(Rcp, oL).v[0];
         // ---- stores of the previous step
         if constexpr (kDefer) {
 #pragma unroll
@@ -503,6 +597,7 @@ void k_pcg_iter(IterArgs<T> a) {
                 bst<T, V, AN>(Rpo[c], st_own ? st_off : kOOB, st_p[c]);
                 bst<T, V, AN>(Rx[c], st_own ? st_off : kOOB, st_x[c]);
                 bst<T, V, AN>(Rqo[c], st_q_do ? st_qoff : kOOB, st_q[c]);
+                bst<T, 4>(Rho[c], st_hoff, st_h[c]);
             }
         }
 #pragma unroll
@@ -537,9 +632,15 @@ void k_pcg_iter(IterArgs<T> a) {
                 for (int e = 0; e < V; ++e) {
                     // theta neighbours: shuffled from the neighbouring row of
                     // the wave, or formed from the loaded row at its edges
-                    const T sU = shfl_lane(pn.v[e], srcU);
-                    const T sD = shfl_lane(pn.v[e], srcD);
-                    const T sct = shfl_lane(ct.v[e], srcU);
+                    T sU, sD, sct;
+                    if constexpr (RPW == 2) {
+                        sU = sD = other_half(pn.v[e]);
+                        sct = other_half(ct.v[e]);
+                    } else {
+                        sU = shfl_lane(pn.v[e], srcU);
+                        sD = shfl_lane(pn.v[e], srcD);
+                        sct = shfl_lane(ct.v[e], srcU);
+                    }
                     const T lU = (rE[c].v[e] - alpha[c] * qE[c].v[e]) + beta[c] * pE[c].v[e];
                     T lD = lU;
                     if constexpr (kSplitUD)
@@ -551,14 +652,18 @@ void k_pcg_iter(IterArgs<T> a) {
                 // p_k at the loaded edge cell (left for lane 0, right for
                 // the last lane of a full segment)
                 const T e_edge = (lr[c] - alpha[c] * lq[c]) + beta[c] * lp_[c];
-                T left0 = shfl_up1(pn.v[V - 1]);
-                T right0 = shfl_dn1(pn.v[0]);
-                T cpl0 = shfl_up1(cp.v[V - 1]);
+                T left0 = lane_prev(pn.v[V - 1]);
+                T right0 = lane_next(pn.v[0]);
+                T cpl0 = lane_prev(cp.v[V - 1]);
                 if (lp == 0) {
                     left0 = vL ? e_edge : T(0);
-                    cpl0 = vL ? lcp : T(0);
+                    cpl0 = vL ? (HALO ? hrec[c].v[2] : lcp) : T(0);
                 }
-                if (eR) right0 = vR ? e_edge : T(0);
+                if constexpr (HALO) {
+                    if (lp == nvl - 1) right0 = e_edge;
+                } else {
+                    if (eR) right0 = vR ? e_edge : T(0);
+                }
 #pragma unroll
                 for (int e = 0; e < V; ++e) {
                     const T left = (e > 0) ? pn.v[e - 1] : left0;
@@ -587,17 +692,25 @@ void k_pcg_iter(IterArgs<T> a) {
                     }
                 }
             }
+            // ---- edge record of the previous plane, complete now that q is
+            VecT<T, 4> hr;
+            hr.v[0] = (lp == 0) ? rn1[c].v[0] : rn1[c].v[V - 1];
+            hr.v[1] = (lp == 0) ? pn1[c].v[0] : pn1[c].v[V - 1];
+            hr.v[2] = cpw1;
+            hr.v[3] = (lp == 0) ? qv.v[0] : qv.v[V - 1];
             // ---- stores
             if constexpr (kDefer) {
                 st_r[c] = rn;
                 st_p[c] = pn;
                 st_x[c] = xn;
                 st_q[c] = qv;
+                st_h[c] = hr;
             } else {
                 bst<T, V, AN>(Rro[c], oo, rn);
                 bst<T, V, AN>(Rpo[c], oo, pn);
                 bst<T, V, AN>(Rx[c], oo, xn);
                 bst<T, V, AN>(Rqo[c], oq, qv);
+                bst<T, 4>(Rho[c], (qdo && wrec) ? rec_off(m1, kt, wside0 ? 0 : 1) : kOOB, hr);
             }
             pn1[c] = pn;
             rn1[c] = rn;
@@ -607,6 +720,10 @@ void k_pcg_iter(IterArgs<T> a) {
         st_off = oo;
         st_q_do = qdo;
         st_qoff = oq;
+        st_hoff = (qdo && wrec) ? rec_off(m1, kt, wside0 ? 0 : 1) : kOOB;
+        // the recording lane's coupling of this plane (side 1 needs it)
+        cpw1 = (lp == 0) ? cp.v[0] : cp.v[V - 1];
+        m1 = m;
 #if MAS_ITER_SYNC
         // keep the block's waves on the same plane so that the rows they
         // load for each other are requested together (L1/L2 reuse)
@@ -623,6 +740,7 @@ void k_pcg_iter(IterArgs<T> a) {
             bst<T, V, AN>(Rpo[c], st_own ? st_off : kOOB, st_p[c]);
             bst<T, V, AN>(Rx[c], st_own ? st_off : kOOB, st_x[c]);
             bst<T, V, AN>(Rqo[c], st_q_do ? st_qoff : kOOB, st_q[c]);
+            bst<T, 4>(Rho[c], st_hoff, st_h[c]);
         }
     }
     __shared__ double sRed[WPB * NR * kNV];

@@ -65,17 +65,30 @@ static constexpr int kRPW = MAS_RPW; // theta rows per wave
 static constexpr int kTI = MAS_TI;
 
 #ifndef MAS_ITER_VEC
-#define MAS_ITER_VEC 16
+#define MAS_ITER_VEC 16  // bytes per lane, double-precision iteration kernel
+#endif
+#ifndef MAS_MULTI_VEC
+#define MAS_MULTI_VEC 1  // several right-hand sides keep the full vector width
+#endif
+#ifndef MAS_ITER_VEC_F32
+#define MAS_ITER_VEC_F32 16  // bytes per lane, single-precision iteration kernel
 #endif
 template <typename T>
+static constexpr int vec_full() {
+    constexpr int bytes = sizeof(T) == 8 ? MAS_ITER_VEC : MAS_ITER_VEC_F32;
+    return bytes / (int)sizeof(T) > 0 ? bytes / (int)sizeof(T) : 1;
+}
+template <typename T>
 static inline int vec_width(int np) {
-    constexpr int v = MAS_ITER_VEC / (int)sizeof(T) > 0 ? MAS_ITER_VEC / (int)sizeof(T) : 1;
+    constexpr int v = vec_full<T>();
     return (np % v == 0) ? v : 1;
 }
 
-#ifndef MAS_MULTI_VEC
-#define MAS_MULTI_VEC 1
-#endif
+// Lanes' vector width of the iteration kernel for nrhs right-hand sides.
+template <typename T>
+static inline int iter_vec(int np, int nrhs) {
+    return (nrhs > 1 && !MAS_MULTI_VEC) ? 1 : vec_width<T>(np);
+}
 
 static inline int64_t align256(int64_t v) { return (v + 255) & ~int64_t(255); }
 
@@ -87,6 +100,15 @@ struct Shape {
     int tiles_j() const { return (nt + kTJ * kRPW - 1) / (kTJ * kRPW); }
     int tiles_i() const { return (nr + kTI - 1) / kTI; }
     int64_t nblk_iter(int v) const { return (int64_t)tiles_k(v) * tiles_j() * tiles_i(); }
+    // bytes of one segment-edge record buffer of the iteration kernel, and
+    // whether the records can be used (every segment spans two lanes, 32-bit
+    // offsets)
+    int64_t halo_bytes(int v, int64_t es) const { return (int64_t)nr * nt * tiles_k(v) * 2 * 4 * es; }
+    bool halo_ok(int v, int64_t es) const {
+        const int seg = (kWave / kRPW) * v;
+        const int last = np - (tiles_k(v) - 1) * seg;
+        return last >= 2 * v && halo_bytes(v, es) < ((int64_t)1 << 31);
+    }
     dim3 simple_grid() const {
         return dim3((np + kWave - 1) / kWave, (nt + kSimpleJ - 1) / kSimpleJ,
                     (nr + kSimpleR - 1) / kSimpleR);
@@ -348,7 +370,8 @@ extern "C" int mas_op_export(const mas_op *op, double *cr, double *ct, double *c
 
 // ------------------------------------------------------------------ workspace
 struct WorkLayout {
-    int64_t ctl, partials, bhat[kMaxRhs], vec[kMaxRhs][6], dh, total;
+    int64_t ctl, partials, bhat[kMaxRhs], vec[kMaxRhs][6], halo[kMaxRhs][2], dh, total;
+    int64_t halo_bytes;  // one record buffer (0: records not used)
 };
 
 // nrhs right-hand sides: control blocks and the iteration partials for all of
@@ -375,6 +398,14 @@ static WorkLayout work_layout(const Shape &s, int precision, int nrhs = 1) {
         L.bhat[c] = take(8 * s.n);
         for (int t = 0; t < 6; ++t) L.vec[c][t] = take(es * s.n);
     }
+    // segment-edge records of the iteration kernel, double-buffered
+    const int v = (precision == MAS_FP32_REFINED) ? iter_vec<float>(s.np, nrhs)
+                                                  : iter_vec<double>(s.np, nrhs);
+    L.halo_bytes = s.halo_ok(v, es) ? s.halo_bytes(v, es) : 0;
+    for (int c = 0; c < kMaxRhs; ++c) L.halo[c][0] = L.halo[c][1] = -1;
+    if (L.halo_bytes > 0)
+        for (int c = 0; c < nrhs; ++c)
+            for (int t = 0; t < 2; ++t) L.halo[c][t] = take(L.halo_bytes);
     L.dh = (precision == MAS_FP32_REFINED) ? take(4 * s.n) : -1;
     L.total = off;
     return L;
@@ -492,6 +523,8 @@ struct RhsSet {
     int n = 0;
     T *r[kMaxRhs][2], *p[kMaxRhs][2], *q[kMaxRhs][2];
     T *x[kMaxRhs];
+    T *halo[kMaxRhs][2];    // segment-edge record buffers (null: not used)
+    uint32_t halo_bytes = 0;
     double tol2[kMaxRhs];
     int max_iter[kMaxRhs];  // last admissible iteration index of each
     bool active[kMaxRhs];
@@ -535,14 +568,15 @@ static int run_pcg(Ctx &cx, const RhsSet<T> &v, const T *const c[3], int mode, i
     a.partials = cx.partials;
     a.ctl = cx.ctl;
     a.d = s.dims();
-    // several right-hand sides: V = 1 unless MAS_MULTI_VEC (register pressure)
-    const int V = (NR > 1 && !MAS_MULTI_VEC) ? 1 : vec_width<T>(s.np);
+    const int V = iter_vec<T>(s.np, NR);
     a.tiles_i = s.tiles_i();
     a.tiles_k = s.tiles_k(V);
     a.tiles_j = s.tiles_j();
     a.ti = kTI;
     a.nblk = (int)s.nblk_iter(V);
     for (int h = 0; h < NR; ++h) a.x[h] = v.x[h];
+    a.halo_bytes = v.halo_bytes;
+    const bool use_halo = v.halo_bytes > 0;
     const dim3 grid((unsigned)a.nblk), block(kWave * kTJ);
 
     // batches of launches; the host polls the device flags one batch behind
@@ -575,7 +609,12 @@ static int run_pcg(Ctx &cx, const RhsSet<T> &v, const T *const c[3], int mode, i
                 a.r_out[h] = v.r[h][nxt];
                 a.p_out[h] = v.p[h][nxt];
                 a.q_out[h] = v.q[h][nxt];
+                a.halo_in[h] = v.halo[h][cur];
+                a.halo_out[h] = v.halo[h][nxt];
             }
+            // the first kernel of a run reads its edge cells directly (no
+            // kernel wrote records for its input); later ones read records
+            const bool halo = use_halo && k != iter0;
             const bool chk = (mode == 0) && ((k % check_every) == 0 || k == max_iter);
             const bool sample = cx.timing && (k % 16 == 7) && cx.ev.size() < 128;
             if (sample) {
@@ -587,17 +626,22 @@ static int run_pcg(Ctx &cx, const RhsSet<T> &v, const T *const c[3], int mode, i
                 cx.ev_iter.push_back(k);
                 HIPCHK(hipEventRecord(e0, st));
             }
-            constexpr int VW = MAS_ITER_VEC / (int)sizeof(T) > 0 ? MAS_ITER_VEC / (int)sizeof(T) : 1;
+            constexpr int VW = vec_full<T>();
+            auto go = [&](auto vw, auto ck, auto hl) {
+                hipLaunchKernelGGL((k_pcg_iter<T, NR, kTJ, kRPW, decltype(vw)::value,
+                                               decltype(ck)::value, decltype(hl)::value>),
+                                   grid, block, 0, st, a);
+            };
+            using F = std::false_type;
+            using Tr = std::true_type;
+            using IW = std::integral_constant<int, VW>;
+            using I1 = std::integral_constant<int, 1>;
             if (V == VW) {
-                if (chk)
-                    hipLaunchKernelGGL((k_pcg_iter<T, NR, kTJ, kRPW, VW, true>), grid, block, 0, st, a);
-                else
-                    hipLaunchKernelGGL((k_pcg_iter<T, NR, kTJ, kRPW, VW, false>), grid, block, 0, st, a);
+                if (chk) halo ? go(IW{}, Tr{}, Tr{}) : go(IW{}, Tr{}, F{});
+                else halo ? go(IW{}, F{}, Tr{}) : go(IW{}, F{}, F{});
             } else {
-                if (chk)
-                    hipLaunchKernelGGL((k_pcg_iter<T, NR, kTJ, kRPW, 1, true>), grid, block, 0, st, a);
-                else
-                    hipLaunchKernelGGL((k_pcg_iter<T, NR, kTJ, kRPW, 1, false>), grid, block, 0, st, a);
+                if (chk) halo ? go(I1{}, Tr{}, Tr{}) : go(I1{}, Tr{}, F{});
+                else halo ? go(I1{}, F{}, Tr{}) : go(I1{}, F{}, F{});
             }
             if (sample) HIPCHK(hipEventRecord(cx.ev.back(), st));
             hipLaunchKernelGGL(k_finalize, dim3(NR), dim3(kRedThreads), 0, st, cx.partials, a.nblk,
@@ -657,6 +701,14 @@ static int status_from_flag(int flag) {
         case FLAG_BREAK: return MAS_EBREAKDOWN;
         default: return MAS_ENOTCONV;
     }
+}
+
+// Record buffers of right-hand side h from the workspace layout.
+template <typename T>
+static void set_halo(RhsSet<T> &v, char *base, const WorkLayout &L, int h = 0) {
+    v.halo_bytes = (uint32_t)L.halo_bytes;
+    for (int t = 0; t < 2; ++t)
+        v.halo[h][t] = L.halo_bytes > 0 ? reinterpret_cast<T *>(base + L.halo[h][t]) : nullptr;
 }
 
 // Solve A x = b with b = V src (src_is_rhs) or b = src; result (unscaled) in x.
@@ -729,6 +781,7 @@ static int solve_core(const mas_op *op, const double *src, int src_is_rhs, doubl
         v.tol2[0] = tol2;
         v.max_iter[0] = o.max_iters;
         v.active[0] = true;
+        set_halo(v, base, L);
         const double *const c[3] = {op->c64[0], op->c64[1], op->c64[2]};
         double rw2 = 0.0;
         st = residual<double>(cx, bhat, x, v.r[0][0], &rw2);
@@ -779,6 +832,7 @@ static int solve_core(const mas_op *op, const double *src, int src_is_rhs, doubl
         float *dh = reinterpret_cast<float *>(base + L.dh);
         v.x[0] = dh;
         v.active[0] = true;
+        set_halo(v, base, L);
         float *const *r = v.r[0];
         float *const *p = v.p[0];
         const float *const c[3] = {op->c32[0], op->c32[1], op->c32[2]};
@@ -904,6 +958,7 @@ static int solve_multi_core(const mas_op *op, const double *rhs, double *x, cons
         }
         v.x[h] = x + h * n;
         kernels[h] = 0;
+        set_halo(v, base, L, h);
         // b^ = W^-1 V rhs, x^ = W x0 or 0, ||b||^2
         hipLaunchKernelGGL(k_setup, sgrid, sblock, 0, stream, rhs + h * n, 1, op->w, op->geo, d,
                            bhat[h], v.x[h], o.use_x0 ? 1 : 0, cx.partials);

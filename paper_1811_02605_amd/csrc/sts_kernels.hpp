@@ -59,8 +59,16 @@ struct StsArgs {
 // Inputs a stage reads besides X and nu (template mask).
 constexpr int kStsZ = 1, kStsL0 = 2, kStsY0 = 4;
 
+#ifndef MAS_STS_WPE
+#define MAS_STS_WPE 0
+#endif
+
 template <int WPB, int RPW, int V, int IN>
-__global__ __launch_bounds__(kWave *WPB) void k_sts_stage(StsArgs a) {
+__global__ __launch_bounds__(kWave *WPB)
+#if MAS_STS_WPE > 0
+__attribute__((amdgpu_waves_per_eu(MAS_STS_WPE, 8)))
+#endif
+void k_sts_stage(StsArgs a) {
     static_assert(kWave % RPW == 0, "rows per wave");
     constexpr int W = kWave / RPW;  // lanes per row
     constexpr int SEG = W * V;
@@ -174,14 +182,22 @@ __global__ __launch_bounds__(kWave *WPB) void k_sts_stage(StsArgs a) {
         const VD &Xp = up ? Xa : Xb, &Xm = up ? Xb : Xa;  // planes m+1, m-1
         const VD &Np = up ? Na : Nb, &Nm = up ? Nb : Na;
 
-        const double xl0 = shfl_up1(Xc.v[V - 1]), nl0 = shfl_up1(Nc.v[V - 1]);
-        const double xr0 = shfl_dn1(Xc.v[0]), nr0 = shfl_dn1(Nc.v[0]);
+        const double xl0 = lane_prev(Xc.v[V - 1]), nl0 = lane_prev(Nc.v[V - 1]);
+        const double xr0 = lane_next(Xc.v[0]), nr0 = lane_next(Nc.v[0]);
         VD o;
 #pragma unroll
         for (int e = 0; e < V; ++e) {
             const double xc = Xc.v[e], nc = Nc.v[e];
-            const double sxu = shfl_lane(xc, srcU), snu = shfl_lane(nc, srcU);
-            const double sxd = shfl_lane(xc, srcD), snd = shfl_lane(nc, srcD);
+            double sxu, snu, sxd, snd;
+            if constexpr (RPW == 2) {
+                sxu = sxd = other_half(xc);
+                snu = snd = other_half(nc);
+            } else {
+                sxu = shfl_lane(xc, srcU);
+                snu = shfl_lane(nc, srcU);
+                sxd = shfl_lane(xc, srcD);
+                snd = shfl_lane(nc, srcD);
+            }
             const double xu = (rr == 0) ? XE.v[e] : sxu, nu_u = (rr == 0) ? NE.v[e] : snu;
             double xd, nu_d;
             if constexpr (RPW == 1) {

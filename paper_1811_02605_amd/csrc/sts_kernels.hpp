@@ -44,7 +44,7 @@ namespace mas {
 #endif
 
 #ifndef MAS_STS_ORDER
-#define MAS_STS_ORDER 0
+#define MAS_STS_ORDER 3
 #endif
 
 struct StsArgs {

@@ -6,7 +6,8 @@ Python binding) never does, and this package imports nothing from the
 product: the two sides share only the seeded inputs they are handed.
 
 ``mas_oracle.c`` holds the arithmetic (geometry, assembly, operator apply,
-Jacobi-preconditioned CG, adjoint gradient, RKL2 super time-step); this module is ctypes
+Jacobi-preconditioned CG, adjoint gradient, RKL2 super time-step, block-Jacobi
+ILU(0) preconditioner and its PCG); this module is ctypes
 marshalling plus numpy array allocation.  ``dense`` holds small dense-matrix
 helpers for tiny grids.
 
@@ -98,6 +99,14 @@ def _load():
         lib.ora_rkl2_stages.restype = ctypes.c_int
         lib.ora_rkl2_step.argtypes = [P(_Op), _dp(), _dp(), ctypes.c_int]
         lib.ora_rkl2_step.restype = ctypes.c_int
+        ci = ctypes.c_int
+        lib.ora_pc2_factor.argtypes = [P(_Op), ci, ci, ci, _dp()]
+        lib.ora_pc2_factor.restype = None
+        lib.ora_pc2_apply.argtypes = [P(_Op), ci, ci, ci, _dp(), _dp(), _dp()]
+        lib.ora_pc2_apply.restype = None
+        lib.ora_pcg_pc2.argtypes = [P(_Op), ci, ci, ci, _dp(), _dp(), ctypes.c_double, ci, ci,
+                                    _dp(), _dp()]
+        lib.ora_pcg_pc2.restype = ci
         _lib = lib
     return _lib
 
@@ -212,6 +221,36 @@ class Operator:
         if _load().ora_rkl2_step(ctypes.byref(self._op), _ptr(u0), _ptr(u1), s) != 0:
             raise ValueError("need at least 2 stages")
         return u1
+
+    def pc2_factor(self, blocks=(8, 8, 32)) -> np.ndarray:
+        """Modified diagonal of the block-Jacobi ILU(0) factorization."""
+        d = np.empty(self.shape)
+        _load().ora_pc2_factor(ctypes.byref(self._op), *map(int, blocks), _ptr(d))
+        return d
+
+    def pc2_apply(self, r, blocks=(8, 8, 32), d=None) -> np.ndarray:
+        """z = M^-1 r for the block-Jacobi ILU(0) preconditioner M."""
+        d = self.pc2_factor(blocks) if d is None else _f64(d).reshape(self.shape)
+        r = _f64(r).reshape(self.shape)
+        z = np.empty(self.shape)
+        _load().ora_pc2_apply(ctypes.byref(self._op), *map(int, blocks), _ptr(d), _ptr(r), _ptr(z))
+        return z
+
+    def pcg_pc2(self, b, blocks=(8, 8, 32), tol=1e-10, max_iters=100000, x0=None, history=False):
+        """PCG with the block-Jacobi ILU(0) preconditioner.  Returns (x, iterations,
+        rel_res_recursive, rel_res_true[, history])."""
+        b = _f64(b).reshape(self.shape)
+        x = np.zeros(self.shape) if x0 is None else _f64(x0).reshape(self.shape).copy()
+        stats = np.zeros(2)
+        hist = np.zeros(max_iters + 1) if history else None
+        it = _load().ora_pcg_pc2(ctypes.byref(self._op), *map(int, blocks), _ptr(b), _ptr(x),
+                                 float(tol), int(max_iters), int(x0 is not None), _ptr(stats),
+                                 _ptr(hist) if history else None)
+        if it < 0:
+            raise FloatingPointError("PCG breakdown: (p, Ap) <= 0")
+        if history:
+            return x, it, stats[0], stats[1], hist[: it + 1]
+        return x, it, stats[0], stats[1]
 
     def rel_residual(self, b, x) -> float:
         b = _f64(b).reshape(self.shape)

@@ -501,3 +501,153 @@ int ora_rkl2_step(const ora_op *op, const double *u0, double *u1, int s) {
     free(mu), free(nu), free(mt), free(gt), free(L0), free(Lj), free(ay), free(ym2), free(ym1), free(yj);
     return 0;
 }
+
+/* ------------------------------------------------------------------ PC2: block-Jacobi ILU(0)
+ * The paper's second preconditioner (Section 2.2): block-Jacobi whose blocks
+ * (one per MPI rank in MAS) are factored by zero-fill incomplete LU (Saad,
+ * Iterative Methods, ILU(0)).  Readings: the blocks are boxes of bi x bj x bk
+ * cells (r, theta, phi) tiling the grid from index 0 (the last ones ragged);
+ * couplings between blocks, and the periodic phi coupling between k = np-1
+ * and k = 0, are left out of the factorization; cells are ordered naturally
+ * (the cell index order).  A block is then a box with the 7-point graph, and
+ * ILU(0) in natural order leaves A's off-diagonal entries as they are and
+ * changes only the diagonal:
+ *     d_c = A_cc - sum_{lower neighbours nb of c in its block} A_{c,nb}^2 / d_nb,
+ * M = (D + L) D^-1 (D + U) with L, U the strict lower / upper parts of the
+ * block-diagonal part of A.  Applying M^-1:
+ *     forward   y_c = (r_c - sum_{nb < c} A_{c,nb} y_nb) / d_c
+ *     backward  z_c = y_c - (sum_{nb > c} A_{c,nb} z_nb) / d_c.
+ * A_{c,nb} = -c_f for the face f between c and nb.
+ */
+typedef struct {
+    int bi, bj, bk;
+} ora_blocks;
+
+static int same_block(int a, int b, int bs) { return a / bs == b / bs; }
+
+/* couplings to the lower neighbours (i-1, j, k), (i, j-1, k), (i, j, k-1) of
+ * cell (i, j, k) inside its block; 0 where the neighbour is outside it */
+static void lower_couplings(const ora_op *op, const ora_blocks *B, int i, int j, int k, double *cr_,
+                            double *ct_, double *cp_) {
+    const ora_grid *g = &op->g;
+    *cr_ = (i > 0 && same_block(i - 1, i, B->bi)) ? op->cr[ridx(g, i, j, k)] : 0.0;
+    *ct_ = (j > 0 && same_block(j - 1, j, B->bj)) ? op->ct[tidx(g, i, j, k)] : 0.0;
+    *cp_ = (k > 0 && same_block(k - 1, k, B->bk)) ? op->cp[cidx(g, i, j, k - 1)] : 0.0;
+}
+
+void ora_pc2_factor(const ora_op *op, int bi, int bj, int bk, double *d) {
+    const ora_grid *g = &op->g;
+    ora_blocks B = {bi, bj, bk};
+    /* the natural order visits every lower neighbour before the cell */
+    for (int i = 0; i < g->nr; i++)
+        for (int j = 0; j < g->nt; j++)
+            for (int k = 0; k < g->np; k++) {
+                double a, b, c;
+                lower_couplings(op, &B, i, j, k, &a, &b, &c);
+                const size_t cc = cidx(g, i, j, k);
+                double s = op->diag[cc];
+                if (a != 0.0) s -= a * a / d[cidx(g, i - 1, j, k)];
+                if (b != 0.0) s -= b * b / d[cidx(g, i, j - 1, k)];
+                if (c != 0.0) s -= c * c / d[cidx(g, i, j, k - 1)];
+                d[cc] = s;
+            }
+}
+
+void ora_pc2_apply(const ora_op *op, int bi, int bj, int bk, const double *d, const double *r,
+                   double *z) {
+    const ora_grid *g = &op->g;
+    ora_blocks B = {bi, bj, bk};
+    const size_t n = ncell(g);
+    double *y = (double *)malloc(sizeof(double) * n);
+    for (int i = 0; i < g->nr; i++)
+        for (int j = 0; j < g->nt; j++)
+            for (int k = 0; k < g->np; k++) {
+                double a, b, c;
+                lower_couplings(op, &B, i, j, k, &a, &b, &c);
+                const size_t cc = cidx(g, i, j, k);
+                double s = r[cc];
+                if (a != 0.0) s += a * y[cidx(g, i - 1, j, k)];
+                if (b != 0.0) s += b * y[cidx(g, i, j - 1, k)];
+                if (c != 0.0) s += c * y[cidx(g, i, j, k - 1)];
+                y[cc] = s / d[cc];
+            }
+    for (int i = g->nr - 1; i >= 0; i--)
+        for (int j = g->nt - 1; j >= 0; j--)
+            for (int k = g->np - 1; k >= 0; k--) {
+                const size_t cc = cidx(g, i, j, k);
+                double s = 0.0, a, b, c;
+                /* upper neighbours: the cells whose lower neighbour c is */
+                if (i + 1 < g->nr) {
+                    lower_couplings(op, &B, i + 1, j, k, &a, &b, &c);
+                    if (a != 0.0) s += a * z[cidx(g, i + 1, j, k)];
+                }
+                if (j + 1 < g->nt) {
+                    lower_couplings(op, &B, i, j + 1, k, &a, &b, &c);
+                    if (b != 0.0) s += b * z[cidx(g, i, j + 1, k)];
+                }
+                if (k + 1 < g->np) {
+                    lower_couplings(op, &B, i, j, k + 1, &a, &b, &c);
+                    if (c != 0.0) s += c * z[cidx(g, i, j, k + 1)];
+                }
+                z[cc] = y[cc] + s / d[cc];
+            }
+    free(y);
+}
+
+/* Preconditioned CG (the same steps as ora_pcg) with z = M^-1 r by PC2.
+ * Returns the iteration count or -1 on breakdown. */
+int ora_pcg_pc2(const ora_op *op, int bi, int bj, int bk, const double *b, double *x, double tol,
+                int max_iters, int use_x0, double *stats, double *hist) {
+    const ora_grid *g = &op->g;
+    const size_t n = ncell(g);
+    double *r = (double *)malloc(sizeof(double) * n);
+    double *z = (double *)malloc(sizeof(double) * n);
+    double *p = (double *)malloc(sizeof(double) * n);
+    double *q = (double *)malloc(sizeof(double) * n);
+    double *d = (double *)malloc(sizeof(double) * n);
+    double *plane = (double *)malloc(sizeof(double) * g->nr);
+    int it = 0, status = 0;
+
+    ora_pc2_factor(op, bi, bj, bk, d);
+    if (!use_x0) memset(x, 0, sizeof(double) * n);
+    ora_apply(op, x, q);
+    for (size_t c = 0; c < n; c++) r[c] = b[c] - q[c];
+    ora_pc2_apply(op, bi, bj, bk, d, r, z);
+    for (size_t c = 0; c < n; c++) p[c] = z[c];
+    double bnorm = sqrt(dot(g, b, b, plane));
+    if (bnorm == 0.0) bnorm = 1.0;
+    double rz = dot(g, r, z, plane);
+    double rnorm = sqrt(dot(g, r, r, plane));
+    if (hist) hist[0] = rnorm / bnorm;
+
+    while (rnorm > tol * bnorm && it < max_iters) {
+        ora_apply(op, p, q);
+        double pq = dot(g, p, q, plane);
+        if (!(pq > 0.0) || !isfinite(pq)) {
+            status = -1;
+            break;
+        }
+        double alpha = rz / pq;
+        for (size_t c = 0; c < n; c++) {
+            x[c] += alpha * p[c];
+            r[c] -= alpha * q[c];
+        }
+        it++;
+        rnorm = sqrt(dot(g, r, r, plane));
+        if (hist) hist[it] = rnorm / bnorm;
+        if (rnorm <= tol * bnorm) break;
+        ora_pc2_apply(op, bi, bj, bk, d, r, z);
+        double rz_new = dot(g, r, z, plane);
+        double beta = rz_new / rz;
+        rz = rz_new;
+        for (size_t c = 0; c < n; c++) p[c] = z[c] + beta * p[c];
+    }
+    if (stats) {
+        stats[0] = rnorm / bnorm;
+        ora_apply(op, x, q);
+        for (size_t c = 0; c < n; c++) r[c] = b[c] - q[c];
+        stats[1] = sqrt(dot(g, r, r, plane)) / bnorm;
+    }
+    free(r), free(z), free(p), free(q), free(d), free(plane);
+    return status < 0 ? status : it;
+}

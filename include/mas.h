@@ -75,6 +75,17 @@ enum { MAS_FP64 = 0, MAS_FP32_REFINED = 1 };
  *     so the Krylov information is not thrown away at each refinement step. */
 enum { MAS_REFINE_RESTART = 0, MAS_REFINE_RELIABLE = 1 };
 
+/* Preconditioner (the paper, Section 2.2).
+ *   MAS_PC1: point Jacobi, the inverse diagonal (the GPU choice in the paper).
+ *   MAS_PC2: block Jacobi with a zero-fill incomplete LU (ILU(0)) factor of
+ *     each block.  Blocks are boxes of 8 r planes x 8 theta rows x 64 phi
+ *     cells tiling the grid from index 0 (the last ones ragged); couplings
+ *     between blocks and the periodic phi coupling are left out of the
+ *     factors; cells are ordered naturally inside a block, so ILU(0) changes
+ *     only the diagonal.  The factor is formed at the start of every solve.
+ *     Double precision only. */
+enum { MAS_PC1 = 0, MAS_PC2 = 1 };
+
 typedef struct {
     int32_t nr, nt, np;       /* cells in r, theta, phi (each >= 1)                   */
     const double *r_faces;    /* host, nr+1, strictly increasing, r_faces[0] > 0       */
@@ -100,6 +111,8 @@ typedef struct {
     int32_t sample_timing;/* nonzero: time a sample of PCG iteration kernels with HIP
                              events (reported in mas_pcg_info)                          (0) */
     int32_t refine;       /* refined: MAS_REFINE_RESTART | MAS_REFINE_RELIABLE   (RELIABLE) */
+    int32_t precond;      /* MAS_PC1 | MAS_PC2 (FP64 only)                          (PC1) */
+    int32_t pad_;
 } mas_pcg_opts;
 
 typedef struct {

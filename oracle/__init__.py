@@ -222,13 +222,13 @@ class Operator:
             raise ValueError("need at least 2 stages")
         return u1
 
-    def pc2_factor(self, blocks=(8, 8, 32)) -> np.ndarray:
+    def pc2_factor(self, blocks=(8, 8, 64)) -> np.ndarray:
         """Modified diagonal of the block-Jacobi ILU(0) factorization."""
         d = np.empty(self.shape)
         _load().ora_pc2_factor(ctypes.byref(self._op), *map(int, blocks), _ptr(d))
         return d
 
-    def pc2_apply(self, r, blocks=(8, 8, 32), d=None) -> np.ndarray:
+    def pc2_apply(self, r, blocks=(8, 8, 64), d=None) -> np.ndarray:
         """z = M^-1 r for the block-Jacobi ILU(0) preconditioner M."""
         d = self.pc2_factor(blocks) if d is None else _f64(d).reshape(self.shape)
         r = _f64(r).reshape(self.shape)
@@ -236,7 +236,7 @@ class Operator:
         _load().ora_pc2_apply(ctypes.byref(self._op), *map(int, blocks), _ptr(d), _ptr(r), _ptr(z))
         return z
 
-    def pcg_pc2(self, b, blocks=(8, 8, 32), tol=1e-10, max_iters=100000, x0=None, history=False):
+    def pcg_pc2(self, b, blocks=(8, 8, 64), tol=1e-10, max_iters=100000, x0=None, history=False):
         """PCG with the block-Jacobi ILU(0) preconditioner.  Returns (x, iterations,
         rel_res_recursive, rel_res_true[, history])."""
         b = _f64(b).reshape(self.shape)

@@ -30,6 +30,9 @@ MAS_FP32_REFINED = 1
 MAS_REFINE_RESTART = 0
 MAS_REFINE_RELIABLE = 1
 
+MAS_PC1 = 0
+MAS_PC2 = 1
+
 
 class mas_grid(ctypes.Structure):
     _fields_ = [("nr", ctypes.c_int32), ("nt", ctypes.c_int32), ("np", ctypes.c_int32),
@@ -43,7 +46,8 @@ class mas_pcg_opts(ctypes.Structure):
                 ("precision", ctypes.c_int32), ("inner_rtol", ctypes.c_double),
                 ("max_outer", ctypes.c_int32), ("check_every", ctypes.c_int32),
                 ("use_x0", ctypes.c_int32), ("max_restarts", ctypes.c_int32),
-                ("sample_timing", ctypes.c_int32), ("refine", ctypes.c_int32)]
+                ("sample_timing", ctypes.c_int32), ("refine", ctypes.c_int32),
+                ("precond", ctypes.c_int32), ("pad_", ctypes.c_int32)]
 
 
 class mas_pcg_info(ctypes.Structure):

@@ -17,6 +17,7 @@
 #include "../../include/mas.h"
 #include "kernels.hpp"
 #include "sts_kernels.hpp"
+#include "pc2_kernels.hpp"
 
 using namespace mas;
 
@@ -246,6 +247,7 @@ extern "C" void mas_pcg_default_opts(mas_pcg_opts *o) {
     o->max_restarts = 3;
     o->sample_timing = 0;
     o->refine = MAS_REFINE_RELIABLE;
+    o->precond = MAS_PC1;
 }
 
 extern "C" int64_t mas_op_storage_bytes(const mas_grid *g, int32_t precision) {
@@ -427,6 +429,10 @@ static int check_opts(const mas_op *op, const mas_pcg_opts *o) {
             return fail(MAS_EINVAL, "unknown refinement strategy %d", o->refine);
     }
     if (o->max_restarts < 0) return fail(MAS_EINVAL, "max_restarts must be >= 0");
+    if (o->precond != MAS_PC1 && o->precond != MAS_PC2)
+        return fail(MAS_EINVAL, "unknown preconditioner %d", o->precond);
+    if (o->precond == MAS_PC2 && o->precision != MAS_FP64)
+        return fail(MAS_EINVAL, "the PC2 preconditioner is double precision only");
     return MAS_OK;
 }
 
@@ -703,6 +709,97 @@ static int status_from_flag(int flag) {
     }
 }
 
+// ------------------------------------------------------------------ PC2 driver
+static int64_t pc2_blocks(const Shape &s, int *nbi, int *nbj, int *nbk) {
+    *nbi = (s.nr + kPc2I - 1) / kPc2I;
+    *nbj = (s.nt + kPc2J - 1) / kPc2J;
+    *nbk = (s.np + kPc2K - 1) / kPc2K;
+    return (int64_t)*nbi * *nbj * *nbk;
+}
+
+// PCG with the block-Jacobi ILU(0) preconditioner on the scaled system, from
+// x (scaled) and r = b^ - A^ x already in r.  Iterations are counted from
+// iter0; the run stops on ||W r||^2 <= tol2 (every iteration), at max_iter
+// or on a breakdown.  The modified diagonal must already be in d.
+static int run_pcg_pc2(Ctx &cx, double *r, double *z, double *const p[2], double *q, double *d,
+                       double *x, int iter0, int max_iter, double tol2, PcgResult *res) {
+    const mas_op *op = cx.op;
+    const Shape &s = op->s;
+    hipStream_t st = cx.stream;
+    int nbi, nbj, nbk;
+    const int64_t nb = pc2_blocks(s, &nbi, &nbj, &nbk);
+    const int nsimple = (int)s.nblk_simple();
+    hipLaunchKernelGGL(k_ctl_init, dim3(1), dim3(64), 0, st, cx.ctl, 0, iter0, max_iter, tol2, 0.0,
+                       (int)FLAG_RUN);
+    Pc2Args a{op->c64[0], op->c64[1], op->c64[2], op->w, d, r, x, z, q, nullptr, cx.partials,
+              cx.ctl, s.dims(), nbi, nbj, nbk, 0};
+    // z = M^-1 r of the initial residual, (r, z), the stopping test
+    hipLaunchKernelGGL(k_pc2_solve, dim3((unsigned)nb), dim3(kWave), 0, st, a);
+    hipLaunchKernelGGL(k_pc2_fin_b, dim3(1), dim3(kRedThreads), 0, st, cx.partials, (int)nb, cx.ctl, 1);
+    LAUNCHCHK();
+    int32_t *pin = nullptr;
+    int e = pinned_buffer(&pin);
+    if (e != MAS_OK) return e;
+    hipEvent_t done[2] = {nullptr, nullptr};
+    HIPCHK(hipEventCreateWithFlags(&done[0], hipEventDisableTiming));
+    HIPCHK(hipEventCreateWithFlags(&done[1], hipEventDisableTiming));
+    struct EvGuard {
+        hipEvent_t *e;
+        ~EvGuard() {
+            (void)hipEventDestroy(e[0]);
+            (void)hipEventDestroy(e[1]);
+        }
+    } guard{done};
+    const Dims dm = s.dims();
+    const dim3 sgrid = s.simple_grid(), sblock(kWave, kSimpleJ);
+    a.update = 1;
+    int k = iter0, nbt = 0;
+    bool stop = false;
+    while (!stop && k < max_iter) {
+        const int kend = std::min(max_iter, k + 16);
+        for (; k < kend; ++k) {
+            // the first direction is z itself (beta = 0): p_old points at z
+            const double *p_old = (k == iter0) ? z : p[k & 1];
+            double *p_new = p[(k + 1) & 1];
+            const bool sample = cx.timing && (k % 16 == 7) && cx.ev.size() < 128;
+            if (sample) {
+                hipEvent_t e0, e1;
+                HIPCHK(hipEventCreate(&e0));
+                HIPCHK(hipEventCreate(&e1));
+                cx.ev.push_back(e0);
+                cx.ev.push_back(e1);
+                cx.ev_iter.push_back(k + 1);
+                HIPCHK(hipEventRecord(e0, st));
+            }
+            hipLaunchKernelGGL(k_pc2_spmv, sgrid, sblock, 0, st, op->c64[0], op->c64[1], op->c64[2],
+                               z, p_old, p_new, q, dm, cx.ctl, cx.partials);
+            hipLaunchKernelGGL(k_pc2_fin_a, dim3(1), dim3(kRedThreads), 0, st, cx.partials, nsimple,
+                               cx.ctl);
+            a.p = p_new;
+            hipLaunchKernelGGL(k_pc2_solve, dim3((unsigned)nb), dim3(kWave), 0, st, a);
+            hipLaunchKernelGGL(k_pc2_fin_b, dim3(1), dim3(kRedThreads), 0, st, cx.partials, (int)nb,
+                               cx.ctl, 0);
+            if (sample) HIPCHK(hipEventRecord(cx.ev.back(), st));
+        }
+        LAUNCHCHK();
+        HIPCHK(hipMemcpyAsync(pin + 2 * (nbt & 1), &cx.ctl->flag, 2 * sizeof(int32_t),
+                              hipMemcpyDeviceToHost, st));
+        HIPCHK(hipEventRecord(done[nbt & 1], st));
+        if (nbt > 0) {
+            HIPCHK(hipEventSynchronize(done[(nbt - 1) & 1]));
+            if (pin[2 * ((nbt - 1) & 1)] != FLAG_RUN) stop = true;
+        }
+        ++nbt;
+    }
+    HIPCHK(hipStreamSynchronize(st));
+    Ctl h;
+    e = read_ctl(cx, &h);
+    if (e != MAS_OK) return e;
+    res->flag[0] = h.flag;
+    res->last_iter[0] = (h.flag == FLAG_RUN) ? max_iter : h.conv_iter;
+    return MAS_OK;
+}
+
 // Record buffers of right-hand side h from the workspace layout.
 template <typename T>
 static void set_halo(RhsSet<T> &v, char *base, const WorkLayout &L, int h = 0) {
@@ -769,7 +866,58 @@ static int solve_core(const mas_op *op, const double *src, int src_is_rhs, doubl
         return MAS_OK;
     }
 
-    if (o.precision == MAS_FP64) {
+    if (o.precond == MAS_PC2) {
+        // vectors: r, z, p[2], q, and the modified diagonal
+        double *r = reinterpret_cast<double *>(base + L.vec[0][0]);
+        double *z = reinterpret_cast<double *>(base + L.vec[0][1]);
+        double *const p[2] = {reinterpret_cast<double *>(base + L.vec[0][2]),
+                              reinterpret_cast<double *>(base + L.vec[0][3])};
+        double *q = reinterpret_cast<double *>(base + L.vec[0][4]);
+        double *dm = reinterpret_cast<double *>(base + L.vec[0][5]);
+        int nbi, nbj, nbk;
+        const int64_t nb = pc2_blocks(s, &nbi, &nbj, &nbk);
+        if (nb * 2 * 8 > L.bhat[0] - L.partials || s.nblk_simple() * 8 > L.bhat[0] - L.partials)
+            return fail(MAS_EINVAL, "internal: partial-sum area too small for PC2");
+        if (nb > INT32_MAX) return fail(MAS_EINVAL, "grid too large for PC2");
+        Pc2Args fa{op->c64[0], op->c64[1], op->c64[2], op->w, dm, nullptr, nullptr, nullptr,
+                   nullptr, nullptr, nullptr, cx.ctl, d, nbi, nbj, nbk, 0};
+        hipLaunchKernelGGL(k_pc2_factor, dim3((unsigned)nb), dim3(kWave), 0, cx.stream, fa);
+        LAUNCHCHK();
+        double rw2 = 0.0;
+        st = residual<double>(cx, bhat, x, r, &rw2);
+        if (st != MAS_OK) return st;
+        info.rel_resid_true = info.rel_resid_recursive = std::sqrt(rw2) / bnorm;
+        status = (rw2 <= tol2) ? MAS_OK : MAS_ENOTCONV;
+        int iter0 = 0;
+        while (status != MAS_OK && iter0 < o.max_iters) {
+            PcgResult pr{};
+            st = run_pcg_pc2(cx, r, z, p, q, dm, x, iter0, o.max_iters, tol2, &pr);
+            if (st != MAS_OK) return st;
+            timing_summary(cx, pr.last_iter[0], &info);
+            info.iters = pr.last_iter[0];
+            Ctl h;
+            st = read_ctl(cx, &h);
+            if (st != MAS_OK) return st;
+            info.rel_resid_recursive = std::sqrt(h.rw) / bnorm;
+            st = residual<double>(cx, bhat, x, r, &rw2);
+            if (st != MAS_OK) return st;
+            info.rel_resid_true = std::sqrt(rw2) / bnorm;
+            if (rw2 <= tol2) {
+                status = MAS_OK;
+                break;
+            }
+            if (pr.flag[0] == FLAG_BREAK) {
+                status = MAS_EBREAKDOWN;
+                break;
+            }
+            if (pr.flag[0] != FLAG_CONV || info.restarts >= o.max_restarts) {
+                status = MAS_ENOTCONV;
+                break;
+            }
+            ++info.restarts;
+            iter0 = pr.last_iter[0];
+        }
+    } else if (o.precision == MAS_FP64) {
         RhsSet<double> v;
         v.n = 1;
         for (int t = 0; t < 2; ++t) {
@@ -1078,6 +1226,8 @@ extern "C" int mas_pcg_solve_multi(const mas_op *op, int32_t nrhs, const double 
     if (o_in) o = *o_in;
     if (o.precision != MAS_FP64)
         return fail(MAS_EINVAL, "solves of several right-hand sides are double precision only");
+    if (o.precond != MAS_PC1)
+        return fail(MAS_EINVAL, "solves of several right-hand sides use the PC1 preconditioner");
     int st = check_opts(op, &o);
     if (st != MAS_OK) return st;
     if (reinterpret_cast<uintptr_t>(work) & 255)

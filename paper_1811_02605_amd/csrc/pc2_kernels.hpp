@@ -1,0 +1,309 @@
+// PC2: block-Jacobi preconditioner with a zero-fill incomplete LU factor per
+// block (the paper, Section 2.2; MAS factors one block per MPI rank, and
+// Section 4.1 notes that its triangular solves are sequential and that PC1
+// performed about as well on GPUs).
+//
+// Blocks are boxes of kPc2I x kPc2J x kPc2K cells (r, theta, phi) tiling the
+// grid from index 0; couplings between blocks and the periodic phi coupling
+// are left out.  On the scaled system A^ = W^-1 A W^-1 (unit diagonal,
+// A^(c, nb) = -c^) with cells in natural order, ILU(0) of a box with the
+// 7-point graph changes only the diagonal:
+//     d_c = 1 - sum_{lower neighbours nb in the block} c^_{c,nb}^2 / d_nb,
+// and M^-1 r is
+//     forward   y_c = (r_c + sum_{lower nb} c^ y_nb) / d_c
+//     backward  z_c = y_c + (sum_{upper nb} c^ z_nb) / d_c.
+// (The ILU(0) factor of the scaled matrix is the scaled ILU(0) factor of A,
+// so PCG on A^ with it has the iterates of PCG on A with the ILU(0) of A.)
+//
+// Factor: one wave per block, lane (i', j') owns the column of kPc2K cells at
+// r offset i' and theta offset j', and the wave sweeps the hyperplanes
+// i' + j' + k' = level: a cell's lower neighbours in r and theta were
+// computed by lanes l - kPc2J and l - 1 on the previous level, its lower phi
+// neighbour by its own lane there.
+// Solve: one wave per block, lane k' owns phi offset k' (coalesced rows), and
+// the wave walks the block's (r, theta) rows in order.  The r and theta
+// terms come from the rows already done (kept in registers); along phi the
+// forward sweep is the first-order recurrence y_k = c_k y_{k-1} + b_k with
+// c_k = c^p_{k-1,k} / d_k, solved by a prefix scan of the affine maps
+// y -> c y + b across the lanes (the backward sweep scans the other way).
+#pragma once
+
+#include "kernels.hpp"
+
+namespace mas {
+
+constexpr int kPc2I = 8, kPc2J = 8, kPc2K = 64;
+static_assert(kPc2I * kPc2J == kWave, "one lane per (r, theta) column of a block");
+static_assert(kPc2K == kWave, "one lane per phi offset of a block");
+constexpr int kPc2Levels = kPc2I + kPc2J + kPc2K - 2;
+
+struct Pc2Args {
+    const double *cr, *ct, *cp;  // scaled couplings to the +r, +theta, +phi neighbours
+    const double *w;
+    double *d;                   // modified diagonal (written by the factor kernel)
+    double *r, *x, *z;           // solve: r -= alpha q, x += alpha p, z = M^-1 r
+    const double *q, *p;
+    double *partials;            // [blocks][2]: (r, z), ||W r||^2
+    const Ctl *ctl;
+    Dims dm;
+    int nbi, nbj, nbk;           // blocks per direction
+    int update;                  // solve: apply the alpha updates first
+};
+
+struct Pc2Col {
+    int ii, jj, i, j, k0, kn;
+    bool ok;
+    int srcLo_i, srcLo_j, srcUp_i, srcUp_j;
+};
+
+__device__ inline Pc2Col pc2_column(const Pc2Args &a) {
+    Pc2Col c;
+    const int blk = blockIdx.x;
+    const int bk = blk % a.nbk, bj = (blk / a.nbk) % a.nbj, bi = blk / (a.nbk * a.nbj);
+    const int lane = threadIdx.x;
+    c.ii = lane / kPc2J;
+    c.jj = lane % kPc2J;
+    c.i = bi * kPc2I + c.ii;
+    c.j = bj * kPc2J + c.jj;
+    c.k0 = bk * kPc2K;
+    c.kn = min(kPc2K, a.dm.np - c.k0);
+    c.ok = c.i < a.dm.nr && c.j < a.dm.nt;
+    c.srcLo_i = (c.ii > 0) ? lane - kPc2J : lane;
+    c.srcLo_j = (c.jj > 0) ? lane - 1 : lane;
+    c.srcUp_i = (c.ii < kPc2I - 1) ? lane + kPc2J : lane;
+    c.srcUp_j = (c.jj < kPc2J - 1) ? lane + 1 : lane;
+    return c;
+}
+
+// d_c for every cell of the block.
+__global__ __launch_bounds__(kWave) void k_pc2_factor(Pc2Args a) {
+    const Pc2Col col = pc2_column(a);
+    const Dims &dm = a.dm;
+    double prev = 0.0;  // this lane's value on the previous level
+    for (int lev = 0; lev < kPc2Levels; ++lev) {
+        const double vi = __shfl(prev, col.srcLo_i, kWave);
+        const double vj = __shfl(prev, col.srcLo_j, kWave);
+        const int kk = lev - col.ii - col.jj;
+        const bool act = col.ok && kk >= 0 && kk < col.kn;
+        double val = 0.0;
+        if (act) {
+            const int64_t c = ((int64_t)col.i * dm.nt + col.j) * dm.np + col.k0 + kk;
+            double s = 1.0;
+            if (col.ii > 0) {
+                const double e = a.cr[c - dm.plane];
+                s -= e * e / vi;
+            }
+            if (col.jj > 0) {
+                const double e = a.ct[c - dm.np];
+                s -= e * e / vj;
+            }
+            if (kk > 0) {
+                const double e = a.cp[c - 1];
+                s -= e * e / prev;
+            }
+            val = s;
+            a.d[c] = val;
+        }
+        prev = val;
+    }
+}
+
+// Inclusive scan of the affine maps y -> C y + B over the lanes, ascending
+// (each lane ends with the composition of its map after those of all lower
+// lanes) or descending.
+template <bool UP>
+__device__ inline double affine_scan(double C, double B, int lane) {
+#pragma unroll
+    for (int off = 1; off < kWave; off <<= 1) {
+        const double Cs = UP ? __shfl_up(C, off, kWave) : __shfl_down(C, off, kWave);
+        const double Bs = UP ? __shfl_up(B, off, kWave) : __shfl_down(B, off, kWave);
+        const bool has = UP ? lane >= off : lane + off < kWave;
+        if (has) {
+            B = C * Bs + B;
+            C = C * Cs;
+        }
+    }
+    return B;
+}
+
+// z = M^-1 r, first applying r -= alpha q and x += alpha p when a.update;
+// per-block partials (r, z) and ||W r||^2.
+__global__ __launch_bounds__(kWave) void k_pc2_solve(Pc2Args a) {
+    if (a.ctl->flag != FLAG_RUN) return;
+    const Dims &dm = a.dm;
+    const int blk = blockIdx.x;
+    const int bk = blk % a.nbk, bj = (blk / a.nbk) % a.nbj, bi = blk / (a.nbk * a.nbj);
+    const int lane = threadIdx.x;
+    const int k0 = bk * kPc2K;
+    const int kn = min(kPc2K, dm.np - k0);
+    const bool act = lane < kn;
+    const int k = k0 + (act ? lane : 0);
+    const int ni = min(kPc2I, dm.nr - bi * kPc2I), nj = min(kPc2J, dm.nt - bj * kPc2J);
+    const double alpha = a.update ? a.ctl->alpha : 0.0;
+    double rw = 0.0, rz = 0.0;
+    double yp[kPc2J];  // previous r plane of the block, one value per theta row
+    // forward sweep: y into z
+#pragma unroll
+    for (int jj = 0; jj < kPc2J; ++jj) yp[jj] = 0.0;
+    for (int ii = 0; ii < ni; ++ii) {
+        const int i = bi * kPc2I + ii;
+        double yrow = 0.0;  // previous theta row
+#pragma unroll
+        for (int jj = 0; jj < kPc2J; ++jj) {
+            if (jj < nj) {
+                const int j = bj * kPc2J + jj;
+                const int64_t c = ((int64_t)i * dm.nt + j) * dm.np + k;
+                double Bc = 0.0, Cc = 0.0;
+                if (act) {
+                    double rc = a.r[c];
+                    if (a.update) {
+                        rc -= alpha * a.q[c];
+                        a.r[c] = rc;
+                        a.x[c] += alpha * a.p[c];
+                    }
+                    const double t = a.w[c] * rc;
+                    rw += t * t;
+                    double sc = rc;
+                    if (ii > 0) sc += a.cr[c - dm.plane] * yp[jj];
+                    if (jj > 0) sc += a.ct[c - dm.np] * yrow;
+                    const double dinv = 1.0 / a.d[c];
+                    Bc = sc * dinv;
+                    Cc = (lane > 0) ? a.cp[c - 1] * dinv : 0.0;
+                }
+                const double y = affine_scan<true>(Cc, Bc, lane);
+                if (act) a.z[c] = y;
+                yp[jj] = y;
+                yrow = y;
+            }
+        }
+    }
+    // backward sweep: z in place
+#pragma unroll
+    for (int jj = 0; jj < kPc2J; ++jj) yp[jj] = 0.0;
+    for (int ii = ni - 1; ii >= 0; --ii) {
+        const int i = bi * kPc2I + ii;
+        double zrow = 0.0;  // next theta row
+#pragma unroll
+        for (int jj = kPc2J - 1; jj >= 0; --jj) {
+            if (jj < nj) {
+                const int j = bj * kPc2J + jj;
+                const int64_t c = ((int64_t)i * dm.nt + j) * dm.np + k;
+                double Bc = 0.0, Cc = 0.0;
+                if (act) {
+                    double sc = 0.0;
+                    if (ii < ni - 1) sc += a.cr[c] * yp[jj];
+                    if (jj < nj - 1) sc += a.ct[c] * zrow;
+                    const double dinv = 1.0 / a.d[c];
+                    Bc = a.z[c] + sc * dinv;
+                    Cc = (lane < kn - 1) ? a.cp[c] * dinv : 0.0;
+                }
+                const double z = affine_scan<false>(Cc, Bc, lane);
+                if (act) {
+                    a.z[c] = z;
+                    rz += a.r[c] * z;
+                }
+                yp[jj] = z;
+                zrow = z;
+            }
+        }
+    }
+    __shared__ double lds[2];
+    double v2[2] = {rz, rw};
+    block_sum_store<2>(v2, a.partials + (int64_t)blockIdx.x * 2, lds);
+}
+
+// p = z + beta p_old (also at the neighbours), q = A^ p, partial (p, q).
+__global__ __launch_bounds__(kWave *kSimpleJ) void k_pc2_spmv(const double *cr, const double *ct,
+                                                              const double *cp, const double *z,
+                                                              const double *p_old, double *p_new,
+                                                              double *q, Dims d, const Ctl *ctl,
+                                                              double *partials) {
+    if (ctl->flag != FLAG_RUN) return;
+    const double beta = ctl->beta;
+    __shared__ double lds[kSimpleJ];
+    double acc[1] = {0.0};
+    MAS_SIMPLE_LOOP(d, {
+        if (cell.ok) {
+            auto pn = [&](int64_t c) { return z[c] + beta * p_old[c]; };
+            const double pc = pn(cell.c);
+            const double qc = scaled_apply(cr, ct, cp, d, cell, pn);
+            p_new[cell.c] = pc;
+            q[cell.c] = qc;
+            acc[0] += pc * qc;
+        }
+    })
+    block_sum_store<1>(acc, partials + simple_block_id(), lds);
+}
+
+// After the SpMV: alpha = (r, z) / (p, q) (or a breakdown).
+__global__ __launch_bounds__(kRedThreads) void k_pc2_fin_a(const double *partials, int nblk,
+                                                           Ctl *ctl) {
+    if (ctl->flag != FLAG_RUN) return;
+    __shared__ double sh[kRedThreads];
+    double v = 0.0;
+    for (int b = threadIdx.x; b < nblk; b += kRedThreads) v += partials[b];
+    sh[threadIdx.x] = v;
+    __syncthreads();
+    for (int s = kRedThreads / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x != 0) return;
+    const double PQ = sh[0];
+    ctl->pq = PQ;
+    if (!(PQ > 0.0) || !isfinite(PQ)) {
+        ctl->flag = FLAG_BREAK;
+        ctl->conv_iter = ctl->iter;
+        ctl->alpha = 0.0;
+        return;
+    }
+    ctl->alpha = ctl->rr / PQ;
+}
+
+// After the preconditioner solve: (r, z), ||W r||^2, stopping test, beta.
+// ctl->iter counts finished iterations; is_first marks the solve of the
+// initial residual (no iteration finished yet).
+__global__ __launch_bounds__(kRedThreads) void k_pc2_fin_b(const double *partials, int nblk,
+                                                           Ctl *ctl, int is_first) {
+    if (ctl->flag != FLAG_RUN) return;
+    __shared__ double sh[kRedThreads * 2];
+    double v0 = 0.0, v1 = 0.0;
+    for (int b = threadIdx.x; b < nblk; b += kRedThreads) {
+        v0 += partials[(int64_t)b * 2];
+        v1 += partials[(int64_t)b * 2 + 1];
+    }
+    sh[threadIdx.x * 2] = v0;
+    sh[threadIdx.x * 2 + 1] = v1;
+    __syncthreads();
+    for (int s = kRedThreads / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) {
+            sh[threadIdx.x * 2] += sh[(threadIdx.x + s) * 2];
+            sh[threadIdx.x * 2 + 1] += sh[(threadIdx.x + s) * 2 + 1];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x != 0) return;
+    const double RZ = sh[0], RW = sh[1];
+    const int k = is_first ? ctl->iter : ctl->iter + 1;
+    ctl->iter = k;
+    ctl->rw = RW;
+    if (RW <= ctl->tol2 || RW == 0.0) {
+        ctl->flag = FLAG_CONV;
+        ctl->conv_iter = k;
+        return;
+    }
+    if (k >= ctl->max_iter) {
+        ctl->flag = FLAG_MAXIT;
+        ctl->conv_iter = k;
+        return;
+    }
+    if (!(RZ > 0.0) || !isfinite(RZ)) {
+        ctl->flag = FLAG_BREAK;
+        ctl->conv_iter = k;
+        return;
+    }
+    ctl->beta = is_first ? 0.0 : RZ / ctl->rr;
+    ctl->rr = RZ;
+}
+
+}  // namespace mas

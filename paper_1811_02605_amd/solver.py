@@ -57,19 +57,23 @@ class Grid:
 
 
 REFINES = {"restart": abi.MAS_REFINE_RESTART, "reliable": abi.MAS_REFINE_RELIABLE}
+PRECONDS = {"pc1": abi.MAS_PC1, "pc2": abi.MAS_PC2}
 
 
 def make_opts(rtol=None, max_iters=None, precision=None, inner_rtol=None, max_outer=None,
-              check_every=None, use_x0=None, max_restarts=None, sample_timing=None, refine=None):
+              check_every=None, use_x0=None, max_restarts=None, sample_timing=None, refine=None,
+              precond=None):
     o = abi.default_opts()
     if isinstance(precision, str):
         precision = PRECISIONS[precision]
     if isinstance(refine, str):
         refine = REFINES[refine]
+    if isinstance(precond, str):
+        precond = PRECONDS[precond]
     for name, v in dict(rtol=rtol, max_iters=max_iters, precision=precision,
                         inner_rtol=inner_rtol, max_outer=max_outer, check_every=check_every,
                         use_x0=use_x0, max_restarts=max_restarts,
-                        sample_timing=sample_timing, refine=refine).items():
+                        sample_timing=sample_timing, refine=refine, precond=precond).items():
         if v is not None:
             setattr(o, name, type(getattr(o, name))(v))
     return o

@@ -108,21 +108,38 @@ __global__ __launch_bounds__(kWave) void k_pc2_factor(Pc2Args a) {
     }
 }
 
-// Inclusive scan of the affine maps y -> C y + B over the lanes, ascending
-// (each lane ends with the composition of its map after those of all lower
-// lanes) or descending.
-template <bool UP>
-__device__ inline double affine_scan(double C, double B, int lane) {
-#pragma unroll
-    for (int off = 1; off < kWave; off <<= 1) {
-        const double Cs = UP ? __shfl_up(C, off, kWave) : __shfl_down(C, off, kWave);
-        const double Bs = UP ? __shfl_up(B, off, kWave) : __shfl_down(B, off, kWave);
-        const bool has = UP ? lane >= off : lane + off < kWave;
-        if (has) {
-            B = C * Bs + B;
-            C = C * Cs;
-        }
-    }
+// Inclusive scan of the affine maps y -> C y + B over the 64 lanes in lane
+// order: each lane ends with the composition of its own map after those of
+// all lower lanes, i.e. B = y_lane for y_-1 = 0.  DPP moves (GFX9 family):
+// row_shr by 1, 2, 4, 8 inside each 16-lane row, then row_bcast:15 (the last
+// lane of rows 0 and 2 to rows 1 and 3) and row_bcast:31 (lane 31 to rows 2
+// and 3).  A lane that receives nothing gets the identity map (1, 0), which
+// composes as a no-op.
+template <int CTRL, int ROWS>
+__device__ inline double dpp_or(double v, double identity) {
+    const uint64_t b = __builtin_bit_cast(uint64_t, v), o = __builtin_bit_cast(uint64_t, identity);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp((int)(uint32_t)o, (int)(uint32_t)b,
+                                                              CTRL, ROWS, 0xf, false);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_update_dpp((int)(uint32_t)(o >> 32),
+                                                              (int)(uint32_t)(b >> 32), CTRL, ROWS,
+                                                              0xf, false);
+    return __builtin_bit_cast(double, (uint64_t)lo | ((uint64_t)hi << 32));
+}
+
+template <int CTRL, int ROWS>
+__device__ inline void affine_step(double &C, double &B) {
+    const double Cs = dpp_or<CTRL, ROWS>(C, 1.0), Bs = dpp_or<CTRL, ROWS>(B, 0.0);
+    B = C * Bs + B;
+    C = C * Cs;
+}
+
+__device__ inline double affine_scan(double C, double B) {
+    affine_step<0x111, 0xf>(C, B);  // row_shr:1
+    affine_step<0x112, 0xf>(C, B);  // row_shr:2
+    affine_step<0x114, 0xf>(C, B);  // row_shr:4
+    affine_step<0x118, 0xf>(C, B);  // row_shr:8
+    affine_step<0x142, 0xa>(C, B);  // row_bcast:15 into rows 1 and 3
+    affine_step<0x143, 0xc>(C, B);  // row_bcast:31 into rows 2 and 3
     return B;
 }
 
@@ -140,6 +157,12 @@ __global__ __launch_bounds__(kWave) void k_pc2_solve(Pc2Args a) {
     const int k = k0 + (act ? lane : 0);
     const int ni = min(kPc2I, dm.nr - bi * kPc2I), nj = min(kPc2J, dm.nt - bj * kPc2J);
     const double alpha = a.update ? a.ctl->alpha : 0.0;
+    // distinct arrays: lets the compiler issue later rows' loads ahead of
+    // earlier rows' stores
+    const double *__restrict__ cr = a.cr, *__restrict__ ct = a.ct, *__restrict__ cp = a.cp;
+    const double *__restrict__ w = a.w, *__restrict__ dd = a.d, *__restrict__ q = a.q;
+    const double *__restrict__ pp = a.p;
+    double *__restrict__ r = a.r, *__restrict__ x = a.x, *__restrict__ z = a.z;
     double rw = 0.0, rz = 0.0;
     double yp[kPc2J];  // previous r plane of the block, one value per theta row
     // forward sweep: y into z
@@ -155,29 +178,31 @@ __global__ __launch_bounds__(kWave) void k_pc2_solve(Pc2Args a) {
                 const int64_t c = ((int64_t)i * dm.nt + j) * dm.np + k;
                 double Bc = 0.0, Cc = 0.0;
                 if (act) {
-                    double rc = a.r[c];
+                    double rc = r[c];
                     if (a.update) {
-                        rc -= alpha * a.q[c];
-                        a.r[c] = rc;
-                        a.x[c] += alpha * a.p[c];
+                        rc -= alpha * q[c];
+                        r[c] = rc;
+                        x[c] += alpha * pp[c];
                     }
-                    const double t = a.w[c] * rc;
+                    const double t = w[c] * rc;
                     rw += t * t;
                     double sc = rc;
-                    if (ii > 0) sc += a.cr[c - dm.plane] * yp[jj];
-                    if (jj > 0) sc += a.ct[c - dm.np] * yrow;
-                    const double dinv = 1.0 / a.d[c];
+                    if (ii > 0) sc += cr[c - dm.plane] * yp[jj];
+                    if (jj > 0) sc += ct[c - dm.np] * yrow;
+                    const double dinv = 1.0 / dd[c];
                     Bc = sc * dinv;
-                    Cc = (lane > 0) ? a.cp[c - 1] * dinv : 0.0;
+                    Cc = (lane > 0) ? cp[c - 1] * dinv : 0.0;
                 }
-                const double y = affine_scan<true>(Cc, Bc, lane);
-                if (act) a.z[c] = y;
+                const double y = affine_scan(Cc, Bc);
+                if (act) z[c] = y;
                 yp[jj] = y;
                 yrow = y;
             }
         }
     }
-    // backward sweep: z in place
+    // backward sweep: z in place; lane l takes phi offset kn-1-l, so the
+    // recurrence z_k = c_k z_{k+1} + b_k runs up the lanes again
+    const int kb = k0 + (act ? kn - 1 - lane : 0);
 #pragma unroll
     for (int jj = 0; jj < kPc2J; ++jj) yp[jj] = 0.0;
     for (int ii = ni - 1; ii >= 0; --ii) {
@@ -187,23 +212,23 @@ __global__ __launch_bounds__(kWave) void k_pc2_solve(Pc2Args a) {
         for (int jj = kPc2J - 1; jj >= 0; --jj) {
             if (jj < nj) {
                 const int j = bj * kPc2J + jj;
-                const int64_t c = ((int64_t)i * dm.nt + j) * dm.np + k;
+                const int64_t c = ((int64_t)i * dm.nt + j) * dm.np + kb;
                 double Bc = 0.0, Cc = 0.0;
                 if (act) {
                     double sc = 0.0;
-                    if (ii < ni - 1) sc += a.cr[c] * yp[jj];
-                    if (jj < nj - 1) sc += a.ct[c] * zrow;
-                    const double dinv = 1.0 / a.d[c];
-                    Bc = a.z[c] + sc * dinv;
-                    Cc = (lane < kn - 1) ? a.cp[c] * dinv : 0.0;
+                    if (ii < ni - 1) sc += cr[c] * yp[jj];
+                    if (jj < nj - 1) sc += ct[c] * zrow;
+                    const double dinv = 1.0 / dd[c];
+                    Bc = z[c] + sc * dinv;
+                    Cc = (lane > 0) ? cp[c] * dinv : 0.0;
                 }
-                const double z = affine_scan<false>(Cc, Bc, lane);
+                const double zc = affine_scan(Cc, Bc);
                 if (act) {
-                    a.z[c] = z;
-                    rz += a.r[c] * z;
+                    z[c] = zc;
+                    rz += r[c] * zc;
                 }
-                yp[jj] = z;
-                zrow = z;
+                yp[jj] = zc;
+                zrow = zc;
             }
         }
     }

@@ -144,7 +144,16 @@ __device__ inline double affine_scan(double C, double B) {
 }
 
 // z = M^-1 r, first applying r -= alpha q and x += alpha p when a.update;
-// per-block partials (r, z) and ||W r||^2.
+// per-block partials (r, z) and ||W r||^2.  Each sweep loads the next row's
+// inputs before it scans the current row, so a wave keeps one row of loads
+// in flight behind its scans.
+struct Pc2Fwd {
+    double r, q, x, p, w, d, cr, ct, cp;
+};
+struct Pc2Bwd {
+    double cr, ct, d, y, cp, r;
+};
+
 __global__ __launch_bounds__(kWave) void k_pc2_solve(Pc2Args a) {
     if (a.ctl->flag != FLAG_RUN) return;
     const Dims &dm = a.dm;
@@ -156,79 +165,117 @@ __global__ __launch_bounds__(kWave) void k_pc2_solve(Pc2Args a) {
     const bool act = lane < kn;
     const int k = k0 + (act ? lane : 0);
     const int ni = min(kPc2I, dm.nr - bi * kPc2I), nj = min(kPc2J, dm.nt - bj * kPc2J);
-    const double alpha = a.update ? a.ctl->alpha : 0.0;
+    const bool upd = a.update != 0;
+    const double alpha = upd ? a.ctl->alpha : 0.0;
     // distinct arrays: lets the compiler issue later rows' loads ahead of
     // earlier rows' stores
     const double *__restrict__ cr = a.cr, *__restrict__ ct = a.ct, *__restrict__ cp = a.cp;
     const double *__restrict__ w = a.w, *__restrict__ dd = a.d, *__restrict__ q = a.q;
     const double *__restrict__ pp = a.p;
     double *__restrict__ r = a.r, *__restrict__ x = a.x, *__restrict__ z = a.z;
+    auto cell = [&](int ii, int jj, int kk) -> int64_t {
+        return ((int64_t)(bi * kPc2I + ii) * dm.nt + (bj * kPc2J + jj)) * dm.np + kk;
+    };
+    auto load_f = [&](int ii, int jj) {
+        Pc2Fwd v{0, 0, 0, 0, 0, 1, 0, 0, 0};
+        if (act && ii < ni && jj < nj) {
+            const int64_t c = cell(ii, jj, k);
+            v.r = r[c];
+            if (upd) {
+                v.q = q[c];
+                v.x = x[c];
+                v.p = pp[c];
+            }
+            v.w = w[c];
+            v.d = dd[c];
+            if (ii > 0) v.cr = cr[c - dm.plane];
+            if (jj > 0) v.ct = ct[c - dm.np];
+            if (lane > 0) v.cp = cp[c - 1];
+        }
+        return v;
+    };
     double rw = 0.0, rz = 0.0;
     double yp[kPc2J];  // previous r plane of the block, one value per theta row
     // forward sweep: y into z
 #pragma unroll
     for (int jj = 0; jj < kPc2J; ++jj) yp[jj] = 0.0;
+    Pc2Fwd cur = load_f(0, 0);
     for (int ii = 0; ii < ni; ++ii) {
-        const int i = bi * kPc2I + ii;
         double yrow = 0.0;  // previous theta row
 #pragma unroll
         for (int jj = 0; jj < kPc2J; ++jj) {
             if (jj < nj) {
-                const int j = bj * kPc2J + jj;
-                const int64_t c = ((int64_t)i * dm.nt + j) * dm.np + k;
+                const Pc2Fwd nxt = (jj + 1 < nj) ? load_f(ii, jj + 1) : load_f(ii + 1, 0);
                 double Bc = 0.0, Cc = 0.0;
+                double rc = cur.r;
                 if (act) {
-                    double rc = r[c];
-                    if (a.update) {
-                        rc -= alpha * q[c];
-                        r[c] = rc;
-                        x[c] += alpha * pp[c];
-                    }
-                    const double t = w[c] * rc;
+                    if (upd) rc -= alpha * cur.q;
+                    const double t = cur.w * rc;
                     rw += t * t;
                     double sc = rc;
-                    if (ii > 0) sc += cr[c - dm.plane] * yp[jj];
-                    if (jj > 0) sc += ct[c - dm.np] * yrow;
-                    const double dinv = 1.0 / dd[c];
+                    if (ii > 0) sc += cur.cr * yp[jj];
+                    if (jj > 0) sc += cur.ct * yrow;
+                    const double dinv = 1.0 / cur.d;
                     Bc = sc * dinv;
-                    Cc = (lane > 0) ? cp[c - 1] * dinv : 0.0;
+                    Cc = cur.cp * dinv;
                 }
                 const double y = affine_scan(Cc, Bc);
-                if (act) z[c] = y;
+                if (act) {
+                    const int64_t c = cell(ii, jj, k);
+                    if (upd) {
+                        r[c] = rc;
+                        x[c] = cur.x + alpha * cur.p;
+                    }
+                    z[c] = y;
+                }
                 yp[jj] = y;
                 yrow = y;
+                cur = nxt;
             }
         }
     }
     // backward sweep: z in place; lane l takes phi offset kn-1-l, so the
     // recurrence z_k = c_k z_{k+1} + b_k runs up the lanes again
     const int kb = k0 + (act ? kn - 1 - lane : 0);
+    auto load_b = [&](int ii, int jj) {
+        Pc2Bwd v{0, 0, 1, 0, 0, 0};
+        if (act && ii >= 0 && jj >= 0) {
+            const int64_t c = cell(ii, jj, kb);
+            if (ii < ni - 1) v.cr = cr[c];
+            if (jj < nj - 1) v.ct = ct[c];
+            v.d = dd[c];
+            v.y = z[c];
+            if (lane > 0) v.cp = cp[c];
+            v.r = r[c];
+        }
+        return v;
+    };
 #pragma unroll
     for (int jj = 0; jj < kPc2J; ++jj) yp[jj] = 0.0;
+    Pc2Bwd bcur = load_b(ni - 1, nj - 1);
     for (int ii = ni - 1; ii >= 0; --ii) {
-        const int i = bi * kPc2I + ii;
         double zrow = 0.0;  // next theta row
 #pragma unroll
         for (int jj = kPc2J - 1; jj >= 0; --jj) {
             if (jj < nj) {
-                const int j = bj * kPc2J + jj;
-                const int64_t c = ((int64_t)i * dm.nt + j) * dm.np + kb;
+                const Pc2Bwd nxt = (jj > 0) ? load_b(ii, jj - 1) : load_b(ii - 1, nj - 1);
                 double Bc = 0.0, Cc = 0.0;
                 if (act) {
                     double sc = 0.0;
-                    if (ii < ni - 1) sc += cr[c] * yp[jj];
-                    if (jj < nj - 1) sc += ct[c] * zrow;
-                    const double dinv = 1.0 / dd[c];
-                    Bc = z[c] + sc * dinv;
-                    Cc = (lane > 0) ? cp[c] * dinv : 0.0;
+                    if (ii < ni - 1) sc += bcur.cr * yp[jj];
+                    if (jj < nj - 1) sc += bcur.ct * zrow;
+                    const double dinv = 1.0 / bcur.d;
+                    Bc = bcur.y + sc * dinv;
+                    Cc = bcur.cp * dinv;
                 }
                 const double zc = affine_scan(Cc, Bc);
                 if (act) {
-                    z[c] = zc;
-                    rz += r[c] * zc;
+                    z[cell(ii, jj, kb)] = zc;
+                    rz += bcur.r * zc;
                 }
                 yp[jj] = zc;
                 zrow = zc;
+                bcur = nxt;
             }
         }
     }

@@ -501,12 +501,15 @@ void k_pcg_iter(IterArgs<T> a) {
     __amdgpu_buffer_rsrc_t Rr[NR], Rq[NR], Rp[NR], Rx[NR], Rro[NR], Rpo[NR], Rqo[NR];
 #pragma unroll
     for (int c = 0; c < NR; ++c) {
+        // q_in, x and r_out may be null: the kernel then only forms the
+        // direction p = r + beta p and q = A^ p (q reads as zero, so r and x
+        // are left as they are and move no bytes)
         const uint32_t nb = run[c] ? nbytes : 0u;
         Rr[c] = make_rsrc(a.r_in[c], nb);
-        Rq[c] = make_rsrc(a.q_in[c], nb);
+        Rq[c] = make_rsrc(a.q_in[c], a.q_in[c] ? nb : 0u);
         Rp[c] = make_rsrc(a.p_in[c], nb);
-        Rx[c] = make_rsrc(a.x[c], nb);
-        Rro[c] = make_rsrc(a.r_out[c], nb);
+        Rx[c] = make_rsrc(a.x[c], a.x[c] ? nb : 0u);
+        Rro[c] = make_rsrc(a.r_out[c], a.r_out[c] ? nb : 0u);
         Rpo[c] = make_rsrc(a.p_out[c], nb);
         Rqo[c] = make_rsrc(a.q_out[c], nb);
     }

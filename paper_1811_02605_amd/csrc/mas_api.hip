@@ -728,7 +728,6 @@ static int run_pcg_pc2(Ctx &cx, double *r, double *z, double *const p[2], double
     hipStream_t st = cx.stream;
     int nbi, nbj, nbk;
     const int64_t nb = pc2_blocks(s, &nbi, &nbj, &nbk);
-    const int nsimple = (int)s.nblk_simple();
     hipLaunchKernelGGL(k_ctl_init, dim3(1), dim3(64), 0, st, cx.ctl, 0, iter0, max_iter, tol2, 0.0,
                        (int)FLAG_RUN);
     Pc2Args a{op->c64[0], op->c64[1], op->c64[2], op->w, d, r, x, z, q, nullptr, cx.partials,
@@ -750,8 +749,25 @@ static int run_pcg_pc2(Ctx &cx, double *r, double *z, double *const p[2], double
             (void)hipEventDestroy(e[1]);
         }
     } guard{done};
-    const Dims dm = s.dims();
-    const dim3 sgrid = s.simple_grid(), sblock(kWave, kSimpleJ);
+    // the direction and SpMV step: the PCG iteration kernel with no r, q or
+    // x (p = z + beta p, q = A^ p, partial (p, q) first of each block's kNV)
+    IterArgs<double> it{};
+    it.cr = op->c64[0];
+    it.ct = op->c64[1];
+    it.cp = op->c64[2];
+    it.w = op->w;
+    it.partials = cx.partials;
+    it.ctl = cx.ctl;
+    it.d = s.dims();
+    const int V = iter_vec<double>(s.np, 1);
+    it.tiles_i = s.tiles_i();
+    it.tiles_k = s.tiles_k(V);
+    it.tiles_j = s.tiles_j();
+    it.ti = kTI;
+    it.nblk = (int)s.nblk_iter(V);
+    it.halo_bytes = 0;
+    constexpr int VW = vec_full<double>();
+    const dim3 igrid((unsigned)it.nblk), iblock(kWave * kTJ);
     a.update = 1;
     int k = iter0, nbt = 0;
     bool stop = false;
@@ -771,10 +787,18 @@ static int run_pcg_pc2(Ctx &cx, double *r, double *z, double *const p[2], double
                 cx.ev_iter.push_back(k + 1);
                 HIPCHK(hipEventRecord(e0, st));
             }
-            hipLaunchKernelGGL(k_pc2_spmv, sgrid, sblock, 0, st, op->c64[0], op->c64[1], op->c64[2],
-                               z, p_old, p_new, q, dm, cx.ctl, cx.partials);
-            hipLaunchKernelGGL(k_pc2_fin_a, dim3(1), dim3(kRedThreads), 0, st, cx.partials, nsimple,
-                               cx.ctl);
+            it.r_in[0] = z;
+            it.p_in[0] = p_old;
+            it.p_out[0] = p_new;
+            it.q_out[0] = q;
+            if (V == VW)
+                hipLaunchKernelGGL((k_pcg_iter<double, 1, kTJ, kRPW, VW, false, false>), igrid, iblock,
+                                   0, st, it);
+            else
+                hipLaunchKernelGGL((k_pcg_iter<double, 1, kTJ, kRPW, 1, false, false>), igrid, iblock,
+                                   0, st, it);
+            hipLaunchKernelGGL(k_pc2_fin_a, dim3(1), dim3(kRedThreads), 0, st, cx.partials, it.nblk,
+                               (int)kNV, cx.ctl);
             a.p = p_new;
             hipLaunchKernelGGL(k_pc2_solve, dim3((unsigned)nb), dim3(kWave), 0, st, a);
             hipLaunchKernelGGL(k_pc2_fin_b, dim3(1), dim3(kRedThreads), 0, st, cx.partials, (int)nb,

@@ -14,6 +14,8 @@
 //     backward  z_c = y_c + (sum_{upper nb} c^ z_nb) / d_c.
 // (The ILU(0) factor of the scaled matrix is the scaled ILU(0) factor of A,
 // so PCG on A^ with it has the iterates of PCG on A with the ILU(0) of A.)
+// The direction and SpMV step of a PC2 iteration (p = z + beta p, q = A^ p,
+// (p, q)) is the PCG iteration kernel run without r, q and x inputs.
 //
 // Factor: one wave per block, lane (i', j') owns the column of kPc2K cells at
 // r offset i' and theta offset j', and the wave sweeps the hyperplanes
@@ -284,36 +286,14 @@ __global__ __launch_bounds__(kWave) void k_pc2_solve(Pc2Args a) {
     block_sum_store<2>(v2, a.partials + (int64_t)blockIdx.x * 2, lds);
 }
 
-// p = z + beta p_old (also at the neighbours), q = A^ p, partial (p, q).
-__global__ __launch_bounds__(kWave *kSimpleJ) void k_pc2_spmv(const double *cr, const double *ct,
-                                                              const double *cp, const double *z,
-                                                              const double *p_old, double *p_new,
-                                                              double *q, Dims d, const Ctl *ctl,
-                                                              double *partials) {
-    if (ctl->flag != FLAG_RUN) return;
-    const double beta = ctl->beta;
-    __shared__ double lds[kSimpleJ];
-    double acc[1] = {0.0};
-    MAS_SIMPLE_LOOP(d, {
-        if (cell.ok) {
-            auto pn = [&](int64_t c) { return z[c] + beta * p_old[c]; };
-            const double pc = pn(cell.c);
-            const double qc = scaled_apply(cr, ct, cp, d, cell, pn);
-            p_new[cell.c] = pc;
-            q[cell.c] = qc;
-            acc[0] += pc * qc;
-        }
-    })
-    block_sum_store<1>(acc, partials + simple_block_id(), lds);
-}
-
-// After the SpMV: alpha = (r, z) / (p, q) (or a breakdown).
+// After the SpMV: alpha = (r, z) / (p, q) (or a breakdown); (p, q) is the
+// first of every `stride` partials.
 __global__ __launch_bounds__(kRedThreads) void k_pc2_fin_a(const double *partials, int nblk,
-                                                           Ctl *ctl) {
+                                                           int stride, Ctl *ctl) {
     if (ctl->flag != FLAG_RUN) return;
     __shared__ double sh[kRedThreads];
     double v = 0.0;
-    for (int b = threadIdx.x; b < nblk; b += kRedThreads) v += partials[b];
+    for (int b = threadIdx.x; b < nblk; b += kRedThreads) v += partials[(int64_t)b * stride];
     sh[threadIdx.x] = v;
     __syncthreads();
     for (int s = kRedThreads / 2; s > 0; s >>= 1) {

@@ -45,12 +45,14 @@ ALG_BYTES_PER_CELL = {"fp64": 14 * 8, "fp32": 14 * 4}
 # q, p, x, c_r, c_theta, c_phi; writes r, p, x, q): 11 words.
 KERNEL_BYTES_PER_CELL = {"fp64": 11 * 8, "fp32": 11 * 4}
 # One RKL2 stage kernel per cell: reads D_{j-1}, nu, D_{j-2}, L_0, writes D_j.
-STS_BYTES_PER_CELL = 5 * 8
+STS_BYTES_PER_CELL = 5 * 8        # one-stage kernel: reads X, nu, Z, L0; writes the stage
+STS_PAIR_BYTES_PER_CELL = 6 * 8   # two-stage kernel: reads X, nu, Z, L0; writes both stages
 CSRC = os.path.join(ROOT, "paper_1811_02605_amd", "csrc")
 KERNEL_SRC = os.path.join(CSRC, "kernels.hpp")
 STS_KERNEL_SRC = os.path.join(CSRC, "sts_kernels.hpp")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "pcg_iter_fp64_c1_traffic.txt")
 STS_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "sts_stage_c1_traffic.txt")
+STS_PAIR_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "sts_pair_c1_traffic.txt")
 
 
 def kernel_hash(*paths) -> str:
@@ -153,37 +155,56 @@ def bench_pc2(S, grid, nu, rhs, p, t_pcg, iters_pc1):
 def bench_sts(S, grid, nu, rhs, p, t_pcg, steps):
     """The explicit alternative for the same viscous step: one RKL2 super
     time-step of the same dt on the same grid and viscosity (u0 = the smooth
-    right-hand-side field), timed with events on the library's stream."""
-    import numpy as np
+    right-hand-side field), timed with events on the library's stream; stages
+    two per kernel (the default) and one per kernel."""
     import torch
 
     op = S.Operator(grid, nu, p.dt, precision="fp64")
-    u = rhs.clone()
-    _, info = op.sts_step(u, sample_timing=True)  # warm-up, stage-kernel sample
-    torch.cuda.synchronize()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record()
-    for _ in range(steps):
-        op.sts_step(u, out=u)
-    e1.record()
-    torch.cuda.synchronize()
-    step_s = e0.elapsed_time(e1) * 1e-3 / steps
-    k_us = info["stage_kernel_us"] if info["stage_kernel_samples"] > 0 else None
-    gbs = STS_BYTES_PER_CELL * grid.n / (k_us * 1e-6) / 1e9 if k_us else None
-    print(f"[bench] RKL2: {info['stages']} stages, {1e3 * step_s:.2f} ms per step, stage kernel "
-          f"{k_us} us", file=sys.stderr, flush=True)
+
+    def run(pairs):
+        u = rhs.clone()
+        _, info = op.sts_step(u, sample_timing=True, stage_pairs=pairs)  # warm-up, kernel sample
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(steps):
+            op.sts_step(u, out=u, stage_pairs=pairs)
+        e1.record()
+        torch.cuda.synchronize()
+        k_us = info["stage_kernel_us"] if info["stage_kernel_samples"] > 0 else None
+        return e0.elapsed_time(e1) * 1e-3 / steps, k_us, info
+
+    step_s, k_us, info = run(True)
+    step1_s, k1_us, info1 = run(False)
+    paired = info["stages_per_kernel"] == 2
+    bpc = STS_PAIR_BYTES_PER_CELL if paired else STS_BYTES_PER_CELL
+    gbs = bpc * grid.n / (k_us * 1e-6) / 1e9 if k_us else None
+    gbs1 = STS_BYTES_PER_CELL * grid.n / (k1_us * 1e-6) / 1e9 if k1_us else None
+    print(f"[bench] RKL2: {info['stages']} stages, {1e3 * step_s:.2f} ms per step (stage kernel "
+          f"{k_us} us, {info['stages_per_kernel']} stages each); one stage per kernel "
+          f"{1e3 * step1_s:.2f} ms (kernel {k1_us} us)", file=sys.stderr, flush=True)
     return {
         "what": "one RKL2 super time-step of the same dt, nu and grid (explicit alternative to "
                 "the implicit solve)",
         "stages": info["stages"], "z_max": info["z_max"],
+        "stages_per_kernel": info["stages_per_kernel"],
         "step_ms": 1e3 * step_s,
         "speedup_vs_fp64_pcg_solve": t_pcg / step_s,
-        "roofline": {"bound": "hbm", "kernel": "k_sts_stage (one RKL2 stage)",
-                     "alg_bytes_per_cell": STS_BYTES_PER_CELL, "kernel_us": k_us,
+        "step_ms_one_stage_per_kernel": 1e3 * step1_s,
+        "roofline": {"bound": "hbm",
+                     "kernel": ("k_sts_pair (two RKL2 stages per launch)" if paired
+                                else "k_sts_stage (one RKL2 stage)"),
+                     "alg_bytes_per_cell": bpc, "kernel_us": k_us,
+                     "kernel_us_per_stage": (k_us / info["stages_per_kernel"]) if k_us else None,
                      "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": (gbs / HBM_PEAK_GBS) if gbs else None,
                      "samples": info["stage_kernel_samples"],
-                     "traffic": read_traffic(STS_TRAFFIC_FILE, (STS_KERNEL_SRC, KERNEL_SRC))},
+                     "traffic": read_traffic(STS_PAIR_TRAFFIC_FILE if paired else STS_TRAFFIC_FILE,
+                                             (STS_KERNEL_SRC, KERNEL_SRC))},
+        "one_stage_kernel": {"kernel": "k_sts_stage", "alg_bytes_per_cell": STS_BYTES_PER_CELL,
+                             "kernel_us": k1_us, "achieved": gbs1,
+                             "frac": (gbs1 / HBM_PEAK_GBS) if gbs1 else None,
+                             "traffic": read_traffic(STS_TRAFFIC_FILE, (STS_KERNEL_SRC, KERNEL_SRC))},
     }
 
 

@@ -227,6 +227,12 @@ typedef struct {
                               than the automatic count may be unstable          (0) */
     int32_t sample_timing; /* nonzero: time the step and a sample of its stage
                               kernels with HIP events and wait for completion    (0) */
+    int32_t single_stage_kernels; /* nonzero: one stage per kernel.  Zero: for even
+                              np, stages 2..s run two per kernel (the second
+                              stage formed from the first on each tile plus a
+                              two-cell overlap ring), equal bit for bit to one
+                              stage per kernel                                   (0) */
+    int32_t pad_;
 } mas_sts_opts;
 
 typedef struct {
@@ -234,9 +240,10 @@ typedef struct {
     int32_t stages;               /* stages run                                          */
     double z_max;                 /* Gershgorin bound of dt * spectral radius of L       */
     double step_us;               /* device time of the whole step (sample_timing only)  */
-    double stage_kernel_us;       /* mean of the sampled stage kernels (us)              */
+    double stage_kernel_us;       /* mean device time of the sampled general stage
+                                     kernels, each running stages_per_kernel stages (us) */
     int32_t stage_kernel_samples; /* samples behind stage_kernel_us (0: not sampled)     */
-    int32_t pad_;
+    int32_t stages_per_kernel;    /* 2 when stages ran in pairs, else 1                  */
 } mas_sts_info;
 
 /* Fill *o with the defaults shown above. */
@@ -246,7 +253,7 @@ void mas_sts_default_opts(mas_sts_opts *o);
  * MAS_EINVAL for a NULL op or a dt needing more than 1000000 stages. */
 int32_t mas_sts_stages(const mas_op *op);
 
-/* Bytes of device workspace mas_sts_step needs (three cell arrays). */
+/* Bytes of device workspace mas_sts_step needs (five cell arrays). */
 int64_t mas_sts_workspace_bytes(const mas_op *op);
 
 /* One RKL2 step of dt: u1 = Y_s from u0 (both dev, N).  u1 may equal u0
@@ -254,10 +261,10 @@ int64_t mas_sts_workspace_bytes(const mas_op *op);
  *   o     host, may be NULL for the defaults
  *   work  dev, >= mas_sts_workspace_bytes(op) bytes, 256-byte aligned
  *   info  host, may be NULL
- * Enqueues s kernels (dtL(u0), then stages 2..s) on hip_stream and returns; with
- * o->sample_timing it also waits for them.  Calls sharing one workspace must
- * be ordered on one stream.  Returns MAS_OK, MAS_EINVAL, MAS_ENOMEM or
- * MAS_EHIP. */
+ * Enqueues the kernels (dtL(u0), then stages 2..s, one or two per kernel) on
+ * hip_stream and returns; with o->sample_timing it also waits for them.
+ * Calls sharing one workspace must be ordered on one stream.  Returns MAS_OK,
+ * MAS_EINVAL, MAS_ENOMEM or MAS_EHIP. */
 int mas_sts_step(const mas_op *op, const double *u0, double *u1, const mas_sts_opts *o,
                  void *work, int64_t work_bytes, void *hip_stream, mas_sts_info *info);
 

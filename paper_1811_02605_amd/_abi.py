@@ -63,17 +63,18 @@ class mas_pcg_info(ctypes.Structure):
 
 
 class mas_sts_opts(ctypes.Structure):
-    _fields_ = [("stages", ctypes.c_int32), ("sample_timing", ctypes.c_int32)]
+    _fields_ = [("stages", ctypes.c_int32), ("sample_timing", ctypes.c_int32),
+                ("single_stage_kernels", ctypes.c_int32), ("pad_", ctypes.c_int32)]
 
 
 class mas_sts_info(ctypes.Structure):
     _fields_ = [("status", ctypes.c_int32), ("stages", ctypes.c_int32),
                 ("z_max", ctypes.c_double), ("step_us", ctypes.c_double),
                 ("stage_kernel_us", ctypes.c_double), ("stage_kernel_samples", ctypes.c_int32),
-                ("pad_", ctypes.c_int32)]
+                ("stages_per_kernel", ctypes.c_int32)]
 
     def as_dict(self):
-        return {f: getattr(self, f) for f, _ in self._fields_ if f != "pad_"}
+        return {f: getattr(self, f) for f, _ in self._fields_}
 
 
 # name -> (restype, argtypes), in the order of include/mas.h

@@ -1302,7 +1302,15 @@ extern "C" int mas_pcg_solve_adjoint(const mas_op *op, const double *x, const do
 #ifndef MAS_STS_TI
 #define MAS_STS_TI 16
 #endif
+#ifndef MAS_PAIR_NW
+#define MAS_PAIR_NW 10
+#endif
+#ifndef MAS_PAIR_TI
+#define MAS_PAIR_TI 32
+#endif
 static constexpr int kStsWPB = MAS_STS_WPB, kStsRPW = MAS_STS_RPW, kStsTI = MAS_STS_TI;
+static constexpr int kPairNW = MAS_PAIR_NW, kPairTI = MAS_PAIR_TI;
+static_assert(kPairTI >= 1 && kPairTI <= kPairMaxTI, "r planes per chunk of the two-stage kernel");
 static constexpr int kStsMaxStages = 1000000;
 static constexpr int kStsMaxSamples = 32;
 
@@ -1347,14 +1355,16 @@ static Rkl2 rkl2_coefficients(int s) {
     return c;
 }
 
+// L_0 and four stage arrays: the two-stage kernel writes D_j, D_{j+1} to a
+// pair of arrays other than the pair it reads.
 struct StsWork {
-    int64_t vec[3], total;
+    int64_t vec[5], total;
 };
 
 static StsWork sts_work_layout(const Shape &s) {
     StsWork L{};
     int64_t off = 0;
-    for (int t = 0; t < 3; ++t) {
+    for (int t = 0; t < 5; ++t) {
         L.vec[t] = off;
         off = align256(off + 8 * s.n);
     }
@@ -1366,6 +1376,8 @@ extern "C" void mas_sts_default_opts(mas_sts_opts *o) {
     if (!o) return;
     o->stages = 0;
     o->sample_timing = 0;
+    o->single_stage_kernels = 0;
+    o->pad_ = 0;
 }
 
 extern "C" int32_t mas_sts_stages(const mas_op *op) {
@@ -1414,6 +1426,39 @@ static int sts_launch(const mas_op *op, hipStream_t stream, const double *X, con
         go(std::integral_constant<int, 2>{});
     else
         go(std::integral_constant<int, 1>{});
+    LAUNCHCHK();
+    return MAS_OK;
+}
+
+// The two-stage kernel keeps the lane's two cells adjacent across the
+// periodic seam only for even np; odd np runs one stage per launch.
+static bool sts_pairs_ok(const Shape &s) { return s.np % 2 == 0; }
+
+// Stages j, j+1 in one kernel (k_sts_pair): outA = aA X + bA Z + gA L0 +
+// mA dtL(X), outB = aB outA + bB X + gB L0 + Y0 + mB dtL(outA).  L0 == nullptr
+// stands for L0 = X; Y0 != nullptr makes B the last stage (outA not written).
+static int sts_pair_launch(const mas_op *op, hipStream_t stream, const double *X, const double *Z,
+                           const double *L0, const double *Y0, double *outA, double *outB, double aA,
+                           double bA, double gA, double mA, double aB, double bB, double gB, double mB) {
+    const Shape &s = op->s;
+    constexpr int RO = 2 * kPairNW - 4;
+    const int64_t tiles_i = (s.nr + kPairTI - 1) / kPairTI;
+    const int64_t tiles_k = (s.np + kPairOut - 1) / kPairOut;
+    const int64_t tiles_j = (s.nt + RO - 1) / RO;
+    const int64_t nblk = tiles_i * tiles_k * tiles_j;
+    if (nblk > INT32_MAX) return fail(MAS_EINVAL, "grid too large for the stage kernel");
+    if (!sts_pairs_ok(s)) return fail(MAS_EINVAL, "internal: two-stage kernel needs an even np");
+    StsPairArgs args{X, op->nu, Z, L0, Y0, outA, outB, aA, bA, gA, mA * op->dt, aB, bB, gB, mB * op->dt,
+                     op->geo, s.dims(), (int)tiles_i, (int)tiles_k, (int)tiles_j, kPairTI, (int)nblk};
+    const int in = (Z ? kPairZ : 0) | (L0 ? kPairL : 0) | (Y0 ? kPairY : 0);
+    const dim3 grid((unsigned)nblk), block(kWave * kPairNW);
+    switch (in) {
+        case 0: hipLaunchKernelGGL((k_sts_pair<kPairNW, 0>), grid, block, 0, stream, args); break;
+        case kPairY: hipLaunchKernelGGL((k_sts_pair<kPairNW, kPairY>), grid, block, 0, stream, args); break;
+        case kPairZ | kPairL: hipLaunchKernelGGL((k_sts_pair<kPairNW, kPairZ | kPairL>), grid, block, 0, stream, args); break;
+        case kPairZ | kPairL | kPairY: hipLaunchKernelGGL((k_sts_pair<kPairNW, kPairZ | kPairL | kPairY>), grid, block, 0, stream, args); break;
+        default: return fail(MAS_EINVAL, "internal: unsupported stage-pair inputs %d", in);
+    }
     LAUNCHCHK();
     return MAS_OK;
 }
@@ -1473,9 +1518,11 @@ extern "C" int mas_sts_step(const mas_op *op, const double *u0, double *u1, cons
     hipStream_t stream = as_stream(hip_stream);
     char *base = static_cast<char *>(work);
     double *L0 = reinterpret_cast<double *>(base + L.vec[0]);
-    double *W[2] = {reinterpret_cast<double *>(base + L.vec[1]),
-                    reinterpret_cast<double *>(base + L.vec[2])};
+    double *W[4];
+    for (int t = 0; t < 4; ++t) W[t] = reinterpret_cast<double *>(base + L.vec[t + 1]);
     const Rkl2 c = rkl2_coefficients(s);
+    const bool pairs = !o->single_stage_kernels && sts_pairs_ok(op->s) && s >= 3;
+    if (info) info->stages_per_kernel = pairs ? 2 : 1;
 
     EventPool pool;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
@@ -1488,41 +1535,72 @@ extern "C" int mas_sts_step(const mas_op *op, const double *u0, double *u1, cons
         if (hipEventRecord(ev0, stream) != hipSuccess)
             return done(fail(MAS_EHIP, "hipEventRecord failed"));
     }
-    // the general stages 4 .. s-1 are sampled, evenly, up to kStsMaxSamples
-    const int ngen = std::max(0, s - 4);
+    // The general kernels (stages 4 .. s-1, or the pairs among them) are
+    // sampled, evenly, up to kStsMaxSamples.
+    const int ngen = pairs ? std::max(0, (s - 3) / 2 - ((s - 3) % 2 == 0 ? 1 : 0)) : std::max(0, s - 4);
     const int every = std::max(1, (ngen + kStsMaxSamples - 1) / kStsMaxSamples);
+    // run one launch, timed when it is general kernel number g (g >= 0) and sampled
+    auto run = [&](int g, auto &&launch) -> int {
+        const bool sample = timing && g >= 0 && g < ngen && (g % every == 0);
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        int st2;
+        if (sample) {
+            if ((st2 = pool.make(&e0)) != MAS_OK || (st2 = pool.make(&e1)) != MAS_OK) return st2;
+            if (hipEventRecord(e0, stream) != hipSuccess) return fail(MAS_EHIP, "hipEventRecord failed");
+        }
+        if ((st2 = launch()) != MAS_OK) return st2;
+        if (sample) {
+            if (hipEventRecord(e1, stream) != hipSuccess) return fail(MAS_EHIP, "hipEventRecord failed");
+            samples.emplace_back(e0, e1);
+        }
+        return MAS_OK;
+    };
 
     // L_0 = dtL(Y_0)
     int st = sts_launch(op, stream, u0, nullptr, nullptr, nullptr, L0, 0.0, 0.0, 0.0, 1.0);
     if (st != MAS_OK) return done(st);
-    for (int j = 2; j <= s; ++j) {
-        const bool last = j == s;
-        double *out = last ? u1 : W[j & 1];
-        const double *Y0 = last ? u0 : nullptr;
-        hipEvent_t e0 = nullptr, e1 = nullptr;
-        const bool sample = timing && !last && j >= 4 && ((j - 4) % every == 0);
-        if (sample) {
-            if ((st = pool.make(&e0)) != MAS_OK || (st = pool.make(&e1)) != MAS_OK) return done(st);
-            if (hipEventRecord(e0, stream) != hipSuccess)
-                return done(fail(MAS_EHIP, "hipEventRecord failed"));
+    // D_2 = (mu_2 mt_1 + mt_2 + gt_2) L_0 + mt_2 mt_1 dtL(L_0)
+    const double a2 = c.mu[2] * c.mt[1] + c.mt[2] + c.gt[2], m2 = c.mt[2] * c.mt[1];
+    // D_3 = mu_3 D_2 + mt_3 dtL(D_2) + (nu_3 mt_1 + mt_3 + gt_3) L_0
+    const double g3 = s >= 3 ? c.nu[3] * c.mt[1] + c.mt[3] + c.gt[3] : 0.0;
+    if (!pairs) {
+        for (int j = 2; j <= s; ++j) {
+            const bool last = j == s;
+            double *out = last ? u1 : W[j & 1];
+            const double *Y0 = last ? u0 : nullptr;
+            st = run(last ? -1 : j - 4, [&] {
+                if (j == 2) return sts_launch(op, stream, L0, nullptr, nullptr, Y0, out, a2, 0.0, 0.0, m2);
+                if (j == 3) return sts_launch(op, stream, W[0], nullptr, L0, Y0, out, c.mu[3], 0.0, g3, c.mt[3]);
+                return sts_launch(op, stream, W[(j - 1) & 1], W[j & 1], L0, Y0, out, c.mu[j], c.nu[j],
+                                  c.mt[j] + c.gt[j], c.mt[j]);
+            });
+            if (st != MAS_OK) return done(st);
         }
-        if (j == 2) {
-            // D_2 = (mu_2 mt_1 + mt_2 + gt_2) L_0 + mt_2 mt_1 dtL(L_0)
-            st = sts_launch(op, stream, L0, nullptr, nullptr, Y0, out,
-                            c.mu[2] * c.mt[1] + c.mt[2] + c.gt[2], 0.0, 0.0, c.mt[2] * c.mt[1]);
-        } else if (j == 3) {
-            // D_3 = mu_3 D_2 + mt_3 dtL(D_2) + (nu_3 mt_1 + mt_3 + gt_3) L_0
-            st = sts_launch(op, stream, W[0], nullptr, L0, Y0, out, c.mu[3], 0.0,
-                            c.nu[3] * c.mt[1] + c.mt[3] + c.gt[3], c.mt[3]);
-        } else {
-            st = sts_launch(op, stream, W[(j - 1) & 1], W[j & 1], L0, Y0, out, c.mu[j], c.nu[j],
-                            c.mt[j] + c.gt[j], c.mt[j]);
-        }
+    } else {
+        // stages 2, 3 (X = L_0), then pairs j, j+1 from j = 4; pair q writes
+        // (D_j, D_{j+1}) to W[2 (q%2)], W[2 (q%2) + 1]; an odd stage left at
+        // the end runs alone
+        st = run(-1, [&] {
+            return sts_pair_launch(op, stream, L0, nullptr, nullptr, s == 3 ? u0 : nullptr, W[0],
+                                   s == 3 ? u1 : W[1], a2, 0.0, 0.0, m2, c.mu[3], 0.0, g3, c.mt[3]);
+        });
         if (st != MAS_OK) return done(st);
-        if (sample) {
-            if (hipEventRecord(e1, stream) != hipSuccess)
-                return done(fail(MAS_EHIP, "hipEventRecord failed"));
-            samples.emplace_back(e0, e1);
+        int j = 4, q = 1;
+        for (; j + 1 <= s; j += 2, ++q) {
+            const bool last = j + 1 == s;
+            const double *X = W[2 * ((q - 1) & 1) + 1], *Z = W[2 * ((q - 1) & 1)];
+            double *oA = W[2 * (q & 1)], *oB = last ? u1 : W[2 * (q & 1) + 1];
+            st = run(last ? -1 : q - 1, [&] {
+                return sts_pair_launch(op, stream, X, Z, L0, last ? u0 : nullptr, oA, oB, c.mu[j], c.nu[j],
+                                       c.mt[j] + c.gt[j], c.mt[j], c.mu[j + 1], c.nu[j + 1],
+                                       c.mt[j + 1] + c.gt[j + 1], c.mt[j + 1]);
+            });
+            if (st != MAS_OK) return done(st);
+        }
+        if (j == s) {
+            const double *X = W[2 * ((q - 1) & 1) + 1], *Z = W[2 * ((q - 1) & 1)];
+            st = sts_launch(op, stream, X, Z, L0, u0, u1, c.mu[s], c.nu[s], c.mt[s] + c.gt[s], c.mt[s]);
+            if (st != MAS_OK) return done(st);
         }
     }
     if (timing) {

@@ -59,6 +59,64 @@ struct StsArgs {
 // Inputs a stage reads besides X and nu (template mask).
 constexpr int kStsZ = 1, kStsL0 = 2, kStsY0 = 4;
 
+// Plane factors of cell row (m, j): half the r-face factors of the faces
+// m | m+1 (zero at m = nr-1) and m-1 | m (zero at m = 0), the Dirichlet wall
+// factor (zero with Neumann walls, whose gw_* are zero) and the stage scale
+// m dt / V.  Shared by the one- and two-stage kernels so that both round alike.
+struct StsPlane {
+    double gq, hRp, hRm, gw, scale;
+};
+
+// The table entries of plane m.
+struct StsPlaneRaw {
+    double gq, gr, grm, vr;  // grm = gr[m - 1], zero at m = 0
+    int m;
+};
+
+__device__ inline StsPlaneRaw sts_plane_raw(const Geo &g, int m) {
+    return StsPlaneRaw{g.gq[m], g.gr[m], (m > 0) ? g.gr[m - 1] : 0.0, g.vr[m], m};
+}
+
+__device__ inline StsPlane sts_plane(const Geo &g, const StsPlaneRaw &t, int nr, double vt, double mdt) {
+    StsPlane p;
+    p.gq = t.gq;
+    p.hRp = 0.5 * t.gr * vt;
+    p.hRm = (t.m > 0) ? 0.5 * t.grm * vt : 0.0;
+    p.gw = (((t.m == 0) ? g.gw_in : 0.0) + ((t.m == nr - 1) ? g.gw_out : 0.0)) * vt;
+    p.scale = mdt / (t.vr * vt);
+    return p;
+}
+
+__device__ inline StsPlane sts_plane(const Geo &g, int m, int nr, double vt, double mdt) {
+    return sts_plane(g, sts_plane_raw(g, m), nr, vt, mdt);
+}
+
+// sum_f G_f (nu_c + nu_nb)/2 (x_c - x_nb) over the six faces of a cell, the
+// halves already folded into the factors (tU, tD, tP: theta-face and
+// phi-face factors of the row times the plane's gq).  Wherever two products
+// meet in one sum the fused multiply-add is written out, so that every kernel
+// using these helpers rounds alike whatever the compiler would contract.
+__device__ inline double sts_flux(const StsPlane &p, double tU, double tD, double tP, double xc, double nc,
+                                  double xp, double np_, double xm, double nm, double xu, double nu_u,
+                                  double xd, double nu_d, double xl, double nl, double xr, double nrr) {
+    double f = (p.hRp * (nc + np_)) * (xc - xp);
+    f = __builtin_fma(p.hRm * (nc + nm), xc - xm, f);
+    f = __builtin_fma(p.gw * nc, xc, f);
+    f = __builtin_fma(tU * (nc + nu_u), xc - xu, f);
+    f = __builtin_fma(tD * (nc + nu_d), xc - xd, f);
+    f = __builtin_fma(tP, __builtin_fma(nc + nl, xc - xl, (nc + nrr) * (xc - xr)), f);
+    return f;
+}
+
+// One stage's value at a cell: a x + b z + g l + y - scale f.
+__device__ inline double sts_combine(double a, double x, double b, double z, double g, double l, double y,
+                                     double scale, double f) {
+    double o = __builtin_fma(a, x, b * z);
+    o = __builtin_fma(g, l, o);
+    o = o + y;
+    return __builtin_fma(-scale, f, o);
+}
+
 #ifndef MAS_STS_WPE
 #define MAS_STS_WPE 0
 #endif
@@ -173,12 +231,8 @@ void k_sts_stage(StsArgs a) {
         bst<double, V, MAS_STS_AUX_ST>(RO, st_off, st);
 
         // ---- plane factors
-        const double gq = a.geo.gq[m];
-        const double hRp = 0.5 * a.geo.gr[m] * vt;                    // face m | m+1 (0 at m = nr-1)
-        const double hRm = (m > 0) ? 0.5 * a.geo.gr[m - 1] * vt : 0.0;  // face m-1 | m
-        const double gw = ((m == 0) ? a.geo.gw_in : 0.0) * vt + ((m == nr - 1) ? a.geo.gw_out : 0.0) * vt;
-        const double scale = a.mdt / (a.geo.vr[m] * vt);
-        const double tU = gq * hU, tD = gq * hD, tP = gq * hP;
+        const StsPlane pf = sts_plane(a.geo, m, nr, vt, a.mdt);
+        const double tU = pf.gq * hU, tD = pf.gq * hD, tP = pf.gq * hP;
         const VD &Xp = up ? Xa : Xb, &Xm = up ? Xb : Xa;  // planes m+1, m-1
         const VD &Np = up ? Na : Nb, &Nm = up ? Nb : Na;
 
@@ -211,13 +265,9 @@ void k_sts_stage(StsArgs a) {
             const double nl = (e > 0) ? Nc.v[e - 1] : ((lp == 0) ? NS : nl0);
             const double xr = (e < V - 1) ? Xc.v[e + 1] : (eR ? XS : xr0);
             const double nrr = (e < V - 1) ? Nc.v[e + 1] : (eR ? NS : nr0);
-            double f = hRp * (nc + Np.v[e]) * (xc - Xp.v[e]);
-            f += hRm * (nc + Nm.v[e]) * (xc - Xm.v[e]);
-            f += gw * nc * xc;
-            f += tU * (nc + nu_u) * (xc - xu);
-            f += tD * (nc + nu_d) * (xc - xd);
-            f += tP * ((nc + nl) * (xc - xl) + (nc + nrr) * (xc - xr));
-            o.v[e] = ((a.a * xc + a.b * Zv.v[e]) + a.g * Lv.v[e] + Yv.v[e]) - scale * f;
+            const double f = sts_flux(pf, tU, tD, tP, xc, nc, Xp.v[e], Np.v[e], Xm.v[e], Nm.v[e], xu, nu_u,
+                                      xd, nu_d, xl, nl, xr, nrr);
+            o.v[e] = sts_combine(a.a, xc, a.b, Zv.v[e], a.g, Lv.v[e], Yv.v[e], pf.scale, f);
         }
         st = o;
         st_off = oo;
@@ -227,6 +277,237 @@ void k_sts_stage(StsArgs a) {
         Nc = Na;
     }
     bst<double, V, MAS_STS_AUX_ST>(RO, st_off, st);
+}
+
+// ---------------------------------------------------------------- two stages per launch
+// Stages j and j+1 of the recursion in one pass (temporal blocking):
+//
+//     A = aA X + bA Z + gA L0 + mA dtL(X)              (stage j,   D_j)
+//     B = aB A + bB X + gB L0 + Y0 + mB dtL(A)         (stage j+1, D_{j+1})
+//
+// Stage j+1 at a cell needs stage j at its six neighbours, which need X two
+// cells away: each block loads a tile of 2 NW theta rows by 64 phi cells (one
+// row per half-wave, two cells per lane), forms A on all of it, and keeps B on
+// the inner (2 NW - 4) x 60 cells; the ring of two cells on each side is
+// overlap with the neighbour tiles.  Along r the block marches its chunk of
+// planes with B one plane behind A, starting and ending one plane outside the
+// chunk.  Per cell and pair of stages it streams X, nu, Z, L0 and writes A and
+// B: 6 words for two stages instead of 10.  A and B go to buffers other than
+// X and Z (neighbour tiles read X and Z on their rings while this one writes).
+// The theta neighbours go through LDS, the phi neighbours through DPP lane
+// shifts (the shifted-in values at the tile's two outer columns are never
+// used), the r neighbours through register queues.  Every value A and B take
+// is formed by the same expressions as in k_sts_stage, so a pair equals two
+// one-stage launches bit for bit.
+//
+// IN mask: kPairZ reads Z (else zero); kPairL reads L0 (else L0 is X: the
+// stage pair 2, 3, where X = L0); kPairY makes B the last stage: it adds Y0,
+// stores B to outB and does not store A.
+constexpr int kPairLanes = 32;             // lanes per tile row, two cells each
+constexpr int kPairCols = 2 * kPairLanes;  // tile columns
+constexpr int kPairOut = kPairCols - 4;    // columns kept
+constexpr int kPairZ = 1, kPairL = 2, kPairY = 4;
+constexpr int kPairMaxTI = 64;             // most r planes per chunk
+
+struct StsPairArgs {
+    const double *X, *nu, *Z, *L0, *Y0;
+    double *outA, *outB;
+    double aA, bA, gA, mdtA;
+    double aB, bB, gB, mdtB;
+    Geo geo;
+    Dims d;
+    int tiles_i, tiles_k, tiles_j, ti, nblk;
+};
+
+// Waves per SIMD the pair kernel is compiled for (the fewest with more
+// registers ran fastest).
+#ifndef MAS_PAIR_WPE
+#define MAS_PAIR_WPE 2
+#endif
+
+template <int NW, int IN>
+__global__ __launch_bounds__(kWave *NW) __attribute__((amdgpu_waves_per_eu(MAS_PAIR_WPE, 8)))
+void k_sts_pair(StsPairArgs a) {
+    constexpr int R = 2 * NW;  // tile rows
+    constexpr int RO = R - 4;  // rows kept
+    constexpr bool HZ = (IN & kPairZ) != 0, HL = (IN & kPairL) != 0, HY = (IN & kPairY) != 0;
+    using VD = VecT<double, 2>;
+    // LDS rings by step index: X of the last two planes, nu and A of the
+    // last four.  One barrier per step: step s writes X and nu of its plane
+    // before the barrier and A after stage B; stage A at step s reads the
+    // plane written before the barrier, stage B the planes of steps s-1 and
+    // s-2.  A slot is rewritten only after every thread has passed the
+    // barrier that follows its last read.
+    __shared__ __attribute__((aligned(16))) double sX[2][R][kPairCols];
+    __shared__ __attribute__((aligned(16))) double sN[4][R][kPairCols];
+    __shared__ __attribute__((aligned(16))) double sY[4][R][kPairCols];
+
+    const int nr = a.d.nr, nt = a.d.nt, np = a.d.np;
+    const int64_t plane = a.d.plane;
+    const int Lb = xcd_remap(blockIdx.x, a.nblk);
+    int it, kt, jt;
+    tile_coords<MAS_STS_ORDER>(Lb, a.tiles_i, a.tiles_k, a.tiles_j, it, kt, jt);
+
+    const int lane = threadIdx.x & (kWave - 1);
+    const int rho = threadIdx.x / kPairLanes;  // tile row
+    const int c = 2 * (lane & (kPairLanes - 1));
+    const int ru = rho > 0 ? rho - 1 : rho, rd = rho < R - 1 ? rho + 1 : rho;
+    const int j = jt * RO - 2 + rho;
+    const int k0 = kt * kPairOut;
+    const int nout = min(kPairOut, np - k0);  // even: np is even
+    const bool rowin = j >= 0 && j < nt;
+    // the lane's two cells k0 - 2 + c, +1 (periodic; np even keeps them adjacent)
+    const bool ld = rowin && c <= nout + 2;
+    int k = k0 - 2 + c;
+    if (k < 0) k += np;
+    else if (k >= np) k -= np;
+    const int64_t col = ld ? (int64_t)j * np + k : 0;
+    const bool own = rowin && rho >= 2 && rho < R - 2 && c >= 2 && c < nout + 2;
+
+    const int jj = rowin ? j : 0;
+    const double vt = a.geo.vt[jj];
+    const double hU = (rowin && j > 0) ? 0.5 * a.geo.gtt[j - 1] : 0.0;
+    const double hD = rowin ? 0.5 * a.geo.gtt[jj] : 0.0;
+    const double hP = (rowin && !a.geo.np_one) ? 0.5 * a.geo.gpt[jj] : 0.0;
+
+    constexpr uint32_t ES = sizeof(double);
+    const uint32_t nbytes = (uint32_t)(a.d.n * (int64_t)ES);
+    const auto RX = make_rsrc(a.X, nbytes), RN = make_rsrc(a.nu, nbytes),
+               RZ = make_rsrc(a.Z, HZ ? nbytes : 0u), RL = make_rsrc(a.L0, HL ? nbytes : 0u),
+               RY = make_rsrc(a.Y0, HY ? nbytes : 0u), RA = make_rsrc(a.outA, HY ? 0u : nbytes),
+               RB = make_rsrc(a.outB, nbytes);
+
+    const int i0 = it * a.ti;
+    const int i1 = min(i0 + a.ti, nr);
+    const int nsteps = i1 - i0 + 2;  // A runs from one plane before the chunk to one after
+    auto ldoff = [&](int m) -> uint32_t {
+        return (ld && m >= 0 && m < nr) ? (uint32_t)((int64_t)m * plane + col) * ES : kOOB;
+    };
+    auto ownoff = [&](int m) -> uint32_t {
+        return (own && m >= i0 && m < i1) ? (uint32_t)((int64_t)m * plane + col) * ES : kOOB;
+    };
+    auto lds2 = [&](const double *row) -> VD { return VD{{row[c], row[c + 1]}}; };
+
+    // The chunk's plane-table entries, planes i0-2 .. i1+1 (clamped into the
+    // grid; A is zero outside it), copied to LDS once: read there each step,
+    // they put no wait on the vector-memory counter that the loads queued for
+    // the next step also count on.
+    __shared__ double sG[kPairMaxTI + 4][4];
+    auto clampm = [&](int m) { return min(max(m, 0), nr - 1); };
+    for (int t = threadIdx.x; t < i1 - i0 + 4; t += kWave * NW) {
+        const StsPlaneRaw r = sts_plane_raw(a.geo, clampm(i0 - 2 + t));
+        sG[t][0] = r.gq;
+        sG[t][1] = r.gr;
+        sG[t][2] = r.grm;
+        sG[t][3] = r.vr;
+    }
+    __syncthreads();
+    auto table = [&](int m) {
+        const int t = m - (i0 - 2);
+        return StsPlaneRaw{sG[t][0], sG[t][1], sG[t][2], sG[t][3], clampm(m)};
+    };
+
+    // chunks march up (even chunk index) or down
+    const bool up = (it & 1) == 0;
+    const int dir = up ? 1 : -1;
+    const int first = up ? i0 - 1 : i1;
+    // register queues: X and nu at planes m - dir (b), m (c), m + dir (a);
+    // Z and L0 at m (c); L0 at m - dir (b).  Each step loads X and nu of plane
+    // m + 2 dir and Z and L0 of plane m + dir for the next step.
+    VD Xb = bld<double, 2, MAS_STS_AUX_XN>(RX, ldoff(first - dir));
+    VD Nb = bld<double, 2, MAS_STS_AUX_XN>(RN, ldoff(first - dir));
+    VD Xc = bld<double, 2, MAS_STS_AUX_XN>(RX, ldoff(first));
+    VD Nc = bld<double, 2, MAS_STS_AUX_XN>(RN, ldoff(first));
+    VD Xa = bld<double, 2, MAS_STS_AUX_XN>(RX, ldoff(first + dir));
+    VD Na = bld<double, 2, MAS_STS_AUX_XN>(RN, ldoff(first + dir));
+    VD Zc{}, Lc{}, Lb_{};
+    if constexpr (HZ) Zc = bld<double, 2>(RZ, ldoff(first));
+    if constexpr (HL) Lc = bld<double, 2>(RL, ldoff(first));
+
+    for (int s = 0; s < nsteps; ++s) {
+        const int m = first + s * dir;
+        const int mb = m - dir;  // plane of stage B
+        const int q0 = s & 3, q1 = (s - 1) & 3, q2 = (s - 2) & 3, x0 = s & 1;
+        // ---- loads for the next step (and Y0 of this step's B)
+        const VD Xn = bld<double, 2, MAS_STS_AUX_XN>(RX, ldoff(m + 2 * dir));
+        const VD Nn = bld<double, 2, MAS_STS_AUX_XN>(RN, ldoff(m + 2 * dir));
+        VD Zn{}, Ln{}, Yo{};
+        if constexpr (HZ) Zn = bld<double, 2>(RZ, ldoff(m + dir));
+        if constexpr (HL) Ln = bld<double, 2>(RL, ldoff(m + dir));
+        if constexpr (HY) Yo = bld<double, 2, MAS_STS_AUX_ZL>(RY, s >= 2 ? ownoff(mb) : kOOB);
+
+        // ---- X and nu of plane m to LDS; A of plane mb went there last step
+        sX[x0][rho][c] = Xc.v[0];
+        sX[x0][rho][c + 1] = Xc.v[1];
+        sN[q0][rho][c] = Nc.v[0];
+        sN[q0][rho][c + 1] = Nc.v[1];
+        __syncthreads();
+
+        // ---- stage A at plane m (zero outside the grid)
+        VD Yc{};
+        const bool inA = rowin && m >= 0 && m < nr;
+        {
+            const VD XU = lds2(sX[x0][ru]), XD = lds2(sX[x0][rd]);
+            const VD NU = lds2(sN[q0][ru]), ND = lds2(sN[q0][rd]);
+            const StsPlane pf = sts_plane(a.geo, table(m), nr, vt, a.mdtA);
+            const double tU = pf.gq * hU, tD = pf.gq * hD, tP = pf.gq * hP;
+            const VD &Xp = up ? Xa : Xb, &Xm = up ? Xb : Xa;
+            const VD &Np = up ? Na : Nb, &Nm = up ? Nb : Na;
+            const double xl0 = lane_prev(Xc.v[1]), nl0 = lane_prev(Nc.v[1]);
+            const double xr1 = lane_next(Xc.v[0]), nr1 = lane_next(Nc.v[0]);
+#pragma unroll
+            for (int e = 0; e < 2; ++e) {
+                const double xc = Xc.v[e], nc = Nc.v[e];
+                const double xl = e ? Xc.v[0] : xl0, nl = e ? Nc.v[0] : nl0;
+                const double xr = e ? xr1 : Xc.v[1], nrr = e ? nr1 : Nc.v[1];
+                const double f = sts_flux(pf, tU, tD, tP, xc, nc, Xp.v[e], Np.v[e], Xm.v[e], Nm.v[e], XU.v[e],
+                                          NU.v[e], XD.v[e], ND.v[e], xl, nl, xr, nrr);
+                const double lv = HL ? Lc.v[e] : xc;
+                const double o = sts_combine(a.aA, xc, a.bA, Zc.v[e], a.gA, lv, 0.0, pf.scale, f);
+                Yc.v[e] = inA ? o : 0.0;
+            }
+        }
+
+        // ---- stage B at plane mb (inside the chunk from the third step on):
+        // A at mb and its theta neighbours, A and nu at m - 2 dir, and nu's
+        // theta neighbours at mb come from the LDS rings, A at m from registers
+        if (s >= 2) {
+            const VD Yb = lds2(sY[q1][rho]), YU = lds2(sY[q1][ru]), YD = lds2(sY[q1][rd]);
+            const VD Yb2 = lds2(sY[q2][rho]), Nbb = lds2(sN[q2][rho]);
+            const VD NU = lds2(sN[q1][ru]), ND = lds2(sN[q1][rd]);
+            const StsPlane pf = sts_plane(a.geo, table(mb), nr, vt, a.mdtB);
+            const double tU = pf.gq * hU, tD = pf.gq * hD, tP = pf.gq * hP;
+            const VD &Yp = up ? Yc : Yb2, &Ym = up ? Yb2 : Yc;
+            const VD &Np = up ? Nc : Nbb, &Nm = up ? Nbb : Nc;
+            const double yl0 = lane_prev(Yb.v[1]), nl0 = lane_prev(Nb.v[1]);
+            const double yr1 = lane_next(Yb.v[0]), nr1 = lane_next(Nb.v[0]);
+            VD o;
+#pragma unroll
+            for (int e = 0; e < 2; ++e) {
+                const double yc = Yb.v[e], nc = Nb.v[e];
+                const double yl = e ? Yb.v[0] : yl0, nl = e ? Nb.v[0] : nl0;
+                const double yr = e ? yr1 : Yb.v[1], nrr = e ? nr1 : Nb.v[1];
+                const double f = sts_flux(pf, tU, tD, tP, yc, nc, Yp.v[e], Np.v[e], Ym.v[e], Nm.v[e], YU.v[e],
+                                          NU.v[e], YD.v[e], ND.v[e], yl, nl, yr, nrr);
+                const double lv = HL ? Lb_.v[e] : Xb.v[e];
+                o.v[e] = sts_combine(a.aB, yc, a.bB, Xb.v[e], a.gB, lv, Yo.v[e], pf.scale, f);
+            }
+            bst<double, 2, MAS_STS_AUX_ST>(RB, ownoff(mb), o);
+        }
+        sY[q0][rho][c] = Yc.v[0];
+        sY[q0][rho][c + 1] = Yc.v[1];
+        if constexpr (!HY) bst<double, 2, MAS_STS_AUX_ST>(RA, ownoff(m), Yc);
+
+        Nb = Nc;
+        Xb = Xc;
+        Lb_ = Lc;
+        Nc = Na;
+        Xc = Xa;
+        Na = Nn;
+        Xa = Xn;
+        Lc = Ln;
+        Zc = Zn;
+    }
 }
 
 }  // namespace mas

@@ -233,9 +233,10 @@ class Operator:
         return s
 
     def sts_step(self, u0: torch.Tensor, stages: int = 0, out: torch.Tensor | None = None,
-                 sample_timing: bool = False):
+                 sample_timing: bool = False, stage_pairs: bool = True):
         """One RKL2 super time-step of du/dt = L u over dt.  Returns (u1, info).
-        out may be u0 itself (in-place step)."""
+        out may be u0 itself (in-place step).  stage_pairs=False runs one stage
+        per kernel (the two-stage kernel's result is the same bit for bit)."""
         _check_vec(u0, self.grid.shape, "u0")
         u1 = out if out is not None else torch.empty_like(u0)
         _check_vec(u1, self.grid.shape, "out")
@@ -250,6 +251,7 @@ class Operator:
         lib.mas_sts_default_opts(ctypes.byref(o))
         o.stages = int(stages)
         o.sample_timing = int(bool(sample_timing))
+        o.single_stage_kernels = int(not stage_pairs)
         info = abi.mas_sts_info()
         with torch.cuda.device(self.device):
             st = lib.mas_sts_step(self._h, u0.data_ptr(), u1.data_ptr(), ctypes.byref(o),

@@ -1,8 +1,11 @@
 """GPU parity of the RKL2 super time-step (mas_sts_step) against the FP64 CPU
-oracle on seeded inputs: small and ragged grids spanning several tiles
-(64-cell phi segments, 8-row theta tiles, 16-plane r chunks marched in
-alternating directions, ragged tails in every direction, odd np), every wall
-combination, automatic and fixed stage counts, in-place steps."""
+oracle on seeded inputs: small and ragged grids spanning several tiles of both
+stage kernels (one stage: 64-cell phi segments, 8-row theta tiles, 16-plane r
+chunks; two stages: 60-cell by 12-row tiles with a two-cell overlap ring,
+32-plane r chunks; chunks marched in alternating directions), ragged tails in
+every direction, odd np (one stage per kernel), every wall combination,
+automatic and fixed stage counts, in-place steps.  Steps with two stages per
+kernel must equal steps with one stage per kernel bit for bit."""
 import sys
 
 import numpy as np
@@ -15,7 +18,10 @@ from paper_1811_02605_amd import _abi as abi
 pytestmark = pytest.mark.gpu
 
 SHAPES = [(4, 4, 8), (5, 7, 13), (3, 9, 70), (33, 17, 129), (65, 8, 64), (1, 3, 2), (6, 3, 1),
-          (2, 1, 5), (9, 16, 32), (17, 9, 66)]
+          (2, 1, 5), (9, 16, 32), (17, 9, 66), (70, 25, 130)]
+# spans of the two-stage kernel's tiles: 60 phi cells, 12 theta rows, 32 r planes
+PAIR_SHAPES = [(70, 25, 130), (33, 13, 64), (3, 1, 2), (1, 12, 4), (40, 26, 122), (65, 8, 64),
+               (9, 16, 32), (2, 3, 6)]
 BCS = [(0, 0), (1, 0), (1, 1)]
 
 # Both sides round each stage differently (the oracle forms u - (A u)/V from
@@ -135,20 +141,57 @@ def test_deterministic():
     assert torch.equal(a, b)
 
 
-def test_timing_info_and_argument_errors():
+@pytest.mark.parametrize("shape", PAIR_SHAPES + [(5, 7, 13)])
+@pytest.mark.parametrize("bc", BCS)
+@pytest.mark.parametrize("stages", [0, 2, 3, 4, 5, 8, 13])
+def test_stage_pairs_equal_single_stage_kernels(shape, bc, stages):
+    p = problem(shape, bc)
+    _, op = gpu_operator(p)
+    u0 = to_dev(np.random.default_rng(29).standard_normal(p.shape))
+    a, ia = op.sts_step(u0, stages=stages)
+    b, ib = op.sts_step(u0, stages=stages, stage_pairs=False)
+    s = ia["stages"]
+    assert ib["stages_per_kernel"] == 1
+    assert ia["stages_per_kernel"] == (2 if p.shape[2] % 2 == 0 and s >= 3 else 1)
+    if not torch.equal(a, b):
+        d = float((a - b).abs().max() / b.abs().max())
+        pytest.fail(f"{shape} bc={bc} s={s}: pairs differ from single stages by {d:.3e} (max rel)")
+
+
+def test_stage_pairs_in_place_and_repeated():
+    p = problem((40, 26, 122), (1, 0))
+    _, op = gpu_operator(p)
+    u0 = to_dev(np.random.default_rng(30).standard_normal(p.shape))
+    u, v = u0.clone(), u0.clone()
+    for _ in range(3):
+        u, _ = op.sts_step(u, out=u)
+        v, _ = op.sts_step(v, out=v, stage_pairs=False)
+    assert torch.equal(u, v)
+
+
+@pytest.mark.parametrize("pairs", [True, False])
+def test_timing_info_and_argument_errors(pairs):
     p = problem("c0", (0, 0))
     _, op = gpu_operator(p)
     u0 = to_dev(np.random.default_rng(28).standard_normal(p.shape))
     s = op.sts_stages()
-    _, info = op.sts_step(u0, sample_timing=True)
-    assert info["stage_kernel_samples"] == len(range(4, s, max(1, -(-(s - 4) // 32))))
+    _, info = op.sts_step(u0, sample_timing=True, stage_pairs=pairs)
+    if pairs:
+        # general pairs: (4, 5), (6, 7), ... short of the last stage
+        ngen = (s - 3) // 2 - (1 if (s - 3) % 2 == 0 else 0)
+        assert info["stages_per_kernel"] == 2
+    else:
+        ngen = s - 4
+        assert info["stages_per_kernel"] == 1
+    every = max(1, -(-ngen // 32))
+    assert info["stage_kernel_samples"] == len(range(0, ngen, every))
     assert 0.0 < info["stage_kernel_us"] < info["step_us"]
     with pytest.raises(abi.MasError, match="stages"):
         op.sts_step(u0, stages=1)
     lib = abi.load()
     out = torch.empty_like(u0)
     need = int(lib.mas_sts_workspace_bytes(op.handle))
-    assert need >= 3 * 8 * p.cfg.n
+    assert need >= 5 * 8 * p.cfg.n
     st = lib.mas_sts_step(op.handle, u0.data_ptr(), out.data_ptr(), None, out.data_ptr(), need - 8,
                           None, None)
     assert st == abi.MAS_ENOMEM

@@ -152,6 +152,37 @@ def bench_pc2(S, grid, nu, rhs, p, t_pcg, iters_pc1):
     }
 
 
+GX_SEED = 600  # dL/dx of the adjoint measurement: N(0,1) per cell
+
+
+def bench_adjoint(S, grid, nu, x, p, opts, t_pcg):
+    """The adjoint of the same solve: for a loss with dL/dx = gx (seeded N(0,1)
+    field) at the FP64 solution x, lambda = A^-1 gx by the same PCG, then one
+    pass of the gradient kernel (dL/dnu, dL/drhs); timed on the host around
+    the blocking call."""
+    import numpy as np
+    import torch
+
+    op = S.Operator(grid, nu, p.dt, precision="fp64")
+    gx = torch.from_numpy(np.random.default_rng(GX_SEED).standard_normal(grid.shape)).to(x.device)
+    op.adjoint(x, gx, opts, allow_notconv=False)  # warm-up
+    torch.cuda.synchronize()
+    ts = []
+    for _ in range(3):
+        t0 = time.perf_counter()
+        _, _, _, info = op.adjoint(x, gx, opts, allow_notconv=False)
+        torch.cuda.synchronize()
+        ts.append(time.perf_counter() - t0)
+    t = float(np.median(ts))
+    print(f"[bench] adjoint: {info['iters']} iterations, {t:.3f} s (solve and gradient)",
+          file=sys.stderr, flush=True)
+    return {"what": "adjoint of the FP64 solve: lambda = A^-1 gx by the same PCG to 1e-10, then "
+                    "dL/dnu and dL/drhs in one gradient-kernel pass (4 words/cell)",
+            "time_s": t, "iters": info["iters"], "rel_resid_true": info["rel_resid_true"],
+            "iteration_kernel_us": info["iter_kernel_us"] if info["iter_kernel_samples"] > 0 else None,
+            "forward_plus_adjoint_s": t_pcg + t}
+
+
 def bench_sts(S, grid, nu, rhs, p, t_pcg, steps):
     """The explicit alternative for the same viscous step: one RKL2 super
     time-step of the same dt on the same grid and viscosity (u0 = the smooth
@@ -219,6 +250,7 @@ def main():
     ap.add_argument("--no-sts", action="store_true")
     ap.add_argument("--no-multi", action="store_true")
     ap.add_argument("--no-pc2", action="store_true")
+    ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--check-every", type=int, default=8)
     args = ap.parse_args()
     if args.gpus != 1:
@@ -336,6 +368,9 @@ def main():
         }
         print(f"[bench] refined: {t_ref:.3f} s vs fp64 {np.median(solve_s):.3f} s",
               file=sys.stderr, flush=True)
+
+    if not args.no_adjoint:
+        out["adjoint"] = bench_adjoint(S, grid, nu, x, p, opts, float(np.median(solve_s)))
 
     if not args.no_pc2:
         out["pc2"] = bench_pc2(S, grid, nu, rhs, p, float(np.median(solve_s)), infos[-1]["iters"])

@@ -383,6 +383,12 @@ void k_sts_pair(StsPairArgs a) {
     auto ldoff = [&](int m) -> uint32_t {
         return (ld && m >= 0 && m < nr) ? (uint32_t)((int64_t)m * plane + col) * ES : kOOB;
     };
+    // Z and L0 enter stage A only, whose values on the outermost tile rows
+    // are never used: those rows do not load them
+    const bool ldzl = ld && rho >= 1 && rho < R - 1;
+    auto zloff = [&](int m) -> uint32_t {
+        return (ldzl && m >= 0 && m < nr) ? (uint32_t)((int64_t)m * plane + col) * ES : kOOB;
+    };
     auto ownoff = [&](int m) -> uint32_t {
         return (own && m >= i0 && m < i1) ? (uint32_t)((int64_t)m * plane + col) * ES : kOOB;
     };
@@ -421,8 +427,8 @@ void k_sts_pair(StsPairArgs a) {
     VD Xa = bld<double, 2, MAS_STS_AUX_XN>(RX, ldoff(first + dir));
     VD Na = bld<double, 2, MAS_STS_AUX_XN>(RN, ldoff(first + dir));
     VD Zc{}, Lc{}, Lb_{};
-    if constexpr (HZ) Zc = bld<double, 2>(RZ, ldoff(first));
-    if constexpr (HL) Lc = bld<double, 2>(RL, ldoff(first));
+    if constexpr (HZ) Zc = bld<double, 2>(RZ, zloff(first));
+    if constexpr (HL) Lc = bld<double, 2>(RL, zloff(first));
 
     for (int s = 0; s < nsteps; ++s) {
         const int m = first + s * dir;
@@ -432,8 +438,8 @@ void k_sts_pair(StsPairArgs a) {
         const VD Xn = bld<double, 2, MAS_STS_AUX_XN>(RX, ldoff(m + 2 * dir));
         const VD Nn = bld<double, 2, MAS_STS_AUX_XN>(RN, ldoff(m + 2 * dir));
         VD Zn{}, Ln{}, Yo{};
-        if constexpr (HZ) Zn = bld<double, 2>(RZ, ldoff(m + dir));
-        if constexpr (HL) Ln = bld<double, 2>(RL, ldoff(m + dir));
+        if constexpr (HZ) Zn = bld<double, 2>(RZ, zloff(m + dir));
+        if constexpr (HL) Ln = bld<double, 2>(RL, zloff(m + dir));
         if constexpr (HY) Yo = bld<double, 2, MAS_STS_AUX_ZL>(RY, s >= 2 ? ownoff(mb) : kOOB);
 
         // ---- X and nu of plane m to LDS; A of plane mb went there last step

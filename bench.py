@@ -47,12 +47,14 @@ KERNEL_BYTES_PER_CELL = {"fp64": 11 * 8, "fp32": 11 * 4}
 # One RKL2 stage kernel per cell: reads D_{j-1}, nu, D_{j-2}, L_0, writes D_j.
 STS_BYTES_PER_CELL = 5 * 8        # one-stage kernel: reads X, nu, Z, L0; writes the stage
 STS_PAIR_BYTES_PER_CELL = 6 * 8   # two-stage kernel: reads X, nu, Z, L0; writes both stages
+GRAD_BYTES_PER_CELL = 4 * 8       # gradient kernel: reads x, lambda; writes dL/dnu, dL/drhs
 CSRC = os.path.join(ROOT, "paper_1811_02605_amd", "csrc")
 KERNEL_SRC = os.path.join(CSRC, "kernels.hpp")
 STS_KERNEL_SRC = os.path.join(CSRC, "sts_kernels.hpp")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "pcg_iter_fp64_c1_traffic.txt")
 STS_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "sts_stage_c1_traffic.txt")
 STS_PAIR_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "sts_pair_c1_traffic.txt")
+GRAD_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "gradient_c1_kernel_trace.txt")
 
 
 def kernel_hash(*paths) -> str:
@@ -174,13 +176,19 @@ def bench_adjoint(S, grid, nu, x, p, opts, t_pcg):
         torch.cuda.synchronize()
         ts.append(time.perf_counter() - t0)
     t = float(np.median(ts))
-    print(f"[bench] adjoint: {info['iters']} iterations, {t:.3f} s (solve and gradient)",
-          file=sys.stderr, flush=True)
+    print(f"[bench] adjoint: {info['iters']} iterations, {t:.3f} s (solve and gradient); "
+          f"gradient kernel {info['grad_kernel_us']:.1f} us", file=sys.stderr, flush=True)
+    kus = info["grad_kernel_us"]
+    achieved = GRAD_BYTES_PER_CELL * grid.n / (kus * 1e-6) / 1e9
     return {"what": "adjoint of the FP64 solve: lambda = A^-1 gx by the same PCG to 1e-10, then "
                     "dL/dnu and dL/drhs in one gradient-kernel pass (4 words/cell)",
             "time_s": t, "iters": info["iters"], "rel_resid_true": info["rel_resid_true"],
             "iteration_kernel_us": info["iter_kernel_us"] if info["iter_kernel_samples"] > 0 else None,
-            "forward_plus_adjoint_s": t_pcg + t}
+            "forward_plus_adjoint_s": t_pcg + t,
+            "gradient_kernel": {"bound": "hbm", "kernel": "k_gradient", "kernel_us": kus,
+                                "alg_bytes_per_cell": GRAD_BYTES_PER_CELL, "achieved": achieved,
+                                "peak": 8000.0, "unit": "GB/s", "frac": achieved / 8000.0,
+                                "traffic": read_traffic(GRAD_TRAFFIC_FILE)}}
 
 
 def bench_sts(S, grid, nu, rhs, p, t_pcg, steps):

@@ -127,6 +127,8 @@ typedef struct {
     double iter_kernel_us;       /* mean duration of the sampled PCG iteration kernels (us)   */
     int32_t iter_kernel_samples; /* number of samples behind iter_kernel_us (0: not sampled) */
     int32_t pad_;
+    double grad_kernel_us;       /* mas_pcg_solve_adjoint with sample_timing: duration of the
+                                    gradient kernel (us), HIP events; otherwise 0             */
 } mas_pcg_info;
 
 /* Fill *o with the defaults shown above. */

@@ -56,7 +56,7 @@ class mas_pcg_info(ctypes.Structure):
                 ("rel_resid_true", ctypes.c_double), ("rel_resid_recursive", ctypes.c_double),
                 ("bnorm", ctypes.c_double), ("seconds", ctypes.c_double),
                 ("iter_kernel_us", ctypes.c_double), ("iter_kernel_samples", ctypes.c_int32),
-                ("pad_", ctypes.c_int32)]
+                ("pad_", ctypes.c_int32), ("grad_kernel_us", ctypes.c_double)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_ if f != "pad_"}

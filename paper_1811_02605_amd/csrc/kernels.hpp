@@ -1101,47 +1101,144 @@ __global__ __launch_bounds__(kWave *kSimpleJ) void k_fill(T *x, Dims d, T v) {
     })
 }
 
-// dL/dnu and dL/drhs from the forward solution x and the adjoint lam.
-__global__ __launch_bounds__(kWave *kSimpleJ) void k_gradient(const double *x, const double *lam,
-                                                              Geo geo, Dims d, double *gnu,
-                                                              double *grhs) {
-    MAS_SIMPLE_LOOP(d, {
-        if (cell.ok) {
-            const int i = cell.i, j = cell.j, k = cell.k;
-            const int64_t c = cell.c;
-            const double xc = x[c], lc = lam[c];
-            const double vt = geo.vt[j];
-            double s = 0.0;
-            if (i > 0) {
-                const int64_t n = c - d.plane;
-                s += 0.5 * geo.gr[i - 1] * vt * (lc - lam[n]) * (xc - x[n]);
-            } else {
-                s += geo.gw_in * vt * lc * xc;
-            }
-            if (i < d.nr - 1) {
-                const int64_t n = c + d.plane;
-                s += 0.5 * geo.gr[i] * vt * (lc - lam[n]) * (xc - x[n]);
-            } else {
-                s += geo.gw_out * vt * lc * xc;
-            }
-            if (j > 0) {
-                const int64_t n = c - d.np;
-                s += 0.5 * geo.gq[i] * geo.gtt[j - 1] * (lc - lam[n]) * (xc - x[n]);
-            }
-            if (j < d.nt - 1) {
-                const int64_t n = c + d.np;
-                s += 0.5 * geo.gq[i] * geo.gtt[j] * (lc - lam[n]) * (xc - x[n]);
-            }
-            if (!geo.np_one) {
-                const double gp = 0.5 * geo.gq[i] * geo.gpt[j];
-                const int64_t nm = c - k + ((k == 0) ? d.np - 1 : k - 1);
-                const int64_t np_ = c - k + ((k == d.np - 1) ? 0 : k + 1);
-                s += gp * ((lc - lam[nm]) * (xc - x[nm]) + (lc - lam[np_]) * (xc - x[np_]));
-            }
-            gnu[c] = -geo.dt * s;
-            if (grhs) grhs[c] = geo.vr[i] * vt * lc;
+// dL/dnu and dL/drhs from the forward solution x and the adjoint lam:
+//   dL/drhs_c = V_c lam_c,
+//   dL/dnu_c  = -dt sum_{faces f of c} (dG_f/dnu_c) (lam_c - lam_nb)(x_c - x_nb),
+// where a face's conductance depends on nu_c with weight 1/2 inside the shell
+// (face mean) and 1 on a Dirichlet wall (lam_nb = x_nb = 0 there).
+// Each wave owns GRPW = 2 consecutive theta rows (32 lanes each, V phi cells
+// per lane) and marches through the r planes of its chunk, keeping x and lam
+// of the planes behind, at and ahead of the current one in registers, so a
+// cell's two fields are fetched once per launch: the theta neighbour inside
+// the wave comes from the other half of the wave, the rows beyond the wave
+// from one edge-row load (the first row needs j-1, the second j+1), the phi
+// neighbours from lane shifts and the two cells past the segment ends from
+// one extra load.
+struct GradArgs {
+    const double *x, *lam;
+    double *gnu, *grhs;
+    Geo geo;
+    Dims d;
+    int tiles_i, tiles_k, tiles_j, ti, nblk;
+};
+constexpr int kGradWPB = 4;  // waves per block
+constexpr int kGradRPW = 2;  // theta rows per wave
+constexpr int kGradTI = 32;  // r planes per chunk
+
+template <int V>
+__global__ __launch_bounds__(kWave *kGradWPB) void k_gradient(GradArgs a) {
+    constexpr int RPW = kGradRPW, W = kWave / RPW, SEG = W * V;
+    using VD = VecT<double, V>;
+    const int nr = a.d.nr, nt = a.d.nt, np = a.d.np;
+    const int64_t plane = a.d.plane;
+
+    const int L = xcd_remap(blockIdx.x, a.nblk);
+    int it, kt, jt;
+    tile_coords<3>(L, a.tiles_i, a.tiles_k, a.tiles_j, it, kt, jt);
+
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wv = threadIdx.x / kWave;
+    const int rr = lane / W, lp = lane % W;
+    const int j = (jt * kGradWPB + wv) * RPW + rr;
+    const int k0 = kt * SEG;
+    const int nseg = min(SEG, np - k0);  // a multiple of V
+    const int nvl = nseg / V;
+    const bool rowok = j < nt;
+    const bool act = rowok && lp < nvl;
+    const int i0 = it * a.ti, i1 = min(i0 + a.ti, nr);
+    const bool up = (it & 1) == 0;  // neighbour chunks share the plane they both read
+    const int dir = up ? 1 : -1;
+    const int first = up ? i0 : i1 - 1;
+
+    // phi: the cell left of the segment (lane 0) and the one right of it (the
+    // row's last lane of a full segment, in the same load; in a short segment,
+    // which always ends at np - 1, the first idle lane loads the row's first
+    // V cells as if they were its own and the shift hands them over)
+    const int64_t colL = (int64_t)j * np + ((k0 == 0) ? np - 1 : k0 - 1);
+    const int64_t colR = (int64_t)j * np + ((k0 + nseg == np) ? 0 : k0 + nseg);
+    const bool pseudoR = rowok && nvl < W && lp == nvl;
+    const bool eL = act && lp == 0;
+    const bool eR = act && nvl == W && lp == W - 1;
+    const int64_t col = act ? (int64_t)j * np + k0 + lp * V : (pseudoR ? colR : 0);
+    const bool ldo = act || pseudoR;
+    // theta: one edge row per lane (row j-1 for the wave's first row, j+1 for
+    // its second), the other neighbour from the other half of the wave
+    const bool ldE = act && ((rr == 0) ? j > 0 : j < nt - 1);
+    const int64_t colE = (rr == 0) ? col - np : col + np;
+
+    // per-row factors: halves of the theta- and phi-face factors
+    const int jj = rowok ? j : 0;
+    const double vt = a.geo.vt[jj];
+    const double hU = (rowok && j > 0) ? 0.5 * a.geo.gtt[j - 1] : 0.0;
+    const double hD = (rowok && j < nt - 1) ? 0.5 * a.geo.gtt[jj] : 0.0;
+    const double hP = (rowok && !a.geo.np_one) ? 0.5 * a.geo.gpt[jj] : 0.0;
+
+    constexpr uint32_t ES = sizeof(double);
+    const uint32_t nbytes = (uint32_t)(a.d.n * (int64_t)ES);
+    const auto RX = make_rsrc(a.x, nbytes), RL = make_rsrc(a.lam, nbytes),
+               RG = make_rsrc(a.gnu, nbytes), RH = make_rsrc(a.grhs, a.grhs ? nbytes : 0u);
+    auto own_off = [&](int m) -> uint32_t {
+        return (ldo && m >= 0 && m < nr) ? (uint32_t)((int64_t)m * plane + col) * ES : kOOB;
+    };
+    VD Xb = bld<double, V>(RX, own_off(first - dir)), Lb = bld<double, V>(RL, own_off(first - dir));
+    VD Xc = bld<double, V>(RX, own_off(first)), Lc = bld<double, V>(RL, own_off(first));
+
+    VD sg{}, sh{};
+    uint32_t st_off = kOOB;
+    const int nsteps = i1 - i0;
+    for (int s = 0; s < nsteps; ++s) {
+        const int m = first + s * dir;
+        const int64_t base = (int64_t)m * plane;
+        const uint32_t oo = act ? (uint32_t)(base + col) * ES : kOOB;
+        const uint32_t oE = ldE ? (uint32_t)(base + colE) * ES : kOOB;
+        const uint32_t oLR = eL ? (uint32_t)(base + colL) * ES : (eR ? (uint32_t)(base + colR) * ES : kOOB);
+        // ---- loads: plane m + dir, then the edge row and phi edge cells of plane m
+        const VD Xa = bld<double, V>(RX, own_off(m + dir)), La = bld<double, V>(RL, own_off(m + dir));
+        const VD XE = bld<double, V>(RX, oE), LE = bld<double, V>(RL, oE);
+        const double XS = bld<double, 1>(RX, oLR).v[0], LS = bld<double, 1>(RL, oLR).v[0];
+        // ---- stores of the previous plane (issued behind this plane's loads)
+        bst<double, V, kAuxNT>(RG, st_off, sg);
+        bst<double, V, kAuxNT>(RH, st_off, sh);
+
+        // ---- plane factors
+        const double gq = a.geo.gq[m];
+        const double cRp = (m < nr - 1) ? 0.5 * a.geo.gr[m] * vt : 0.0;
+        const double cRm = (m > 0) ? 0.5 * a.geo.gr[m - 1] * vt : 0.0;
+        const double cW = (((m == 0) ? a.geo.gw_in : 0.0) + ((m == nr - 1) ? a.geo.gw_out : 0.0)) * vt;
+        const double cU = gq * hU, cD = gq * hD, cP = gq * hP;
+        const double vol = a.geo.vr[m] * vt;
+        const VD &Xp = up ? Xa : Xb, &Xm = up ? Xb : Xa;  // planes m+1, m-1
+        const VD &Lp = up ? La : Lb, &Lm = up ? Lb : La;
+
+        const double xl0 = lane_prev(Xc.v[V - 1]), ll0 = lane_prev(Lc.v[V - 1]);
+        const double xr0 = lane_next(Xc.v[0]), lr0 = lane_next(Lc.v[0]);
+#pragma unroll
+        for (int e = 0; e < V; ++e) {
+            const double xc = Xc.v[e], lc = Lc.v[e];
+            const double xo = other_half(xc), lo = other_half(lc);
+            const double xu = (rr == 0) ? XE.v[e] : xo, lu = (rr == 0) ? LE.v[e] : lo;
+            const double xd = (rr == 0) ? xo : XE.v[e], ld = (rr == 0) ? lo : LE.v[e];
+            const double xl = (e > 0) ? Xc.v[e - 1] : ((lp == 0) ? XS : xl0);
+            const double ll = (e > 0) ? Lc.v[e - 1] : ((lp == 0) ? LS : ll0);
+            const double xr = (e < V - 1) ? Xc.v[e + 1] : (eR ? XS : xr0);
+            const double lr = (e < V - 1) ? Lc.v[e + 1] : (eR ? LS : lr0);
+            double t = cW * (lc * xc);
+            t += cRp * ((lc - Lp.v[e]) * (xc - Xp.v[e]));
+            t += cRm * ((lc - Lm.v[e]) * (xc - Xm.v[e]));
+            t += cU * ((lc - lu) * (xc - xu));
+            t += cD * ((lc - ld) * (xc - xd));
+            t += cP * ((lc - ll) * (xc - xl) + (lc - lr) * (xc - xr));
+            sg.v[e] = -a.geo.dt * t;
+            sh.v[e] = vol * lc;
         }
-    })
+        st_off = oo;
+        Xb = Xc;
+        Lb = Lc;
+        Xc = Xa;
+        Lc = La;
+    }
+    bst<double, V, kAuxNT>(RG, st_off, sg);
+    bst<double, V, kAuxNT>(RH, st_off, sh);
 }
 
 // Streaming copy: each block copies one contiguous chunk of kCopyChunk

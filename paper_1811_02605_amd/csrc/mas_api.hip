@@ -1276,6 +1276,44 @@ extern "C" int mas_pcg_solve_multi(const mas_op *op, int32_t nrhs, const double 
     return st;
 }
 
+namespace {
+struct EventPool {
+    std::vector<hipEvent_t> ev;
+    ~EventPool() {
+        for (auto e : ev) (void)hipEventDestroy(e);
+    }
+    int make(hipEvent_t *out) {
+        hipEvent_t e;
+        HIPCHK(hipEventCreate(&e));
+        ev.push_back(e);
+        *out = e;
+        return MAS_OK;
+    }
+};
+}  // namespace
+
+// The gradient kernel over the whole grid (one launch).
+static int gradient_launch(const mas_op *op, const double *x, const double *lambda, double *g_nu,
+                           double *g_rhs, hipStream_t stream) {
+    const Shape &s = op->s;
+    const int v = (s.np % 2 == 0) ? 2 : 1;
+    const int seg = (kWave / kGradRPW) * v;
+    const int64_t tiles_i = (s.nr + kGradTI - 1) / kGradTI;
+    const int64_t tiles_k = (s.np + seg - 1) / seg;
+    const int64_t tiles_j = (s.nt + kGradWPB * kGradRPW - 1) / (kGradWPB * kGradRPW);
+    const int64_t nblk = tiles_i * tiles_k * tiles_j;
+    if (nblk > INT32_MAX) return fail(MAS_EINVAL, "grid too large for the gradient kernel");
+    GradArgs ga{x, lambda, g_nu, g_rhs, op->geo, s.dims(), (int)tiles_i, (int)tiles_k, (int)tiles_j,
+                kGradTI, (int)nblk};
+    const dim3 grid((unsigned)nblk), block(kWave * kGradWPB);
+    if (v == 2)
+        hipLaunchKernelGGL(k_gradient<2>, grid, block, 0, stream, ga);
+    else
+        hipLaunchKernelGGL(k_gradient<1>, grid, block, 0, stream, ga);
+    LAUNCHCHK();
+    return MAS_OK;
+}
+
 extern "C" int mas_pcg_solve_adjoint(const mas_op *op, const double *x, const double *gx,
                                      double *lambda, double *g_nu, double *g_rhs,
                                      const mas_pcg_opts *o, void *work, int64_t work_bytes,
@@ -1285,10 +1323,24 @@ extern "C" int mas_pcg_solve_adjoint(const mas_op *op, const double *x, const do
         return fail(MAS_EINVAL, "op, x, gx, lambda and g_nu must not be NULL");
     int st = solve_core(op, gx, 0, lambda, o, work, work_bytes, hip_stream, info);
     if (st < 0) return st;
-    hipLaunchKernelGGL(k_gradient, op->s.simple_grid(), dim3(kWave, kSimpleJ), 0,
-                       as_stream(hip_stream), x, lambda, op->geo, op->s.dims(), g_nu, g_rhs);
-    LAUNCHCHK();
-    HIPCHK(hipStreamSynchronize(as_stream(hip_stream)));
+    hipStream_t stream = as_stream(hip_stream);
+    const bool timing = o && o->sample_timing;
+    EventPool pool;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    int st2;
+    if (timing) {
+        if ((st2 = pool.make(&e0)) != MAS_OK || (st2 = pool.make(&e1)) != MAS_OK) return st2;
+        HIPCHK(hipEventRecord(e0, stream));
+    }
+    st2 = gradient_launch(op, x, lambda, g_nu, g_rhs, stream);
+    if (st2 != MAS_OK) return st2;
+    if (timing) HIPCHK(hipEventRecord(e1, stream));
+    HIPCHK(hipStreamSynchronize(stream));
+    if (timing && info) {
+        float ms = 0.0f;
+        HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+        info->grad_kernel_us = 1e3 * (double)ms;
+    }
     return st;
 }
 
@@ -1463,21 +1515,6 @@ static int sts_pair_launch(const mas_op *op, hipStream_t stream, const double *X
     return MAS_OK;
 }
 
-namespace {
-struct EventPool {
-    std::vector<hipEvent_t> ev;
-    ~EventPool() {
-        for (auto e : ev) (void)hipEventDestroy(e);
-    }
-    int make(hipEvent_t *out) {
-        hipEvent_t e;
-        HIPCHK(hipEventCreate(&e));
-        ev.push_back(e);
-        *out = e;
-        return MAS_OK;
-    }
-};
-}  // namespace
 
 // The recursion runs on D_j = Y_j - Y_0 (linearity of L gives
 // dtL(Y_{j-1}) = dtL(D_{j-1}) + L_0 with L_0 = dtL(Y_0)):

@@ -122,6 +122,7 @@ def test_sts_defaults_and_null_operator():
     lib.mas_sts_default_opts(ctypes.byref(o))
     assert o.stages == 0 and o.sample_timing == 0 and o.single_stage_kernels == 0
     assert ctypes.sizeof(abi.mas_sts_opts) == 16 and ctypes.sizeof(abi.mas_sts_info) == 40
+    assert ctypes.sizeof(abi.mas_pcg_info) == 72
     info = abi.mas_sts_info()
     assert lib.mas_sts_stages(None) == abi.MAS_EINVAL
     assert lib.mas_sts_workspace_bytes(None) == abi.MAS_EINVAL

@@ -207,6 +207,42 @@ def test_adjoint_matches_oracle_gradient(precision):
     assert ora.rel_residual(gx, to_host(lam)) <= 1e-10
 
 
+# The gradient kernel's tiles: 64-cell phi segments (32 lanes x 2; 32 x 1 for
+# odd np), 8 theta rows per block, 32-plane r chunks marched up or down.
+GRAD_SHAPES = [(33, 17, 129), (3, 9, 70), (70, 9, 66), (65, 4, 34), (5, 9, 128), (4, 7, 64),
+               (3, 5, 2), (6, 3, 1), (2, 1, 5), (1, 2, 4), (97, 11, 130)]
+
+
+@pytest.mark.parametrize("shape", GRAD_SHAPES)
+@pytest.mark.parametrize("bc", [(0, 1), (1, 0), (0, 0)])
+def test_gradient_kernel_matches_oracle_formula(shape, bc):
+    """dL/dnu and dL/drhs at the GPU's own lambda and an arbitrary x, against the
+    oracle's formula at the same fields: the kernel alone, element by element."""
+    p = problem(shape, bc)
+    _, op = gpu_operator(p)
+    ora = oracle_operator(p)
+    rng = np.random.default_rng(17)
+    x = rng.standard_normal(p.shape)
+    gx = rng.standard_normal(p.shape)
+    lam, gnu, grhs, info = op.adjoint(to_dev(x), to_dev(gx), S.make_opts(rtol=1e-10),
+                                      allow_notconv=False)
+    assert info["grad_kernel_us"] == 0.0  # not sampled
+    gnu_o, grhs_o = (np.asarray(t).reshape(p.shape) for t in ora.gradient(x, to_host(lam)))
+    g, h = to_host(gnu), to_host(grhs)
+    # each entry is a sum of at most seven products formed in the same way on
+    # both sides; the bound is relative to the largest entry
+    assert np.max(np.abs(g - gnu_o)) <= 1e-13 * np.max(np.abs(gnu_o))
+    assert np.max(np.abs(h - grhs_o)) <= 1e-14 * np.max(np.abs(grhs_o))
+
+
+def test_gradient_kernel_timing_sample():
+    p = problem((9, 16, 32))
+    _, op = gpu_operator(p)
+    x = to_dev(np.random.default_rng(3).standard_normal(p.shape))
+    _, _, _, info = op.adjoint(x, x, S.make_opts(rtol=1e-10, sample_timing=1), allow_notconv=False)
+    assert info["grad_kernel_us"] > 0.0
+
+
 def test_autograd_function():
     p = problem((6, 8, 16))
     grid = S.Grid.from_problem(p)

@@ -93,6 +93,41 @@ static inline int iter_vec(int np, int nrhs) {
 
 static inline int64_t align256(int64_t v) { return (v + 255) & ~int64_t(255); }
 
+// Array stagger.  Arrays of n cells sit at offsets that differ by multiples
+// of their length, which at the production sizes is a multiple of 16 MiB
+// (c1: 400 MiB), so element c of every array would share the low address
+// bits that pick the HBM channel; a stencil kernel reading element c of
+// seven arrays at once then sends them to one channel.  Each array of a
+// layout is moved by its own multiple of kStagger bytes, and the workspace
+// and the stage arrays start at other multiples than the operator storage.
+// 2304 = 9 x 256: sixteen consecutive arrays start in sixteen different
+// 256-byte slots of a 4 KiB interleave unit (measured 1-2% faster iteration
+// and stage kernels than no stagger).
+#ifndef MAS_STAGGER
+#define MAS_STAGGER 2304
+#endif
+static constexpr int64_t kStagger = MAS_STAGGER;
+static_assert(kStagger % 256 == 0, "stagger keeps 256-byte alignment");
+enum { kPhaseStorage = 0, kPhaseWork = 8, kPhaseSts = 20 };
+
+// Offsets of a layout: small tables packed at 256-byte alignment, arrays of
+// the grid's size each staggered (see above).
+struct LayoutCursor {
+    int64_t off = 0;
+    int64_t lead;  // extra stagger before the first array: the layout's phase
+    explicit LayoutCursor(int phase) : lead(phase * kStagger) {}
+    int64_t take(int64_t bytes) {
+        const int64_t o = off;
+        off = align256(off + bytes);
+        return o;
+    }
+    int64_t take_array(int64_t bytes) {
+        off += kStagger + lead;
+        lead = 0;
+        return take(bytes);
+    }
+};
+
 struct Shape {
     int nr, nt, np;
     int64_t plane, n;
@@ -141,24 +176,20 @@ struct StorageLayout {
 
 static StorageLayout storage_layout(const Shape &s, int precision) {
     StorageLayout L{};
-    int64_t off = 0;
-    auto take = [&](int64_t bytes) {
-        int64_t o = off;
-        off = align256(off + bytes);
-        return o;
-    };
-    L.flags = take(256);
-    L.vr = take(8 * (int64_t)s.nr);
-    L.vt = take(8 * (int64_t)s.nt);
-    L.gr = take(8 * (int64_t)s.nr);
-    L.gq = take(8 * (int64_t)s.nr);
-    L.gtt = take(8 * (int64_t)s.nt);
-    L.gpt = take(8 * (int64_t)s.nt);
-    L.w = take(8 * s.n);
-    for (int t = 0; t < 3; ++t) L.c64[t] = take(8 * s.n);
-    for (int t = 0; t < 3; ++t) L.c32[t] = (precision == MAS_FP32_REFINED) ? take(4 * s.n) : -1;
-    L.nu = take(8 * s.n);
-    L.total = off;
+    LayoutCursor cur(kPhaseStorage);
+    L.flags = cur.take(256);
+    L.vr = cur.take(8 * (int64_t)s.nr);
+    L.vt = cur.take(8 * (int64_t)s.nt);
+    L.gr = cur.take(8 * (int64_t)s.nr);
+    L.gq = cur.take(8 * (int64_t)s.nr);
+    L.gtt = cur.take(8 * (int64_t)s.nt);
+    L.gpt = cur.take(8 * (int64_t)s.nt);
+    L.w = cur.take_array(8 * s.n);
+    for (int t = 0; t < 3; ++t) L.c64[t] = cur.take_array(8 * s.n);
+    for (int t = 0; t < 3; ++t)
+        L.c32[t] = (precision == MAS_FP32_REFINED) ? cur.take_array(4 * s.n) : -1;
+    L.nu = cur.take_array(8 * s.n);
+    L.total = cur.off;
     return L;
 }
 
@@ -380,12 +411,9 @@ struct WorkLayout {
 // them, then b^ and the six PCG vectors of each.
 static WorkLayout work_layout(const Shape &s, int precision, int nrhs = 1) {
     WorkLayout L{};
-    int64_t off = 0;
-    auto take = [&](int64_t bytes) {
-        int64_t o = off;
-        off = align256(off + bytes);
-        return o;
-    };
+    LayoutCursor cur(kPhaseWork);
+    auto take = [&](int64_t bytes) { return cur.take(bytes); };
+    auto take_array = [&](int64_t bytes) { return cur.take_array(bytes); };
     // the iteration kernel writes nrhs * kNV partials per block (most blocks
     // with V = 1), the simple-tile kernels up to kSimpleNV
     const int64_t nparts = std::max(s.nblk_iter(1) * kNV * nrhs, s.nblk_simple() * kSimpleNV);
@@ -397,8 +425,8 @@ static WorkLayout work_layout(const Shape &s, int precision, int nrhs = 1) {
         for (int t = 0; t < 6; ++t) L.vec[c][t] = -1;
     }
     for (int c = 0; c < nrhs; ++c) {
-        L.bhat[c] = take(8 * s.n);
-        for (int t = 0; t < 6; ++t) L.vec[c][t] = take(es * s.n);
+        L.bhat[c] = take_array(8 * s.n);
+        for (int t = 0; t < 6; ++t) L.vec[c][t] = take_array(es * s.n);
     }
     // segment-edge records of the iteration kernel, double-buffered
     const int v = (precision == MAS_FP32_REFINED) ? iter_vec<float>(s.np, nrhs)
@@ -408,8 +436,8 @@ static WorkLayout work_layout(const Shape &s, int precision, int nrhs = 1) {
     if (L.halo_bytes > 0)
         for (int c = 0; c < nrhs; ++c)
             for (int t = 0; t < 2; ++t) L.halo[c][t] = take(L.halo_bytes);
-    L.dh = (precision == MAS_FP32_REFINED) ? take(4 * s.n) : -1;
-    L.total = off;
+    L.dh = (precision == MAS_FP32_REFINED) ? take_array(4 * s.n) : -1;
+    L.total = cur.off;
     return L;
 }
 
@@ -1415,12 +1443,9 @@ struct StsWork {
 
 static StsWork sts_work_layout(const Shape &s) {
     StsWork L{};
-    int64_t off = 0;
-    for (int t = 0; t < 5; ++t) {
-        L.vec[t] = off;
-        off = align256(off + 8 * s.n);
-    }
-    L.total = off;
+    LayoutCursor cur(kPhaseSts);
+    for (int t = 0; t < 5; ++t) L.vec[t] = cur.take_array(8 * s.n);
+    L.total = cur.off;
     return L;
 }
 

@@ -242,9 +242,10 @@ typedef struct {
     int32_t stages;               /* stages run                                          */
     double z_max;                 /* Gershgorin bound of dt * spectral radius of L       */
     double step_us;               /* device time of the whole step (sample_timing only)  */
-    double stage_kernel_us;       /* mean device time of the sampled general stage
-                                     kernels, each running stages_per_kernel stages (us) */
-    int32_t stage_kernel_samples; /* samples behind stage_kernel_us (0: not sampled)     */
+    double stage_kernel_us;       /* mean device time of the general stage kernels, each
+                                     running stages_per_kernel stages (us), from one event
+                                     pair around their back-to-back run                  */
+    int32_t stage_kernel_samples; /* kernels behind stage_kernel_us (0: not timed)       */
     int32_t stages_per_kernel;    /* 2 when stages ran in pairs, else 1                  */
 } mas_sts_info;
 

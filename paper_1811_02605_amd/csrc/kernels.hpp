@@ -1123,7 +1123,7 @@ struct GradArgs {
 };
 constexpr int kGradWPB = 4;  // waves per block
 constexpr int kGradRPW = 2;  // theta rows per wave
-constexpr int kGradTI = 32;  // r planes per chunk
+constexpr int kGradTI = 32;  // shortest r chunk
 
 template <int V>
 __global__ __launch_bounds__(kWave *kGradWPB) void k_gradient(GradArgs a) {

@@ -16,9 +16,11 @@ from paper_1811_02605_amd import solver as S
 pytestmark = pytest.mark.gpu
 
 # (nr, nt, np): single tile, ragged phi (70, 129), ragged theta (7, 17), two r
-# chunks (33, 65), degenerate 1-cell directions, the small benchmark grid.
-SHAPES = [(4, 4, 8), (5, 7, 13), (3, 9, 70), (33, 17, 129), (65, 8, 64), (1, 3, 2), (6, 3, 1),
-          (2, 1, 5), (9, 16, 32)]
+# chunks (33, 65), eight 18-plane chunks with a ragged last one (137: the
+# chunk length grows with nr beyond 128 planes), degenerate 1-cell
+# directions, the small benchmark grid.
+SHAPES = [(4, 4, 8), (5, 7, 13), (3, 9, 70), (33, 17, 129), (65, 8, 64), (137, 5, 16), (1, 3, 2),
+          (6, 3, 1), (2, 1, 5), (9, 16, 32)]
 BCS = [(0, 0), (1, 0), (1, 1)]
 
 # Elementwise bound for the exported entries: both sides form each conductance
@@ -209,7 +211,7 @@ def test_adjoint_matches_oracle_gradient(precision):
 
 # The gradient kernel's tiles: 64-cell phi segments (32 lanes x 2; 32 x 1 for
 # odd np), 8 theta rows per block, 32-plane r chunks marched up or down.
-GRAD_SHAPES = [(33, 17, 129), (3, 9, 70), (70, 9, 66), (65, 4, 34), (5, 9, 128), (4, 7, 64),
+GRAD_SHAPES = [(33, 17, 129), (3, 9, 70), (70, 9, 66), (65, 4, 34), (5, 9, 128), (4, 7, 64), (261, 3, 8),
                (3, 5, 2), (6, 3, 1), (2, 1, 5), (1, 2, 4), (97, 11, 130)]
 
 

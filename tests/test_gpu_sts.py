@@ -183,9 +183,9 @@ def test_timing_info_and_argument_errors(pairs):
     else:
         ngen = s - 4
         assert info["stages_per_kernel"] == 1
-    every = max(1, -(-ngen // 32))
-    assert info["stage_kernel_samples"] == len(range(0, ngen, every))
-    assert 0.0 < info["stage_kernel_us"] < info["step_us"]
+    # one event pair around the back-to-back run of all general kernels
+    assert info["stage_kernel_samples"] == ngen
+    assert 0.0 < info["stage_kernel_us"] * ngen < info["step_us"]
     with pytest.raises(abi.MasError, match="stages"):
         op.sts_step(u0, stages=1)
     lib = abi.load()

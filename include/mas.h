@@ -83,7 +83,10 @@ enum { MAS_REFINE_RESTART = 0, MAS_REFINE_RELIABLE = 1 };
  *     between blocks and the periodic phi coupling are left out of the
  *     factors; cells are ordered naturally inside a block, so ILU(0) changes
  *     only the diagonal.  The factor is formed at the start of every solve.
- *     Double precision only. */
+ *     With MAS_FP32_REFINED the factor is the double-precision one rounded
+ *     to single precision, the inner PC2-PCG runs in single precision, and
+ *     every refinement step restarts it from the replaced residual
+ *     (MAS_REFINE_RESTART whatever o->refine says). */
 enum { MAS_PC1 = 0, MAS_PC2 = 1 };
 
 typedef struct {
@@ -111,7 +114,7 @@ typedef struct {
     int32_t sample_timing;/* nonzero: time a sample of PCG iteration kernels with HIP
                              events (reported in mas_pcg_info)                          (0) */
     int32_t refine;       /* refined: MAS_REFINE_RESTART | MAS_REFINE_RELIABLE   (RELIABLE) */
-    int32_t precond;      /* MAS_PC1 | MAS_PC2 (FP64 only)                          (PC1) */
+    int32_t precond;      /* MAS_PC1 | MAS_PC2                                      (PC1) */
     int32_t pad_;
 } mas_pcg_opts;
 
@@ -172,8 +175,9 @@ int mas_op_export(const mas_op *op, double *cr, double *ct, double *cp, double *
  * the defaults).  The same size serves mas_pcg_solve_adjoint. */
 int64_t mas_pcg_workspace_bytes(const mas_op *op, const mas_pcg_opts *o);
 
-/* Solve A x = V .* rhs by point-Jacobi preconditioned CG (paper Section 2.2,
- * PC1), or by the single-precision PCG inside double-precision refinement.
+/* Solve A x = V .* rhs by preconditioned CG (paper Section 2.2: PC1 or PC2),
+ * in double precision or by the single-precision PCG inside double-precision
+ * refinement.
  *   rhs   dev, N
  *   x     dev, N: initial guess on entry if o->use_x0, solution on exit
  *   work  dev, >= mas_pcg_workspace_bytes(op, o), 256-byte aligned

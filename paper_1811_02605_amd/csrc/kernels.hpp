@@ -1094,6 +1094,16 @@ __global__ __launch_bounds__(kWave *kSimpleJ) void k_refine_fold(float *dh, cons
     })
 }
 
+// x^ += d^ (a single-precision correction accumulated in double), then d^ = 0.
+__global__ __launch_bounds__(kWave *kSimpleJ) void k_fold(float *dh, Dims d, double *x) {
+    MAS_SIMPLE_LOOP(d, {
+        if (cell.ok) {
+            x[cell.c] = x[cell.c] + (double)dh[cell.c];
+            dh[cell.c] = 0.0f;
+        }
+    })
+}
+
 template <typename T>
 __global__ __launch_bounds__(kWave *kSimpleJ) void k_fill(T *x, Dims d, T v) {
     MAS_SIMPLE_LOOP(d, {

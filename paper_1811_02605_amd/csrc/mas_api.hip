@@ -465,8 +465,6 @@ static int check_opts(const mas_op *op, const mas_pcg_opts *o) {
     if (o->max_restarts < 0) return fail(MAS_EINVAL, "max_restarts must be >= 0");
     if (o->precond != MAS_PC1 && o->precond != MAS_PC2)
         return fail(MAS_EINVAL, "unknown preconditioner %d", o->precond);
-    if (o->precond == MAS_PC2 && o->precision != MAS_FP64)
-        return fail(MAS_EINVAL, "the PC2 preconditioner is double precision only");
     return MAS_OK;
 }
 
@@ -755,19 +753,26 @@ static int64_t pc2_blocks(const Shape &s, int *nbi, int *nbj, int *nbk) {
 // x (scaled) and r = b^ - A^ x already in r.  Iterations are counted from
 // iter0; the run stops on ||W r||^2 <= tol2 (every iteration), at max_iter
 // or on a breakdown.  The modified diagonal must already be in d.
-static int run_pcg_pc2(Ctx &cx, double *r, double *z, double *const p[2], double *q, double *d,
-                       double *x, int iter0, int max_iter, double tol2, PcgResult *res) {
+template <typename T>
+static int run_pcg_pc2(Ctx &cx, T *r, T *z, T *const p[2], T *q, T *d, T *x, int iter0,
+                       int max_iter, double tol2, PcgResult *res) {
     const mas_op *op = cx.op;
     const Shape &s = op->s;
     hipStream_t st = cx.stream;
     int nbi, nbj, nbk;
     const int64_t nb = pc2_blocks(s, &nbi, &nbj, &nbk);
+    const T *cc[3];
+    if constexpr (std::is_same<T, float>::value) {
+        for (int t = 0; t < 3; ++t) cc[t] = op->c32[t];
+    } else {
+        for (int t = 0; t < 3; ++t) cc[t] = op->c64[t];
+    }
     hipLaunchKernelGGL(k_ctl_init, dim3(1), dim3(64), 0, st, cx.ctl, 0, iter0, max_iter, tol2, 0.0,
                        (int)FLAG_RUN);
-    Pc2Args a{op->c64[0], op->c64[1], op->c64[2], op->w, d, r, x, z, q, nullptr, cx.partials,
-              cx.ctl, s.dims(), nbi, nbj, nbk, 0};
+    Pc2Args<T> a{cc[0], cc[1], cc[2], op->w, d, r, x, z, q, nullptr, cx.partials,
+                 cx.ctl, s.dims(), nbi, nbj, nbk, 0};
     // z = M^-1 r of the initial residual, (r, z), the stopping test
-    hipLaunchKernelGGL(k_pc2_solve, dim3((unsigned)nb), dim3(kWave), 0, st, a);
+    hipLaunchKernelGGL(k_pc2_solve<T>, dim3((unsigned)nb), dim3(kWave), 0, st, a);
     hipLaunchKernelGGL(k_pc2_fin_b, dim3(1), dim3(kRedThreads), 0, st, cx.partials, (int)nb, cx.ctl, 1);
     LAUNCHCHK();
     int32_t *pin = nullptr;
@@ -785,22 +790,22 @@ static int run_pcg_pc2(Ctx &cx, double *r, double *z, double *const p[2], double
     } guard{done};
     // the direction and SpMV step: the PCG iteration kernel with no r, q or
     // x (p = z + beta p, q = A^ p, partial (p, q) first of each block's kNV)
-    IterArgs<double> it{};
-    it.cr = op->c64[0];
-    it.ct = op->c64[1];
-    it.cp = op->c64[2];
+    IterArgs<T> it{};
+    it.cr = cc[0];
+    it.ct = cc[1];
+    it.cp = cc[2];
     it.w = op->w;
     it.partials = cx.partials;
     it.ctl = cx.ctl;
     it.d = s.dims();
-    const int V = iter_vec<double>(s.np, 1);
+    const int V = iter_vec<T>(s.np, 1);
     it.tiles_i = s.tiles_i();
     it.tiles_k = s.tiles_k(V);
     it.tiles_j = s.tiles_j();
     it.ti = s.ti();
     it.nblk = (int)s.nblk_iter(V);
     it.halo_bytes = 0;
-    constexpr int VW = vec_full<double>();
+    constexpr int VW = vec_full<T>();
     const dim3 igrid((unsigned)it.nblk), iblock(kWave * kTJ);
     a.update = 1;
     int k = iter0, nbt = 0;
@@ -809,8 +814,8 @@ static int run_pcg_pc2(Ctx &cx, double *r, double *z, double *const p[2], double
         const int kend = std::min(max_iter, k + 16);
         for (; k < kend; ++k) {
             // the first direction is z itself (beta = 0): p_old points at z
-            const double *p_old = (k == iter0) ? z : p[k & 1];
-            double *p_new = p[(k + 1) & 1];
+            const T *p_old = (k == iter0) ? z : p[k & 1];
+            T *p_new = p[(k + 1) & 1];
             const bool sample = cx.timing && (k % 16 == 7) && cx.ev.size() < 128;
             if (sample) {
                 hipEvent_t e0, e1;
@@ -826,15 +831,15 @@ static int run_pcg_pc2(Ctx &cx, double *r, double *z, double *const p[2], double
             it.p_out[0] = p_new;
             it.q_out[0] = q;
             if (V == VW)
-                hipLaunchKernelGGL((k_pcg_iter<double, 1, kTJ, kRPW, VW, false, false>), igrid, iblock,
+                hipLaunchKernelGGL((k_pcg_iter<T, 1, kTJ, kRPW, VW, false, false>), igrid, iblock,
                                    0, st, it);
             else
-                hipLaunchKernelGGL((k_pcg_iter<double, 1, kTJ, kRPW, 1, false, false>), igrid, iblock,
+                hipLaunchKernelGGL((k_pcg_iter<T, 1, kTJ, kRPW, 1, false, false>), igrid, iblock,
                                    0, st, it);
             hipLaunchKernelGGL(k_pc2_fin_a, dim3(1), dim3(kRedThreads), 0, st, cx.partials, it.nblk,
                                (int)kNV, cx.ctl);
             a.p = p_new;
-            hipLaunchKernelGGL(k_pc2_solve, dim3((unsigned)nb), dim3(kWave), 0, st, a);
+            hipLaunchKernelGGL(k_pc2_solve<T>, dim3((unsigned)nb), dim3(kWave), 0, st, a);
             hipLaunchKernelGGL(k_pc2_fin_b, dim3(1), dim3(kRedThreads), 0, st, cx.partials, (int)nb,
                                cx.ctl, 0);
             if (sample) HIPCHK(hipEventRecord(cx.ev.back(), st));
@@ -924,7 +929,62 @@ static int solve_core(const mas_op *op, const double *src, int src_is_rhs, doubl
         return MAS_OK;
     }
 
-    if (o.precond == MAS_PC2) {
+    if (o.precond == MAS_PC2 && o.precision == MAS_FP32_REFINED) {
+        // Single-precision PC2-PCG inside double-precision refinement: each
+        // outer step solves A^ d = r^ (the double-precision residual, rounded)
+        // from d = 0 until its recursive residual is inner_rtol below ||W r||
+        // (or a quarter of the final tolerance), then x^ += d in double and
+        // r^ = b^ - A^ x^ in double.  The factor is the double-precision one,
+        // rounded.
+        float *r = reinterpret_cast<float *>(base + L.vec[0][0]);
+        float *z = reinterpret_cast<float *>(base + L.vec[0][1]);
+        float *const p[2] = {reinterpret_cast<float *>(base + L.vec[0][2]),
+                             reinterpret_cast<float *>(base + L.vec[0][3])};
+        float *q = reinterpret_cast<float *>(base + L.vec[0][4]);
+        float *dm = reinterpret_cast<float *>(base + L.vec[0][5]);
+        float *dh = reinterpret_cast<float *>(base + L.dh);
+        int nbi, nbj, nbk;
+        const int64_t nb = pc2_blocks(s, &nbi, &nbj, &nbk);
+        if (nb * 2 * 8 > L.bhat[0] - L.partials || s.nblk_simple() * 8 > L.bhat[0] - L.partials)
+            return fail(MAS_EINVAL, "internal: partial-sum area too small for PC2");
+        if (nb > INT32_MAX) return fail(MAS_EINVAL, "grid too large for PC2");
+        Pc2Args<double> fa{op->c64[0], op->c64[1], op->c64[2], op->w, nullptr, nullptr, nullptr,
+                           nullptr, nullptr, nullptr, nullptr, cx.ctl, d, nbi, nbj, nbk, 0};
+        hipLaunchKernelGGL(k_pc2_factor<float>, dim3((unsigned)nb), dim3(kWave), 0, cx.stream, fa, dm);
+        hipLaunchKernelGGL(k_fill<float>, sgrid, sblock, 0, cx.stream, dh, d, 0.0f);
+        LAUNCHCHK();
+        double rw2 = 0.0;
+        st = residual<float>(cx, bhat, x, r, &rw2);
+        if (st != MAS_OK) return st;
+        info.rel_resid_true = info.rel_resid_recursive = std::sqrt(rw2) / bnorm;
+        status = (rw2 <= tol2) ? MAS_OK : MAS_ENOTCONV;
+        const double d2 = o.inner_rtol * o.inner_rtol;
+        int used = 0;
+        while (status != MAS_OK && info.outer_iters < o.max_outer && used < o.max_iters) {
+            const double thr = std::max(d2 * rw2, 0.25 * tol2);
+            PcgResult pr{};
+            st = run_pcg_pc2<float>(cx, r, z, p, q, dm, dh, 0, o.max_iters - used, thr, &pr);
+            if (st != MAS_OK) return st;
+            timing_summary(cx, pr.last_iter[0], &info);
+            used += pr.last_iter[0];
+            info.outer_iters++;
+            if (pr.flag[0] == FLAG_BREAK && pr.last_iter[0] == 0) {
+                status = MAS_EBREAKDOWN;
+                break;
+            }
+            Ctl h;
+            st = read_ctl(cx, &h);
+            if (st != MAS_OK) return st;
+            info.rel_resid_recursive = std::sqrt(h.rw) / bnorm;
+            hipLaunchKernelGGL(k_fold, sgrid, sblock, 0, cx.stream, dh, d, x);
+            LAUNCHCHK();
+            st = residual<float>(cx, bhat, x, r, &rw2);
+            if (st != MAS_OK) return st;
+            info.rel_resid_true = std::sqrt(rw2) / bnorm;
+            if (rw2 <= tol2) status = MAS_OK;
+        }
+        info.iters = used;
+    } else if (o.precond == MAS_PC2) {
         // vectors: r, z, p[2], q, and the modified diagonal
         double *r = reinterpret_cast<double *>(base + L.vec[0][0]);
         double *z = reinterpret_cast<double *>(base + L.vec[0][1]);
@@ -937,9 +997,9 @@ static int solve_core(const mas_op *op, const double *src, int src_is_rhs, doubl
         if (nb * 2 * 8 > L.bhat[0] - L.partials || s.nblk_simple() * 8 > L.bhat[0] - L.partials)
             return fail(MAS_EINVAL, "internal: partial-sum area too small for PC2");
         if (nb > INT32_MAX) return fail(MAS_EINVAL, "grid too large for PC2");
-        Pc2Args fa{op->c64[0], op->c64[1], op->c64[2], op->w, dm, nullptr, nullptr, nullptr,
-                   nullptr, nullptr, nullptr, cx.ctl, d, nbi, nbj, nbk, 0};
-        hipLaunchKernelGGL(k_pc2_factor, dim3((unsigned)nb), dim3(kWave), 0, cx.stream, fa);
+        Pc2Args<double> fa{op->c64[0], op->c64[1], op->c64[2], op->w, dm, nullptr, nullptr, nullptr,
+                           nullptr, nullptr, nullptr, cx.ctl, d, nbi, nbj, nbk, 0};
+        hipLaunchKernelGGL(k_pc2_factor<double>, dim3((unsigned)nb), dim3(kWave), 0, cx.stream, fa, dm);
         LAUNCHCHK();
         double rw2 = 0.0;
         st = residual<double>(cx, bhat, x, r, &rw2);

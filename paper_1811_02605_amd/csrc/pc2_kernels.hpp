@@ -39,12 +39,16 @@ static_assert(kPc2I * kPc2J == kWave, "one lane per (r, theta) column of a block
 static_assert(kPc2K == kWave, "one lane per phi offset of a block");
 constexpr int kPc2Levels = kPc2I + kPc2J + kPc2K - 2;
 
+// T: the precision of the couplings, the modified diagonal and the PCG
+// vectors (double, or float inside double-precision refinement); w and the
+// partial sums are double.
+template <typename T>
 struct Pc2Args {
-    const double *cr, *ct, *cp;  // scaled couplings to the +r, +theta, +phi neighbours
+    const T *cr, *ct, *cp;       // scaled couplings to the +r, +theta, +phi neighbours
     const double *w;
-    double *d;                   // modified diagonal (written by the factor kernel)
-    double *r, *x, *z;           // solve: r -= alpha q, x += alpha p, z = M^-1 r
-    const double *q, *p;
+    T *d;                        // modified diagonal (written by the factor kernel)
+    T *r, *x, *z;                // solve: r -= alpha q, x += alpha p, z = M^-1 r
+    const T *q, *p;
     double *partials;            // [blocks][2]: (r, z), ||W r||^2
     const Ctl *ctl;
     Dims dm;
@@ -58,7 +62,8 @@ struct Pc2Col {
     int srcLo_i, srcLo_j, srcUp_i, srcUp_j;
 };
 
-__device__ inline Pc2Col pc2_column(const Pc2Args &a) {
+template <typename A>
+__device__ inline Pc2Col pc2_column(const A &a) {
     Pc2Col c;
     const int blk = blockIdx.x;
     const int bk = blk % a.nbk, bj = (blk / a.nbk) % a.nbj, bi = blk / (a.nbk * a.nbj);
@@ -77,8 +82,10 @@ __device__ inline Pc2Col pc2_column(const Pc2Args &a) {
     return c;
 }
 
-// d_c for every cell of the block.
-__global__ __launch_bounds__(kWave) void k_pc2_factor(Pc2Args a) {
+// d_c for every cell of the block, from the double-precision couplings (a
+// single-precision factor is the double one rounded: dout = float).
+template <typename TOUT>
+__global__ __launch_bounds__(kWave) void k_pc2_factor(Pc2Args<double> a, TOUT *dout) {
     const Pc2Col col = pc2_column(a);
     const Dims &dm = a.dm;
     double prev = 0.0;  // this lane's value on the previous level
@@ -104,7 +111,7 @@ __global__ __launch_bounds__(kWave) void k_pc2_factor(Pc2Args a) {
                 s -= e * e / prev;
             }
             val = s;
-            a.d[c] = val;
+            dout[c] = (TOUT)val;
         }
         prev = val;
     }
@@ -129,13 +136,21 @@ __device__ inline double dpp_or(double v, double identity) {
 }
 
 template <int CTRL, int ROWS>
-__device__ inline void affine_step(double &C, double &B) {
-    const double Cs = dpp_or<CTRL, ROWS>(C, 1.0), Bs = dpp_or<CTRL, ROWS>(B, 0.0);
+__device__ inline float dpp_or(float v, float identity) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(__builtin_bit_cast(int, identity),
+                                                                 __builtin_bit_cast(int, v), CTRL,
+                                                                 ROWS, 0xf, false));
+}
+
+template <int CTRL, int ROWS, typename T>
+__device__ inline void affine_step(T &C, T &B) {
+    const T Cs = dpp_or<CTRL, ROWS>(C, T(1)), Bs = dpp_or<CTRL, ROWS>(B, T(0));
     B = C * Bs + B;
     C = C * Cs;
 }
 
-__device__ inline double affine_scan(double C, double B) {
+template <typename T>
+__device__ inline T affine_scan(T C, T B) {
     affine_step<0x111, 0xf>(C, B);  // row_shr:1
     affine_step<0x112, 0xf>(C, B);  // row_shr:2
     affine_step<0x114, 0xf>(C, B);  // row_shr:4
@@ -149,14 +164,19 @@ __device__ inline double affine_scan(double C, double B) {
 // per-block partials (r, z) and ||W r||^2.  Each sweep loads the next row's
 // inputs before it scans the current row, so a wave keeps one row of loads
 // in flight behind its scans.
+template <typename T>
 struct Pc2Fwd {
-    double r, q, x, p, w, d, cr, ct, cp;
+    T r, q, x, p;
+    double w;
+    T d, cr, ct, cp;
 };
+template <typename T>
 struct Pc2Bwd {
-    double cr, ct, d, y, cp, r;
+    T cr, ct, d, y, cp, r;
 };
 
-__global__ __launch_bounds__(kWave) void k_pc2_solve(Pc2Args a) {
+template <typename T>
+__global__ __launch_bounds__(kWave) void k_pc2_solve(Pc2Args<T> a) {
     if (a.ctl->flag != FLAG_RUN) return;
     const Dims &dm = a.dm;
     const int blk = blockIdx.x;
@@ -168,18 +188,19 @@ __global__ __launch_bounds__(kWave) void k_pc2_solve(Pc2Args a) {
     const int k = k0 + (act ? lane : 0);
     const int ni = min(kPc2I, dm.nr - bi * kPc2I), nj = min(kPc2J, dm.nt - bj * kPc2J);
     const bool upd = a.update != 0;
-    const double alpha = upd ? a.ctl->alpha : 0.0;
+    const T alpha = upd ? (T)a.ctl->alpha : T(0);
     // distinct arrays: lets the compiler issue later rows' loads ahead of
     // earlier rows' stores
-    const double *__restrict__ cr = a.cr, *__restrict__ ct = a.ct, *__restrict__ cp = a.cp;
-    const double *__restrict__ w = a.w, *__restrict__ dd = a.d, *__restrict__ q = a.q;
-    const double *__restrict__ pp = a.p;
-    double *__restrict__ r = a.r, *__restrict__ x = a.x, *__restrict__ z = a.z;
+    const T *__restrict__ cr = a.cr, *__restrict__ ct = a.ct, *__restrict__ cp = a.cp;
+    const double *__restrict__ w = a.w;
+    const T *__restrict__ dd = a.d, *__restrict__ q = a.q;
+    const T *__restrict__ pp = a.p;
+    T *__restrict__ r = a.r, *__restrict__ x = a.x, *__restrict__ z = a.z;
     auto cell = [&](int ii, int jj, int kk) -> int64_t {
         return ((int64_t)(bi * kPc2I + ii) * dm.nt + (bj * kPc2J + jj)) * dm.np + kk;
     };
     auto load_f = [&](int ii, int jj) {
-        Pc2Fwd v{0, 0, 0, 0, 0, 1, 0, 0, 0};
+        Pc2Fwd<T> v{0, 0, 0, 0, 0.0, 1, 0, 0, 0};
         if (act && ii < ni && jj < nj) {
             const int64_t c = cell(ii, jj, k);
             v.r = r[c];
@@ -197,31 +218,31 @@ __global__ __launch_bounds__(kWave) void k_pc2_solve(Pc2Args a) {
         return v;
     };
     double rw = 0.0, rz = 0.0;
-    double yp[kPc2J];  // previous r plane of the block, one value per theta row
+    T yp[kPc2J];  // previous r plane of the block, one value per theta row
     // forward sweep: y into z
 #pragma unroll
-    for (int jj = 0; jj < kPc2J; ++jj) yp[jj] = 0.0;
-    Pc2Fwd cur = load_f(0, 0);
+    for (int jj = 0; jj < kPc2J; ++jj) yp[jj] = T(0);
+    Pc2Fwd<T> cur = load_f(0, 0);
     for (int ii = 0; ii < ni; ++ii) {
-        double yrow = 0.0;  // previous theta row
+        T yrow = T(0);  // previous theta row
 #pragma unroll
         for (int jj = 0; jj < kPc2J; ++jj) {
             if (jj < nj) {
-                const Pc2Fwd nxt = (jj + 1 < nj) ? load_f(ii, jj + 1) : load_f(ii + 1, 0);
-                double Bc = 0.0, Cc = 0.0;
-                double rc = cur.r;
+                const Pc2Fwd<T> nxt = (jj + 1 < nj) ? load_f(ii, jj + 1) : load_f(ii + 1, 0);
+                T Bc = T(0), Cc = T(0);
+                T rc = cur.r;
                 if (act) {
                     if (upd) rc -= alpha * cur.q;
-                    const double t = cur.w * rc;
+                    const double t = cur.w * (double)rc;
                     rw += t * t;
-                    double sc = rc;
+                    T sc = rc;
                     if (ii > 0) sc += cur.cr * yp[jj];
                     if (jj > 0) sc += cur.ct * yrow;
-                    const double dinv = 1.0 / cur.d;
+                    const T dinv = T(1) / cur.d;
                     Bc = sc * dinv;
                     Cc = cur.cp * dinv;
                 }
-                const double y = affine_scan(Cc, Bc);
+                const T y = affine_scan(Cc, Bc);
                 if (act) {
                     const int64_t c = cell(ii, jj, k);
                     if (upd) {
@@ -240,7 +261,7 @@ __global__ __launch_bounds__(kWave) void k_pc2_solve(Pc2Args a) {
     // recurrence z_k = c_k z_{k+1} + b_k runs up the lanes again
     const int kb = k0 + (act ? kn - 1 - lane : 0);
     auto load_b = [&](int ii, int jj) {
-        Pc2Bwd v{0, 0, 1, 0, 0, 0};
+        Pc2Bwd<T> v{0, 0, 1, 0, 0, 0};
         if (act && ii >= 0 && jj >= 0) {
             const int64_t c = cell(ii, jj, kb);
             if (ii < ni - 1) v.cr = cr[c];
@@ -253,27 +274,27 @@ __global__ __launch_bounds__(kWave) void k_pc2_solve(Pc2Args a) {
         return v;
     };
 #pragma unroll
-    for (int jj = 0; jj < kPc2J; ++jj) yp[jj] = 0.0;
-    Pc2Bwd bcur = load_b(ni - 1, nj - 1);
+    for (int jj = 0; jj < kPc2J; ++jj) yp[jj] = T(0);
+    Pc2Bwd<T> bcur = load_b(ni - 1, nj - 1);
     for (int ii = ni - 1; ii >= 0; --ii) {
-        double zrow = 0.0;  // next theta row
+        T zrow = T(0);  // next theta row
 #pragma unroll
         for (int jj = kPc2J - 1; jj >= 0; --jj) {
             if (jj < nj) {
-                const Pc2Bwd nxt = (jj > 0) ? load_b(ii, jj - 1) : load_b(ii - 1, nj - 1);
-                double Bc = 0.0, Cc = 0.0;
+                const Pc2Bwd<T> nxt = (jj > 0) ? load_b(ii, jj - 1) : load_b(ii - 1, nj - 1);
+                T Bc = T(0), Cc = T(0);
                 if (act) {
-                    double sc = 0.0;
+                    T sc = T(0);
                     if (ii < ni - 1) sc += bcur.cr * yp[jj];
                     if (jj < nj - 1) sc += bcur.ct * zrow;
-                    const double dinv = 1.0 / bcur.d;
+                    const T dinv = T(1) / bcur.d;
                     Bc = bcur.y + sc * dinv;
                     Cc = bcur.cp * dinv;
                 }
-                const double zc = affine_scan(Cc, Bc);
+                const T zc = affine_scan(Cc, Bc);
                 if (act) {
                     z[cell(ii, jj, kb)] = zc;
-                    rz += bcur.r * zc;
+                    rz += (double)bcur.r * (double)zc;
                 }
                 yp[jj] = zc;
                 zrow = zc;

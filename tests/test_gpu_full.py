@@ -134,6 +134,26 @@ def test_c1_pc2_solve_full(c1, c1_oracle):
     assert r <= 1e-10 and i2["iters"] < i1["iters"]
 
 
+def test_c1_pc2_refined_solve_full(c1, c1_oracle):
+    """Single-precision PC2-PCG inside double-precision refinement at the
+    full size: the oracle's residual of the GPU solution on all 52.4M cells
+    and the difference from the double-precision PC2 solution."""
+    grid = S.Grid.from_problem(c1)
+    rhs = to_dev(c1.rhs)
+    op = S.Operator(grid, to_dev(c1.nu), c1.dt, precision="fp32_refined")
+    xr, ir = op.solve(rhs, S.make_opts(rtol=1e-10, precision="fp32_refined", precond="pc2",
+                                       sample_timing=1), allow_notconv=False)
+    x2, i2 = op.solve(rhs, S.make_opts(rtol=1e-10, precond="pc2"), allow_notconv=False)
+    say(f"c1 refined PC2: {ir['iters']} inner iterations, {ir['outer_iters']} outer, "
+        f"{ir['seconds']:.3f} s; FP64 PC2 {i2['iters']} iterations, {i2['seconds']:.3f} s")
+    d = float(torch.linalg.vector_norm(xr - x2) / torch.linalg.vector_norm(x2))
+    xr = to_host(xr)
+    del op, x2
+    r = c1_oracle.rel_residual(c1_oracle.rhs_to_b(c1.rhs), xr)
+    say(f"c1 refined PC2 oracle residual {r:.3e}; relative difference from FP64 PC2 {d:.2e}")
+    assert r <= 1e-10 and d <= 1e-6
+
+
 @pytest.fixture(scope="module")
 def c3():
     p = W.make_problem("c3")

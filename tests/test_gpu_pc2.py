@@ -83,12 +83,55 @@ def test_pc2_adjoint_and_warm_start():
     assert i2["iters"] <= 1
 
 
+@pytest.mark.parametrize("shape", SHAPES)
+@pytest.mark.parametrize("bc", [(0, 0), (1, 0)])
+def test_pc2_refined_matches_oracle(shape, bc):
+    """Single-precision PC2-PCG inside double-precision refinement: the
+    oracle's residual of the result meets 1e-10 and the result is the
+    oracle's 1e-13 PC2 solution to its conditioning."""
+    p = problem(shape, bc)
+    _, op = gpu_operator(p, "fp32_refined")
+    ora = oracle_operator(p)
+    b = ora.rhs_to_b(p.rhs)
+    x, info = op.solve(to_dev(p.rhs), S.make_opts(rtol=1e-10, precision="fp32_refined",
+                                                  precond="pc2"), allow_notconv=False)
+    x = to_host(x)
+    res = ora.rel_residual(b, x)
+    say(f"{shape} bc={bc}: refined PC2 {info['iters']} inner, {info['outer_iters']} outer, "
+        f"residual {res:.2e}")
+    assert res <= 1e-10
+    assert abs(info["rel_resid_true"] - res) <= 1e-3 * res + 1e-13
+    assert info["outer_iters"] >= 1
+    xt = ora.pcg_pc2(b, BLOCKS, tol=1e-13)[0]
+    assert rel(x, xt) <= 1e-6
+
+
+def test_pc2_refined_fewer_iterations_and_adjoint():
+    p = problem("c0", (0, 0))
+    _, op = gpu_operator(p, "fp32_refined")
+    ora = oracle_operator(p)
+    rhs = to_dev(p.rhs)
+    o1 = S.make_opts(rtol=1e-10, precision="fp32_refined")
+    o2 = S.make_opts(rtol=1e-10, precision="fp32_refined", precond="pc2")
+    x1, i1 = op.solve(rhs, o1, allow_notconv=False)
+    x2, i2 = op.solve(rhs, o2, allow_notconv=False)
+    say(f"c0 refined: PC1 {i1['iters']} inner iterations, PC2 {i2['iters']}")
+    assert i2["iters"] < i1["iters"]
+    gx = x2.clone()
+    lam, gnu, grhs, _ = op.adjoint(x2, gx, o2, allow_notconv=False)
+    lamh = to_host(lam)
+    assert ora.rel_residual(to_host(gx), lamh) <= 1e-10
+    gnu_o, grhs_o = ora.gradient(to_host(x2), lamh)
+    assert rel(to_host(gnu), gnu_o) <= 1e-12 and rel(to_host(grhs), grhs_o) <= 1e-14
+
+
 def test_pc2_error_paths():
     p = problem((9, 16, 32), (0, 0))
     _, op = gpu_operator(p, "fp32_refined")
     rhs = to_dev(p.rhs)
-    with pytest.raises(abi.MasError, match="PC2"):
-        op.solve(rhs, S.make_opts(precision="fp32_refined", precond="pc2"))
+    o = S.make_opts(precision="fp32_refined", precond="pc2", max_iters=3, max_outer=20)
+    x, info = op.solve(rhs, o)
+    assert info["status"] == abi.MAS_ENOTCONV and info["iters"] == 3
     o = S.make_opts()
     o.precond = 7
     with pytest.raises(abi.MasError, match="preconditioner"):

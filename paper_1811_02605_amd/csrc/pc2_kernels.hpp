@@ -17,11 +17,10 @@
 // The direction and SpMV step of a PC2 iteration (p = z + beta p, q = A^ p,
 // (p, q)) is the PCG iteration kernel run without r, q and x inputs.
 //
-// Factor: one wave per block, lane (i', j') owns the column of kPc2K cells at
-// r offset i' and theta offset j', and the wave sweeps the hyperplanes
-// i' + j' + k' = level: a cell's lower neighbours in r and theta were
-// computed by lanes l - kPc2J and l - 1 on the previous level, its lower phi
-// neighbour by its own lane there.
+// Factor: one wave per block, lane k' owns phi offset k', the wave walks the
+// block's (r, theta) rows in order and solves each row's phi recurrence
+// d_k = s_k - c^2 / d_{k-1} by a prefix scan of 2 x 2 matrices (the maps
+// d -> (s d - c^2) / d compose as matrix products).
 // Solve: one wave per block, lane k' owns phi offset k' (coalesced rows), and
 // the wave walks the block's (r, theta) rows in order.  The r and theta
 // terms come from the rows already done (kept in registers); along phi the
@@ -35,9 +34,7 @@
 namespace mas {
 
 constexpr int kPc2I = 8, kPc2J = 8, kPc2K = 64;
-static_assert(kPc2I * kPc2J == kWave, "one lane per (r, theta) column of a block");
 static_assert(kPc2K == kWave, "one lane per phi offset of a block");
-constexpr int kPc2Levels = kPc2I + kPc2J + kPc2K - 2;
 
 // T: the precision of the couplings, the modified diagonal and the PCG
 // vectors (double, or float inside double-precision refinement); w and the
@@ -55,67 +52,6 @@ struct Pc2Args {
     int nbi, nbj, nbk;           // blocks per direction
     int update;                  // solve: apply the alpha updates first
 };
-
-struct Pc2Col {
-    int ii, jj, i, j, k0, kn;
-    bool ok;
-    int srcLo_i, srcLo_j, srcUp_i, srcUp_j;
-};
-
-template <typename A>
-__device__ inline Pc2Col pc2_column(const A &a) {
-    Pc2Col c;
-    const int blk = blockIdx.x;
-    const int bk = blk % a.nbk, bj = (blk / a.nbk) % a.nbj, bi = blk / (a.nbk * a.nbj);
-    const int lane = threadIdx.x;
-    c.ii = lane / kPc2J;
-    c.jj = lane % kPc2J;
-    c.i = bi * kPc2I + c.ii;
-    c.j = bj * kPc2J + c.jj;
-    c.k0 = bk * kPc2K;
-    c.kn = min(kPc2K, a.dm.np - c.k0);
-    c.ok = c.i < a.dm.nr && c.j < a.dm.nt;
-    c.srcLo_i = (c.ii > 0) ? lane - kPc2J : lane;
-    c.srcLo_j = (c.jj > 0) ? lane - 1 : lane;
-    c.srcUp_i = (c.ii < kPc2I - 1) ? lane + kPc2J : lane;
-    c.srcUp_j = (c.jj < kPc2J - 1) ? lane + 1 : lane;
-    return c;
-}
-
-// d_c for every cell of the block, from the double-precision couplings (a
-// single-precision factor is the double one rounded: dout = float).
-template <typename TOUT>
-__global__ __launch_bounds__(kWave) void k_pc2_factor(Pc2Args<double> a, TOUT *dout) {
-    const Pc2Col col = pc2_column(a);
-    const Dims &dm = a.dm;
-    double prev = 0.0;  // this lane's value on the previous level
-    for (int lev = 0; lev < kPc2Levels; ++lev) {
-        const double vi = __shfl(prev, col.srcLo_i, kWave);
-        const double vj = __shfl(prev, col.srcLo_j, kWave);
-        const int kk = lev - col.ii - col.jj;
-        const bool act = col.ok && kk >= 0 && kk < col.kn;
-        double val = 0.0;
-        if (act) {
-            const int64_t c = ((int64_t)col.i * dm.nt + col.j) * dm.np + col.k0 + kk;
-            double s = 1.0;
-            if (col.ii > 0) {
-                const double e = a.cr[c - dm.plane];
-                s -= e * e / vi;
-            }
-            if (col.jj > 0) {
-                const double e = a.ct[c - dm.np];
-                s -= e * e / vj;
-            }
-            if (kk > 0) {
-                const double e = a.cp[c - 1];
-                s -= e * e / prev;
-            }
-            val = s;
-            dout[c] = (TOUT)val;
-        }
-        prev = val;
-    }
-}
 
 // Inclusive scan of the affine maps y -> C y + B over the 64 lanes in lane
 // order: each lane ends with the composition of its own map after those of
@@ -160,10 +96,111 @@ __device__ inline T affine_scan(T C, T B) {
     return B;
 }
 
+// Linear-fractional maps d -> (m00 d + m01) / (m10 d + m11) as 2 x 2 matrices
+// (projective: a common factor does not change the map).
+struct Mob {
+    double m00, m01, m10, m11;
+};
+
+// Inclusive scan of such maps over the 64 lanes in lane order (the same DPP
+// moves as affine_scan; a lane that receives nothing composes with the
+// identity), each product rescaled by a power of two (exact) so that long
+// chains neither overflow nor underflow.
+template <int CTRL, int ROWS>
+__device__ inline void mobius_step(Mob &P) {
+    const double q00 = dpp_or<CTRL, ROWS>(P.m00, 1.0), q01 = dpp_or<CTRL, ROWS>(P.m01, 0.0);
+    const double q10 = dpp_or<CTRL, ROWS>(P.m10, 0.0), q11 = dpp_or<CTRL, ROWS>(P.m11, 1.0);
+    const double r00 = P.m00 * q00 + P.m01 * q10, r01 = P.m00 * q01 + P.m01 * q11;
+    const double r10 = P.m10 * q00 + P.m11 * q10, r11 = P.m10 * q01 + P.m11 * q11;
+    const double m = fmax(fmax(fabs(r00), fabs(r01)), fmax(fabs(r10), fabs(r11)));
+    const int ex = (m > 0.0) ? ilogb(m) : 0;
+    P = Mob{ldexp(r00, -ex), ldexp(r01, -ex), ldexp(r10, -ex), ldexp(r11, -ex)};
+}
+
+__device__ inline Mob mobius_scan(Mob P) {
+    mobius_step<0x111, 0xf>(P);  // row_shr:1
+    mobius_step<0x112, 0xf>(P);  // row_shr:2
+    mobius_step<0x114, 0xf>(P);  // row_shr:4
+    mobius_step<0x118, 0xf>(P);  // row_shr:8
+    mobius_step<0x142, 0xa>(P);  // row_bcast:15 into rows 1 and 3
+    mobius_step<0x143, 0xc>(P);  // row_bcast:31 into rows 2 and 3
+    return P;
+}
+
+// d_c for every cell of the block, from the double-precision couplings (a
+// single-precision factor is the double one rounded: TOUT = float).  Lanes
+// run along phi (coalesced rows) and the wave walks the block's (r, theta)
+// rows in order, as the solve does; with the r and theta terms of a row
+// known from the rows done, the phi recurrence
+//     d_k = s_k - cp_{k-1,k}^2 / d_{k-1},   s_k = 1 - (r and theta terms),
+// is the composition of the maps d -> (s_k d - cp^2) / d, solved by a prefix
+// scan of their matrices [s_k, -cp^2; 1, 0] (the first lane of a block has
+// no phi term: [s_0, 0; 1, 0], which gives d_0 = s_0 from any start).  Each
+// row's couplings are loaded before the previous row is scanned.
+struct Pc2Fac {
+    double cr, ct, cp;
+};
+
+template <typename TOUT>
+__global__ __launch_bounds__(kWave) void k_pc2_factor(Pc2Args<double> a, TOUT *dout) {
+    const Dims &dm = a.dm;
+    const int blk = blockIdx.x;
+    const int bk = blk % a.nbk, bj = (blk / a.nbk) % a.nbj, bi = blk / (a.nbk * a.nbj);
+    const int lane = threadIdx.x;
+    const int k0 = bk * kPc2K;
+    const int kn = min(kPc2K, dm.np - k0);
+    const bool act = lane < kn;
+    const int k = k0 + (act ? lane : 0);
+    const int ni = min(kPc2I, dm.nr - bi * kPc2I), nj = min(kPc2J, dm.nt - bj * kPc2J);
+    auto cell = [&](int ii, int jj) -> int64_t {
+        return ((int64_t)(bi * kPc2I + ii) * dm.nt + (bj * kPc2J + jj)) * dm.np + k;
+    };
+    auto load = [&](int ii, int jj) {
+        Pc2Fac v{0.0, 0.0, 0.0};
+        if (act && ii < ni && jj < nj) {
+            const int64_t c = cell(ii, jj);
+            if (ii > 0) v.cr = a.cr[c - dm.plane];
+            if (jj > 0) v.ct = a.ct[c - dm.np];
+            if (lane > 0) v.cp = a.cp[c - 1];
+        }
+        return v;
+    };
+    double dp[kPc2J];  // d of the previous r plane of the block, per theta row
+#pragma unroll
+    for (int jj = 0; jj < kPc2J; ++jj) dp[jj] = 1.0;
+    Pc2Fac cur = load(0, 0);
+    for (int ii = 0; ii < ni; ++ii) {
+        double drow = 1.0;  // d of the previous theta row
+#pragma unroll
+        for (int jj = 0; jj < kPc2J; ++jj) {
+            if (jj < nj) {
+                const Pc2Fac nxt = (jj + 1 < nj) ? load(ii, jj + 1) : load(ii + 1, 0);
+                Mob P{1.0, 0.0, 0.0, 1.0};
+                if (act) {
+                    double sk = 1.0;
+                    if (ii > 0) sk -= cur.cr * cur.cr / dp[jj];
+                    if (jj > 0) sk -= cur.ct * cur.ct / drow;
+                    P = Mob{sk, -(cur.cp * cur.cp), 1.0, 0.0};
+                }
+                P = mobius_scan(P);
+                const double dv = (P.m00 + P.m01) / (P.m10 + P.m11);  // the map of d = 1
+                if (act) dout[cell(ii, jj)] = (TOUT)dv;
+                dp[jj] = dv;
+                drow = dv;
+                cur = nxt;
+            }
+        }
+    }
+}
+
 // z = M^-1 r, first applying r -= alpha q and x += alpha p when a.update;
 // per-block partials (r, z) and ||W r||^2.  Each sweep loads the next row's
 // inputs before it scans the current row, so a wave keeps one row of loads
 // in flight behind its scans.
+// With L the strictly lower couplings and D = diag(d), M = (D - L) D^-1 (D - L^T),
+// the forward sweep gives y = (D - L)^-1 r and z = (D - L^T)^-1 D y, so
+// (r, z) = r^T (D - L^T)^-1 D (D - L)^-1 r = y^T D y: the forward sweep
+// accumulates it and the backward sweep need not read r again.
 template <typename T>
 struct Pc2Fwd {
     T r, q, x, p;
@@ -172,7 +209,7 @@ struct Pc2Fwd {
 };
 template <typename T>
 struct Pc2Bwd {
-    T cr, ct, d, y, cp, r;
+    T cr, ct, d, y, cp;
 };
 
 template <typename T>
@@ -244,6 +281,8 @@ __global__ __launch_bounds__(kWave) void k_pc2_solve(Pc2Args<T> a) {
                 }
                 const T y = affine_scan(Cc, Bc);
                 if (act) {
+                    // (r, M^-1 r) = y^T D y (see below)
+                    rz += (double)cur.d * (double)y * (double)y;
                     const int64_t c = cell(ii, jj, k);
                     if (upd) {
                         r[c] = rc;
@@ -261,7 +300,7 @@ __global__ __launch_bounds__(kWave) void k_pc2_solve(Pc2Args<T> a) {
     // recurrence z_k = c_k z_{k+1} + b_k runs up the lanes again
     const int kb = k0 + (act ? kn - 1 - lane : 0);
     auto load_b = [&](int ii, int jj) {
-        Pc2Bwd<T> v{0, 0, 1, 0, 0, 0};
+        Pc2Bwd<T> v{0, 0, 1, 0, 0};
         if (act && ii >= 0 && jj >= 0) {
             const int64_t c = cell(ii, jj, kb);
             if (ii < ni - 1) v.cr = cr[c];
@@ -269,7 +308,6 @@ __global__ __launch_bounds__(kWave) void k_pc2_solve(Pc2Args<T> a) {
             v.d = dd[c];
             v.y = z[c];
             if (lane > 0) v.cp = cp[c];
-            v.r = r[c];
         }
         return v;
     };
@@ -292,10 +330,7 @@ __global__ __launch_bounds__(kWave) void k_pc2_solve(Pc2Args<T> a) {
                     Cc = bcur.cp * dinv;
                 }
                 const T zc = affine_scan(Cc, Bc);
-                if (act) {
-                    z[cell(ii, jj, kb)] = zc;
-                    rz += (double)bcur.r * (double)zc;
-                }
+                if (act) z[cell(ii, jj, kb)] = zc;
                 yp[jj] = zc;
                 zrow = zc;
                 bcur = nxt;

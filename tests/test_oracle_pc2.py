@@ -81,6 +81,23 @@ def test_apply_equals_textbook_ilu0(ora, shape, blocks, bc):
     np.testing.assert_allclose(op.pc2_factor(blocks).reshape(-1), np.diag(U), rtol=1e-13)
 
 
+@pytest.mark.parametrize("shape,blocks", [((4, 4, 8), (2, 2, 4)), ((3, 5, 7), (2, 3, 3)),
+                                          ((5, 3, 6), (1, 1, 6))])
+def test_energy_of_the_forward_sweep(ora, shape, blocks):
+    """A symmetric matrix's ILU(0) is M = L D L^T (L unit lower, D = diag U),
+    so (r, M^-1 r) = u^T D^-1 u with u = L^-1 r: the dot product of a PC2
+    iteration follows from the forward sweep alone (the GPU solve kernel
+    forms it so)."""
+    p, op = _op(ora, shape, (0, 1))
+    L, U = _ilu0(_block_matrix(op, blocks))
+    d = np.diag(U)
+    np.testing.assert_allclose(U, d[:, None] * L.T, rtol=1e-12, atol=1e-15)  # U = D L^T
+    r = np.random.default_rng(11).standard_normal(op.shape).reshape(-1)
+    u = np.linalg.solve(L, r)
+    rz = float(r @ op.pc2_apply(r, blocks).reshape(-1))
+    assert abs(rz - float(np.sum(u * u / d))) <= 1e-12 * abs(rz)
+
+
 def test_preconditioner_is_spd(ora):
     p, op = _op(ora, (4, 5, 6), seed=2)
     blocks = (2, 3, 4)

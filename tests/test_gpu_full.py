@@ -225,14 +225,22 @@ def test_c4_stress_refined_forward_and_adjoint():
     gx = (x - xt).contiguous()
     lam, gnu, grhs, ainfo = op.adjoint(x, gx, o, allow_notconv=False)
     say(f"c4 refined adjoint: {ainfo['iters']} inner, {ainfo['seconds']:.3f} s")
+    # the same forward solve with PC2 inside the refinement
+    o2 = S.make_opts(rtol=1e-10, precision="fp32_refined", precond="pc2")
+    x2, info2 = op.solve(rhs, o2, allow_notconv=False)
+    say(f"c4 refined PC2 forward: {info2['iters']} inner, {info2['outer_iters']} outer, "
+        f"{info2['seconds']:.3f} s, residual {info2['rel_resid_true']:.2e}")
+    x2 = to_host(x2)
     del op
     x, lam, gnu, grhs, gx = (to_host(t) for t in (x, lam, gnu, grhs, gx))
     torch.cuda.empty_cache()
     ora = oracle_operator(p)
     b = ora.rhs_to_b(p.rhs)
     rf, ra = ora.rel_residual(b, x), ora.rel_residual(gx, lam)
-    say(f"c4 oracle residuals: forward {rf:.3e}, adjoint {ra:.3e}")
-    assert rf <= 1e-10 and ra <= 1e-10
+    r2 = ora.rel_residual(b, x2)
+    say(f"c4 oracle residuals: forward {rf:.3e}, adjoint {ra:.3e}, PC2 forward {r2:.3e}")
+    assert rf <= 1e-10 and ra <= 1e-10 and r2 <= 1e-10
+    del x2
     # the gradient kernel against the oracle's formula at the same x, lambda
     gnu_o, grhs_o = ora.gradient(x, lam)
     e_nu, e_rhs = rel(gnu, gnu_o), rel(grhs, grhs_o)

@@ -212,8 +212,10 @@ struct Pc2Bwd {
     T cr, ct, d, y, cp;
 };
 
-template <typename T>
+// PF: rows of loads in flight ahead of the row being scanned.
+template <typename T, int PF>
 __global__ __launch_bounds__(kWave) void k_pc2_solve(Pc2Args<T> a) {
+    static_assert(PF == 1 || PF == 2, "prefetch depth");
     if (a.ctl->flag != FLAG_RUN) return;
     const Dims &dm = a.dm;
     const int blk = blockIdx.x;
@@ -259,13 +261,17 @@ __global__ __launch_bounds__(kWave) void k_pc2_solve(Pc2Args<T> a) {
     // forward sweep: y into z
 #pragma unroll
     for (int jj = 0; jj < kPc2J; ++jj) yp[jj] = T(0);
+    // rows in order t = ii nj + jj; row t + PF is loaded before row t is scanned
+    auto load_ft = [&](int t) { return load_f(t / nj, t % nj); };
     Pc2Fwd<T> cur = load_f(0, 0);
+    Pc2Fwd<T> ahead{};
+    if constexpr (PF == 2) ahead = load_ft(1);
     for (int ii = 0; ii < ni; ++ii) {
         T yrow = T(0);  // previous theta row
 #pragma unroll
         for (int jj = 0; jj < kPc2J; ++jj) {
             if (jj < nj) {
-                const Pc2Fwd<T> nxt = (jj + 1 < nj) ? load_f(ii, jj + 1) : load_f(ii + 1, 0);
+                const Pc2Fwd<T> nxt = load_ft(ii * nj + jj + PF);
                 T Bc = T(0), Cc = T(0);
                 T rc = cur.r;
                 if (act) {
@@ -292,7 +298,12 @@ __global__ __launch_bounds__(kWave) void k_pc2_solve(Pc2Args<T> a) {
                 }
                 yp[jj] = y;
                 yrow = y;
-                cur = nxt;
+                if constexpr (PF == 2) {
+                    cur = ahead;
+                    ahead = nxt;
+                } else {
+                    cur = nxt;
+                }
             }
         }
     }
@@ -313,13 +324,18 @@ __global__ __launch_bounds__(kWave) void k_pc2_solve(Pc2Args<T> a) {
     };
 #pragma unroll
     for (int jj = 0; jj < kPc2J; ++jj) yp[jj] = T(0);
+    // rows in reverse order; row t - PF is loaded before row t is scanned
+    // (t < 0 divides to ii = 0, jj < 0 or to ii < 0: no load)
+    auto load_bt = [&](int t) { return load_b(t / nj, t % nj); };
     Pc2Bwd<T> bcur = load_b(ni - 1, nj - 1);
+    Pc2Bwd<T> bahead{};
+    if constexpr (PF == 2) bahead = load_bt(ni * nj - 2);
     for (int ii = ni - 1; ii >= 0; --ii) {
         T zrow = T(0);  // next theta row
 #pragma unroll
         for (int jj = kPc2J - 1; jj >= 0; --jj) {
             if (jj < nj) {
-                const Pc2Bwd<T> nxt = (jj > 0) ? load_b(ii, jj - 1) : load_b(ii - 1, nj - 1);
+                const Pc2Bwd<T> nxt = load_bt(ii * nj + jj - PF);
                 T Bc = T(0), Cc = T(0);
                 if (act) {
                     T sc = T(0);
@@ -333,7 +349,12 @@ __global__ __launch_bounds__(kWave) void k_pc2_solve(Pc2Args<T> a) {
                 if (act) z[cell(ii, jj, kb)] = zc;
                 yp[jj] = zc;
                 zrow = zc;
-                bcur = nxt;
+                if constexpr (PF == 2) {
+                    bcur = bahead;
+                    bahead = nxt;
+                } else {
+                    bcur = nxt;
+                }
             }
         }
     }

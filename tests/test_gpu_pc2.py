@@ -125,6 +125,24 @@ def test_pc2_refined_fewer_iterations_and_adjoint():
     assert rel(to_host(gnu), gnu_o) <= 1e-12 and rel(to_host(grhs), grhs_o) <= 1e-14
 
 
+def test_pc2_refined_autograd():
+    """The differentiable solve with PC2 inside refinement: gradients of
+    L = 1/2 ||x||^2 against the oracle's formula at its own solutions."""
+    import torch
+    p = problem((6, 8, 16), (0, 0))
+    grid = S.Grid.from_problem(p)
+    nu = to_dev(p.nu).requires_grad_(True)
+    rhs = to_dev(p.rhs).requires_grad_(True)
+    x = S.solve(nu, rhs, grid, p.dt, rtol=1e-12, precision="fp32_refined", precond="pc2")
+    (0.5 * (x ** 2).sum()).backward()
+    ora = oracle_operator(p)
+    xo = ora.solve_rhs(p.rhs, tol=1e-13)
+    lo = ora.pcg(xo, tol=1e-13)[0]
+    gnu_o, grhs_o = ora.gradient(xo, lo)
+    assert rel(to_host(nu.grad), gnu_o) <= 1e-8
+    assert rel(to_host(rhs.grad), grhs_o) <= 1e-8
+
+
 def test_pc2_error_paths():
     p = problem((9, 16, 32), (0, 0))
     _, op = gpu_operator(p, "fp32_refined")

@@ -292,8 +292,13 @@ __device__ inline void bst(__amdgpu_buffer_rsrc_t r, uint32_t off, const VecT<T,
 #ifndef MAS_ITER_ORDER
 #define MAS_ITER_ORDER 3
 #endif
-#ifndef MAS_ITER_SYNC
-#define MAS_ITER_SYNC 0
+// Block barrier after every plane step for kernels carrying at least this
+// many right-hand sides (keeps the block's waves on one plane, so the rows
+// they load for each other are requested together).  Measured at one fixed
+// placement at c1: three right-hand sides 2438 -> 2401 us, one right-hand
+// side 948 -> 954 us (so not used there).
+#ifndef MAS_ITER_SYNC_MIN_NR
+#define MAS_ITER_SYNC_MIN_NR 2
 #endif
 #ifndef MAS_ITER_NT
 #define MAS_ITER_NT 1
@@ -727,11 +732,7 @@ void k_pcg_iter(IterArgs<T> a) {
         // the recording lane's coupling of this plane (side 1 needs it)
         cpw1 = (lp == 0) ? cp.v[0] : cp.v[V - 1];
         m1 = m;
-#if MAS_ITER_SYNC
-        // keep the block's waves on the same plane so that the rows they
-        // load for each other are requested together (L1/L2 reuse)
-        __syncthreads();
-#endif
+        if constexpr (NR >= MAS_ITER_SYNC_MIN_NR) __syncthreads();
         cr1 = cr;
         if (CHECK) w1 = w;
         base1 = base;

@@ -290,14 +290,19 @@ int mas_sts_step(const mas_op *op, const double *u0, double *u1, const mas_sts_o
  * sides (1 <= nrhs <= 4).  Negative status on error. */
 int64_t mas_pcg_multi_workspace_bytes(const mas_op *op, int32_t nrhs);
 
-/* Solve A x_h = V .* rhs_h, h = 0..nrhs-1, by Jacobi PCG in double precision.
+/* Solve A x_h = V .* rhs_h, h = 0..nrhs-1, by PCG in double precision with
+ * o->precond: MAS_PC1 (Jacobi; one iteration kernel for all right-hand sides)
+ * or MAS_PC2 (block-Jacobi ILU(0), the factor formed once for all; each PC2
+ * iteration runs one direction/SpMV launch carrying all right-hand sides and
+ * a block solve per right-hand side, and gives each right-hand side the
+ * iterates of its single PC2 solve bit for bit).
  *   nrhs  1..4
  *   rhs   dev, nrhs*N, right-hand side h at rhs + h*N
  *   x     dev, nrhs*N, same layout: initial guesses on entry if o->use_x0,
  *         solutions on exit
  *   o     host, may be NULL; o->precision must be MAS_FP64; rtol, max_iters,
- *         check_every, max_restarts and sample_timing apply to every
- *         right-hand side
+ *         check_every, max_restarts, precond and sample_timing apply to
+ *         every right-hand side
  *   work  dev, >= mas_pcg_multi_workspace_bytes(op, nrhs), 256-byte aligned
  *   info  host array of nrhs entries, may be NULL; entry h describes
  *         right-hand side h (iter_kernel_us is the shared kernel's time)

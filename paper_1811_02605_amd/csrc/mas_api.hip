@@ -877,6 +877,137 @@ static int run_pcg_pc2(Ctx &cx, T *r, T *z, T *const p[2], T *q, T *d, T *x, int
     return MAS_OK;
 }
 
+// PC2-PCG for NR right-hand sides under one operator (FP64): per right-hand
+// side its control block, r, z, p (two), q and x; the modified diagonal d and
+// the couplings are shared.  The direction and SpMV step of all of them is
+// one launch of the several-right-hand-side iteration kernel (couplings read
+// once); the block solves and the finalize kernels run per right-hand side.
+// Right-hand sides with active[h] false get a stopped control block and move
+// no bytes.  All start at iteration iter0.
+template <int NR>
+static int run_pcg_pc2_multi(Ctx &cx, double *const r[NR], double *const z[NR],
+                             double *const p[NR][2], double *const q[NR], const double *d,
+                             double *const x[NR], const bool active[NR], const int max_iter[NR],
+                             const double tol2[NR], int iter0, PcgResult *res) {
+    const mas_op *op = cx.op;
+    const Shape &s = op->s;
+    hipStream_t st = cx.stream;
+    int nbi, nbj, nbk;
+    const int64_t nb = pc2_blocks(s, &nbi, &nbj, &nbk);
+    Pc2Args<double> a[NR];
+    for (int h = 0; h < NR; ++h) {
+        hipLaunchKernelGGL(k_ctl_init, dim3(1), dim3(64), 0, st, cx.ctl + h, 0, iter0,
+                           active[h] ? max_iter[h] : iter0, tol2[h], 0.0,
+                           (int)(active[h] ? FLAG_RUN : FLAG_CONV));
+        a[h] = Pc2Args<double>{op->c64[0], op->c64[1], op->c64[2], op->w, const_cast<double *>(d),
+                               r[h], x[h], z[h], q[h], nullptr, cx.partials, cx.ctl + h, s.dims(),
+                               nbi, nbj, nbk, 0};
+        // z = M^-1 r of the initial residual, (r, z), the stopping test
+        hipLaunchKernelGGL((k_pc2_solve<double, pc2_prefetch<double>()>), dim3((unsigned)nb), dim3(kWave),
+                           0, st, a[h]);
+        hipLaunchKernelGGL(k_pc2_fin_b, dim3(1), dim3(kRedThreads), 0, st, cx.partials, (int)nb,
+                           cx.ctl + h, 1);
+        a[h].update = 1;
+    }
+    LAUNCHCHK();
+    int32_t *pin = nullptr;
+    int e = pinned_buffer(&pin);
+    if (e != MAS_OK) return e;
+    hipEvent_t done[2] = {nullptr, nullptr};
+    HIPCHK(hipEventCreateWithFlags(&done[0], hipEventDisableTiming));
+    HIPCHK(hipEventCreateWithFlags(&done[1], hipEventDisableTiming));
+    struct EvGuard {
+        hipEvent_t *e;
+        ~EvGuard() {
+            (void)hipEventDestroy(e[0]);
+            (void)hipEventDestroy(e[1]);
+        }
+    } guard{done};
+    IterArgs<double> it{};
+    it.cr = op->c64[0];
+    it.ct = op->c64[1];
+    it.cp = op->c64[2];
+    it.w = op->w;
+    it.partials = cx.partials;
+    it.ctl = cx.ctl;
+    it.d = s.dims();
+    const int V = iter_vec<double>(s.np, NR);
+    it.tiles_i = s.tiles_i();
+    it.tiles_k = s.tiles_k(V);
+    it.tiles_j = s.tiles_j();
+    it.ti = s.ti();
+    it.nblk = (int)s.nblk_iter(V);
+    it.halo_bytes = 0;
+    constexpr int VW = vec_full<double>();
+    const dim3 igrid((unsigned)it.nblk), iblock(kWave * kTJ);
+    int kmax = iter0;
+    for (int h = 0; h < NR; ++h)
+        if (active[h]) kmax = std::max(kmax, max_iter[h]);
+    int k = iter0, nbt = 0;
+    bool stop = false;
+    while (!stop && k < kmax) {
+        const int kend = std::min(kmax, k + 16);
+        for (; k < kend; ++k) {
+            const bool sample = cx.timing && (k % 16 == 7) && cx.ev.size() < 128;
+            if (sample) {
+                hipEvent_t e0, e1;
+                HIPCHK(hipEventCreate(&e0));
+                HIPCHK(hipEventCreate(&e1));
+                cx.ev.push_back(e0);
+                cx.ev.push_back(e1);
+                cx.ev_iter.push_back(k + 1);
+                HIPCHK(hipEventRecord(e0, st));
+            }
+            for (int h = 0; h < NR; ++h) {
+                // the first direction is z itself (beta = 0): p_old points at z
+                it.r_in[h] = z[h];
+                it.p_in[h] = (k == iter0) ? z[h] : p[h][k & 1];
+                it.p_out[h] = p[h][(k + 1) & 1];
+                it.q_out[h] = q[h];
+            }
+            if (V == VW)
+                hipLaunchKernelGGL((k_pcg_iter<double, NR, kTJ, kRPW, VW, false, false>), igrid, iblock,
+                                   0, st, it);
+            else
+                hipLaunchKernelGGL((k_pcg_iter<double, NR, kTJ, kRPW, 1, false, false>), igrid, iblock,
+                                   0, st, it);
+            for (int h = 0; h < NR; ++h)
+                hipLaunchKernelGGL(k_pc2_fin_a, dim3(1), dim3(kRedThreads), 0, st,
+                                   cx.partials + h * kNV, it.nblk, (int)(NR * kNV), cx.ctl + h);
+            for (int h = 0; h < NR; ++h) {
+                a[h].p = p[h][(k + 1) & 1];
+                hipLaunchKernelGGL((k_pc2_solve<double, pc2_prefetch<double>()>), dim3((unsigned)nb),
+                                   dim3(kWave), 0, st, a[h]);
+                hipLaunchKernelGGL(k_pc2_fin_b, dim3(1), dim3(kRedThreads), 0, st, cx.partials,
+                                   (int)nb, cx.ctl + h, 0);
+            }
+            if (sample) HIPCHK(hipEventRecord(cx.ev.back(), st));
+        }
+        LAUNCHCHK();
+        int32_t *slot = pin + 8 * (nbt & 1);
+        for (int h = 0; h < NR; ++h)
+            HIPCHK(hipMemcpyAsync(slot + h, &cx.ctl[h].flag, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+        HIPCHK(hipEventRecord(done[nbt & 1], st));
+        if (nbt > 0) {
+            HIPCHK(hipEventSynchronize(done[(nbt - 1) & 1]));
+            const int32_t *prev = pin + 8 * ((nbt - 1) & 1);
+            bool anyrun = false;
+            for (int h = 0; h < NR; ++h) anyrun = anyrun || prev[h] == FLAG_RUN;
+            if (!anyrun) stop = true;
+        }
+        ++nbt;
+    }
+    HIPCHK(hipStreamSynchronize(st));
+    for (int h = 0; h < NR; ++h) {
+        Ctl hc;
+        e = read_ctl(cx, &hc, h);
+        if (e != MAS_OK) return e;
+        res->flag[h] = hc.flag;
+        res->last_iter[h] = (hc.flag == FLAG_RUN) ? max_iter[h] : hc.conv_iter;
+    }
+    return MAS_OK;
+}
+
 // Record buffers of right-hand side h from the workspace layout.
 template <typename T>
 static void set_halo(RhsSet<T> &v, char *base, const WorkLayout &L, int h = 0) {
@@ -1268,9 +1399,79 @@ static int solve_multi_core(const mas_op *op, const double *rhs, double *x, cons
             info[h].status = MAS_OK;
         }
     }
+    if (o.precond == MAS_PC2) {
+        // vectors of right-hand side h: r, z, p (two), q; the shared modified
+        // diagonal in right-hand side 0's sixth vector
+        double *r[NR], *z[NR], *p[NR][2], *q[NR], *xs[NR];
+        for (int h = 0; h < NR; ++h) {
+            r[h] = reinterpret_cast<double *>(base + L.vec[h][0]);
+            z[h] = reinterpret_cast<double *>(base + L.vec[h][1]);
+            p[h][0] = reinterpret_cast<double *>(base + L.vec[h][2]);
+            p[h][1] = reinterpret_cast<double *>(base + L.vec[h][3]);
+            q[h] = reinterpret_cast<double *>(base + L.vec[h][4]);
+            xs[h] = v.x[h];
+        }
+        double *dm = reinterpret_cast<double *>(base + L.vec[0][5]);
+        int nbi, nbj, nbk;
+        const int64_t nb = pc2_blocks(s, &nbi, &nbj, &nbk);
+        if (nb * 2 * 8 > L.bhat[0] - L.partials)
+            return fail(MAS_EINVAL, "internal: partial-sum area too small for PC2");
+        if (nb > INT32_MAX) return fail(MAS_EINVAL, "grid too large for PC2");
+        Pc2Args<double> fa{op->c64[0], op->c64[1], op->c64[2], op->w, dm, nullptr, nullptr, nullptr,
+                           nullptr, nullptr, nullptr, cx.ctl, d, nbi, nbj, nbk, 0};
+        hipLaunchKernelGGL(k_pc2_factor<double>, dim3((unsigned)nb), dim3(kWave), 0, stream, fa, dm);
+        LAUNCHCHK();
+        int iter0 = 0, restarts = 0;
+        for (;;) {
+            bool active[NR], any = false;
+            int maxit[NR];
+            for (int h = 0; h < NR; ++h) {
+                active[h] = !done[h] && info[h].iters < o.max_iters;
+                maxit[h] = iter0 + (o.max_iters - info[h].iters);
+                any = any || active[h];
+            }
+            if (!any) break;
+            PcgResult pr{};
+            int st = run_pcg_pc2_multi<NR>(cx, r, z, p, q, dm, xs, active, maxit, v.tol2, iter0, &pr);
+            if (st != MAS_OK) return st;
+            int last = iter0;
+            for (int h = 0; h < NR; ++h) {
+                if (!active[h]) continue;
+                last = std::max(last, pr.last_iter[h]);
+                info[h].iters += pr.last_iter[h] - iter0;
+                Ctl hc;
+                st = read_ctl(cx, &hc, h);
+                if (st != MAS_OK) return st;
+                info[h].rel_resid_recursive = std::sqrt(hc.rw) / bnorm[h];
+                st = residual<double>(cx, bhat[h], v.x[h], r[h], &rw2[h]);
+                if (st != MAS_OK) return st;
+                info[h].rel_resid_true = std::sqrt(rw2[h]) / bnorm[h];
+                if (rw2[h] <= v.tol2[h]) {
+                    done[h] = true;
+                    info[h].status = MAS_OK;
+                } else if (pr.flag[h] == FLAG_BREAK) {
+                    done[h] = true;
+                    info[h].status = MAS_EBREAKDOWN;
+                } else if (pr.flag[h] != FLAG_CONV || restarts >= o.max_restarts) {
+                    done[h] = true;
+                    info[h].status = MAS_ENOTCONV;
+                } else {
+                    info[h].restarts++;
+                }
+            }
+            mas_pcg_info tinfo{};
+            timing_summary(cx, last, &tinfo);
+            for (int h = 0; h < NR; ++h) {
+                info[h].iter_kernel_us = tinfo.iter_kernel_us;
+                info[h].iter_kernel_samples = tinfo.iter_kernel_samples;
+            }
+            ++restarts;
+            iter0 = last;
+        }
+    }
     int iter0 = 0;
     int restarts = 0;
-    for (;;) {
+    for (; o.precond != MAS_PC2;) {
         bool any = false;
         // as in the single solve, at most max_iters + 1 iteration kernels
         // (the first of a run only forms q = A p) and iters = kernels - 1
@@ -1358,8 +1559,6 @@ extern "C" int mas_pcg_solve_multi(const mas_op *op, int32_t nrhs, const double 
     if (o_in) o = *o_in;
     if (o.precision != MAS_FP64)
         return fail(MAS_EINVAL, "solves of several right-hand sides are double precision only");
-    if (o.precond != MAS_PC1)
-        return fail(MAS_EINVAL, "solves of several right-hand sides use the PC1 preconditioner");
     int st = check_opts(op, &o);
     if (st != MAS_OK) return st;
     if (reinterpret_cast<uintptr_t>(work) & 255)

@@ -134,6 +134,25 @@ def test_c1_pc2_solve_full(c1, c1_oracle):
     assert r <= 1e-10 and i2["iters"] < i1["iters"]
 
 
+def test_c1_pc2_three_components_full(c1, c1_oracle):
+    """Three components under PC2 at the full size: one SpMV launch for all of
+    them per iteration; the oracle's residual of each on all 52.4M cells."""
+    grid = S.Grid.from_problem(c1)
+    op = S.Operator(grid, to_dev(c1.nu), c1.dt)
+    B = to_dev(W.component_rhs(c1.cfg, 3))
+    X, infos = op.solve_multi(B, S.make_opts(rtol=1e-10, precond="pc2", sample_timing=1),
+                              allow_notconv=False)
+    say(f"c1 PC2, 3 components: {[i['iters'] for i in infos]} iterations, "
+        f"{infos[0]['seconds']:.3f} s")
+    Xh = to_host(X)
+    Bh = to_host(B)
+    del op, X, B
+    for h in range(3):
+        r = c1_oracle.rel_residual(c1_oracle.rhs_to_b(Bh[h]), Xh[h])
+        say(f"c1 PC2 component {h}: oracle residual {r:.3e}")
+        assert r <= 1e-10
+
+
 def test_c1_pc2_refined_solve_full(c1, c1_oracle):
     """Single-precision PC2-PCG inside double-precision refinement at the
     full size: the oracle's residual of the GPU solution on all 52.4M cells

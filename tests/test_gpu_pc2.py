@@ -143,6 +143,49 @@ def test_pc2_refined_autograd():
     assert rel(to_host(rhs.grad), grhs_o) <= 1e-8
 
 
+@pytest.mark.parametrize("shape", [(9, 17, 33), (17, 9, 70), (12, 10, 130), (3, 1, 5), "c0"])
+@pytest.mark.parametrize("m", [2, 3, 4])
+def test_pc2_several_rhs_equal_single_solves(shape, m):
+    """PC2 for several right-hand sides (one SpMV launch for all of them):
+    each component's iterations and solution are those of its single PC2
+    solve, bit for bit, and the oracle's residual of each meets 1e-10."""
+    import torch
+    from paper_1811_02605_amd import workloads as W
+    p = problem(shape, (0, 1))
+    _, op = gpu_operator(p)
+    ora = oracle_operator(p)
+    B = to_dev(W.component_rhs(p.cfg, m))
+    o = S.make_opts(rtol=1e-10, precond="pc2")
+    X, infos = op.solve_multi(B, o, allow_notconv=False)
+    for h in range(m):
+        x1, i1 = op.solve(B[h].contiguous(), o, allow_notconv=False)
+        assert infos[h]["iters"] == i1["iters"], (h, infos[h]["iters"], i1["iters"])
+        assert torch.equal(X[h], x1), h
+        res = ora.rel_residual(ora.rhs_to_b(to_host(B[h])), to_host(X[h]))
+        assert res <= 1e-10 and abs(infos[h]["rel_resid_true"] - res) <= 1e-3 * res + 1e-13
+
+
+def test_pc2_several_rhs_independent_stopping():
+    """A zero component, a component already solved (warm start) and one a
+    factor 1e9 smaller stop on their own."""
+    import torch
+    from paper_1811_02605_amd import workloads as W
+    p = problem((9, 17, 33), (0, 0))
+    _, op = gpu_operator(p)
+    B = to_dev(W.component_rhs(p.cfg, 3))
+    B[1] = 0.0
+    B[2] *= 1e-9
+    o = S.make_opts(rtol=1e-10, precond="pc2")
+    X, infos = op.solve_multi(B, o, allow_notconv=False)
+    assert infos[1]["iters"] == 0 and float(X[1].abs().max()) == 0.0
+    x0, _ = op.solve(B[0].contiguous(), o, allow_notconv=False)
+    x2, _ = op.solve(B[2].contiguous(), o, allow_notconv=False)
+    assert torch.equal(X[0], x0) and torch.equal(X[2], x2)
+    X0 = torch.stack([x0, torch.zeros_like(x0), x2]).contiguous()
+    X2, infos2 = op.solve_multi(B, o, x0=X0, allow_notconv=False)
+    assert all(i["iters"] <= 1 for i in infos2)
+
+
 def test_pc2_error_paths():
     p = problem((9, 16, 32), (0, 0))
     _, op = gpu_operator(p, "fp32_refined")
@@ -157,7 +200,7 @@ def test_pc2_error_paths():
     _, op64 = gpu_operator(p)
     import torch
     B = torch.stack([rhs, rhs]).contiguous()
-    with pytest.raises(abi.MasError, match="PC1"):
-        op64.solve_multi(B, S.make_opts(precond="pc2"))
+    with pytest.raises(abi.MasError, match="double precision"):
+        op64.solve_multi(B, S.make_opts(precond="pc2", precision="fp32_refined"))
     x, info = op64.solve(rhs, S.make_opts(max_iters=2, max_restarts=0, precond="pc2"))
     assert info["status"] == abi.MAS_ENOTCONV and info["iters"] == 2

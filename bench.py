@@ -136,8 +136,8 @@ def bench_multi(S, W, grid, nu, p, t_pcg, k_single_us, m=3):
         "bytes_per_cell": multi_bytes_per_cell(m),
         "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
         "frac": (gbs / HBM_PEAK_GBS) if gbs else None,
-        "pc2": {"what": "the same components with block-Jacobi ILU(0): one SpMV launch carries "
-                        "all of them, block solves per component; factor included",
+        "pc2": {"what": "the same components with block-Jacobi ILU(0): per iteration one SpMV "
+                        "launch and one block-solve launch carry all of them; factor included",
                 "iters": [r["iters"] for r in runs2[-1]], "time_to_tol_s": t2,
                 "speedup_vs_pc1_together": t / t2,
                 "iteration_us": runs2[-1][0]["iter_kernel_us"] or None},

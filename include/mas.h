@@ -293,9 +293,10 @@ int64_t mas_pcg_multi_workspace_bytes(const mas_op *op, int32_t nrhs);
 /* Solve A x_h = V .* rhs_h, h = 0..nrhs-1, by PCG in double precision with
  * o->precond: MAS_PC1 (Jacobi; one iteration kernel for all right-hand sides)
  * or MAS_PC2 (block-Jacobi ILU(0), the factor formed once for all; each PC2
- * iteration runs one direction/SpMV launch carrying all right-hand sides and
- * a block solve per right-hand side, and gives each right-hand side the
- * iterates of its single PC2 solve bit for bit).
+ * iteration runs one direction/SpMV launch and one block-solve launch, each
+ * carrying all right-hand sides with the operator read once per cell, and
+ * gives each right-hand side the iterates of its single PC2 solve bit for
+ * bit).
  *   nrhs  1..4
  *   rhs   dev, nrhs*N, right-hand side h at rhs + h*N
  *   x     dev, nrhs*N, same layout: initial guesses on entry if o->use_x0,

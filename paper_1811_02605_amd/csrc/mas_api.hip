@@ -894,21 +894,41 @@ static int run_pcg_pc2_multi(Ctx &cx, double *const r[NR], double *const z[NR],
     hipStream_t st = cx.stream;
     int nbi, nbj, nbk;
     const int64_t nb = pc2_blocks(s, &nbi, &nbj, &nbk);
-    Pc2Args<double> a[NR];
-    for (int h = 0; h < NR; ++h) {
+    for (int h = 0; h < NR; ++h)
         hipLaunchKernelGGL(k_ctl_init, dim3(1), dim3(64), 0, st, cx.ctl + h, 0, iter0,
                            active[h] ? max_iter[h] : iter0, tol2[h], 0.0,
                            (int)(active[h] ? FLAG_RUN : FLAG_CONV));
-        a[h] = Pc2Args<double>{op->c64[0], op->c64[1], op->c64[2], op->w, const_cast<double *>(d),
-                               r[h], x[h], z[h], q[h], nullptr, cx.partials, cx.ctl + h, s.dims(),
-                               nbi, nbj, nbk, 0};
-        // z = M^-1 r of the initial residual, (r, z), the stopping test
-        hipLaunchKernelGGL((k_pc2_solve<double, pc2_prefetch<double>()>), dim3((unsigned)nb), dim3(kWave),
-                           0, st, a[h]);
-        hipLaunchKernelGGL(k_pc2_fin_b, dim3(1), dim3(kRedThreads), 0, st, cx.partials, (int)nb,
-                           cx.ctl + h, 1);
-        a[h].update = 1;
+    // the block solves of all right-hand sides in one launch (couplings, w
+    // and d read once); right-hand side h's partials at partials + 2 h nb
+    Pc2MultiArgs<NR> a{};
+    a.cr = op->c64[0];
+    a.ct = op->c64[1];
+    a.cp = op->c64[2];
+    a.w = op->w;
+    a.d = d;
+    for (int h = 0; h < NR; ++h) {
+        a.r[h] = r[h];
+        a.x[h] = x[h];
+        a.z[h] = z[h];
+        a.q[h] = q[h];
+        a.p[h] = nullptr;
     }
+    a.partials = cx.partials;
+    a.ctl = cx.ctl;
+    a.dm = s.dims();
+    a.nbi = nbi;
+    a.nbj = nbj;
+    a.nbk = nbk;
+    a.update = 0;
+    auto solve_all = [&](int is_first) {
+        hipLaunchKernelGGL(k_pc2_solve_multi<NR>, dim3((unsigned)nb), dim3(kWave), 0, st, a);
+        for (int h = 0; h < NR; ++h)
+            hipLaunchKernelGGL(k_pc2_fin_b, dim3(1), dim3(kRedThreads), 0, st,
+                               cx.partials + 2 * h * nb, (int)nb, cx.ctl + h, is_first);
+    };
+    // z = M^-1 r of the initial residuals, (r, z), the stopping tests
+    solve_all(1);
+    a.update = 1;
     LAUNCHCHK();
     int32_t *pin = nullptr;
     int e = pinned_buffer(&pin);
@@ -974,13 +994,8 @@ static int run_pcg_pc2_multi(Ctx &cx, double *const r[NR], double *const z[NR],
             for (int h = 0; h < NR; ++h)
                 hipLaunchKernelGGL(k_pc2_fin_a, dim3(1), dim3(kRedThreads), 0, st,
                                    cx.partials + h * kNV, it.nblk, (int)(NR * kNV), cx.ctl + h);
-            for (int h = 0; h < NR; ++h) {
-                a[h].p = p[h][(k + 1) & 1];
-                hipLaunchKernelGGL((k_pc2_solve<double, pc2_prefetch<double>()>), dim3((unsigned)nb),
-                                   dim3(kWave), 0, st, a[h]);
-                hipLaunchKernelGGL(k_pc2_fin_b, dim3(1), dim3(kRedThreads), 0, st, cx.partials,
-                                   (int)nb, cx.ctl + h, 0);
-            }
+            for (int h = 0; h < NR; ++h) a.p[h] = p[h][(k + 1) & 1];
+            solve_all(0);
             if (sample) HIPCHK(hipEventRecord(cx.ev.back(), st));
         }
         LAUNCHCHK();
@@ -1414,7 +1429,7 @@ static int solve_multi_core(const mas_op *op, const double *rhs, double *x, cons
         double *dm = reinterpret_cast<double *>(base + L.vec[0][5]);
         int nbi, nbj, nbk;
         const int64_t nb = pc2_blocks(s, &nbi, &nbj, &nbk);
-        if (nb * 2 * 8 > L.bhat[0] - L.partials)
+        if (NR * nb * 2 * 8 > L.bhat[0] - L.partials)
             return fail(MAS_EINVAL, "internal: partial-sum area too small for PC2");
         if (nb > INT32_MAX) return fail(MAS_EINVAL, "grid too large for PC2");
         Pc2Args<double> fa{op->c64[0], op->c64[1], op->c64[2], op->w, dm, nullptr, nullptr, nullptr,

@@ -210,6 +210,21 @@ def bench_adjoint(S, grid, nu, x, p, opts, t_pcg):
           f"gradient kernel {info['grad_kernel_us']:.1f} us", file=sys.stderr, flush=True)
     kus = info["grad_kernel_us"]
     achieved = GRAD_BYTES_PER_CELL * grid.n / (kus * 1e-6) / 1e9
+    del op
+    # the same adjoint with PC2 inside refinement (the fastest solver here)
+    opr = S.Operator(grid, nu, p.dt, precision="fp32_refined")
+    orf = S.make_opts(rtol=p.cfg.rtol, precision="fp32_refined", precond="pc2")
+    opr.adjoint(x, gx, orf, allow_notconv=False)  # warm-up
+    torch.cuda.synchronize()
+    tr = []
+    for _ in range(3):
+        t0 = time.perf_counter()
+        _, _, _, infr = opr.adjoint(x, gx, orf, allow_notconv=False)
+        torch.cuda.synchronize()
+        tr.append(time.perf_counter() - t0)
+    t_r = float(np.median(tr))
+    print(f"[bench] adjoint with refined PC2: {infr['iters']} inner iterations, {t_r:.3f} s",
+          file=sys.stderr, flush=True)
     return {"what": "adjoint of the FP64 solve: lambda = A^-1 gx by the same PCG to 1e-10, then "
                     "dL/dnu and dL/drhs in one gradient-kernel pass (4 words/cell)",
             "time_s": t, "iters": info["iters"], "rel_resid_true": info["rel_resid_true"],
@@ -218,7 +233,12 @@ def bench_adjoint(S, grid, nu, x, p, opts, t_pcg):
             "gradient_kernel": {"bound": "hbm", "kernel": "k_gradient", "kernel_us": kus,
                                 "alg_bytes_per_cell": GRAD_BYTES_PER_CELL, "achieved": achieved,
                                 "peak": 8000.0, "unit": "GB/s", "frac": achieved / 8000.0,
-                                "traffic": read_traffic(GRAD_TRAFFIC_FILE)}}
+                                "traffic": read_traffic(GRAD_TRAFFIC_FILE)},
+            "pc2_refined": {"what": "the same adjoint with single-precision PC2-PCG inside "
+                                    "double-precision refinement",
+                            "time_s": t_r, "inner_iters": infr["iters"],
+                            "outer_iters": infr["outer_iters"],
+                            "rel_resid_true": infr["rel_resid_true"]}}
 
 
 def bench_sts(S, grid, nu, rhs, p, t_pcg, steps):

@@ -37,9 +37,9 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-# Algorithmic bytes of one PCG iteration per cell, as the survey of the method
-# counts them for a fused two-kernel iteration (SpMV with the p update, then
-# the r update with the Jacobi step and the dots): 14 words.
+# Algorithmic bytes of one Jacobi-PCG iteration per cell in its fused
+# two-kernel form (SpMV with the p update, then the r update with the Jacobi
+# step and the dots; the stored operator streamed once): 14 words.
 ALG_BYTES_PER_CELL = {"fp64": 14 * 8, "fp32": 14 * 4}
 # What this library's single-kernel iteration has to move per cell (reads r,
 # q, p, x, c_r, c_theta, c_phi; writes r, p, x, q): 11 words.
@@ -314,7 +314,7 @@ def main():
     ap.add_argument("--check-every", type=int, default=8)
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
+        print(f"bench.py: the library runs on one GPU; --gpus {args.gpus} is not supported "
               "(the multi-GPU r-slab decomposition is a design note, not code).", file=sys.stderr)
         sys.exit(2)
 

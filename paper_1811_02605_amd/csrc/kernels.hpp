@@ -295,8 +295,8 @@ __device__ inline void bst(__amdgpu_buffer_rsrc_t r, uint32_t off, const VecT<T,
 // Block barrier after every plane step for kernels carrying at least this
 // many right-hand sides (keeps the block's waves on one plane, so the rows
 // they load for each other are requested together).  Measured at one fixed
-// placement at c1: three right-hand sides 2438 -> 2401 us, one right-hand
-// side 948 -> 954 us (so not used there).
+// placement on the 256 x 320 x 640 grid: three right-hand sides 2438 -> 2401
+// us, one right-hand side 948 -> 954 us (so not used there).
 #ifndef MAS_ITER_SYNC_MIN_NR
 #define MAS_ITER_SYNC_MIN_NR 2
 #endif

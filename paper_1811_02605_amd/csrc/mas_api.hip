@@ -95,9 +95,9 @@ static inline int64_t align256(int64_t v) { return (v + 255) & ~int64_t(255); }
 
 // Array stagger.  Arrays of n cells sit at offsets that differ by multiples
 // of their length, which at the production sizes is a multiple of 16 MiB
-// (c1: 400 MiB), so element c of every array would share the low address
-// bits that pick the HBM channel; a stencil kernel reading element c of
-// seven arrays at once then sends them to one channel.  Each array of a
+// (256 x 320 x 640 cells: 400 MiB), so element c of every array would share
+// the low address bits that pick the HBM channel; a stencil kernel reading
+// element c of seven arrays at once then sends them to one channel.  Each array of a
 // layout is moved by its own multiple of kStagger bytes, and the workspace
 // and the stage arrays start at other multiples than the operator storage.
 // 2304 = 9 x 256: sixteen consecutive arrays start in sixteen different
@@ -137,8 +137,9 @@ struct Shape {
     // r planes per chunk: the tiles of one chunk are consecutive logical
     // blocks, and xcd_remap hands each of the 8 XCDs a contiguous eighth of
     // them, so with 8 chunks (or a multiple) every XCD owns whole r slabs
-    // and only the planes at slab boundaries are read by two XCDs (c1:
-    // 32-plane chunks, 1.4% faster than 16).  At least kTI planes.
+    // and only the planes at slab boundaries are read by two XCDs (256 x 320
+    // x 640 cells: 32-plane chunks, 1.4% faster than 16).  At least kTI
+    // planes.
     int ti() const { return std::max(kTI, (nr + 7) / 8); }
     int tiles_i() const { return (nr + ti() - 1) / ti(); }
     int64_t nblk_iter(int v) const { return (int64_t)tiles_k(v) * tiles_j() * tiles_i(); }
@@ -754,8 +755,9 @@ static int64_t pc2_blocks(const Shape &s, int *nbi, int *nbj, int *nbk) {
 // iter0; the run stops on ||W r||^2 <= tol2 (every iteration), at max_iter
 // or on a breakdown.  The modified diagonal must already be in d.
 // PC2 solve: rows of loads in flight ahead of the scan.  Measured at one
-// fixed placement at c1: two rows 1.2% faster than one in double precision
-// (2007 vs 2031 us per PC2 iteration), no gain in single precision.
+// fixed placement on the 256 x 320 x 640 grid: two rows 1.2% faster than one
+// in double precision (2007 vs 2031 us per PC2 iteration), no gain in single
+// precision.
 #ifndef MAS_PC2_PF64
 #define MAS_PC2_PF64 2
 #endif

@@ -1686,6 +1686,9 @@ extern "C" int mas_pcg_solve_adjoint(const mas_op *op, const double *x, const do
 #define MAS_PAIR_TI 32
 #endif
 static constexpr int kStsWPB = MAS_STS_WPB, kStsRPW = MAS_STS_RPW, kStsTI = MAS_STS_TI;
+#ifndef MAS_PAIR_SLAB
+#define MAS_PAIR_SLAB 1
+#endif
 static constexpr int kPairNW = MAS_PAIR_NW, kPairTI = MAS_PAIR_TI;
 static_assert(kPairTI >= 1 && kPairTI <= kPairMaxTI, "r planes per chunk of the two-stage kernel");
 static constexpr int kStsMaxStages = 1000000;
@@ -1815,14 +1818,17 @@ static int sts_pair_launch(const mas_op *op, hipStream_t stream, const double *X
                            double bA, double gA, double mA, double aB, double bB, double gB, double mB) {
     const Shape &s = op->s;
     constexpr int RO = 2 * kPairNW - 4;
-    const int64_t tiles_i = (s.nr + kPairTI - 1) / kPairTI;
+    // r chunks: at least kPairTI planes, and long enough that there are at
+    // most 8 of them (whole r slabs per XCD, as for the iteration kernel)
+    const int ti = MAS_PAIR_SLAB ? std::min(kPairMaxTI, std::max(kPairTI, (s.nr + 7) / 8)) : kPairTI;
+    const int64_t tiles_i = (s.nr + ti - 1) / ti;
     const int64_t tiles_k = (s.np + kPairOut - 1) / kPairOut;
     const int64_t tiles_j = (s.nt + RO - 1) / RO;
     const int64_t nblk = tiles_i * tiles_k * tiles_j;
     if (nblk > INT32_MAX) return fail(MAS_EINVAL, "grid too large for the stage kernel");
     if (!sts_pairs_ok(s)) return fail(MAS_EINVAL, "internal: two-stage kernel needs an even np");
     StsPairArgs args{X, op->nu, Z, L0, Y0, outA, outB, aA, bA, gA, mA * op->dt, aB, bB, gB, mB * op->dt,
-                     op->geo, s.dims(), (int)tiles_i, (int)tiles_k, (int)tiles_j, kPairTI, (int)nblk};
+                     op->geo, s.dims(), (int)tiles_i, (int)tiles_k, (int)tiles_j, ti, (int)nblk};
     const int in = (Z ? kPairZ : 0) | (L0 ? kPairL : 0) | (Y0 ? kPairY : 0);
     const dim3 grid((unsigned)nblk), block(kWave * kPairNW);
     switch (in) {

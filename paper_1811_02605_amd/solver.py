@@ -79,6 +79,16 @@ def make_opts(rtol=None, max_iters=None, precision=None, inner_rtol=None, max_ou
     return o
 
 
+def _copy_opts(opts, **overrides):
+    """A private copy of an options struct (the caller's object is never
+    modified), with the given fields replaced."""
+    o = abi.mas_pcg_opts()
+    ctypes.pointer(o)[0] = opts if opts is not None else make_opts()
+    for name, v in overrides.items():
+        setattr(o, name, type(getattr(o, name))(v))
+    return o
+
+
 def _stream(device) -> int:
     return torch.cuda.current_stream(device).cuda_stream
 
@@ -86,8 +96,11 @@ def _stream(device) -> int:
 def _check_vec(t: torch.Tensor, shape, name):
     if not isinstance(t, torch.Tensor) or t.dtype != torch.float64 or not t.is_cuda:
         raise TypeError(f"{name} must be a float64 CUDA/HIP tensor")
-    if tuple(t.shape) != tuple(shape) and t.numel() != int(np.prod(shape)):
-        raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {tuple(shape)}")
+    # the arrays are read phi-fastest as (.., nr, nt, np): accept exactly that
+    # shape or a flat vector of the same length, nothing else
+    flat = (int(np.prod(shape)),)
+    if tuple(t.shape) != tuple(shape) and tuple(t.shape) != flat:
+        raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {tuple(shape)} or {flat}")
     if not t.is_contiguous():
         raise ValueError(f"{name} must be contiguous")
 
@@ -162,11 +175,12 @@ class Operator:
               out: torch.Tensor | None = None, allow_notconv=True):
         """x = A^-1 (V .* rhs).  Returns (x, info dict)."""
         _check_vec(rhs, self.grid.shape, "rhs")
-        opts = opts if opts is not None else make_opts()
         x = out if out is not None else torch.empty_like(rhs)
+        # the solution buffer is the starting guess only when x0 is given
         if x0 is not None:
+            _check_vec(x0, self.grid.shape, "x0")
             x.copy_(x0)
-            opts.use_x0 = 1
+        opts = _copy_opts(opts, use_x0=int(x0 is not None))
         work, nbytes = self.workspace(opts)
         info = abi.mas_pcg_info()
         with torch.cuda.device(self.device):
@@ -185,12 +199,12 @@ class Operator:
         m = int(rhs.shape[0])
         shape = (m,) + tuple(self.grid.shape)
         _check_vec(rhs, shape, "rhs")
-        opts = opts if opts is not None else make_opts()
         x = out if out is not None else torch.empty_like(rhs)
         _check_vec(x, shape, "out")
         if x0 is not None:
+            _check_vec(x0, shape, "x0")
             x.copy_(x0)
-            opts.use_x0 = 1
+        opts = _copy_opts(opts, use_x0=int(x0 is not None))
         lib = abi.load()
         nbytes = int(lib.mas_pcg_multi_workspace_bytes(self._h, m))
         abi.check(nbytes if nbytes < 0 else 0, "mas_pcg_multi_workspace_bytes")
@@ -212,7 +226,8 @@ class Operator:
         """(lambda, dL/dnu, dL/drhs, info) for dL/dx = gx at the solution x."""
         _check_vec(x, self.grid.shape, "x")
         _check_vec(gx, self.grid.shape, "gx")
-        opts = opts if opts is not None else make_opts()
+        # lambda starts from zero: its buffer is fresh memory
+        opts = _copy_opts(opts, use_x0=0)
         lam = torch.empty_like(x)
         gnu = torch.empty_like(x)
         grhs = torch.empty_like(x)
@@ -275,6 +290,7 @@ class MasSolve(torch.autograd.Function):
     @staticmethod
     def forward(ctx, nu, rhs, grid, dt, opts_kw):
         opts_kw = dict(opts_kw or {})
+        opts_kw.pop("use_x0", None)  # the solution buffer is fresh memory: start from zero
         op = Operator(grid, nu.detach().contiguous(), dt,
                       precision=opts_kw.get("precision", "fp64"))
         x, info = op.solve(rhs.detach().contiguous(), make_opts(**opts_kw), allow_notconv=False)

@@ -135,3 +135,13 @@ def test_status_strings():
     for s in (0, 1, -1, -2, -3, -4):
         assert abi.status_string(s).startswith("MAS_")
     assert abi.status_string(99) == "unknown status"
+
+
+def test_solver_copies_options_instead_of_changing_them():
+    from paper_1811_02605_amd import solver as S
+    o = S.make_opts(rtol=1e-8, check_every=4)
+    c = S._copy_opts(o, use_x0=1)
+    assert o.use_x0 == 0 and c.use_x0 == 1
+    assert c.rtol == 1e-8 and c.check_every == 4
+    c.rtol = 1.0
+    assert o.rtol == 1e-8

@@ -147,6 +147,29 @@ def test_warm_start_from_solution():
     assert iw["status"] == 0 and iw["iters"] < ic["iters"]
 
 
+def test_reused_opts_keep_no_warm_start():
+    """An options object used for a warm-started solve is not changed by it: a
+    following adjoint and a cold solve with the same object start from zero
+    and take the iterations of fresh calls."""
+    p = problem((9, 16, 32))
+    _, op = gpu_operator(p)
+    rhs = to_dev(p.rhs)
+    o = S.make_opts(rtol=1e-10)
+    x, ic = op.solve(rhs, o, allow_notconv=False)
+    _, iw = op.solve(rhs, o, x0=x, allow_notconv=False)  # starts at the solution
+    assert o.use_x0 == 0 and iw["iters"] == 0 < ic["iters"]
+    _, ic2 = op.solve(rhs, o, allow_notconv=False)
+    assert ic2["iters"] == ic["iters"]
+    gx = to_dev(np.random.default_rng(5).standard_normal(p.shape))
+    _, _, _, ia = op.adjoint(x, gx, o, allow_notconv=False)
+    _, _, _, ia_fresh = op.adjoint(x, gx, S.make_opts(rtol=1e-10), allow_notconv=False)
+    assert ia["iters"] == ia_fresh["iters"]
+    # use_x0 set by the caller without an x0 tensor is ignored: the output
+    # buffer is fresh memory, never a starting guess
+    _, iu = op.solve(rhs, S.make_opts(rtol=1e-10, use_x0=1), allow_notconv=False)
+    assert iu["iters"] == ic["iters"]
+
+
 def test_zero_time_step_and_zero_rhs():
     p = problem((5, 7, 13))
     _, op = gpu_operator(p, dt=0.0)

@@ -314,6 +314,27 @@ int mas_pcg_solve_multi(const mas_op *op, int32_t nrhs, const double *rhs, doubl
                         const mas_pcg_opts *o, void *work, int64_t work_bytes, void *hip_stream,
                         mas_pcg_info *info);
 
+/* ---------------------------------------------------------------- allocation-free solve
+ * For callers that cannot allocate device or pinned memory or create HIP
+ * objects during a solve: code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc.  The same solve as mas_pcg_solve (same
+ * kernels, options, results and status codes), with its workspace taken from
+ * a static device array of MAS_NOALLOC_WORK_BYTES inside the library (one per
+ * GPU, held until the process ends) instead of a caller buffer; the host
+ * reads the run flags with synchronous copies instead of a pinned buffer and
+ * events.  It calls no hipMalloc, hipFree, hipHostMalloc or hipEventCreate.
+ *   rhs, x, o, info  as for mas_pcg_solve; o->sample_timing must be 0
+ * Returns MAS_ENOMEM when mas_pcg_workspace_bytes(op, o) exceeds
+ * MAS_NOALLOC_WORK_BYTES (64 MiB: about 1.1M cells in double precision),
+ * MAS_EINVAL for sample_timing; otherwise as mas_pcg_solve.  All calls on
+ * one GPU share that GPU's array: calls that overlap in time on one GPU
+ * (other host threads, other streams) race and must be serialised by the
+ * caller.  Every value the solve reads from the array is written by the same
+ * call first.  Blocks until the solve has finished. */
+#define MAS_NOALLOC_WORK_BYTES (64LL * 1024 * 1024)
+int mas_pcg_solve_noalloc(const mas_op *op, const double *rhs, double *x, const mas_pcg_opts *o,
+                          void *hip_stream, mas_pcg_info *info);
+
 /* Bandwidth probe: dst[0:bytes) = src[0:bytes), both dev, 16-byte aligned,
  * bytes a multiple of 16.  A plain streaming copy used to calibrate the HBM
  * byte counters.  Enqueues only. */

@@ -33,6 +33,9 @@ MAS_REFINE_RELIABLE = 1
 MAS_PC1 = 0
 MAS_PC2 = 1
 
+# workspace of the allocation-free solve (a static device array in the library)
+MAS_NOALLOC_WORK_BYTES = 64 * 1024 * 1024
+
 
 class mas_grid(ctypes.Structure):
     _fields_ = [("nr", ctypes.c_int32), ("nt", ctypes.c_int32), ("np", ctypes.c_int32),
@@ -102,6 +105,8 @@ _SIGS = {
     "mas_sts_workspace_bytes": (ctypes.c_int64, [_VP]),
     "mas_sts_step": (ctypes.c_int, [_VP, _VP, _VP, ctypes.POINTER(mas_sts_opts), _VP,
                                     ctypes.c_int64, _VP, ctypes.POINTER(mas_sts_info)]),
+    "mas_pcg_solve_noalloc": (ctypes.c_int, [_VP, _VP, _VP, ctypes.POINTER(mas_pcg_opts), _VP,
+                                             ctypes.POINTER(mas_pcg_info)]),
     "mas_probe_copy": (ctypes.c_int, [_VP, _VP, ctypes.c_int64, _VP]),
     "mas_status_string": (ctypes.c_char_p, [ctypes.c_int]),
     "mas_last_error": (ctypes.c_char_p, []),

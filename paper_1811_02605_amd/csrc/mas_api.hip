@@ -9,6 +9,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <type_traits>
@@ -510,6 +511,7 @@ struct Ctx {
     Ctl *ctl;  // [nrhs]; ctl[0] also receives k_reduce sums
     double *partials;
     bool timing;
+    bool no_alloc = false;  // allocation-free entry point: no pinned buffer, no events
     // event samples of the iteration kernel
     std::vector<hipEvent_t> ev;
     std::vector<int> ev_iter;
@@ -524,6 +526,62 @@ static int read_ctl(Ctx &cx, Ctl *h, int c = 0) {
     HIPCHK(hipStreamSynchronize(cx.stream));
     return MAS_OK;
 }
+
+// Host polling of the run flags of control blocks ctl[0:n] after each batch
+// of launches.  Normally one batch behind: the flags are copied into a pinned
+// buffer behind the batch and the host waits for the previous batch's event,
+// so the device queue never runs dry.  For the allocation-free entry point
+// (no pinned buffer, no events) the flags are copied synchronously after
+// each batch.
+struct FlagPoll {
+    Ctx &cx;
+    int32_t *pin = nullptr;
+    hipEvent_t done[2] = {nullptr, nullptr};
+    int nb = 0;  // batches polled
+    explicit FlagPoll(Ctx &c) : cx(c) {}
+    ~FlagPoll() {
+        for (auto e : done)
+            if (e) (void)hipEventDestroy(e);
+    }
+    int init() {
+        if (cx.no_alloc) return MAS_OK;
+        int e = pinned_buffer(&pin);
+        if (e != MAS_OK) return e;
+        HIPCHK(hipEventCreateWithFlags(&done[0], hipEventDisableTiming));
+        HIPCHK(hipEventCreateWithFlags(&done[1], hipEventDisableTiming));
+        return MAS_OK;
+    }
+    // Call after enqueueing a batch; *stop becomes true once every flag seen
+    // has left FLAG_RUN.
+    int after_batch(int n, bool *stop) {
+        if (cx.no_alloc) {
+            int32_t fl[kMaxRhs];
+            for (int h = 0; h < n; ++h)
+                HIPCHK(hipMemcpyAsync(fl + h, &cx.ctl[h].flag, sizeof(int32_t),
+                                      hipMemcpyDeviceToHost, cx.stream));
+            HIPCHK(hipStreamSynchronize(cx.stream));
+            bool any = false;
+            for (int h = 0; h < n; ++h) any = any || fl[h] == FLAG_RUN;
+            *stop = !any;
+            ++nb;
+            return MAS_OK;
+        }
+        int32_t *slot = pin + kMaxRhs * (nb & 1);
+        for (int h = 0; h < n; ++h)
+            HIPCHK(hipMemcpyAsync(slot + h, &cx.ctl[h].flag, sizeof(int32_t),
+                                  hipMemcpyDeviceToHost, cx.stream));
+        HIPCHK(hipEventRecord(done[nb & 1], cx.stream));
+        if (nb > 0) {
+            HIPCHK(hipEventSynchronize(done[(nb - 1) & 1]));
+            const int32_t *prev = pin + kMaxRhs * ((nb - 1) & 1);
+            bool any = false;
+            for (int h = 0; h < n; ++h) any = any || prev[h] == FLAG_RUN;
+            if (!any) *stop = true;
+        }
+        ++nb;
+        return MAS_OK;
+    }
+};
 
 // Sum nv values of the simple-kernel partials into ctl->sums[0:nv] and
 // copy them to the host (synchronous).
@@ -595,8 +653,8 @@ static int run_pcg(Ctx &cx, const RhsSet<T> &v, const T *const c[3], int mode, i
         if (v.active[h]) max_iter = std::max(max_iter, v.max_iter[h]);
     }
     LAUNCHCHK();
-    int32_t *pin = nullptr;
-    int e = pinned_buffer(&pin);
+    FlagPoll poll(cx);
+    int e = poll.init();
     if (e != MAS_OK) return e;
 
     IterArgs<T> a{};
@@ -620,19 +678,7 @@ static int run_pcg(Ctx &cx, const RhsSet<T> &v, const T *const c[3], int mode, i
 
     // batches of launches; the host polls the device flags one batch behind
     const int batch = std::max(check_every, 16);
-    hipEvent_t done[2] = {nullptr, nullptr};
-    HIPCHK(hipEventCreateWithFlags(&done[0], hipEventDisableTiming));
-    HIPCHK(hipEventCreateWithFlags(&done[1], hipEventDisableTiming));
-    struct EvGuard {
-        hipEvent_t *e;
-        ~EvGuard() {
-            (void)hipEventDestroy(e[0]);
-            (void)hipEventDestroy(e[1]);
-        }
-    } guard{done};
-
     int k = iter0;
-    int nb = 0;
     bool stop = false;
     while (!stop && k <= max_iter) {
         const int kend = std::min(max_iter, k + batch - 1);
@@ -687,19 +733,8 @@ static int run_pcg(Ctx &cx, const RhsSet<T> &v, const T *const c[3], int mode, i
                                cx.ctl, chk ? 1 : 0);
         }
         LAUNCHCHK();
-        int32_t *slot = pin + 2 * kMaxRhs * (nb & 1);
-        for (int h = 0; h < NR; ++h)
-            HIPCHK(hipMemcpyAsync(slot + 2 * h, &cx.ctl[h].flag, 2 * sizeof(int32_t),
-                                  hipMemcpyDeviceToHost, st));
-        HIPCHK(hipEventRecord(done[nb & 1], st));
-        if (nb > 0) {
-            HIPCHK(hipEventSynchronize(done[(nb - 1) & 1]));
-            const int32_t *prev = pin + 2 * kMaxRhs * ((nb - 1) & 1);
-            bool any = false;
-            for (int h = 0; h < NR; ++h) any = any || prev[2 * h] == FLAG_RUN;
-            if (!any) stop = true;
-        }
-        ++nb;
+        e = poll.after_batch(NR, &stop);
+        if (e != MAS_OK) return e;
     }
     HIPCHK(hipStreamSynchronize(st));
     for (int h = 0; h < NR; ++h) {
@@ -791,19 +826,9 @@ static int run_pcg_pc2(Ctx &cx, T *r, T *z, T *const p[2], T *q, T *d, T *x, int
     hipLaunchKernelGGL((k_pc2_solve<T, pc2_prefetch<T>()>), dim3((unsigned)nb), dim3(kWave), 0, st, a);
     hipLaunchKernelGGL(k_pc2_fin_b, dim3(1), dim3(kRedThreads), 0, st, cx.partials, (int)nb, cx.ctl, 1);
     LAUNCHCHK();
-    int32_t *pin = nullptr;
-    int e = pinned_buffer(&pin);
+    FlagPoll poll(cx);
+    int e = poll.init();
     if (e != MAS_OK) return e;
-    hipEvent_t done[2] = {nullptr, nullptr};
-    HIPCHK(hipEventCreateWithFlags(&done[0], hipEventDisableTiming));
-    HIPCHK(hipEventCreateWithFlags(&done[1], hipEventDisableTiming));
-    struct EvGuard {
-        hipEvent_t *e;
-        ~EvGuard() {
-            (void)hipEventDestroy(e[0]);
-            (void)hipEventDestroy(e[1]);
-        }
-    } guard{done};
     // the direction and SpMV step: the PCG iteration kernel with no r, q or
     // x (p = z + beta p, q = A^ p, partial (p, q) first of each block's kNV)
     IterArgs<T> it{};
@@ -824,7 +849,7 @@ static int run_pcg_pc2(Ctx &cx, T *r, T *z, T *const p[2], T *q, T *d, T *x, int
     constexpr int VW = vec_full<T>();
     const dim3 igrid((unsigned)it.nblk), iblock(kWave * kTJ);
     a.update = 1;
-    int k = iter0, nbt = 0;
+    int k = iter0;
     bool stop = false;
     while (!stop && k < max_iter) {
         const int kend = std::min(max_iter, k + 16);
@@ -861,14 +886,8 @@ static int run_pcg_pc2(Ctx &cx, T *r, T *z, T *const p[2], T *q, T *d, T *x, int
             if (sample) HIPCHK(hipEventRecord(cx.ev.back(), st));
         }
         LAUNCHCHK();
-        HIPCHK(hipMemcpyAsync(pin + 2 * (nbt & 1), &cx.ctl->flag, 2 * sizeof(int32_t),
-                              hipMemcpyDeviceToHost, st));
-        HIPCHK(hipEventRecord(done[nbt & 1], st));
-        if (nbt > 0) {
-            HIPCHK(hipEventSynchronize(done[(nbt - 1) & 1]));
-            if (pin[2 * ((nbt - 1) & 1)] != FLAG_RUN) stop = true;
-        }
-        ++nbt;
+        e = poll.after_batch(1, &stop);
+        if (e != MAS_OK) return e;
     }
     HIPCHK(hipStreamSynchronize(st));
     Ctl h;
@@ -932,19 +951,9 @@ static int run_pcg_pc2_multi(Ctx &cx, double *const r[NR], double *const z[NR],
     solve_all(1);
     a.update = 1;
     LAUNCHCHK();
-    int32_t *pin = nullptr;
-    int e = pinned_buffer(&pin);
+    FlagPoll poll(cx);
+    int e = poll.init();
     if (e != MAS_OK) return e;
-    hipEvent_t done[2] = {nullptr, nullptr};
-    HIPCHK(hipEventCreateWithFlags(&done[0], hipEventDisableTiming));
-    HIPCHK(hipEventCreateWithFlags(&done[1], hipEventDisableTiming));
-    struct EvGuard {
-        hipEvent_t *e;
-        ~EvGuard() {
-            (void)hipEventDestroy(e[0]);
-            (void)hipEventDestroy(e[1]);
-        }
-    } guard{done};
     IterArgs<double> it{};
     it.cr = op->c64[0];
     it.ct = op->c64[1];
@@ -965,7 +974,7 @@ static int run_pcg_pc2_multi(Ctx &cx, double *const r[NR], double *const z[NR],
     int kmax = iter0;
     for (int h = 0; h < NR; ++h)
         if (active[h]) kmax = std::max(kmax, max_iter[h]);
-    int k = iter0, nbt = 0;
+    int k = iter0;
     bool stop = false;
     while (!stop && k < kmax) {
         const int kend = std::min(kmax, k + 16);
@@ -1001,18 +1010,8 @@ static int run_pcg_pc2_multi(Ctx &cx, double *const r[NR], double *const z[NR],
             if (sample) HIPCHK(hipEventRecord(cx.ev.back(), st));
         }
         LAUNCHCHK();
-        int32_t *slot = pin + 8 * (nbt & 1);
-        for (int h = 0; h < NR; ++h)
-            HIPCHK(hipMemcpyAsync(slot + h, &cx.ctl[h].flag, sizeof(int32_t), hipMemcpyDeviceToHost, st));
-        HIPCHK(hipEventRecord(done[nbt & 1], st));
-        if (nbt > 0) {
-            HIPCHK(hipEventSynchronize(done[(nbt - 1) & 1]));
-            const int32_t *prev = pin + 8 * ((nbt - 1) & 1);
-            bool anyrun = false;
-            for (int h = 0; h < NR; ++h) anyrun = anyrun || prev[h] == FLAG_RUN;
-            if (!anyrun) stop = true;
-        }
-        ++nbt;
+        e = poll.after_batch(NR, &stop);
+        if (e != MAS_OK) return e;
     }
     HIPCHK(hipStreamSynchronize(st));
     for (int h = 0; h < NR; ++h) {
@@ -1034,9 +1033,11 @@ static void set_halo(RhsSet<T> &v, char *base, const WorkLayout &L, int h = 0) {
 }
 
 // Solve A x = b with b = V src (src_is_rhs) or b = src; result (unscaled) in x.
+// no_alloc: the allocation-free entry point's call (no pinned buffer, no
+// events; timing samples are refused).
 static int solve_core(const mas_op *op, const double *src, int src_is_rhs, double *x,
                       const mas_pcg_opts *o_in, void *work, int64_t work_bytes, void *hip_stream,
-                      mas_pcg_info *info_out) {
+                      mas_pcg_info *info_out, bool no_alloc = false) {
     const auto t0 = std::chrono::steady_clock::now();
     mas_pcg_info info{};
     mas_pcg_opts o;
@@ -1046,6 +1047,8 @@ static int solve_core(const mas_op *op, const double *src, int src_is_rhs, doubl
         return fail(MAS_EINVAL, "op, right-hand side, solution and work must not be NULL");
     int st = check_opts(op, &o);
     if (st != MAS_OK) return st;
+    if (no_alloc && o.sample_timing)
+        return fail(MAS_EINVAL, "sample_timing needs HIP events: not available without allocation");
     if (reinterpret_cast<uintptr_t>(work) & 255)
         return fail(MAS_EINVAL, "work must be 256-byte aligned");
     const Shape &s = op->s;
@@ -1065,6 +1068,7 @@ static int solve_core(const mas_op *op, const double *src, int src_is_rhs, doubl
     cx.partials = reinterpret_cast<double *>(base + L.partials);
     double *bhat = reinterpret_cast<double *>(base + L.bhat[0]);
     cx.timing = o.sample_timing != 0;
+    cx.no_alloc = no_alloc;
     const Dims d = s.dims();
     const dim3 sgrid = s.simple_grid(), sblock(kWave, kSimpleJ);
 
@@ -1562,6 +1566,55 @@ extern "C" int mas_pcg_solve(const mas_op *op, const double *rhs, double *x, con
                              void *work, int64_t work_bytes, void *hip_stream, mas_pcg_info *info) {
     g_last_error.clear();
     return solve_core(op, rhs, 1, x, o, work, work_bytes, hip_stream, info);
+}
+
+// ------------------------------------------------------------------ allocation-free solve
+// The workspace of mas_pcg_solve_noalloc: a static device array, one copy per
+// GPU, kept until the process ends.  Host code never uses the array's name
+// as an address (on the host it is only a stand-in for the symbol): the
+// device address of each GPU's copy comes from hipGetSymbolAddress, taken
+// once per device with that device current.
+static __device__ __align__(256) unsigned char scratch[MAS_NOALLOC_WORK_BYTES];
+
+static constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static void *g_scratch_ptr[kMaxDevices] = {};
+
+static int scratch_of_current_device(void **out) {
+    int dev = -1;
+    HIPCHK(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return fail(MAS_EINVAL, "device index %d out of range", dev);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr)
+            return fail(MAS_EHIP, "hipGetSymbolAddress(scratch) failed on device %d: %s", dev,
+                        hipGetErrorString(e));
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return MAS_OK;
+}
+
+extern "C" int mas_pcg_solve_noalloc(const mas_op *op, const double *rhs, double *x,
+                                     const mas_pcg_opts *o, void *hip_stream, mas_pcg_info *info) {
+    g_last_error.clear();
+    if (!op) return fail(MAS_EINVAL, "op must not be NULL");
+    mas_pcg_opts def;
+    mas_pcg_default_opts(&def);
+    const mas_pcg_opts *oo = o ? o : &def;
+    int st = check_opts(op, oo);
+    if (st != MAS_OK) return st;
+    const int64_t need = work_layout(op->s, oo->precision).total;
+    if (need > (int64_t)MAS_NOALLOC_WORK_BYTES)
+        return fail(MAS_ENOMEM, "grid too large for the allocation-free solve: workspace %lld > %lld bytes",
+                    (long long)need, (long long)MAS_NOALLOC_WORK_BYTES);
+    void *work = nullptr;
+    st = scratch_of_current_device(&work);
+    if (st != MAS_OK) return st;
+    return solve_core(op, rhs, 1, x, oo, work, (int64_t)MAS_NOALLOC_WORK_BYTES, hip_stream, info,
+                      true);
 }
 
 extern "C" int mas_pcg_solve_multi(const mas_op *op, int32_t nrhs, const double *rhs, double *x,

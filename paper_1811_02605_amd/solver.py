@@ -7,6 +7,7 @@ Nothing here computes on tensors.
     grid = Grid(r_faces, t_faces, np)
     op = Operator(grid, nu, dt, precision="fp64")        # mas_op_build
     x, info = op.solve(rhs)                              # mas_pcg_solve
+    x, info = op.solve_noalloc(rhs)                      # mas_pcg_solve_noalloc (no allocation)
     lam, g_nu, g_rhs, info = op.adjoint(x, gx)           # mas_pcg_solve_adjoint
     u1, info = op.sts_step(u0)                           # mas_sts_step (explicit RKL2)
     X, infos = op.solve_multi(RHS)                       # mas_pcg_solve_multi (RHS: (m, nr, nt, np))
@@ -190,6 +191,29 @@ class Operator:
         abi.check(st, "mas_pcg_solve", allow_notconv=allow_notconv)
         if st == abi.MAS_ENOTCONV:
             warnings.warn(f"mas_pcg_solve did not converge: {info.as_dict()}")
+        return x, info.as_dict()
+
+    def solve_noalloc(self, rhs: torch.Tensor, opts=None, x0: torch.Tensor | None = None,
+                      out: torch.Tensor | None = None, allow_notconv=True):
+        """The same solve as solve(), through mas_pcg_solve_noalloc: the
+        library takes the workspace from its static device array and
+        allocates nothing during the call (out, when given, must be a
+        preallocated float64 tensor of the grid's shape)."""
+        _check_vec(rhs, self.grid.shape, "rhs")
+        x = out if out is not None else torch.empty_like(rhs)
+        _check_vec(x, self.grid.shape, "out")
+        if x0 is not None:
+            _check_vec(x0, self.grid.shape, "x0")
+            x.copy_(x0)
+        opts = _copy_opts(opts, use_x0=int(x0 is not None))
+        info = abi.mas_pcg_info()
+        with torch.cuda.device(self.device):
+            st = abi.load().mas_pcg_solve_noalloc(self._h, rhs.data_ptr(), x.data_ptr(),
+                                                  ctypes.byref(opts), _stream(self.device),
+                                                  ctypes.byref(info))
+        abi.check(st, "mas_pcg_solve_noalloc", allow_notconv=allow_notconv)
+        if st == abi.MAS_ENOTCONV:
+            warnings.warn(f"mas_pcg_solve_noalloc did not converge: {info.as_dict()}")
         return x, info.as_dict()
 
     def solve_multi(self, rhs: torch.Tensor, opts=None, x0: torch.Tensor | None = None,

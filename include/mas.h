@@ -115,7 +115,9 @@ typedef struct {
                              events (reported in mas_pcg_info)                          (0) */
     int32_t refine;       /* refined: MAS_REFINE_RESTART | MAS_REFINE_RELIABLE   (RELIABLE) */
     int32_t precond;      /* MAS_PC1 | MAS_PC2                                      (PC1) */
-    int32_t pad_;
+    int32_t chunk_planes; /* r planes each block of the PCG iteration kernel marches
+                             through; 0: automatic (at least 16 and an eighth of nr,
+                             fewer on grids too small to fill the GPU)             (0) */
 } mas_pcg_opts;
 
 typedef struct {

@@ -50,7 +50,7 @@ class mas_pcg_opts(ctypes.Structure):
                 ("max_outer", ctypes.c_int32), ("check_every", ctypes.c_int32),
                 ("use_x0", ctypes.c_int32), ("max_restarts", ctypes.c_int32),
                 ("sample_timing", ctypes.c_int32), ("refine", ctypes.c_int32),
-                ("precond", ctypes.c_int32), ("pad_", ctypes.c_int32)]
+                ("precond", ctypes.c_int32), ("chunk_planes", ctypes.c_int32)]
 
 
 class mas_pcg_info(ctypes.Structure):

@@ -51,12 +51,15 @@ struct Ctl {
     double rr_next;    // (r_{k+1}, r_{k+1}) predicted by the recurrence at the last finalize
     double pq, rq, qq; // last sums (diagnostics)
     double sums[8];    // results of k_reduce
+    double wratio;     // ||W r||^2 / (r,r) at the last check (predicts ||W r||^2 from (r,r))
     int32_t flag;      // 0 running, 1 converged, 2 iteration limit, -2 breakdown
     int32_t iter;      // index of the next iteration kernel
     int32_t max_iter;  // last admissible iteration index
     int32_t mode;      // 0: ||W r||^2 <= tol2 on check iterations; 1: (r,r) <= tol2 every iteration
     int32_t conv_iter; // iteration index at which flag was set
-    int32_t pad[3];
+    int32_t check;     // mode 0: the next iteration kernel forms ||W r||^2
+    int32_t check_every;  // mode 0: a check at least every check_every iterations
+    int32_t pad;
 };
 
 enum { FLAG_RUN = 0, FLAG_CONV = 1, FLAG_MAXIT = 2, FLAG_BREAK = -2 };
@@ -111,6 +114,104 @@ __device__ inline void block_sum_store(double (&v)[NV], double *out, double *lds
             for (int u = 0; u < nw; ++u) s += lds[u * NV + t];
             out[t] = s;
         }
+    }
+}
+
+// ---------------------------------------------------------------- CG finalize
+// Fixed-order sum of the kNV partials of right-hand side c over nblk blocks
+// ([nblk][nrhs][kNV]) by the NT threads of one block: thread t adds blocks
+// t, t + NT, ... in order, the waves combine by a butterfly, the wave sums
+// are added in wave order (bitwise reproducible).  Every thread gets the
+// sums.
+template <int NT>
+__device__ inline void sum_partials(const double *partials, int nblk, int nrhs, int c,
+                                    double (&out)[kNV], double *lds) {
+    double v[kNV] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    for (int b = threadIdx.x; b < nblk; b += NT) {
+#pragma unroll
+        for (int t = 0; t < kNV; ++t) v[t] += partials[((int64_t)b * nrhs + c) * kNV + t];
+    }
+#pragma unroll
+    for (int t = 0; t < kNV; ++t) v[t] = wave_sum(v[t]);
+    const int wv = threadIdx.x / kWave;
+    if ((threadIdx.x & (kWave - 1)) == 0) {
+#pragma unroll
+        for (int t = 0; t < kNV; ++t) lds[wv * kNV + t] = v[t];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int t = 0; t < kNV; ++t) {
+        double s = 0.0;
+        for (int u = 0; u < NT / kWave; ++u) s += lds[u * kNV + t];
+        out[t] = s;
+    }
+    __syncthreads();
+}
+
+// Residual check: a kernel forms ||W r||^2 (reading w) periodically, at the
+// last admissible iteration, and at every iteration once the value predicted
+// from (r, r) and the ratio ||W r||^2/(r, r) of the last check is within
+// this factor of the threshold, so the run stops at the first checked
+// iteration below it instead of up to check_every - 1 iterations late.
+constexpr double kCheckMargin = 4.0;
+
+// The scalar recurrences and stopping tests after PCG iteration kernel k
+// (one thread), from the sums S = [(p,q), (r,q), (q,q), (r,r), ||W r||^2]:
+//   alpha_k = (r_k,r_k)/(p_k,q_k)
+//   (r_{k+1},r_{k+1}) = (r_k,r_k) - 2 alpha_k (r_k,q_k) + alpha_k^2 (q_k,q_k)
+//   beta_{k+1} = (r_{k+1},r_{k+1}) / (r_k,r_k)
+__device__ inline void pcg_finalize(Ctl *ctl, const double (&S)[kNV]) {
+    const double PQ = S[0], RQ = S[1], QQ = S[2], RR = S[3], RW = S[4];
+    const int k = ctl->iter;
+    ctl->pq = PQ;
+    ctl->rq = RQ;
+    ctl->qq = QQ;
+    bool conv = false;
+    if (ctl->mode == 0) {
+        if (ctl->check) {
+            ctl->rw = RW;
+            conv = RW <= ctl->tol2;
+            if (RR > 0.0 && isfinite(RW)) ctl->wratio = RW / RR;
+        }
+    } else {
+        conv = RR <= ctl->tol2;
+    }
+    ctl->rr = RR;
+    // an exactly zero scaled residual is an exact solution (W r = 0 as well)
+    if (RR == 0.0) conv = true;
+    // alpha_k and the predicted (r_{k+1}, r_{k+1}) are recorded even when
+    // stopping: a refinement step that keeps the search direction folds the
+    // pending alpha_k p_k into the solution and compares the replaced
+    // residual with the prediction
+    {
+        const double al = (PQ > 0.0 && isfinite(PQ)) ? RR / PQ : 0.0;
+        ctl->alpha = al;
+        ctl->rr_next = RR - 2.0 * al * RQ + al * al * QQ;
+    }
+    if (conv) {
+        ctl->flag = FLAG_CONV;
+        ctl->conv_iter = k;
+        return;
+    }
+    if (k >= ctl->max_iter) {
+        ctl->flag = FLAG_MAXIT;
+        ctl->conv_iter = k;
+        return;
+    }
+    if (!(PQ > 0.0) || !isfinite(PQ) || !isfinite(RR)) {
+        ctl->flag = FLAG_BREAK;
+        ctl->conv_iter = k;
+        return;
+    }
+    const double alpha = RR / PQ;
+    const double rho1 = RR - 2.0 * alpha * RQ + alpha * alpha * QQ;
+    ctl->alpha = alpha;
+    ctl->beta = (rho1 > 0.0 && RR > 0.0) ? rho1 / RR : 0.0;
+    ctl->iter = k + 1;
+    if (ctl->mode == 0) {
+        const int kn = k + 1;
+        ctl->check = (kn % ctl->check_every) == 0 || kn >= ctl->max_iter ||
+                     ctl->wratio * rho1 <= kCheckMargin * ctl->tol2;
     }
 }
 
@@ -400,7 +501,7 @@ __device__ inline float lane_next(float v) { return lanes32<lane_next_u32>(v); }
 // the edges of a whole row into a few lines.  Without HALO (the first kernel
 // of a run, whose input no kernel wrote records for) the edge cells are
 // loaded directly.  HALO needs every segment to span at least two lanes.
-template <typename T, int NR, int WPB, int RPW, int V, bool CHECK, bool HALO>
+template <typename T, int NR, int WPB, int RPW, int V, bool HALO>
 __global__ __launch_bounds__(kWave *WPB)
 #if MAS_ITER_WPE > 0
 __attribute__((amdgpu_waves_per_eu(MAS_ITER_WPE, 8)))
@@ -414,12 +515,14 @@ void k_pcg_iter(IterArgs<T> a) {
 
     bool run[NR];
     T alpha[NR], beta[NR];
-    bool any = false;
+    bool any = false, check = false;
 #pragma unroll
     for (int c = 0; c < NR; ++c) {
         const Ctl *ctl = a.ctl + c;
         run[c] = ctl->flag == FLAG_RUN;
         any = any || run[c];
+        // ||W r||^2 is formed when any running right-hand side asks for it
+        check = check || (run[c] && ctl->check);
         alpha[c] = (T)ctl->alpha;
         beta[c] = (T)ctl->beta;
     }
@@ -483,7 +586,6 @@ void k_pcg_iter(IterArgs<T> a) {
     VT pn1[NR], rn1[NR], S1[NR], cr1{};
 #pragma unroll
     for (int c = 0; c < NR; ++c) pn1[c] = rn1[c] = S1[c] = VT{};
-    VecT<double, V> w1{};
     int64_t base1 = 0;
     // results of the previous step, stored only after this step's loads are
     // issued: the in-order vector-memory counter then never makes a load
@@ -526,7 +628,7 @@ void k_pcg_iter(IterArgs<T> a) {
     }
     const auto Rcr = make_rsrc(a.cr, nbytes), Rct = make_rsrc(a.ct, nbytes),
                Rcp = make_rsrc(a.cp, nbytes),
-               Rw = make_rsrc(a.w, (uint32_t)(a.d.n * (int64_t)sizeof(double)));
+               Rw = make_rsrc(a.w, check ? (uint32_t)(a.d.n * (int64_t)sizeof(double)) : 0u);
     constexpr uint32_t ES = sizeof(T);
     const int nsteps = i1 - i0 + 2;
     for (int s = 0; s < nsteps; ++s) {
@@ -569,8 +671,8 @@ void k_pcg_iter(IterArgs<T> a) {
         for (int c = 0; c < NR; ++c) x[c] = bld<T, V, AN>(Rx[c], oo);
         VT ct = bld<T, V>(Rct, oo);
         VT cp = bld<T, V, AN>(Rcp, oo);
-        VecT<double, V> w{};
-        if (CHECK) w = bld<double, V>(Rw, vown ? (uint32_t)(base + col) * 8u : kOOB);
+        // w only on check iterations (otherwise a zero-length resource: zeros, no bytes)
+        const VecT<double, V> w = bld<double, V>(Rw, vown ? (uint32_t)(base + col) * 8u : kOOB);
 #pragma unroll
         for (int c = 0; c < NR; ++c) {
             rE[c] = bld<T, V>(Rr[c], oE);
@@ -631,6 +733,15 @@ void k_pcg_iter(IterArgs<T> a) {
                 pn.v[e] = rn.v[e] + beta[c] * p[c].v[e];
                 xn.v[e] = x[c].v[e] + alpha[c] * p[c].v[e];
                 if (!vin) pn.v[e] = T(0);
+            }
+            // (r_k, r_k) and ||W r_k||^2 over the cells this tile owns
+            if (vown) {
+#pragma unroll
+                for (int e = 0; e < V; ++e) {
+                    const double rd = (double)rn.v[e], t = w.v[e] * rd;
+                    acc[c * kNV + 3] += rd * rd;
+                    acc[c * kNV + 4] += t * t;
+                }
             }
             // ---- in-plane part of q_k(m) plus the visited r neighbour
             VT S{};
@@ -693,11 +804,6 @@ void k_pcg_iter(IterArgs<T> a) {
                     acc[c * kNV + 0] += pd * qd;
                     acc[c * kNV + 1] += rd * qd;
                     acc[c * kNV + 2] += qd * qd;
-                    acc[c * kNV + 3] += rd * rd;
-                    if (CHECK) {
-                        const double t = w1.v[e] * rd;
-                        acc[c * kNV + 4] += t * t;
-                    }
                 }
             }
             // ---- edge record of the previous plane, complete now that q is
@@ -734,7 +840,6 @@ void k_pcg_iter(IterArgs<T> a) {
         m1 = m;
         if constexpr (NR >= MAS_ITER_SYNC_MIN_NR) __syncthreads();
         cr1 = cr;
-        if (CHECK) w1 = w;
         base1 = base;
     }
     if constexpr (kDefer) {
@@ -751,78 +856,21 @@ void k_pcg_iter(IterArgs<T> a) {
     block_sum_store<NR * kNV>(acc, a.partials + (int64_t)L * NR * kNV, sRed);
 }
 
-// One block: fixed-order sum of the iteration partials, then the scalar
-// recurrences and the stopping tests.
-// With several right-hand sides, block c of the launch finalizes right-hand
-// side c (partials [nblk][nrhs][kNV], control blocks ctl[0:nrhs]).
+// One block: the finalize of right-hand side blockIdx.x after an iteration
+// kernel (partials [nblk][gridDim.x][kNV]).  A launch of its own: folding it
+// into the iteration kernel (the last block to finish sums the partials
+// after an agent-scope fence) made that kernel 17% slower on the 52.4M-cell
+// grid, the fence writing back the XCD's L2, and gained nothing on small
+// grids.
 __global__ __launch_bounds__(kRedThreads) void k_finalize(const double *partials, int nblk,
-                                                         Ctl *ctl_all, int is_check) {
+                                                         Ctl *ctl_all) {
     const int c = blockIdx.x, nrhs = gridDim.x;
     Ctl *ctl = ctl_all + c;
     if (ctl->flag != FLAG_RUN) return;
-    __shared__ double sh[kRedThreads * kNV];
-    double v[kNV] = {0.0, 0.0, 0.0, 0.0, 0.0};
-    for (int b = threadIdx.x; b < nblk; b += kRedThreads) {
-#pragma unroll
-        for (int t = 0; t < kNV; ++t) v[t] += partials[((int64_t)b * nrhs + c) * kNV + t];
-    }
-#pragma unroll
-    for (int t = 0; t < kNV; ++t) sh[threadIdx.x * kNV + t] = v[t];
-    __syncthreads();
-    for (int s = kRedThreads / 2; s > 0; s >>= 1) {
-        if ((int)threadIdx.x < s) {
-#pragma unroll
-            for (int t = 0; t < kNV; ++t) sh[threadIdx.x * kNV + t] += sh[(threadIdx.x + s) * kNV + t];
-        }
-        __syncthreads();
-    }
-    if (threadIdx.x != 0) return;
-    const double PQ = sh[0], RQ = sh[1], QQ = sh[2], RR = sh[3], RW = sh[4];
-    const int k = ctl->iter;
-    ctl->pq = PQ;
-    ctl->rq = RQ;
-    ctl->qq = QQ;
-    bool conv = false;
-    if (ctl->mode == 0) {
-        if (is_check) {
-            ctl->rw = RW;
-            conv = RW <= ctl->tol2;
-        }
-    } else {
-        conv = RR <= ctl->tol2;
-    }
-    ctl->rr = RR;
-    // an exactly zero scaled residual is an exact solution (W r = 0 as well)
-    if (RR == 0.0) conv = true;
-    // alpha_k and the predicted (r_{k+1}, r_{k+1}) are recorded even when
-    // stopping: a refinement step that keeps the search direction folds the
-    // pending alpha_k p_k into the solution and compares the replaced
-    // residual with the prediction
-    {
-        const double al = (PQ > 0.0 && isfinite(PQ)) ? RR / PQ : 0.0;
-        ctl->alpha = al;
-        ctl->rr_next = RR - 2.0 * al * RQ + al * al * QQ;
-    }
-    if (conv) {
-        ctl->flag = FLAG_CONV;
-        ctl->conv_iter = k;
-        return;
-    }
-    if (k >= ctl->max_iter) {
-        ctl->flag = FLAG_MAXIT;
-        ctl->conv_iter = k;
-        return;
-    }
-    if (!(PQ > 0.0) || !isfinite(PQ) || !isfinite(RR)) {
-        ctl->flag = FLAG_BREAK;
-        ctl->conv_iter = k;
-        return;
-    }
-    const double alpha = RR / PQ;
-    const double rho1 = RR - 2.0 * alpha * RQ + alpha * alpha * QQ;
-    ctl->alpha = alpha;
-    ctl->beta = (rho1 > 0.0 && RR > 0.0) ? rho1 / RR : 0.0;
-    ctl->iter = k + 1;
+    __shared__ double lds[(kRedThreads / kWave) * kNV];
+    double S[kNV];
+    sum_partials<kRedThreads>(partials, nblk, nrhs, c, S, lds);
+    if (threadIdx.x == 0) pcg_finalize(ctl, S);
 }
 
 // Generic fixed-order sum of [nblk][nv] partials into ctl->sums[0:nv].
@@ -847,19 +895,25 @@ __global__ __launch_bounds__(kRedThreads) void k_reduce(const double *partials, 
 // is safe inside captured graphs as well).
 // flag0 = FLAG_RUN starts the run; another flag leaves this control block
 // (one right-hand side of several) stopped from the start.
+// check0: the first iteration kernel of the run forms ||W r||^2 (in mode 0
+// its ratio to (r, r) starts the prediction of the check); then every
+// check_every-th and those near the threshold (pcg_finalize).
 __global__ void k_ctl_init(Ctl *ctl, int mode, int iter0, int max_iter, double tol2,
-                           double beta0, int flag0) {
+                           double beta0, int flag0, int check0, int check_every) {
     if (threadIdx.x != 0) return;
     ctl->alpha = 0.0;
     ctl->beta = beta0;
     ctl->rr = 0.0;
     ctl->rw = 0.0;
     ctl->tol2 = tol2;
+    ctl->wratio = 0.0;
     ctl->flag = flag0;
     ctl->iter = iter0;
     ctl->max_iter = max_iter;
     ctl->mode = mode;
     ctl->conv_iter = -1;
+    ctl->check = check0;
+    ctl->check_every = check_every > 0 ? check_every : 1;
 }
 
 // ---------------------------------------------------------------- simple stencil tiles

@@ -65,6 +65,14 @@ static int fail(int status, const char *fmt, ...) {
 static constexpr int kTJ = MAS_TJ;   // waves per block
 static constexpr int kRPW = MAS_RPW; // theta rows per wave
 static constexpr int kTI = MAS_TI;
+#ifndef MAS_MIN_BLOCKS
+#define MAS_MIN_BLOCKS 1024
+#endif
+#ifndef MAS_SMALL_TI
+#define MAS_SMALL_TI 1
+#endif
+static constexpr int64_t kMinBlocks = MAS_MIN_BLOCKS;
+static constexpr int kSmallTI = MAS_SMALL_TI;
 
 #ifndef MAS_ITER_VEC
 #define MAS_ITER_VEC 16  // bytes per lane, double-precision iteration kernel
@@ -140,10 +148,24 @@ struct Shape {
     // them, so with 8 chunks (or a multiple) every XCD owns whole r slabs
     // and only the planes at slab boundaries are read by two XCDs (256 x 320
     // x 640 cells: 32-plane chunks, 1.4% faster than 16).  At least kTI
-    // planes.
-    int ti() const { return std::max(kTI, (nr + 7) / 8); }
-    int tiles_i() const { return (nr + ti() - 1) / ti(); }
-    int64_t nblk_iter(int v) const { return (int64_t)tiles_k(v) * tiles_j() * tiles_i(); }
+    // planes, unless that leaves fewer than kMinBlocks blocks: a small grid
+    // is latency-bound (each wave's plane steps run one after another), so
+    // its chunks shrink, down to kSmallTI planes, until about kMinBlocks
+    // blocks share the work.
+    int ti(int v, int forced = 0) const {
+        if (forced > 0) return forced;
+        const int big = std::max(kTI, (nr + 7) / 8);
+        const int64_t tiles = (int64_t)tiles_k(v) * tiles_j();
+        if (tiles * ((nr + big - 1) / big) >= kMinBlocks) return big;
+        const int64_t want = (tiles * nr + kMinBlocks - 1) / kMinBlocks;
+        return (int)std::min<int64_t>(big, std::max<int64_t>(kSmallTI, want));
+    }
+    int tiles_i(int v, int forced = 0) const { return (nr + ti(v, forced) - 1) / ti(v, forced); }
+    int64_t nblk_iter(int v, int forced = 0) const {
+        return (int64_t)tiles_k(v) * tiles_j() * tiles_i(v, forced);
+    }
+    // most blocks any launch of the iteration kernel can have (one-plane chunks)
+    int64_t nblk_iter_max() const { return nblk_iter(1, 1); }
     // bytes of one segment-edge record buffer of the iteration kernel, and
     // whether the records can be used (every segment spans two lanes, 32-bit
     // offsets)
@@ -287,6 +309,7 @@ extern "C" void mas_pcg_default_opts(mas_pcg_opts *o) {
     o->sample_timing = 0;
     o->refine = MAS_REFINE_RELIABLE;
     o->precond = MAS_PC1;
+    o->chunk_planes = 0;
 }
 
 extern "C" int64_t mas_op_storage_bytes(const mas_grid *g, int32_t precision) {
@@ -424,7 +447,7 @@ static WorkLayout work_layout(const Shape &s, int precision, int nrhs = 1) {
     auto take_array = [&](int64_t bytes) { return cur.take_array(bytes); };
     // the iteration kernel writes nrhs * kNV partials per block (most blocks
     // with V = 1), the simple-tile kernels up to kSimpleNV
-    const int64_t nparts = std::max(s.nblk_iter(1) * kNV * nrhs, s.nblk_simple() * kSimpleNV);
+    const int64_t nparts = std::max(s.nblk_iter_max() * kNV * nrhs, s.nblk_simple() * kSimpleNV);
     L.ctl = take(sizeof(Ctl) * nrhs);
     L.partials = take(8 * nparts);
     const int64_t es = (precision == MAS_FP32_REFINED) ? 4 : 8;
@@ -465,6 +488,7 @@ static int check_opts(const mas_op *op, const mas_pcg_opts *o) {
             return fail(MAS_EINVAL, "unknown refinement strategy %d", o->refine);
     }
     if (o->max_restarts < 0) return fail(MAS_EINVAL, "max_restarts must be >= 0");
+    if (o->chunk_planes < 0) return fail(MAS_EINVAL, "chunk_planes must be >= 0");
     if (o->precond != MAS_PC1 && o->precond != MAS_PC2)
         return fail(MAS_EINVAL, "unknown preconditioner %d", o->precond);
     return MAS_OK;
@@ -512,6 +536,7 @@ struct Ctx {
     double *partials;
     bool timing;
     bool no_alloc = false;  // allocation-free entry point: no pinned buffer, no events
+    int chunk = 0;          // r planes per chunk of the iteration kernel (0: automatic)
     // event samples of the iteration kernel
     std::vector<hipEvent_t> ev;
     std::vector<int> ev_iter;
@@ -649,7 +674,8 @@ static int run_pcg(Ctx &cx, const RhsSet<T> &v, const T *const c[3], int mode, i
     int max_iter = iter0;
     for (int h = 0; h < NR; ++h) {
         hipLaunchKernelGGL(k_ctl_init, dim3(1), dim3(64), 0, st, cx.ctl + h, mode, iter0,
-                           v.max_iter[h], v.tol2[h], beta0, v.active[h] ? FLAG_RUN : FLAG_CONV);
+                           v.max_iter[h], v.tol2[h], beta0, v.active[h] ? FLAG_RUN : FLAG_CONV,
+                           mode == 0 ? 1 : 0, check_every);
         if (v.active[h]) max_iter = std::max(max_iter, v.max_iter[h]);
     }
     LAUNCHCHK();
@@ -666,11 +692,11 @@ static int run_pcg(Ctx &cx, const RhsSet<T> &v, const T *const c[3], int mode, i
     a.ctl = cx.ctl;
     a.d = s.dims();
     const int V = iter_vec<T>(s.np, NR);
-    a.tiles_i = s.tiles_i();
+    a.tiles_i = s.tiles_i(V, cx.chunk);
     a.tiles_k = s.tiles_k(V);
     a.tiles_j = s.tiles_j();
-    a.ti = s.ti();
-    a.nblk = (int)s.nblk_iter(V);
+    a.ti = s.ti(V, cx.chunk);
+    a.nblk = (int)s.nblk_iter(V, cx.chunk);
     for (int h = 0; h < NR; ++h) a.x[h] = v.x[h];
     a.halo_bytes = v.halo_bytes;
     const bool use_halo = v.halo_bytes > 0;
@@ -700,7 +726,6 @@ static int run_pcg(Ctx &cx, const RhsSet<T> &v, const T *const c[3], int mode, i
             // the first kernel of a run reads its edge cells directly (no
             // kernel wrote records for its input); later ones read records
             const bool halo = use_halo && k != iter0;
-            const bool chk = (mode == 0) && ((k % check_every) == 0 || k == max_iter);
             const bool sample = cx.timing && (k % 16 == 7) && cx.ev.size() < 128;
             if (sample) {
                 hipEvent_t e0, e1;
@@ -712,25 +737,22 @@ static int run_pcg(Ctx &cx, const RhsSet<T> &v, const T *const c[3], int mode, i
                 HIPCHK(hipEventRecord(e0, st));
             }
             constexpr int VW = vec_full<T>();
-            auto go = [&](auto vw, auto ck, auto hl) {
+            auto go = [&](auto vw, auto hl) {
                 hipLaunchKernelGGL((k_pcg_iter<T, NR, kTJ, kRPW, decltype(vw)::value,
-                                               decltype(ck)::value, decltype(hl)::value>),
+                                               decltype(hl)::value>),
                                    grid, block, 0, st, a);
             };
             using F = std::false_type;
             using Tr = std::true_type;
             using IW = std::integral_constant<int, VW>;
             using I1 = std::integral_constant<int, 1>;
-            if (V == VW) {
-                if (chk) halo ? go(IW{}, Tr{}, Tr{}) : go(IW{}, Tr{}, F{});
-                else halo ? go(IW{}, F{}, Tr{}) : go(IW{}, F{}, F{});
-            } else {
-                if (chk) halo ? go(I1{}, Tr{}, Tr{}) : go(I1{}, Tr{}, F{});
-                else halo ? go(I1{}, F{}, Tr{}) : go(I1{}, F{}, F{});
-            }
+            if (V == VW)
+                halo ? go(IW{}, Tr{}) : go(IW{}, F{});
+            else
+                halo ? go(I1{}, Tr{}) : go(I1{}, F{});
             if (sample) HIPCHK(hipEventRecord(cx.ev.back(), st));
             hipLaunchKernelGGL(k_finalize, dim3(NR), dim3(kRedThreads), 0, st, cx.partials, a.nblk,
-                               cx.ctl, chk ? 1 : 0);
+                               cx.ctl);
         }
         LAUNCHCHK();
         e = poll.after_batch(NR, &stop);
@@ -819,7 +841,7 @@ static int run_pcg_pc2(Ctx &cx, T *r, T *z, T *const p[2], T *q, T *d, T *x, int
         for (int t = 0; t < 3; ++t) cc[t] = op->c64[t];
     }
     hipLaunchKernelGGL(k_ctl_init, dim3(1), dim3(64), 0, st, cx.ctl, 0, iter0, max_iter, tol2, 0.0,
-                       (int)FLAG_RUN);
+                       (int)FLAG_RUN, 0, 1);
     Pc2Args<T> a{cc[0], cc[1], cc[2], op->w, d, r, x, z, q, nullptr, cx.partials,
                  cx.ctl, s.dims(), nbi, nbj, nbk, 0};
     // z = M^-1 r of the initial residual, (r, z), the stopping test
@@ -840,11 +862,11 @@ static int run_pcg_pc2(Ctx &cx, T *r, T *z, T *const p[2], T *q, T *d, T *x, int
     it.ctl = cx.ctl;
     it.d = s.dims();
     const int V = iter_vec<T>(s.np, 1);
-    it.tiles_i = s.tiles_i();
+    it.tiles_i = s.tiles_i(V, cx.chunk);
     it.tiles_k = s.tiles_k(V);
     it.tiles_j = s.tiles_j();
-    it.ti = s.ti();
-    it.nblk = (int)s.nblk_iter(V);
+    it.ti = s.ti(V, cx.chunk);
+    it.nblk = (int)s.nblk_iter(V, cx.chunk);
     it.halo_bytes = 0;
     constexpr int VW = vec_full<T>();
     const dim3 igrid((unsigned)it.nblk), iblock(kWave * kTJ);
@@ -872,10 +894,10 @@ static int run_pcg_pc2(Ctx &cx, T *r, T *z, T *const p[2], T *q, T *d, T *x, int
             it.p_out[0] = p_new;
             it.q_out[0] = q;
             if (V == VW)
-                hipLaunchKernelGGL((k_pcg_iter<T, 1, kTJ, kRPW, VW, false, false>), igrid, iblock,
+                hipLaunchKernelGGL((k_pcg_iter<T, 1, kTJ, kRPW, VW, false>), igrid, iblock,
                                    0, st, it);
             else
-                hipLaunchKernelGGL((k_pcg_iter<T, 1, kTJ, kRPW, 1, false, false>), igrid, iblock,
+                hipLaunchKernelGGL((k_pcg_iter<T, 1, kTJ, kRPW, 1, false>), igrid, iblock,
                                    0, st, it);
             hipLaunchKernelGGL(k_pc2_fin_a, dim3(1), dim3(kRedThreads), 0, st, cx.partials, it.nblk,
                                (int)kNV, cx.ctl);
@@ -918,7 +940,7 @@ static int run_pcg_pc2_multi(Ctx &cx, double *const r[NR], double *const z[NR],
     for (int h = 0; h < NR; ++h)
         hipLaunchKernelGGL(k_ctl_init, dim3(1), dim3(64), 0, st, cx.ctl + h, 0, iter0,
                            active[h] ? max_iter[h] : iter0, tol2[h], 0.0,
-                           (int)(active[h] ? FLAG_RUN : FLAG_CONV));
+                           (int)(active[h] ? FLAG_RUN : FLAG_CONV), 0, 1);
     // the block solves of all right-hand sides in one launch (couplings, w
     // and d read once); right-hand side h's partials at partials + 2 h nb
     Pc2MultiArgs<NR> a{};
@@ -963,11 +985,11 @@ static int run_pcg_pc2_multi(Ctx &cx, double *const r[NR], double *const z[NR],
     it.ctl = cx.ctl;
     it.d = s.dims();
     const int V = iter_vec<double>(s.np, NR);
-    it.tiles_i = s.tiles_i();
+    it.tiles_i = s.tiles_i(V, cx.chunk);
     it.tiles_k = s.tiles_k(V);
     it.tiles_j = s.tiles_j();
-    it.ti = s.ti();
-    it.nblk = (int)s.nblk_iter(V);
+    it.ti = s.ti(V, cx.chunk);
+    it.nblk = (int)s.nblk_iter(V, cx.chunk);
     it.halo_bytes = 0;
     constexpr int VW = vec_full<double>();
     const dim3 igrid((unsigned)it.nblk), iblock(kWave * kTJ);
@@ -997,10 +1019,10 @@ static int run_pcg_pc2_multi(Ctx &cx, double *const r[NR], double *const z[NR],
                 it.q_out[h] = q[h];
             }
             if (V == VW)
-                hipLaunchKernelGGL((k_pcg_iter<double, NR, kTJ, kRPW, VW, false, false>), igrid, iblock,
+                hipLaunchKernelGGL((k_pcg_iter<double, NR, kTJ, kRPW, VW, false>), igrid, iblock,
                                    0, st, it);
             else
-                hipLaunchKernelGGL((k_pcg_iter<double, NR, kTJ, kRPW, 1, false, false>), igrid, iblock,
+                hipLaunchKernelGGL((k_pcg_iter<double, NR, kTJ, kRPW, 1, false>), igrid, iblock,
                                    0, st, it);
             for (int h = 0; h < NR; ++h)
                 hipLaunchKernelGGL(k_pc2_fin_a, dim3(1), dim3(kRedThreads), 0, st,
@@ -1057,7 +1079,7 @@ static int solve_core(const mas_op *op, const double *src, int src_is_rhs, doubl
         return fail(MAS_ENOMEM, "workspace too small: %lld < %lld bytes", (long long)work_bytes,
                     (long long)L.total);
 
-    if (std::max(s.nblk_iter(1) * kNV, s.nblk_simple() * kSimpleNV) * 8 >
+    if (std::max(s.nblk_iter_max() * kNV, s.nblk_simple() * kSimpleNV) * 8 >
         L.bhat[0] - L.partials)
         return fail(MAS_EINVAL, "internal: partial-sum area too small");
     char *base = static_cast<char *>(work);
@@ -1069,6 +1091,7 @@ static int solve_core(const mas_op *op, const double *src, int src_is_rhs, doubl
     double *bhat = reinterpret_cast<double *>(base + L.bhat[0]);
     cx.timing = o.sample_timing != 0;
     cx.no_alloc = no_alloc;
+    cx.chunk = o.chunk_planes;
     const Dims d = s.dims();
     const dim3 sgrid = s.simple_grid(), sblock(kWave, kSimpleJ);
 
@@ -1323,7 +1346,7 @@ static int solve_core(const mas_op *op, const double *src, int src_is_rhs, doubl
             } else {
                 // classical refinement: x^ += d^; the next inner solve restarts
                 hipLaunchKernelGGL(k_ctl_init, dim3(1), dim3(64), 0, cx.stream, cx.ctl, 1, 0, 0,
-                                   0.0, 0.0, (int)FLAG_RUN);  // alpha = 0 for the fold
+                                   0.0, 0.0, (int)FLAG_RUN, 0, 1);  // alpha = 0 for the fold
                 hipLaunchKernelGGL(k_refine_fold, sgrid, sblock, 0, cx.stream, dh, p[nxt], cx.ctl,
                                    d, x);
                 LAUNCHCHK();
@@ -1370,6 +1393,7 @@ static int solve_multi_core(const mas_op *op, const double *rhs, double *x, cons
     cx.ctl = reinterpret_cast<Ctl *>(base + L.ctl);
     cx.partials = reinterpret_cast<double *>(base + L.partials);
     cx.timing = o.sample_timing != 0;
+    cx.chunk = o.chunk_planes;
     const Dims d = s.dims();
     const dim3 sgrid = s.simple_grid(), sblock(kWave, kSimpleJ);
     const double *const c[3] = {op->c64[0], op->c64[1], op->c64[2]};

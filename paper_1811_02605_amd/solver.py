@@ -63,7 +63,7 @@ PRECONDS = {"pc1": abi.MAS_PC1, "pc2": abi.MAS_PC2}
 
 def make_opts(rtol=None, max_iters=None, precision=None, inner_rtol=None, max_outer=None,
               check_every=None, use_x0=None, max_restarts=None, sample_timing=None, refine=None,
-              precond=None):
+              precond=None, chunk_planes=None):
     o = abi.default_opts()
     if isinstance(precision, str):
         precision = PRECISIONS[precision]
@@ -74,7 +74,8 @@ def make_opts(rtol=None, max_iters=None, precision=None, inner_rtol=None, max_ou
     for name, v in dict(rtol=rtol, max_iters=max_iters, precision=precision,
                         inner_rtol=inner_rtol, max_outer=max_outer, check_every=check_every,
                         use_x0=use_x0, max_restarts=max_restarts,
-                        sample_timing=sample_timing, refine=refine, precond=precond).items():
+                        sample_timing=sample_timing, refine=refine, precond=precond,
+                        chunk_planes=chunk_planes).items():
         if v is not None:
             setattr(o, name, type(getattr(o, name))(v))
     return o

@@ -54,3 +54,18 @@ def rel(a, b):
     b = np.asarray(b).reshape(-1)
     nb = np.linalg.norm(b)
     return float(np.linalg.norm(a - b) / (nb if nb > 0 else 1.0))
+
+
+def residual_rounding_floor(ora, b, x) -> float:
+    """How far two correct evaluations of ||b - A x||/||b|| may differ by
+    rounding alone.  Each side forms every component of b - A x from about
+    ten products and sums (and the GPU's x passes through the symmetric
+    scaling once more), so the computed residual vectors differ by at most
+    c eps (|b| + |A||x|) componentwise with c about 10; in norm the reported
+    values differ by at most 16 eps (||b|| + || |A||x| ||)/||b||.  A has a
+    positive diagonal D and non-positive off-diagonal entries, so
+    |A||x| = 2 D|x| - A|x|."""
+    ax = np.abs(np.asarray(x, dtype=np.float64).reshape(ora.shape))
+    abs_ax = 2.0 * ora.diag * ax - ora.apply(ax)
+    nb = np.linalg.norm(np.asarray(b).reshape(-1))
+    return 16.0 * np.finfo(np.float64).eps * (nb + np.linalg.norm(abs_ax.reshape(-1))) / nb

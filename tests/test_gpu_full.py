@@ -68,6 +68,11 @@ def test_c1_fp64_and_refined_solves_full(c1, c1_oracle):
     say(f"c1 oracle residuals: fp64 {r64:.3e} ({i64['iters']} it), refined {rmp:.3e} "
         f"({imp['iters']} inner, {imp['outer_iters']} outer), restarted {rr:.3e} ({ir['iters']} inner)")
     assert r64 <= 1e-10 and rmp <= 1e-10 and rr <= 1e-10
+    # the FP64 run stops where the oracle's PCG meets the same tolerance (the
+    # crossing can move by one iteration with the summation order)
+    it_10 = c1_oracle.pcg(b, tol=1e-10)[1]
+    say(f"c1 iterations to 1e-10: gpu {i64['iters']}, oracle {it_10}")
+    assert abs(i64["iters"] - it_10) <= 1
     # the FP64 oracle's own solution, to 1e-12
     xo, it_o, _, res_o = c1_oracle.pcg(b, tol=1e-12)
     e64, emp, er = rel(x64, xo), rel(xmp, xo), rel(xr, xo)

@@ -29,14 +29,18 @@ def _rhs(p, m):
     return W.component_rhs(p.cfg, m)
 
 
+# 0: the automatic r-chunk length (short chunks on these small grids); 16:
+# the chunk length of grids large enough to fill the GPU
+@pytest.mark.parametrize("chunk", [0, 16])
 @pytest.mark.parametrize("m", [2, 3, 4])
 @pytest.mark.parametrize("shape", SHAPES + ["c0"])
-def test_components_match_oracle(shape, m):
+def test_components_match_oracle(shape, m, chunk):
     p = problem(shape, (0, 1))
     _, op = gpu_operator(p)
     ora = oracle_operator(p)
     B = _rhs(p, m)
-    X, infos = op.solve_multi(to_dev(B), S.make_opts(rtol=1e-10), allow_notconv=False)
+    X, infos = op.solve_multi(to_dev(B), S.make_opts(rtol=1e-10, chunk_planes=chunk),
+                              allow_notconv=False)
     X = to_host(X)
     for h in range(m):
         b = ora.rhs_to_b(B[h])
@@ -46,17 +50,19 @@ def test_components_match_oracle(shape, m):
         assert rel(X[h], xo) <= 1e-6
 
 
+@pytest.mark.parametrize("chunk", [0, 16])
 @pytest.mark.parametrize("m", [1, 3])
 @pytest.mark.parametrize("shape", [(33, 17, 129), (9, 16, 32), "c0"])
-def test_components_match_single_solves(shape, m):
+def test_components_match_single_solves(shape, m, chunk):
     """The per-component iterations are those of the single solve: same
     iteration counts, solutions equal to rounding."""
     p = problem(shape, (0, 0))
     _, op = gpu_operator(p)
     B = _rhs(p, m)
-    X, infos = op.solve_multi(to_dev(B), S.make_opts(rtol=1e-10), allow_notconv=False)
+    o = S.make_opts(rtol=1e-10, chunk_planes=chunk)
+    X, infos = op.solve_multi(to_dev(B), o, allow_notconv=False)
     for h in range(m):
-        x1, i1 = op.solve(to_dev(B[h]), S.make_opts(rtol=1e-10), allow_notconv=False)
+        x1, i1 = op.solve(to_dev(B[h]), o, allow_notconv=False)
         assert infos[h]["iters"] == i1["iters"], (h, infos[h], i1)
         assert rel(to_host(X[h]), to_host(x1)) <= 1e-13
         say(f"{shape} m={m} h={h}: {i1['iters']} iterations, bitwise equal: "

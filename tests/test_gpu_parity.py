@@ -8,7 +8,7 @@ import pytest
 import torch
 
 from gpu_util import (DEV, gpu_operator, oracle_operator, oracle_plus_face_arrays, problem, rel,
-                      to_dev, to_host)
+                      residual_rounding_floor, to_dev, to_host)
 from oracle import dense
 from paper_1811_02605_amd import _abi as abi
 from paper_1811_02605_amd import solver as S
@@ -53,19 +53,29 @@ def test_apply_matches_oracle(shape, precision):
     assert rel(y, ora.apply(x)) <= 1e-13
 
 
+# r planes per chunk of the iteration kernel: 0 is the automatic choice
+# (short chunks on these small grids, which cannot fill the GPU otherwise),
+# 16 and 18 the chunk lengths of grids large enough to fill it
+CHUNKS = [0, 16]
+
+
+@pytest.mark.parametrize("chunk", CHUNKS)
 @pytest.mark.parametrize("shape", SHAPES + ["c0"])
 @pytest.mark.parametrize("bc", [(0, 0), (1, 1)])
-def test_fp64_solve_matches_oracle(shape, bc):
+def test_fp64_solve_matches_oracle(shape, bc, chunk):
     p = problem(shape, bc)
     _, op = gpu_operator(p)
     ora = oracle_operator(p)
-    x, info = op.solve(to_dev(p.rhs), S.make_opts(rtol=1e-10), allow_notconv=False)
+    x, info = op.solve(to_dev(p.rhs), S.make_opts(rtol=1e-10, chunk_planes=chunk),
+                       allow_notconv=False)
     x = to_host(x)
     b = ora.rhs_to_b(p.rhs)
     res = ora.rel_residual(b, x)
     assert res <= 1e-10, res
     assert info["rel_resid_true"] <= 1e-10
-    assert abs(info["rel_resid_true"] - res) <= 1e-3 * res + 1e-13
+    # the reported residual is the oracle's up to the rounding of b - A x
+    floor = residual_rounding_floor(ora, b, x)
+    assert abs(info["rel_resid_true"] - res) <= floor, (info["rel_resid_true"], res, floor)
     xo, it_o, _, _ = ora.pcg(b, tol=1e-13)
     err = rel(x, xo)
     print(f"{shape} bc={bc}: iters gpu {info['iters']} oracle(1e-13) {it_o}; "
@@ -73,38 +83,52 @@ def test_fp64_solve_matches_oracle(shape, bc):
     assert err <= 1e-6
 
 
-def test_iteration_count_tracks_oracle_at_small_config():
-    p = problem("c0")
+@pytest.mark.parametrize("check_every", [1, 8, 64])
+@pytest.mark.parametrize("shape", ["c0", (33, 17, 129), (65, 8, 64), (9, 16, 32)])
+def test_iteration_count_tracks_oracle(shape, check_every):
+    """The run stops at the first iteration whose ||b - A x_k|| meets the
+    tolerance, as the oracle's does: the residual norm is formed on the
+    periodic check iterations and on every iteration once its value,
+    predicted from (r, r), is near the threshold."""
+    p = problem(shape)
     _, op = gpu_operator(p)
     ora = oracle_operator(p)
-    x, info = op.solve(to_dev(p.rhs), S.make_opts(rtol=1e-10, check_every=1), allow_notconv=False)
+    x, info = op.solve(to_dev(p.rhs), S.make_opts(rtol=1e-10, check_every=check_every),
+                       allow_notconv=False)
     _, it_o, _, _ = ora.pcg(ora.rhs_to_b(p.rhs), tol=1e-10)
-    assert abs(info["iters"] - it_o) <= max(2, 0.03 * it_o), (info["iters"], it_o)
+    print(f"{shape} check_every={check_every}: gpu {info['iters']} oracle {it_o}")
+    # the two sum their dot products in different orders (R17): the crossing
+    # can move by an iteration
+    assert abs(info["iters"] - it_o) <= 1, (info["iters"], it_o)
 
 
+@pytest.mark.parametrize("chunk", CHUNKS + [1, 5])
 @pytest.mark.parametrize("k", [0, 1, 2, 5, 20])
 @pytest.mark.parametrize("shape", [(5, 7, 13), (33, 17, 129), "c0"])
-def test_iterates_match_oracle(shape, k):
+def test_iterates_match_oracle(shape, k, chunk):
     # the GPU's scaled single-reduction recurrence and the oracle's classical
     # PCG produce the same iterates in exact arithmetic
     p = problem(shape)
     _, op = gpu_operator(p)
     ora = oracle_operator(p)
-    x, info = op.solve(to_dev(p.rhs), S.make_opts(rtol=0.0, max_iters=k, check_every=1))
+    x, info = op.solve(to_dev(p.rhs), S.make_opts(rtol=0.0, max_iters=k, check_every=1,
+                                                  chunk_planes=chunk))
     assert info["status"] == abi.MAS_ENOTCONV and info["iters"] == k
     xo = ora.pcg(ora.rhs_to_b(p.rhs), tol=0.0, max_iters=k)[0]
     e = rel(to_host(x), xo)
     assert e <= 1e-11 * max(1, k), e
 
 
+@pytest.mark.parametrize("chunk", CHUNKS)
 @pytest.mark.parametrize("refine", ["reliable", "restart"])
 @pytest.mark.parametrize("shape", [(5, 7, 13), (33, 17, 129), (1, 3, 2), (9, 16, 32), "c0"])
-def test_mixed_precision_reaches_fp64_residual(shape, refine):
+def test_mixed_precision_reaches_fp64_residual(shape, refine, chunk):
     p = problem(shape)
     _, op = gpu_operator(p, "fp32_refined")
     ora = oracle_operator(p)
     x, info = op.solve(to_dev(p.rhs), S.make_opts(rtol=1e-10, precision="fp32_refined",
-                                                  refine=refine), allow_notconv=False)
+                                                  refine=refine, chunk_planes=chunk),
+                       allow_notconv=False)
     x = to_host(x)
     b = ora.rhs_to_b(p.rhs)
     res = ora.rel_residual(b, x)
@@ -112,7 +136,8 @@ def test_mixed_precision_reaches_fp64_residual(shape, refine):
     print(f"{shape} refined/{refine}: outer {info['outer_iters']} inner {info['iters']} "
           f"(oracle FP64 at 1e-13: {it_o}) residual {res:.2e} error vs FP64 oracle {rel(x, xo):.2e}")
     assert res <= 1e-10 and info["rel_resid_true"] <= 1e-10
-    assert abs(info["rel_resid_true"] - res) <= 1e-3 * res + 1e-13
+    floor = residual_rounding_floor(ora, b, x)
+    assert abs(info["rel_resid_true"] - res) <= floor, (info["rel_resid_true"], res, floor)
     assert info["outer_iters"] >= 1
     assert rel(x, xo) <= 1e-6
 

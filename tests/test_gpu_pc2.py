@@ -37,20 +37,23 @@ def test_pc2_solve_matches_oracle(shape, bc):
     xo, it_o, _, _ = ora.pcg_pc2(b, BLOCKS, tol=1e-10)
     say(f"{shape} bc={bc}: gpu {info['iters']} it, oracle {it_o} it, residual {res:.2e}")
     assert res <= 1e-10
-    assert abs(info["iters"] - it_o) <= max(2, it_o // 20)
+    # both test the residual at every iteration; only the summation order of
+    # the dot products differs (R17), which can move the crossing by one
+    assert abs(info["iters"] - it_o) <= 1
     xt = ora.pcg_pc2(b, BLOCKS, tol=1e-13)[0]
     assert rel(x, xt) <= 1e-6
 
 
+@pytest.mark.parametrize("chunk", [0, 16])
 @pytest.mark.parametrize("shape", [(9, 17, 33), (17, 9, 70), "c0"])
-def test_pc2_iterates_match_oracle(shape):
+def test_pc2_iterates_match_oracle(shape, chunk):
     p = problem(shape, (0, 0))
     _, op = gpu_operator(p)
     ora = oracle_operator(p)
     b = ora.rhs_to_b(p.rhs)
     rhs = to_dev(p.rhs)
     for k in (1, 2, 5, 10):
-        o = S.make_opts(rtol=0.0, max_iters=k, max_restarts=0, precond="pc2")
+        o = S.make_opts(rtol=0.0, max_iters=k, max_restarts=0, precond="pc2", chunk_planes=chunk)
         x, info = op.solve(rhs, o)
         assert info["iters"] == k
         xo = ora.pcg_pc2(b, BLOCKS, tol=0.0, max_iters=k)[0]

@@ -9,12 +9,14 @@ before the timed region.
 
 One step = build the operator from (nu, dt) + one full FP64 PCG solve to the
 tolerance.  `value` is PCG iterations per second of wall time over the K
-timed steps.  Alongside, the same grid and data are solved with the
-single-precision inner PCG inside double-precision refinement and both
-times-to-1e-10 are reported; the same solve with the paper's second
-preconditioner (block-Jacobi ILU(0)) is timed; three components under the
-same operator are solved together; and one explicit RKL2 super time-step of
-the same dt (the paper's faster GPU choice for the viscous term) is timed.
+timed steps.  Alongside, on the same grid and data: the operator build on
+its own; the single-precision inner PCG inside double-precision refinement
+(both strategies); the adjoint; the paper's second preconditioner
+(block-Jacobi ILU(0)) in FP64 and inside refinement; three components under
+the same operator; one explicit RKL2 super time-step of the same dt.  Then
+the 65,536-cell grid (latency-bound iterations/s), the 96M-cell stress case
+(refined forward solves and the adjoint), streaming probes with the kernels'
+byte mixes, and the FP64 CPU oracle on the host cores.
 
 The dominant kernel is the fused PCG iteration kernel; its duration is
 sampled with HIP events on the solver's stream (inside the library) and
@@ -22,6 +24,7 @@ converted to algorithmic HBM bytes per second.
 
     python bench.py [--steps K] [--warmup W] [--gpus 1] [--workload c1]
                     [--no-cpu-baseline] [--no-refined] [--no-sts] [--no-multi] [--no-pc2]
+                    [--no-adjoint] [--no-c0] [--no-c4] [--no-probe]
 """
 from __future__ import annotations
 
@@ -77,24 +80,171 @@ def read_traffic(path=TRAFFIC_FILE, srcs=(KERNEL_SRC,)):
     return float(m_bytes.group(1))
 
 
-def cpu_baseline(p, max_iters=400):
-    """The FP64 CPU oracle, as it stands, on the same workload: assemble, then
-    its Jacobi-PCG from x0 = 0 to the same 1e-10 tolerance (bounded at
-    max_iters iterations); PCG iterations per second of its solve."""
+def _cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(p, x_gpu=None, budget_iters=400, single_iters=12):
+    """The FP64 CPU oracle, as it stands, built -O3 -march=native on this
+    host, on the same workload: assemble, then its Jacobi-PCG from x0 = 0 to
+    the same 1e-10 tolerance (bounded at budget_iters iterations); PCG
+    iterations per second on all the host threads OpenMP uses and on one.
+    Also full solves of the 65,536-cell grid and the 9.4M-cell gradient-check
+    grid's forward system, and (x_gpu) the oracle's residual of the GPU
+    solutions on the benchmark grid."""
     import oracle
-    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    from paper_1811_02605_amd import workloads as W
+
+    oracle.use_native_build()
+    threads = oracle.max_threads()
+    out = {"unit": "PCG iters/s", "cores": threads, "kind": "oracle",
+           "build": "gcc " + " ".join(oracle.NATIVE_FLAGS) + " -fopenmp",
+           "cpu_model": _cpu_model(), "nproc": len(os.sched_getaffinity(0)),
+           "omp_threads": threads}
     t0 = time.perf_counter()
     ora = oracle.Operator(p.r_faces, p.t_faces, p.cfg.np_, p.nu, p.dt)
     b = ora.rhs_to_b(p.rhs)
     t1 = time.perf_counter()
-    _, iters, rel_rec, rel_true = ora.pcg(b, tol=p.cfg.rtol, max_iters=max_iters)
+    _, iters, _, rel_true = ora.pcg(b, tol=p.cfg.rtol, max_iters=budget_iters)
     t2 = time.perf_counter()
-    return {"value": iters / (t2 - t1), "unit": "PCG iters/s", "cores": threads,
-            "kind": "oracle",
-            "sample": f"{p.cfg.name} grid {p.cfg.nr}x{p.cfg.nt}x{p.cfg.np_}: oracle PCG from x0=0 "
-                      f"to rel. residual {rel_true:.2e} in {iters} iterations, {t2 - t1:.1f} s "
-                      f"(time to solution); assembly {t1 - t0:.1f} s not counted",
-            "time_to_tol_s": t2 - t1}
+    out["value"] = iters / (t2 - t1)
+    out["sample"] = (f"{p.cfg.name} grid {p.cfg.nr}x{p.cfg.nt}x{p.cfg.np_}: oracle PCG from x0=0 "
+                     f"on {threads} threads, {iters} iterations to rel. residual {rel_true:.2e} "
+                     f"in {t2 - t1:.1f} s (time to solution; at most {budget_iters} iterations); "
+                     f"assembly {t1 - t0:.1f} s not counted")
+    out["time_to_tol_s"] = (t2 - t1) if rel_true <= p.cfg.rtol else None
+    if x_gpu:
+        out["gpu_solutions_rel_resid_by_oracle"] = {k: ora.rel_residual(b, v) for k, v in x_gpu.items()}
+    # one core: a bounded sample of the same solve
+    oracle.set_threads(1)
+    t3 = time.perf_counter()
+    _, it1, _, _ = ora.pcg(b, tol=0.0, max_iters=single_iters)
+    t4 = time.perf_counter()
+    out["single_core"] = {"value": it1 / (t4 - t3), "unit": "PCG iters/s", "cores": 1,
+                          "sample": f"{p.cfg.name}: {it1} oracle PCG iterations on one thread, "
+                                    f"{t4 - t3:.1f} s"}
+    oracle.set_threads(threads)
+    del ora
+    # full solves of the two smaller configurations
+    for name in ("c0", "c3"):
+        q = W.make_problem(W.CONFIGS[name])
+        o2 = oracle.Operator(q.r_faces, q.t_faces, q.cfg.np_, q.nu, q.dt)
+        b2 = o2.rhs_to_b(q.rhs)
+        t5 = time.perf_counter()
+        _, it2, _, res2 = o2.pcg(b2, tol=q.cfg.rtol)
+        t6 = time.perf_counter()
+        out[name] = {"iters": it2, "time_to_tol_s": t6 - t5, "iters_per_s": it2 / (t6 - t5),
+                     "rel_resid": res2, "cells": q.cfg.n,
+                     "what": f"{name} {q.cfg.nr}x{q.cfg.nt}x{q.cfg.np_} FP64 Jacobi-PCG to "
+                             f"{q.cfg.rtol:g} from x0=0 on {threads} threads"}
+        del o2
+    return out
+
+
+def bench_build(S, grid, nu, p, reps=5):
+    """The operator build on its own (mas_op_build: geometry upload, the
+    one-pass build kernel, the validity read-back), host clock around the
+    blocking call, after a warm-up; FP64 and with single-precision copies."""
+    import numpy as np
+    import torch
+
+    res = {"what": "mas_op_build alone (host clock around the blocking call, median of "
+                   f"{reps}): w, three scaled couplings and the copy of nu (48 B/cell moved; "
+                   "60 B/cell with single-precision copies)"}
+    for prec, bpc in (("fp64", 48), ("fp32_refined", 60)):
+        S.Operator(grid, nu, p.dt, precision=prec)
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            op = S.Operator(grid, nu, p.dt, precision=prec)
+            ts.append(time.perf_counter() - t0)
+            del op
+        ms = 1e3 * float(np.median(ts))
+        res[prec] = {"ms": ms, "bytes_per_cell": bpc,
+                     "GBs_at_host_time": bpc * grid.n / (ms * 1e-3) / 1e9}
+    print(f"[bench] op build: {res['fp64']['ms']:.3f} ms (fp64), {res['fp32_refined']['ms']:.3f} ms "
+          "(with fp32 copies)", file=sys.stderr, flush=True)
+    return res
+
+
+def bench_c0(S, W, dev, reps=20):
+    """The 65,536-cell grid (32 x 32 x 64): cache-resident and latency-bound,
+    iterations per second of full FP64 solves (and through the
+    allocation-free entry point)."""
+    import numpy as np
+    import torch
+
+    q = W.make_problem(W.CONFIGS["c0"])
+    g0 = S.Grid.from_problem(q)
+    nu0 = torch.from_numpy(q.nu).to(dev)
+    rhs0 = torch.from_numpy(q.rhs).to(dev)
+    x0 = torch.empty_like(rhs0)
+    op = S.Operator(g0, nu0, q.dt)
+    o = S.make_opts(rtol=q.cfg.rtol)
+    op.solve(rhs0, o, out=x0, allow_notconv=False)
+    runs = [op.solve(rhs0, o, out=x0, allow_notconv=False)[1] for _ in range(reps)]
+    t = float(np.median([r["seconds"] for r in runs]))
+    op.solve_noalloc(rhs0, o, out=x0, allow_notconv=False)
+    runs_na = [op.solve_noalloc(rhs0, o, out=x0, allow_notconv=False)[1] for _ in range(reps)]
+    t_na = float(np.median([r["seconds"] for r in runs_na]))
+    it = runs[-1]["iters"]
+    print(f"[bench] c0: {it} iterations, {1e3 * t:.2f} ms ({it / t:.0f} iters/s); allocation-free "
+          f"{1e3 * t_na:.2f} ms", file=sys.stderr, flush=True)
+    return {"what": "c0: 32x32x64 (65,536 cells) FP64 Jacobi-PCG to 1e-10, median of "
+                    f"{reps} solves (cache-resident, latency-bound: no HBM fraction)",
+            "cells": q.cfg.n, "iters": it, "time_to_tol_s": t, "iters_per_s": it / t,
+            "rel_resid_true": runs[-1]["rel_resid_true"],
+            "noalloc": {"time_to_tol_s": t_na, "iters_per_s": runs_na[-1]["iters"] / t_na}}
+
+
+def bench_c4(S, W, dev):
+    """The 96M-cell stress case (300 x 400 x 800, clustered theta, 1000x
+    viscosity contrast, diffusion number 5000): the FP32/FP64-refined forward
+    solve with PC1 and with PC2, and the adjoint (refined PC2 solve plus the
+    gradient kernel), each after a warm-up."""
+    import numpy as np
+    import torch
+
+    q = W.make_problem(W.CONFIGS["c4"])
+    g4 = S.Grid.from_problem(q)
+    nu4 = torch.from_numpy(q.nu).to(dev)
+    rhs4 = torch.from_numpy(q.rhs).to(dev)
+    x4 = torch.empty_like(rhs4)
+    op = S.Operator(g4, nu4, q.dt, precision="fp32_refined")
+    res = {"what": "c4: 300x400x800 (96M cells) stress case, FP32 inner / FP64 refinement to 1e-10",
+           "cells": q.cfg.n}
+    for name, kw in (("refined_pc1", {}), ("refined_pc2", {"precond": "pc2"})):
+        o = S.make_opts(rtol=q.cfg.rtol, precision="fp32_refined", **kw)
+        op.solve(rhs4, o, out=x4, allow_notconv=False)
+        runs = [op.solve(rhs4, o, out=x4, allow_notconv=False)[1] for _ in range(2)]
+        res[name] = {"time_to_tol_s": float(np.median([r["seconds"] for r in runs])),
+                     "inner_iters": runs[-1]["iters"], "outer_iters": runs[-1]["outer_iters"],
+                     "rel_resid_true": runs[-1]["rel_resid_true"]}
+    gx = torch.from_numpy(np.random.default_rng(GX_SEED).standard_normal(g4.shape)).to(dev)
+    o = S.make_opts(rtol=q.cfg.rtol, precision="fp32_refined", precond="pc2", sample_timing=0)
+    op.adjoint(x4, gx, o, allow_notconv=False)
+    torch.cuda.synchronize()
+    ts = []
+    for _ in range(2):
+        t0 = time.perf_counter()
+        _, _, _, ia = op.adjoint(x4, gx, o, allow_notconv=False)
+        torch.cuda.synchronize()
+        ts.append(time.perf_counter() - t0)
+    res["adjoint_refined_pc2"] = {"time_s": float(np.median(ts)), "inner_iters": ia["iters"],
+                                  "outer_iters": ia["outer_iters"],
+                                  "rel_resid_true": ia["rel_resid_true"]}
+    res["forward_plus_adjoint_s"] = res["refined_pc2"]["time_to_tol_s"] + res["adjoint_refined_pc2"]["time_s"]
+    print(f"[bench] c4: refined PC1 {res['refined_pc1']['time_to_tol_s']:.3f} s, refined PC2 "
+          f"{res['refined_pc2']['time_to_tol_s']:.3f} s, adjoint {res['adjoint_refined_pc2']['time_s']:.3f} s",
+          file=sys.stderr, flush=True)
+    return res
 
 
 # One iteration kernel with m right-hand sides: the couplings (3 words) once,
@@ -311,6 +461,10 @@ def main():
     ap.add_argument("--no-multi", action="store_true")
     ap.add_argument("--no-pc2", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--no-build", action="store_true")
+    ap.add_argument("--no-c0", action="store_true")
+    ap.add_argument("--no-c4", action="store_true")
+    ap.add_argument("--no-probe", action="store_true")
     ap.add_argument("--check-every", type=int, default=8)
     args = ap.parse_args()
     if args.gpus != 1:
@@ -429,6 +583,9 @@ def main():
         print(f"[bench] refined: {t_ref:.3f} s vs fp64 {np.median(solve_s):.3f} s",
               file=sys.stderr, flush=True)
 
+    if not args.no_build:
+        out["op_build"] = bench_build(S, grid, nu, p)
+
     if not args.no_adjoint:
         out["adjoint"] = bench_adjoint(S, grid, nu, x, p, opts, float(np.median(solve_s)))
 
@@ -442,24 +599,41 @@ def main():
     if not args.no_sts:
         out["sts"] = bench_sts(S, grid, nu, rhs, p, float(np.median(solve_s)), args.steps)
 
-    # practical HBM ceiling: a plain streaming copy of 2 GiB (read + write)
-    src = torch.empty(1 << 28, dtype=torch.float64, device=dev).fill_(1.0)
-    dst = torch.empty_like(src)
-    S.probe_copy(src, dst)
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record()
-    for _ in range(10):
-        S.probe_copy(src, dst)
-    e1.record()
-    torch.cuda.synchronize()
-    copy_gbs = 10 * 2 * src.numel() * 8 / (e0.elapsed_time(e1) * 1e-3) / 1e9
-    out["roofline"]["copy_probe_GBs"] = copy_gbs
-    out["roofline"]["kernel_bytes_frac_of_copy"] = (kern_gbs / copy_gbs) if kern_gbs else None
-    del src, dst
-    print(f"[bench] copy probe {copy_gbs:.0f} GB/s", file=sys.stderr, flush=True)
+    if not args.no_c0:
+        out["c0"] = bench_c0(S, W, dev)
+
+    x_host = {"fp64": x.cpu().numpy()}
+    if "refined" in out:
+        x_host["refined"] = xm.cpu().numpy()
+        del xm, opm
+    torch.cuda.empty_cache()
+
+    if not args.no_c4:
+        out["c4"] = bench_c4(S, W, dev)
+        torch.cuda.empty_cache()
+
+    if not args.no_probe:
+        # achievable bandwidth of the byte mixes the kernels stream, at the
+        # workload's size (streaming probes of the library), and a plain copy
+        stream_gbs = S.probe_stream(n, 7, 4, dev)
+        grad_mix_gbs = S.probe_stream(n, 2, 2, dev)
+        copy_gbs = S.probe_stream(n, 1, 1, dev)
+        torch.cuda.empty_cache()
+        out["roofline"]["stream_7r4w_GBs"] = stream_gbs
+        out["roofline"]["copy_probe_GBs"] = copy_gbs
+        out["roofline"]["kernel_bytes_frac_of_stream"] = (kern_gbs / stream_gbs) if kern_gbs else None
+        if "adjoint" in out:
+            out["adjoint"]["gradient_kernel"]["stream_2r2w_GBs"] = grad_mix_gbs
+        print(f"[bench] stream probes: 7 read / 4 write {stream_gbs:.0f} GB/s, 2/2 "
+              f"{grad_mix_gbs:.0f} GB/s, copy {copy_gbs:.0f} GB/s", file=sys.stderr, flush=True)
 
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(p)
+        cb = cpu_baseline(p, x_host)
+        rr = cb.pop("gpu_solutions_rel_resid_by_oracle", {})
+        out["config"]["rel_resid_by_oracle"] = rr.get("fp64")
+        if "refined" in out:
+            out["refined"]["rel_resid_by_oracle"] = rr.get("refined")
+        out["cpu_baseline"] = cb
         print(f"[bench] cpu baseline {out['cpu_baseline']}", file=sys.stderr, flush=True)
 
     print(json.dumps(out), flush=True)

@@ -342,6 +342,20 @@ int mas_pcg_solve_noalloc(const mas_op *op, const double *rhs, double *x, const 
  * byte counters.  Enqueues only. */
 int mas_probe_copy(const void *src, void *dst, int64_t bytes, void *hip_stream);
 
+/* Streaming probe with the byte mix of a stencil kernel: nin arrays of n
+ * doubles read and nout written, each block walking one contiguous chunk of
+ * every array as the marching kernels walk their r chunks, non-temporal
+ * accesses, out_t = in_0 + ... + in_{nin-1} + t.  The arrays are laid out
+ * in buf (dev, 256-byte aligned, >= mas_probe_stream_bytes(n, nin, nout))
+ * with the library's stagger.  Supported mixes: 7/4 (the PCG iteration
+ * kernel), 2/2 (the gradient kernel), 4/1 (an RKL2 stage), 1/1 (a copy).
+ * It measures the bandwidth that access pattern reaches, the ceiling the
+ * kernels are compared with beside the 8 TB/s peak.  Enqueues only.
+ * Returns MAS_OK, MAS_EINVAL, MAS_ENOMEM or MAS_EHIP. */
+int64_t mas_probe_stream_bytes(int64_t n, int32_t nin, int32_t nout);
+int mas_probe_stream(void *buf, int64_t bytes, int64_t n, int32_t nin, int32_t nout,
+                     void *hip_stream);
+
 /* Static description of a status code. */
 const char *mas_status_string(int status);
 

@@ -27,23 +27,55 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "mas_oracle.c")
 _LIB = os.path.join(_HERE, "libmas_oracle.so")
+# the same source built -O3 -march=native on the machine that times it (the
+# CPU-baseline leg of the benchmark; tests use the portable -O2 build)
+_LIB_NATIVE = os.path.join(_HERE, "libmas_oracle_native.so")
+NATIVE_FLAGS = ["-O3", "-march=native"]
 
 DIRICHLET = 0
 NEUMANN = 1
 
 
-def build(force: bool = True) -> str:
-    """Compile the oracle with gcc into oracle/libmas_oracle.so."""
-    if force or not os.path.exists(_LIB):
-        tmp = _LIB + f".tmp{os.getpid()}"
-        cmd = ["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-std=gnu11",
-               "-o", tmp, _SRC, "-lm"]
+def build(force: bool = True, native: bool = False) -> str:
+    """Compile the oracle with gcc into oracle/libmas_oracle.so (native:
+    oracle/libmas_oracle_native.so, -O3 -march=native)."""
+    lib = _LIB_NATIVE if native else _LIB
+    if force or not os.path.exists(lib):
+        tmp = lib + f".tmp{os.getpid()}"
+        opt = NATIVE_FLAGS if native else ["-O2"]
+        cmd = ["gcc", *opt, "-fopenmp", "-fPIC", "-shared", "-std=gnu11", "-o", tmp, _SRC, "-lm"]
         subprocess.run(cmd, check=True)
-        os.replace(tmp, _LIB)
-    return _LIB
+        os.replace(tmp, lib)
+    return lib
 
 
 _lib = None
+_lib_path = _LIB
+
+
+def use_native_build() -> str:
+    """Build and load the -O3 -march=native oracle (for timing only); must be
+    called before anything else in this process uses the oracle."""
+    global _lib_path
+    if _lib is not None and _lib_path != _LIB_NATIVE:
+        raise RuntimeError("the oracle library is already loaded")
+    _lib_path = build(force=True, native=True)
+    return _lib_path
+
+
+def _gomp():
+    return ctypes.CDLL("libgomp.so.1")
+
+
+def set_threads(n: int) -> None:
+    """OpenMP threads of the oracle's parallel loops."""
+    _load()
+    _gomp().omp_set_num_threads(int(n))
+
+
+def max_threads() -> int:
+    _load()
+    return int(_gomp().omp_get_max_threads())
 
 
 def _dp():
@@ -74,9 +106,9 @@ def rkl2_coefficients(s: int):
 def _load():
     global _lib
     if _lib is None:
-        if not os.path.exists(_LIB):
-            build(force=False)
-        lib = ctypes.CDLL(_LIB)
+        if not os.path.exists(_lib_path):
+            build(force=False, native=_lib_path == _LIB_NATIVE)
+        lib = ctypes.CDLL(_lib_path)
         P = ctypes.POINTER
         lib.ora_geometry.argtypes = [P(_Op)]
         lib.ora_geometry.restype = ctypes.c_int

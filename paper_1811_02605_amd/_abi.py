@@ -108,6 +108,9 @@ _SIGS = {
     "mas_pcg_solve_noalloc": (ctypes.c_int, [_VP, _VP, _VP, ctypes.POINTER(mas_pcg_opts), _VP,
                                              ctypes.POINTER(mas_pcg_info)]),
     "mas_probe_copy": (ctypes.c_int, [_VP, _VP, ctypes.c_int64, _VP]),
+    "mas_probe_stream_bytes": (ctypes.c_int64, [ctypes.c_int64, ctypes.c_int32, ctypes.c_int32]),
+    "mas_probe_stream": (ctypes.c_int, [_VP, ctypes.c_int64, ctypes.c_int64, ctypes.c_int32,
+                                        ctypes.c_int32, _VP]),
     "mas_status_string": (ctypes.c_char_p, [ctypes.c_int]),
     "mas_last_error": (ctypes.c_char_p, []),
 }

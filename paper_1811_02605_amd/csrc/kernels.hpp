@@ -920,7 +920,7 @@ __global__ void k_ctl_init(Ctl *ctl, int mode, int iter0, int max_iter, double t
 // Block (64, 4): 64 phi cells x 4 theta rows, looping over kSimpleR r planes.
 constexpr int kSimpleJ = 4;
 constexpr int kSimpleR = 16;
-constexpr int kSimpleNV = 2;  // most partial sums a simple-tile kernel writes per block
+constexpr int kSimpleNV = 3;  // most partial sums a simple-tile kernel writes per block
 
 struct SimpleCell {
     int i, j, k;
@@ -946,93 +946,277 @@ __device__ inline int64_t simple_block_id() {
     return ((int64_t)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
 }
 
+// ---------------------------------------------------------------- operator build
+// One pass over nu builds the stored operator: w = sqrt(A_cc), the scaled
+// couplings c^ to the +r, +theta, +phi neighbours (and their single-
+// precision copies), a copy of nu (the explicit stages form conductances
+// from it), the validity of nu and z_max = max_c 2 (A_cc - V_c)/V_c, the
+// Gershgorin bound of dt times the spectral radius of V^-1 (A - V), kept as
+// the bits of a non-negative double so that an integer maximum finds it.
+//   A_cc = V_c + sum_f c_f,  c_f = dt nu_f G_f,  nu_f = (nu_a + nu_b)/2
+//   (the cell's own nu on a Dirichlet wall), c^_f = c_f / (w_a w_b).
+// c^ needs w at the + neighbours, and w needs nu at every neighbour, so a
+// coupling reads nu two cells away.  Each block owns a tile of kBuR theta
+// rows x kBuC phi cells and marches up its r chunk with a ring of three
+// planes of nu in LDS (the tile plus one row and one column on each side,
+// and a second row and column on the + sides), forms w one plane ahead on
+// the tile grown by one row and one column (the + neighbours' w), and then
+// the couplings of the plane behind: every value of nu is fetched from
+// memory once per block and every output is written once.  The next plane
+// of nu is loaded into registers while the current plane is computed.
+constexpr int kBuR = 16;                     // theta rows per tile
+constexpr int kBuC = 64;                     // phi cells per tile (one per lane)
+constexpr int kBuWaves = 4;                  // each wave owns rows wv, wv + 4, ...
+constexpr int kBuThreads = kWave * kBuWaves;
+constexpr int kBuPR = kBuR + 3, kBuPC = kBuC + 3;  // nu patch: rows J0-1..J0+R+1, cells k0-1..k0+C+1
+constexpr int kBuWR = kBuR + 1, kBuWC = kBuC + 1;  // w patch:  rows J0..J0+R,     cells k0..k0+C
+constexpr int kBuLoads = (kBuPR * kBuPC + kBuThreads - 1) / kBuThreads;
+
+struct BuildArgs {
+    const double *nu;
+    double *w, *cr, *ct, *cp, *nu_copy;
+    float *cr32, *ct32, *cp32;  // null unless single-precision copies are kept
+    int32_t *bad;
+    unsigned long long *zmax_bits;
+    Geo geo;
+    Dims d;
+    int tiles_i, tiles_k, tiles_j, ti, nblk;
+};
+
 // Face conductance dt * nu_f * G_f, the single definition used by the build.
 __device__ inline double face_c(double dt, double nua, double nub, double g) {
     return dt * (0.5 * (nua + nub)) * g;
 }
 
-// Diagonal of A, its square root, and validity of nu; also a copy of nu
-// (the explicit stages form their conductances from it) and the largest
-// z_c = 2 (A_cc - V_c) / V_c, a Gershgorin bound of dt times the spectral
-// radius of V^-1 (A - V), kept as the bits of a non-negative double so that
-// an integer maximum finds it.
-__global__ __launch_bounds__(kWave *kSimpleJ) void k_build_diag(const double *nu, Geo geo, Dims d,
-                                                                double *w, double *nu_copy,
-                                                                int32_t *bad,
-                                                                unsigned long long *zmax_bits) {
+// Factors of one r plane m and of one theta row j (see struct Geo):
+//   P = [vr[m], r- face factor, r+ face factor, gq[m]], where the r- factor
+//   is gr[m-1] (or the inner wall's gw_in when m = 0) and the r+ factor
+//   gr[m] (gw_out when m = nr - 1);
+//   R = [vt[j], gtt[j-1] (0 at the pole), gtt[j] (0 at the pole), gpt[j]].
+struct PlaneF {
+    double vr, grm, grp, gq;
+};
+struct RowF {
+    double vt, gttm, gttp, gpt;
+};
+
+// A_cc at plane m, row j (in the grid), from n(pr, pc, dm) = nu at patch row
+// pr, patch column pc, plane m + dm; the cell sits at patch (pr, pc).
+// Terms in the order r-, r+, theta-, theta+, phi-, phi+.
+template <typename NU>
+__device__ inline double build_diag(const Geo &g, const Dims &d, int m, int j, int pr, int pc,
+                                    const PlaneF &P, const RowF &R, NU n) {
+    const double nc = n(pr, pc, 0);
+    double s = P.vr * R.vt;
+    if (m > 0) s += face_c(g.dt, nc, n(pr, pc, -1), P.grm * R.vt);
+    else s += g.dt * nc * (P.grm * R.vt);
+    if (m < d.nr - 1) s += face_c(g.dt, nc, n(pr, pc, 1), P.grp * R.vt);
+    else s += g.dt * nc * (P.grp * R.vt);
+    if (j > 0) s += face_c(g.dt, nc, n(pr - 1, pc, 0), P.gq * R.gttm);
+    if (j < d.nt - 1) s += face_c(g.dt, nc, n(pr + 1, pc, 0), P.gq * R.gttp);
+    if (!g.np_one) {
+        const double gp = P.gq * R.gpt;
+        s += face_c(g.dt, nc, n(pr, pc - 1, 0), gp);
+        s += face_c(g.dt, nc, n(pr, pc + 1, 0), gp);
+    }
+    return s;
+}
+
+template <bool F32>
+__global__ __launch_bounds__(kBuThreads) void k_build(BuildArgs a) {
+    __shared__ double sNu[3][kBuPR][kBuPC];  // nu of planes m, m + 1, m + 2 (ring)
+    __shared__ double sIw[kBuWR][kBuWC];     // 1/w of plane m on the grown tile
+    __shared__ RowF sR[kBuWR];               // rows J0 .. J0 + R (39.9 KB in all: 4 blocks per CU)
+    const Dims d = a.d;
+    const Geo &g = a.geo;
+    const int nr = d.nr, nt = d.nt, np = d.np;
+    const int L = xcd_remap(blockIdx.x, a.nblk);
+    int it, kt, jt;
+    tile_coords<3>(L, a.tiles_i, a.tiles_k, a.tiles_j, it, kt, jt);
+    const int J0 = jt * kBuR, k0 = kt * kBuC;
+    const int nseg = min(kBuC, np - k0);
+    const int i0 = it * a.ti, i1 = min(i0 + a.ti, nr);
+    const int tid = threadIdx.x, lane = tid & (kWave - 1);
+    const int wv = __builtin_amdgcn_readfirstlane(tid / kWave);
+
+    // factors of a plane (uniform: scalar loads, once per plane step) and
+    // the table of the tile's rows in LDS (rows outside the grid: zeros,
+    // never used)
+    auto plane_f = [&](int m) {
+        PlaneF P{0.0, 0.0, 0.0, 0.0};
+        if (m >= 0 && m < nr) {
+            P.vr = g.vr[m];
+            P.grm = (m > 0) ? g.gr[m - 1] : g.gw_in;
+            P.grp = (m < nr - 1) ? g.gr[m] : g.gw_out;
+            P.gq = g.gq[m];
+        }
+        return P;
+    };
+    if (tid < kBuWR) {
+        const int j = J0 + tid;
+        RowF R{0.0, 0.0, 0.0, 0.0};
+        if (j < nt) {
+            R.vt = g.vt[j];
+            R.gttm = (j > 0) ? g.gtt[j - 1] : 0.0;
+            R.gttp = g.gtt[j];
+            R.gpt = g.gpt[j];
+        }
+        sR[tid] = R;
+    }
+
+    // this thread's elements of the nu patch: offsets inside a plane
+    // (-1: outside the grid in theta, read as zero; -2: no element)
+    int32_t poff[kBuLoads];
+#pragma unroll
+    for (int q = 0; q < kBuLoads; ++q) {
+        const int e = tid + q * kBuThreads;
+        poff[q] = -2;
+        if (e < kBuPR * kBuPC) {
+            const int pr = e / kBuPC, pc = e % kBuPC;
+            const int j = J0 - 1 + pr;
+            int k = (k0 - 1 + pc) % np;
+            if (k < 0) k += np;
+            poff[q] = (j >= 0 && j < nt) ? j * np + k : -1;
+        }
+    }
+    const auto Rnu = make_rsrc(a.nu, (uint32_t)(d.n * (int64_t)sizeof(double)));
+    auto load_plane = [&](int m, double (&v)[kBuLoads]) {
+#pragma unroll
+        for (int q = 0; q < kBuLoads; ++q) {
+            const bool ok = m >= 0 && m < nr && poff[q] >= 0;
+            v[q] = bld<double, 1>(Rnu, ok ? (uint32_t)(((int64_t)m * d.plane + poff[q]) * 8) : kOOB).v[0];
+        }
+    };
+    auto store_plane = [&](int m, const double (&v)[kBuLoads]) {
+        double *flat = &sNu[((m % 3) + 3) % 3][0][0];
+#pragma unroll
+        for (int q = 0; q < kBuLoads; ++q)
+            if (poff[q] != -2) flat[tid + q * kBuThreads] = v[q];
+    };
+    auto slot_of = [](int m) { return ((m % 3) + 3) % 3; };
+
+    // A_cc at patch-relative (er, ec) of plane m (the tile grown by one row
+    // and one column); own cells also check nu and raise z_max
     int badv = 0;
     double zmax = 0.0;
-    MAS_SIMPLE_LOOP(d, {
-        if (cell.ok) {
-            const int i = cell.i, j = cell.j, k = cell.k;
-            const int64_t c = cell.c;
-            const double nc = nu[c];
+    auto diag_at = [&](int m, const PlaneF &P, int er, int ec) -> double {
+        const int j = J0 + er;
+        if (j >= nt) return 1.0;  // outside the grid: never used
+        const int s0 = slot_of(m), sm = slot_of(m - 1), sp = slot_of(m + 1);
+        auto n = [&](int pr, int pc, int dm) {
+            return sNu[dm == 0 ? s0 : (dm < 0 ? sm : sp)][pr][pc];
+        };
+        const RowF R = sR[er];
+        const double s = build_diag(g, d, m, j, er + 1, ec + 1, P, R, n);
+        if (er < kBuR && ec < nseg && m >= i0 && m < i1) {
+            const double nc = n(er + 1, ec + 1, 0);
             if (!(nc > 0.0) || !isfinite(nc)) badv = 1;
-            const double vt = geo.vt[j];
-            double s = geo.vr[i] * vt;
-            // r faces
-            if (i > 0) s += face_c(geo.dt, nc, nu[c - d.plane], geo.gr[i - 1] * vt);
-            else s += geo.dt * nc * (geo.gw_in * vt);
-            if (i < d.nr - 1) s += face_c(geo.dt, nc, nu[c + d.plane], geo.gr[i] * vt);
-            else s += geo.dt * nc * (geo.gw_out * vt);
-            // theta faces (zero at the poles)
-            if (j > 0) s += face_c(geo.dt, nc, nu[c - d.np], geo.gq[i] * geo.gtt[j - 1]);
-            if (j < d.nt - 1) s += face_c(geo.dt, nc, nu[c + d.np], geo.gq[i] * geo.gtt[j]);
-            // phi faces (periodic)
-            if (!geo.np_one) {
-                const int km = (k == 0) ? d.np - 1 : k - 1;
-                const int kp = (k == d.np - 1) ? 0 : k + 1;
-                const double gp = geo.gq[i] * geo.gpt[j];
-                s += face_c(geo.dt, nc, nu[c - k + km], gp);
-                s += face_c(geo.dt, nc, nu[c - k + kp], gp);
-            }
-            w[c] = sqrt(s);
-            nu_copy[c] = nc;
-            const double vc = geo.vr[i] * vt;
+            const double vc = P.vr * R.vt;
             const double z = 2.0 * (s - vc) / vc;
             zmax = (z > zmax) ? z : zmax;  // false for NaN: nu was then flagged bad
         }
-    })
-    if (badv) atomicOr(bad, 1);
+        return s;
+    };
+    constexpr int NQ = kBuR / kBuWaves;
+    // w and 1/w of plane m at this thread's cells (rows wv + 4q, column
+    // lane) and at its point of the grown border (wave 0: the row below the
+    // tile; wave 1: the column right of it)
+    double w[NQ], iw[NQ], wn[NQ], iwn[NQ], iwb = 0.0;
+    const bool hasb = (wv == 0) || (wv == 1 && lane < kBuWR);
+    const int ber = (wv == 0) ? kBuR : lane, bec = (wv == 0) ? lane : kBuC;
+    auto w_plane = [&](int m, const PlaneF &P, double (&wo)[NQ], double (&iwo)[NQ]) {
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+            wo[q] = sqrt(diag_at(m, P, wv + kBuWaves * q, lane));
+            iwo[q] = 1.0 / wo[q];
+        }
+        if (hasb) iwb = 1.0 / sqrt(diag_at(m, P, ber, bec));
+    };
+    auto put_iw = [&](const double (&iwo)[NQ]) {
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) sIw[wv + kBuWaves * q][lane] = iwo[q];
+        if (hasb) sIw[ber][bec] = iwb;
+    };
+
+    const uint32_t ob = (uint32_t)(d.n * (int64_t)sizeof(double));
+    const auto Rw = make_rsrc(a.w, ob), Rcr = make_rsrc(a.cr, ob), Rct = make_rsrc(a.ct, ob),
+               Rcp = make_rsrc(a.cp, ob), Rnc = make_rsrc(a.nu_copy, ob);
+    const uint32_t of = F32 ? (uint32_t)(d.n * (int64_t)sizeof(float)) : 0u;
+    const auto Rcr32 = make_rsrc(a.cr32, of), Rct32 = make_rsrc(a.ct32, of), Rcp32 = make_rsrc(a.cp32, of);
+
+    // prologue: nu of planes i0 - 1, i0, i0 + 1; w of plane i0; nu of i0 + 2
+    {
+        double v[kBuLoads];
+        for (int m = i0 - 1; m <= i0 + 1; ++m) {
+            load_plane(m, v);
+            store_plane(m, v);
+        }
+    }
+    __syncthreads();
+    PlaneF Pm = plane_f(i0);
+    w_plane(i0, Pm, w, iw);
+    double nxt[kBuLoads];
+    load_plane(i0 + 2, nxt);
+    __syncthreads();  // plane i0 - 1's slot is reused for plane i0 + 2
+    put_iw(iw);
+    store_plane(i0 + 2, nxt);
+    __syncthreads();
+
+    for (int m = i0; m < i1; ++m) {
+        // nu of plane m + 3 in flight while plane m is computed
+        load_plane(m + 3, nxt);
+        // w of plane m + 1 (kept in registers until the couplings of plane m
+        // no longer read 1/w of plane m)
+        const PlaneF Pn = plane_f(m + 1);
+        w_plane(m + 1, Pn, wn, iwn);
+        // couplings of plane m: c^_f = c_f (1/w_c) (1/w_nb)
+        const int s0 = slot_of(m), s1 = slot_of(m + 1);
+        const PlaneF P = Pm;
+        const int c = lane;
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+            const int r = wv + kBuWaves * q;
+            const int j = J0 + r;
+            const bool own = j < nt && c < nseg;
+            const RowF R = sR[r];
+            const double nc = sNu[s0][r + 1][c + 1];
+            double vr = 0.0, vth = 0.0, vp = 0.0;
+            if (m < nr - 1) vr = face_c(g.dt, nc, sNu[s1][r + 1][c + 1], P.grp * R.vt) * iw[q] * iwn[q];
+            if (j < nt - 1) vth = face_c(g.dt, nc, sNu[s0][r + 2][c + 1], P.gq * R.gttp) * iw[q] * sIw[r + 1][c];
+            if (!g.np_one) vp = face_c(g.dt, nc, sNu[s0][r + 1][c + 2], P.gq * R.gpt) * iw[q] * sIw[r][c + 1];
+            const uint32_t o = own ? (uint32_t)(((int64_t)m * d.plane + (int64_t)j * np + k0 + c) * 8) : kOOB;
+            bst<double, 1, kAuxNT>(Rw, o, VecT<double, 1>{{w[q]}});
+            bst<double, 1, kAuxNT>(Rnc, o, VecT<double, 1>{{nc}});
+            bst<double, 1, kAuxNT>(Rcr, o, VecT<double, 1>{{vr}});
+            bst<double, 1, kAuxNT>(Rct, o, VecT<double, 1>{{vth}});
+            bst<double, 1, kAuxNT>(Rcp, o, VecT<double, 1>{{vp}});
+            if constexpr (F32) {
+                const uint32_t o4 = own ? o / 2u : kOOB;
+                bst<float, 1, kAuxNT>(Rcr32, o4, VecT<float, 1>{{(float)vr}});
+                bst<float, 1, kAuxNT>(Rct32, o4, VecT<float, 1>{{(float)vth}});
+                bst<float, 1, kAuxNT>(Rcp32, o4, VecT<float, 1>{{(float)vp}});
+            }
+        }
+        __syncthreads();  // every read of plane m's nu slot and of 1/w of plane m is done
+        put_iw(iwn);
+        store_plane(m + 3, nxt);
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+            w[q] = wn[q];
+            iw[q] = iwn[q];
+        }
+        Pm = Pn;
+        __syncthreads();
+    }
+
+    if (badv) atomicOr(a.bad, 1);
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) {
         const double t = __shfl_xor(zmax, o, kWave);
         zmax = (t > zmax) ? t : zmax;
     }
-    if ((threadIdx.x & (kWave - 1)) == 0 && zmax > 0.0)
-        atomicMax(zmax_bits, (unsigned long long)__double_as_longlong(zmax));
-}
-
-// Scaled couplings to the +r, +theta, +phi neighbours.
-template <bool F32>
-__global__ __launch_bounds__(kWave *kSimpleJ) void k_build_coef(const double *nu, const double *w,
-                                                                Geo geo, Dims d, double *cr,
-                                                                double *ct, double *cp, float *cr32,
-                                                                float *ct32, float *cp32) {
-    MAS_SIMPLE_LOOP(d, {
-        if (cell.ok) {
-            const int i = cell.i, j = cell.j, k = cell.k;
-            const int64_t c = cell.c;
-            const double nc = nu[c], wc = w[c];
-            double vr = 0.0, vth = 0.0, vp = 0.0;
-            if (i < d.nr - 1)
-                vr = face_c(geo.dt, nc, nu[c + d.plane], geo.gr[i] * geo.vt[j]) / (wc * w[c + d.plane]);
-            if (j < d.nt - 1)
-                vth = face_c(geo.dt, nc, nu[c + d.np], geo.gq[i] * geo.gtt[j]) / (wc * w[c + d.np]);
-            if (!geo.np_one) {
-                const int64_t cn = c - k + ((k == d.np - 1) ? 0 : k + 1);
-                vp = face_c(geo.dt, nc, nu[cn], geo.gq[i] * geo.gpt[j]) / (wc * w[cn]);
-            }
-            cr[c] = vr;
-            ct[c] = vth;
-            cp[c] = vp;
-            if (F32) {
-                cr32[c] = (float)vr;
-                ct32[c] = (float)vth;
-                cp32[c] = (float)vp;
-            }
-        }
-    })
+    if (lane == 0 && zmax > 0.0)
+        atomicMax(a.zmax_bits, (unsigned long long)__double_as_longlong(zmax));
 }
 
 // Unscaled entries as the solver uses them: -A(c, nb) = w_c c^ w_nb, A_cc = w_c^2.
@@ -1106,26 +1290,38 @@ __global__ __launch_bounds__(kWave *kSimpleJ) void k_residual(const double *bhat
     block_sum_store<2>(acc, partials + 2 * simple_block_id(), lds);
 }
 
-// b^ = V src / w (src = rhs) or src / w (src = adjoint seed), partial ||b||^2;
-// x^ = w x0 (warm start) or 0.
+// b^ = V src / w (src = rhs) or src / w (src = adjoint seed); x^ = w x0
+// (warm start) or 0.  Partials [||b||^2, ||W r^||^2, ||r^||^2] of the
+// initial residual when it is known here: from x^ = 0, r^ = b^ exactly, and
+// it is written to rout (as TOUT) so that no residual kernel has to form it
+// (rout may be null; with a warm start the last two partials are 0).
+template <typename TOUT>
 __global__ __launch_bounds__(kWave *kSimpleJ) void k_setup(const double *src, int src_is_rhs,
                                                            const double *w, Geo geo, Dims d,
                                                            double *bhat, double *x, int use_x0,
-                                                           double *partials) {
-    __shared__ double lds[kSimpleJ * 1];
-    double acc[1] = {0.0};
+                                                           TOUT *rout, double *partials) {
+    static_assert(kSimpleNV >= 3, "partials per simple block");
+    __shared__ double lds[kSimpleJ * 3];
+    double acc[3] = {0.0, 0.0, 0.0};
     MAS_SIMPLE_LOOP(d, {
         if (cell.ok) {
             const int64_t c = cell.c;
             double b = src[c];
             if (src_is_rhs) b *= geo.vr[cell.i] * geo.vt[cell.j];
             const double wc = w[c];
-            bhat[c] = b / wc;
+            const double bh = b / wc;
+            bhat[c] = bh;
             x[c] = use_x0 ? wc * x[c] : 0.0;
             acc[0] += b * b;
+            if (!use_x0) {
+                if (rout) rout[c] = (TOUT)bh;
+                const double t = wc * bh;
+                acc[1] += t * t;
+                acc[2] += bh * bh;
+            }
         }
     })
-    block_sum_store<1>(acc, partials + simple_block_id(), lds);
+    block_sum_store<3>(acc, partials + 3 * simple_block_id(), lds);
 }
 
 // x = x^ / w, in place.
@@ -1325,6 +1521,43 @@ __global__ __launch_bounds__(256) void k_copy16(const double2 *__restrict__ src,
         for (int u = 0; u < kCopyU; ++u) {
             const int64_t t = t0 + u * 256;
             if (t < end) dst[t] = v[u];
+        }
+    }
+}
+
+// Streaming probe with a stencil kernel's byte mix: NIN arrays read and
+// NOUT written, each block walking one contiguous chunk of kStreamChunk
+// cells of every array (as the marching kernels walk their r chunks), two
+// cells per lane, non-temporal.  out_t[c] = in_0[c] + ... + in_{NIN-1}[c] +
+// t, so no load is dead.
+constexpr int64_t kStreamChunk = 16384;
+constexpr int kStreamMaxIn = 8, kStreamMaxOut = 4;
+struct StreamArgs {
+    const double *in[kStreamMaxIn];
+    double *out[kStreamMaxOut];
+    int64_t n;
+};
+
+template <int NIN, int NOUT>
+__global__ __launch_bounds__(256) void k_stream(StreamArgs a) {
+    const int64_t beg = (int64_t)blockIdx.x * kStreamChunk;
+    const int64_t end = min(beg + kStreamChunk, a.n);
+    for (int64_t c = beg + 2 * (int64_t)threadIdx.x; c < end; c += 2 * 256) {
+        double s0 = 0.0, s1 = 0.0;
+        if (c + 1 < end) {
+#pragma unroll
+            for (int t = 0; t < NIN; ++t) {
+                const VecT<double, 2> v = ldv_nt<double, 2>(a.in[t], c);
+                s0 += v.v[0];
+                s1 += v.v[1];
+            }
+#pragma unroll
+            for (int t = 0; t < NOUT; ++t) stv_nt<double, 2>(a.out[t], c, VecT<double, 2>{{s0 + t, s1 + t}});
+        } else {
+#pragma unroll
+            for (int t = 0; t < NIN; ++t) s0 += a.in[t][c];
+#pragma unroll
+            for (int t = 0; t < NOUT; ++t) a.out[t][c] = s0 + t;
         }
     }
 }

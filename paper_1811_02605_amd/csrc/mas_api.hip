@@ -154,8 +154,11 @@ struct Shape {
     // blocks share the work.
     int ti(int v, int forced = 0) const {
         if (forced > 0) return forced;
+        return chunk_for((int64_t)tiles_k(v) * tiles_j());
+    }
+    // the same rule for any marching kernel with `tiles` tiles per plane
+    int chunk_for(int64_t tiles) const {
         const int big = std::max(kTI, (nr + 7) / 8);
-        const int64_t tiles = (int64_t)tiles_k(v) * tiles_j();
         if (tiles * ((nr + big - 1) / big) >= kMinBlocks) return big;
         const int64_t want = (tiles * nr + kMinBlocks - 1) / kMinBlocks;
         return (int)std::min<int64_t>(big, std::max<int64_t>(kSmallTI, want));
@@ -371,32 +374,62 @@ extern "C" int mas_op_build(const mas_grid *g, const double *nu, double dt, int3
         delete op;
         return status;
     };
-    struct Up {
-        double *dst;
-        const std::vector<double> *src;
-    } ups[] = {{vr, &h.vr}, {vt, &h.vt}, {gr, &h.gr}, {gq, &h.gq}, {gtt, &h.gtt}, {gpt, &h.gpt}};
-    for (auto &u : ups) {
-        hipError_t e = hipMemcpyAsync(u.dst, u.src->data(), 8 * u.src->size(),
-                                      hipMemcpyHostToDevice, stream);
+    // the six tables sit back to back in the storage (vr .. gpt): one upload
+    // from a staging buffer that lives until the build has been waited for
+    std::vector<char> stage;
+    {
+        const int64_t span = L.gpt + 8 * (int64_t)s.nt - L.vr;
+        stage.assign((size_t)span, 0);
+        struct Up {
+            int64_t off;
+            const std::vector<double> *src;
+        } ups[] = {{L.vr, &h.vr}, {L.vt, &h.vt}, {L.gr, &h.gr},
+                   {L.gq, &h.gq}, {L.gtt, &h.gtt}, {L.gpt, &h.gpt}};
+        for (auto &u : ups)
+            std::memcpy(stage.data() + (u.off - L.vr), u.src->data(), 8 * u.src->size());
+        hipError_t e = hipMemcpyAsync(vr, stage.data(), (size_t)span, hipMemcpyHostToDevice, stream);
         if (e != hipSuccess)
             return cleanup_fail(fail(MAS_EHIP, "geometry upload failed: %s", hipGetErrorString(e)));
     }
     const Dims d = s.dims();
-    const dim3 grid = s.simple_grid(), block(kWave, kSimpleJ);
-    hipLaunchKernelGGL(k_fill<int32_t>, dim3(1, 1, 1), block, 0, stream, flags,
+    hipLaunchKernelGGL(k_fill<int32_t>, dim3(1, 1, 1), dim3(kWave, kSimpleJ), 0, stream, flags,
                        Dims{1, 1, 4, 4, 4}, 0);
-    hipLaunchKernelGGL(k_build_diag, grid, block, 0, stream, nu, op->geo, d, op->w, op->nu, flags,
-                       reinterpret_cast<unsigned long long *>(flags + 2));
-    if (precision == MAS_FP32_REFINED)
-        hipLaunchKernelGGL(k_build_coef<true>, grid, block, 0, stream, nu, op->w, op->geo, d,
-                           op->c64[0], op->c64[1], op->c64[2], op->c32[0], op->c32[1], op->c32[2]);
-    else
-        hipLaunchKernelGGL(k_build_coef<false>, grid, block, 0, stream, nu, op->w, op->geo, d,
-                           op->c64[0], op->c64[1], op->c64[2], nullptr, nullptr, nullptr);
+    {
+        BuildArgs ba{};
+        ba.nu = nu;
+        ba.w = op->w;
+        ba.cr = op->c64[0];
+        ba.ct = op->c64[1];
+        ba.cp = op->c64[2];
+        ba.nu_copy = op->nu;
+        ba.cr32 = op->c32[0];
+        ba.ct32 = op->c32[1];
+        ba.cp32 = op->c32[2];
+        ba.bad = flags;
+        ba.zmax_bits = reinterpret_cast<unsigned long long *>(flags + 2);
+        ba.geo = op->geo;
+        ba.d = d;
+        ba.tiles_k = (s.np + kBuC - 1) / kBuC;
+        ba.tiles_j = (s.nt + kBuR - 1) / kBuR;
+        ba.ti = s.chunk_for((int64_t)ba.tiles_k * ba.tiles_j);
+        ba.tiles_i = (s.nr + ba.ti - 1) / ba.ti;
+        const int64_t nblk = (int64_t)ba.tiles_i * ba.tiles_j * ba.tiles_k;
+        if (nblk > INT32_MAX) {
+            (void)hipStreamSynchronize(stream);
+            return cleanup_fail(fail(MAS_EINVAL, "grid too large for the build kernel"));
+        }
+        ba.nblk = (int)nblk;
+        if (precision == MAS_FP32_REFINED)
+            hipLaunchKernelGGL(k_build<true>, dim3((unsigned)nblk), dim3(kBuThreads), 0, stream, ba);
+        else
+            hipLaunchKernelGGL(k_build<false>, dim3((unsigned)nblk), dim3(kBuThreads), 0, stream, ba);
+    }
     {
         hipError_t e = hipGetLastError();
-        if (e != hipSuccess)
+        if (e != hipSuccess) {
+            (void)hipStreamSynchronize(stream);  // the upload may still read the staging buffer
             return cleanup_fail(fail(MAS_EHIP, "build launch failed: %s", hipGetErrorString(e)));
+        }
     }
     int32_t fl[4] = {0, 0, 0, 0};
     {
@@ -1095,13 +1128,32 @@ static int solve_core(const mas_op *op, const double *src, int src_is_rhs, doubl
     const Dims d = s.dims();
     const dim3 sgrid = s.simple_grid(), sblock(kWave, kSimpleJ);
 
-    // b^ = W^-1 b, x^ = W x0 or 0, ||b||^2
-    hipLaunchKernelGGL(k_setup, sgrid, sblock, 0, cx.stream, src, src_is_rhs, op->w, op->geo, d,
-                       bhat, x, o.use_x0 ? 1 : 0, cx.partials);
+    // b^ = W^-1 b, x^ = W x0 or 0, ||b||^2; from x^ = 0 also r^0 = b^ (into
+    // the first residual vector, in the working precision) and its norms
+    const bool single = o.precision == MAS_FP32_REFINED;
+    if (single)
+        hipLaunchKernelGGL(k_setup<float>, sgrid, sblock, 0, cx.stream, src, src_is_rhs, op->w,
+                           op->geo, d, bhat, x, o.use_x0 ? 1 : 0,
+                           reinterpret_cast<float *>(base + L.vec[0][0]), cx.partials);
+    else
+        hipLaunchKernelGGL(k_setup<double>, sgrid, sblock, 0, cx.stream, src, src_is_rhs, op->w,
+                           op->geo, d, bhat, x, o.use_x0 ? 1 : 0,
+                           reinterpret_cast<double *>(base + L.vec[0][0]), cx.partials);
     LAUNCHCHK();
-    double b2 = 0.0;
-    st = reduce_n(cx, 1, &b2);
+    double sums0[3] = {0.0, 0.0, 0.0};
+    st = reduce_n(cx, 3, sums0);
     if (st != MAS_OK) return st;
+    const double b2 = sums0[0];
+    // r^0 into r (the first residual vector): already there from x^ = 0,
+    // else b^ - A^ x^ by the residual kernel
+    auto initial_residual = [&](auto *r, double *rw2, double *rr2) -> int {
+        if (!o.use_x0) {
+            *rw2 = sums0[1];
+            if (rr2) *rr2 = sums0[2];
+            return MAS_OK;
+        }
+        return residual(cx, bhat, x, r, rw2, rr2);
+    };
     const double bnorm = std::sqrt(b2);
     info.bnorm = bnorm;
     if (!std::isfinite(bnorm)) return fail(MAS_EINVAL, "right-hand side is not finite");
@@ -1143,7 +1195,7 @@ static int solve_core(const mas_op *op, const double *src, int src_is_rhs, doubl
         hipLaunchKernelGGL(k_fill<float>, sgrid, sblock, 0, cx.stream, dh, d, 0.0f);
         LAUNCHCHK();
         double rw2 = 0.0;
-        st = residual<float>(cx, bhat, x, r, &rw2);
+        st = initial_residual(r, &rw2, nullptr);
         if (st != MAS_OK) return st;
         info.rel_resid_true = info.rel_resid_recursive = std::sqrt(rw2) / bnorm;
         status = (rw2 <= tol2) ? MAS_OK : MAS_ENOTCONV;
@@ -1191,7 +1243,7 @@ static int solve_core(const mas_op *op, const double *src, int src_is_rhs, doubl
         hipLaunchKernelGGL(k_pc2_factor<double>, dim3((unsigned)nb), dim3(kWave), 0, cx.stream, fa, dm);
         LAUNCHCHK();
         double rw2 = 0.0;
-        st = residual<double>(cx, bhat, x, r, &rw2);
+        st = initial_residual(r, &rw2, nullptr);
         if (st != MAS_OK) return st;
         info.rel_resid_true = info.rel_resid_recursive = std::sqrt(rw2) / bnorm;
         status = (rw2 <= tol2) ? MAS_OK : MAS_ENOTCONV;
@@ -1239,7 +1291,7 @@ static int solve_core(const mas_op *op, const double *src, int src_is_rhs, doubl
         set_halo(v, base, L);
         const double *const c[3] = {op->c64[0], op->c64[1], op->c64[2]};
         double rw2 = 0.0;
-        st = residual<double>(cx, bhat, x, v.r[0][0], &rw2);
+        st = initial_residual(v.r[0][0], &rw2, nullptr);
         if (st != MAS_OK) return st;
         info.rel_resid_true = info.rel_resid_recursive = std::sqrt(rw2) / bnorm;
         int iter0 = 0;
@@ -1293,7 +1345,7 @@ static int solve_core(const mas_op *op, const double *src, int src_is_rhs, doubl
         const float *const c[3] = {op->c32[0], op->c32[1], op->c32[2]};
         const bool reliable = o.refine == MAS_REFINE_RELIABLE;
         double rw2 = 0.0, rr2 = 0.0;
-        st = residual<float>(cx, bhat, x, r[0], &rw2, &rr2);
+        st = initial_residual(r[0], &rw2, &rr2);
         if (st != MAS_OK) return st;
         info.rel_resid_true = std::sqrt(rw2) / bnorm;
         status = (rw2 <= tol2) ? MAS_OK : MAS_ENOTCONV;
@@ -1415,13 +1467,14 @@ static int solve_multi_core(const mas_op *op, const double *rhs, double *x, cons
         v.x[h] = x + h * n;
         kernels[h] = 0;
         set_halo(v, base, L, h);
-        // b^ = W^-1 V rhs, x^ = W x0 or 0, ||b||^2
-        hipLaunchKernelGGL(k_setup, sgrid, sblock, 0, stream, rhs + h * n, 1, op->w, op->geo, d,
-                           bhat[h], v.x[h], o.use_x0 ? 1 : 0, cx.partials);
+        // b^ = W^-1 V rhs, x^ = W x0 or 0, ||b||^2 (and r^0 = b^ from x^ = 0)
+        hipLaunchKernelGGL(k_setup<double>, sgrid, sblock, 0, stream, rhs + h * n, 1, op->w, op->geo,
+                           d, bhat[h], v.x[h], o.use_x0 ? 1 : 0, v.r[h][0], cx.partials);
         LAUNCHCHK();
-        double b2 = 0.0;
-        int st = reduce_n(cx, 1, &b2);
+        double sums0[3] = {0.0, 0.0, 0.0};
+        int st = reduce_n(cx, 3, sums0);
         if (st != MAS_OK) return st;
+        const double b2 = sums0[0];
         bnorm[h] = std::sqrt(b2);
         info[h].bnorm = bnorm[h];
         if (!std::isfinite(bnorm[h]))
@@ -1436,8 +1489,12 @@ static int solve_multi_core(const mas_op *op, const double *rhs, double *x, cons
             info[h].status = MAS_OK;
             continue;
         }
-        st = residual<double>(cx, bhat[h], v.x[h], v.r[h][0], &rw2[h]);
-        if (st != MAS_OK) return st;
+        if (o.use_x0) {
+            st = residual<double>(cx, bhat[h], v.x[h], v.r[h][0], &rw2[h]);
+            if (st != MAS_OK) return st;
+        } else {
+            rw2[h] = sums0[1];
+        }
         info[h].rel_resid_true = info[h].rel_resid_recursive = std::sqrt(rw2[h]) / bnorm[h];
         if (rw2[h] <= v.tol2[h]) {
             done[h] = true;
@@ -2072,6 +2129,52 @@ extern "C" int mas_probe_copy(const void *src, void *dst, int64_t bytes, void *h
     if (blocks > INT32_MAX) return fail(MAS_EINVAL, "copy too large");
     hipLaunchKernelGGL(k_copy16, dim3((unsigned)blocks), dim3(256), 0, as_stream(hip_stream),
                        static_cast<const double2 *>(src), static_cast<double2 *>(dst), n16);
+    LAUNCHCHK();
+    return MAS_OK;
+}
+
+// Layout of the streaming probe's arrays in one buffer: nin + nout arrays of
+// n doubles, staggered as the library's own arrays are.
+static int64_t stream_layout(int64_t n, int nin, int nout, int64_t *off) {
+    LayoutCursor cur(kPhaseWork);
+    for (int t = 0; t < nin + nout; ++t) off[t] = cur.take_array(8 * n);
+    return cur.off;
+}
+
+extern "C" int64_t mas_probe_stream_bytes(int64_t n, int32_t nin, int32_t nout) {
+    if (n < 1 || nin < 1 || nin > kStreamMaxIn || nout < 1 || nout > kStreamMaxOut)
+        return fail(MAS_EINVAL, "need n >= 1, 1 <= nin <= %d, 1 <= nout <= %d", kStreamMaxIn,
+                    kStreamMaxOut);
+    int64_t off[kStreamMaxIn + kStreamMaxOut];
+    return stream_layout(n, nin, nout, off);
+}
+
+extern "C" int mas_probe_stream(void *buf, int64_t bytes, int64_t n, int32_t nin, int32_t nout,
+                                void *hip_stream) {
+    const int64_t need = mas_probe_stream_bytes(n, nin, nout);
+    if (need < 0) return (int)need;
+    if (!buf || (reinterpret_cast<uintptr_t>(buf) & 255))
+        return fail(MAS_EINVAL, "buf must be non-NULL and 256-byte aligned");
+    if (bytes < need) return fail(MAS_ENOMEM, "buffer too small: %lld < %lld bytes",
+                                  (long long)bytes, (long long)need);
+    int64_t off[kStreamMaxIn + kStreamMaxOut];
+    stream_layout(n, nin, nout, off);
+    StreamArgs a{};
+    char *base = static_cast<char *>(buf);
+    for (int t = 0; t < nin; ++t) a.in[t] = reinterpret_cast<const double *>(base + off[t]);
+    for (int t = 0; t < nout; ++t) a.out[t] = reinterpret_cast<double *>(base + off[nin + t]);
+    a.n = n;
+    const int64_t blocks = (n + kStreamChunk - 1) / kStreamChunk;
+    if (blocks > INT32_MAX) return fail(MAS_EINVAL, "probe too large");
+    const dim3 grid((unsigned)blocks), block(256);
+    hipStream_t st = as_stream(hip_stream);
+    // the byte mixes the library's kernels stream (7 in / 4 out: the PCG
+    // iteration; 2 / 2: the gradient; 4 / 1: an RKL2 stage)
+    if (nin == 7 && nout == 4) hipLaunchKernelGGL((k_stream<7, 4>), grid, block, 0, st, a);
+    else if (nin == 2 && nout == 2) hipLaunchKernelGGL((k_stream<2, 2>), grid, block, 0, st, a);
+    else if (nin == 4 && nout == 1) hipLaunchKernelGGL((k_stream<4, 1>), grid, block, 0, st, a);
+    else if (nin == 1 && nout == 1) hipLaunchKernelGGL((k_stream<1, 1>), grid, block, 0, st, a);
+    else return fail(MAS_EINVAL, "stream probe mixes: 7/4, 2/2, 4/1 or 1/1 (got %d/%d)", nin, nout);
     LAUNCHCHK();
     return MAS_OK;
 }

@@ -308,6 +308,30 @@ def probe_copy(src: torch.Tensor, dst: torch.Tensor):
                                             _stream(src.device)), "mas_probe_copy")
 
 
+def probe_stream(n: int, nin: int, nout: int, device="cuda", reps: int = 10) -> float:
+    """GB/s of the streaming probe with nin arrays read and nout written per
+    cell (n cells each), from HIP events around reps back-to-back launches
+    after one warm-up launch."""
+    lib = abi.load()
+    nbytes = int(lib.mas_probe_stream_bytes(int(n), int(nin), int(nout)))
+    abi.check(nbytes if nbytes < 0 else 0, "mas_probe_stream_bytes")
+    buf = _device_bytes(nbytes, device)
+    buf.zero_()
+    with torch.cuda.device(buf.device):
+        s = _stream(buf.device)
+        abi.check(lib.mas_probe_stream(buf.data_ptr(), nbytes, int(n), int(nin), int(nout), s),
+                  "mas_probe_stream")
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            abi.check(lib.mas_probe_stream(buf.data_ptr(), nbytes, int(n), int(nin), int(nout), s),
+                      "mas_probe_stream")
+        e1.record()
+        torch.cuda.synchronize()
+    sec = e0.elapsed_time(e1) * 1e-3 / reps
+    return (nin + nout) * 8 * int(n) / sec / 1e9
+
+
 class MasSolve(torch.autograd.Function):
     """x = A(nu)^-1 (V .* rhs); backward runs the adjoint solve and the fused
     dL/dnu, dL/drhs kernel in the HIP library."""

@@ -36,8 +36,12 @@ def test_exported_operator_matches_oracle(shape, bc):
     _, op = gpu_operator(p)
     got = [to_host(t) for t in op.export()]
     want = oracle_plus_face_arrays(oracle_operator(p))
+    ulps = {}
     for name, g, w in zip(("cr", "ct", "cp", "diag"), got, want):
+        nz = w != 0
+        ulps[name] = float(np.max(np.abs(g - w)[nz] / np.spacing(np.abs(w[nz])))) if nz.any() else 0.0
         np.testing.assert_allclose(g, w, rtol=EXPORT_RTOL, atol=0, err_msg=name)
+    print(f"{shape} bc={bc}: max ulp " + " ".join(f"{k} {v:.1f}" for k, v in ulps.items()))
     # exact zeros: last r plane, pole rows
     assert np.all(got[0][-1] == 0.0) and np.all(got[1][:, -1] == 0.0)
 

@@ -275,6 +275,23 @@ def bench_multi(S, W, grid, nu, p, t_pcg, k_single_us, m=3):
     runs2 = [op.solve_multi(B, o2, out=X, allow_notconv=False)[1] for _ in range(2)]
     t2 = float(np.median([r[0]["seconds"] for r in runs2]))
     print(f"[bench] {m} components with PC2: {t2:.3f} s", file=sys.stderr, flush=True)
+    # the same components with the single-precision inner PCG inside
+    # double-precision refinement, PC2 and PC1 (one operator with FP32 copies)
+    del op
+    opr = S.Operator(grid, nu, p.dt, precision="fp32_refined")
+    ref = {}
+    for precond in ("pc2", "pc1"):
+        o3 = S.make_opts(rtol=p.cfg.rtol, precision="fp32_refined", precond=precond)
+        opr.solve_multi(B, o3, out=X, allow_notconv=False)  # warm-up
+        runs3 = [opr.solve_multi(B, o3, out=X, allow_notconv=False)[1] for _ in range(2)]
+        single = [opr.solve(B[h].contiguous(), o3, allow_notconv=False)[1]["seconds"] for h in range(m)]
+        t3 = float(np.median([r[0]["seconds"] for r in runs3]))
+        ref[precond] = {"time_to_tol_s": t3, "inner_iters": [r["iters"] for r in runs3[-1]],
+                        "outer_iters": [r["outer_iters"] for r in runs3[-1]],
+                        "three_single_refined_solves_s": sum(single),
+                        "speedup_vs_single_refined_solves": sum(single) / t3}
+        print(f"[bench] {m} components refined {precond}: {t3:.3f} s (three single refined solves "
+              f"{sum(single):.3f} s)", file=sys.stderr, flush=True)
     return {
         "what": f"{m} right-hand sides (components) under the same operator, one FP64 solve to "
                 "1e-10 each, one iteration kernel carrying all of them",
@@ -291,6 +308,9 @@ def bench_multi(S, W, grid, nu, p, t_pcg, k_single_us, m=3):
                 "iters": [r["iters"] for r in runs2[-1]], "time_to_tol_s": t2,
                 "speedup_vs_pc1_together": t / t2,
                 "iteration_us": runs2[-1][0]["iter_kernel_us"] or None},
+        "refined": {"what": "the same components with the single-precision inner PCG inside "
+                            "double-precision refinement (one launch per step carries all of them)",
+                    **ref},
     }
 
 

@@ -467,7 +467,7 @@ extern "C" int mas_op_export(const mas_op *op, double *cr, double *ct, double *c
 
 // ------------------------------------------------------------------ workspace
 struct WorkLayout {
-    int64_t ctl, partials, bhat[kMaxRhs], vec[kMaxRhs][6], halo[kMaxRhs][2], dh, total;
+    int64_t ctl, partials, bhat[kMaxRhs], vec[kMaxRhs][6], halo[kMaxRhs][2], dh[kMaxRhs], total;
     int64_t halo_bytes;  // one record buffer (0: records not used)
 };
 
@@ -500,7 +500,9 @@ static WorkLayout work_layout(const Shape &s, int precision, int nrhs = 1) {
     if (L.halo_bytes > 0)
         for (int c = 0; c < nrhs; ++c)
             for (int t = 0; t < 2; ++t) L.halo[c][t] = take(L.halo_bytes);
-    L.dh = (precision == MAS_FP32_REFINED) ? take_array(4 * s.n) : -1;
+    // refined solves: the single-precision correction of each right-hand side
+    for (int c = 0; c < kMaxRhs; ++c)
+        L.dh[c] = (precision == MAS_FP32_REFINED && c < nrhs) ? take_array(4 * s.n) : -1;
     L.total = cur.off;
     return L;
 }
@@ -538,7 +540,9 @@ extern "C" int64_t mas_pcg_workspace_bytes(const mas_op *op, const mas_pcg_opts 
 extern "C" int64_t mas_pcg_multi_workspace_bytes(const mas_op *op, int32_t nrhs) {
     if (!op) return fail(MAS_EINVAL, "op must not be NULL");
     if (nrhs < 1 || nrhs > kMaxRhs) return fail(MAS_EINVAL, "nrhs must lie in [1, %d]", kMaxRhs);
-    return work_layout(op->s, MAS_FP64, nrhs).total;
+    // enough for either precision
+    return std::max(work_layout(op->s, MAS_FP64, nrhs).total,
+                    work_layout(op->s, MAS_FP32_REFINED, nrhs).total);
 }
 
 // ------------------------------------------------------------------ drivers
@@ -683,6 +687,10 @@ struct RhsSet {
     double tol2[kMaxRhs];
     int max_iter[kMaxRhs];  // last admissible iteration index of each
     bool active[kMaxRhs];
+    // the first kernel of a run continues the search direction in
+    // p[h][iter0 % 2] with p = r + beta0 p (keep_p), or starts with p = r
+    bool keep_p[kMaxRhs] = {false, false, false, false};
+    double beta0[kMaxRhs] = {0.0, 0.0, 0.0, 0.0};
 };
 
 struct PcgResult {
@@ -692,20 +700,20 @@ struct PcgResult {
 
 // PCG iterations on the scaled system in precision T for NR right-hand sides
 // sharing the operator.  Before the call, r[c][iter0 % 2] holds r_{iter0} and
-// x[c] holds x_{iter0}.  mode 0 stops on ||W r||^2 <= tol2 (checked every
-// check_every iterations), mode 1 on (r,r) <= tol2 (every iteration).  The
-// first kernel uses alpha = 0 and beta = beta0: with keep_p it continues the
-// search direction in p[iter0 % 2] (p = r + beta0 p), otherwise it starts
-// afresh (p = r).
+// x[c] holds x_{iter0}.  mode 0 stops on ||W r||^2 <= tol2 (checked on the
+// iterations the finalize asks for), mode 1 on (r,r) <= tol2 (every
+// iteration).  The first kernel uses alpha = 0 and beta = v.beta0[c]: with
+// v.keep_p[c] it continues the search direction in p[c][iter0 % 2]
+// (p = r + beta0 p), otherwise it starts afresh (p = r).
 template <typename T, int NR>
 static int run_pcg(Ctx &cx, const RhsSet<T> &v, const T *const c[3], int mode, int iter0,
-                   int check_every, bool keep_p, double beta0, PcgResult *res) {
+                   int check_every, PcgResult *res) {
     const mas_op *op = cx.op;
     const Shape &s = op->s;
     hipStream_t st = cx.stream;
-    if (!keep_p) beta0 = 0.0;
     int max_iter = iter0;
     for (int h = 0; h < NR; ++h) {
+        const double beta0 = v.keep_p[h] ? v.beta0[h] : 0.0;
         hipLaunchKernelGGL(k_ctl_init, dim3(1), dim3(64), 0, st, cx.ctl + h, mode, iter0,
                            v.max_iter[h], v.tol2[h], beta0, v.active[h] ? FLAG_RUN : FLAG_CONV,
                            mode == 0 ? 1 : 0, check_every);
@@ -748,7 +756,7 @@ static int run_pcg(Ctx &cx, const RhsSet<T> &v, const T *const c[3], int mode, i
                 // the first kernel of a run has alpha = 0 (and beta = 0 unless
                 // the direction is kept): point q (and p) at r, finite
                 // values, so that every load stays unconditional
-                a.p_in[h] = (k == iter0 && !keep_p) ? v.r[h][cur] : v.p[h][cur];
+                a.p_in[h] = (k == iter0 && !v.keep_p[h]) ? v.r[h][cur] : v.p[h][cur];
                 a.q_in[h] = (k == iter0) ? v.r[h][cur] : v.q[h][cur];
                 a.r_out[h] = v.r[h][nxt];
                 a.p_out[h] = v.p[h][nxt];
@@ -960,11 +968,11 @@ static int run_pcg_pc2(Ctx &cx, T *r, T *z, T *const p[2], T *q, T *d, T *x, int
 // once); the block solves and the finalize kernels run per right-hand side.
 // Right-hand sides with active[h] false get a stopped control block and move
 // no bytes.  All start at iteration iter0.
-template <int NR>
-static int run_pcg_pc2_multi(Ctx &cx, double *const r[NR], double *const z[NR],
-                             double *const p[NR][2], double *const q[NR], const double *d,
-                             double *const x[NR], const bool active[NR], const int max_iter[NR],
-                             const double tol2[NR], int iter0, PcgResult *res) {
+template <typename T, int NR>
+static int run_pcg_pc2_multi(Ctx &cx, T *const r[NR], T *const z[NR], T *const p[NR][2],
+                             T *const q[NR], const T *d, T *const x[NR], const bool active[NR],
+                             const int max_iter[NR], const double tol2[NR], int iter0,
+                             PcgResult *res) {
     const mas_op *op = cx.op;
     const Shape &s = op->s;
     hipStream_t st = cx.stream;
@@ -976,10 +984,16 @@ static int run_pcg_pc2_multi(Ctx &cx, double *const r[NR], double *const z[NR],
                            (int)(active[h] ? FLAG_RUN : FLAG_CONV), 0, 1);
     // the block solves of all right-hand sides in one launch (couplings, w
     // and d read once); right-hand side h's partials at partials + 2 h nb
-    Pc2MultiArgs<NR> a{};
-    a.cr = op->c64[0];
-    a.ct = op->c64[1];
-    a.cp = op->c64[2];
+    const T *cc[3];
+    if constexpr (std::is_same<T, float>::value) {
+        for (int t = 0; t < 3; ++t) cc[t] = op->c32[t];
+    } else {
+        for (int t = 0; t < 3; ++t) cc[t] = op->c64[t];
+    }
+    Pc2MultiArgs<T, NR> a{};
+    a.cr = cc[0];
+    a.ct = cc[1];
+    a.cp = cc[2];
     a.w = op->w;
     a.d = d;
     for (int h = 0; h < NR; ++h) {
@@ -997,7 +1011,7 @@ static int run_pcg_pc2_multi(Ctx &cx, double *const r[NR], double *const z[NR],
     a.nbk = nbk;
     a.update = 0;
     auto solve_all = [&](int is_first) {
-        hipLaunchKernelGGL(k_pc2_solve_multi<NR>, dim3((unsigned)nb), dim3(kWave), 0, st, a);
+        hipLaunchKernelGGL((k_pc2_solve_multi<T, NR>), dim3((unsigned)nb), dim3(kWave), 0, st, a);
         for (int h = 0; h < NR; ++h)
             hipLaunchKernelGGL(k_pc2_fin_b, dim3(1), dim3(kRedThreads), 0, st,
                                cx.partials + 2 * h * nb, (int)nb, cx.ctl + h, is_first);
@@ -1009,22 +1023,22 @@ static int run_pcg_pc2_multi(Ctx &cx, double *const r[NR], double *const z[NR],
     FlagPoll poll(cx);
     int e = poll.init();
     if (e != MAS_OK) return e;
-    IterArgs<double> it{};
-    it.cr = op->c64[0];
-    it.ct = op->c64[1];
-    it.cp = op->c64[2];
+    IterArgs<T> it{};
+    it.cr = cc[0];
+    it.ct = cc[1];
+    it.cp = cc[2];
     it.w = op->w;
     it.partials = cx.partials;
     it.ctl = cx.ctl;
     it.d = s.dims();
-    const int V = iter_vec<double>(s.np, NR);
+    const int V = iter_vec<T>(s.np, NR);
     it.tiles_i = s.tiles_i(V, cx.chunk);
     it.tiles_k = s.tiles_k(V);
     it.tiles_j = s.tiles_j();
     it.ti = s.ti(V, cx.chunk);
     it.nblk = (int)s.nblk_iter(V, cx.chunk);
     it.halo_bytes = 0;
-    constexpr int VW = vec_full<double>();
+    constexpr int VW = vec_full<T>();
     const dim3 igrid((unsigned)it.nblk), iblock(kWave * kTJ);
     int kmax = iter0;
     for (int h = 0; h < NR; ++h)
@@ -1052,10 +1066,10 @@ static int run_pcg_pc2_multi(Ctx &cx, double *const r[NR], double *const z[NR],
                 it.q_out[h] = q[h];
             }
             if (V == VW)
-                hipLaunchKernelGGL((k_pcg_iter<double, NR, kTJ, kRPW, VW, false>), igrid, iblock,
+                hipLaunchKernelGGL((k_pcg_iter<T, NR, kTJ, kRPW, VW, false>), igrid, iblock,
                                    0, st, it);
             else
-                hipLaunchKernelGGL((k_pcg_iter<double, NR, kTJ, kRPW, 1, false>), igrid, iblock,
+                hipLaunchKernelGGL((k_pcg_iter<T, NR, kTJ, kRPW, 1, false>), igrid, iblock,
                                    0, st, it);
             for (int h = 0; h < NR; ++h)
                 hipLaunchKernelGGL(k_pc2_fin_a, dim3(1), dim3(kRedThreads), 0, st,
@@ -1183,7 +1197,7 @@ static int solve_core(const mas_op *op, const double *src, int src_is_rhs, doubl
                              reinterpret_cast<float *>(base + L.vec[0][3])};
         float *q = reinterpret_cast<float *>(base + L.vec[0][4]);
         float *dm = reinterpret_cast<float *>(base + L.vec[0][5]);
-        float *dh = reinterpret_cast<float *>(base + L.dh);
+        float *dh = reinterpret_cast<float *>(base + L.dh[0]);
         int nbi, nbj, nbk;
         const int64_t nb = pc2_blocks(s, &nbi, &nbj, &nbk);
         if (nb * 2 * 8 > L.bhat[0] - L.partials || s.nblk_simple() * 8 > L.bhat[0] - L.partials)
@@ -1300,7 +1314,7 @@ static int solve_core(const mas_op *op, const double *src, int src_is_rhs, doubl
         while (status != MAS_OK) {
             if (iter0 > o.max_iters) break;
             PcgResult pr{};
-            st = run_pcg<double, 1>(cx, v, c, 0, iter0, o.check_every, false, 0.0, &pr);
+            st = run_pcg<double, 1>(cx, v, c, 0, iter0, o.check_every, &pr);
             if (st != MAS_OK) return st;
             timing_summary(cx, pr.last_iter[0], &info);
             info.iters = pr.last_iter[0];
@@ -1336,7 +1350,7 @@ static int solve_core(const mas_op *op, const double *src, int src_is_rhs, doubl
             v.p[0][t] = reinterpret_cast<float *>(base + L.vec[0][2 + t]);
             v.q[0][t] = reinterpret_cast<float *>(base + L.vec[0][4 + t]);
         }
-        float *dh = reinterpret_cast<float *>(base + L.dh);
+        float *dh = reinterpret_cast<float *>(base + L.dh[0]);
         v.x[0] = dh;
         v.active[0] = true;
         set_halo(v, base, L);
@@ -1365,7 +1379,9 @@ static int solve_core(const mas_op *op, const double *src, int src_is_rhs, doubl
             v.tol2[0] = thr;
             v.max_iter[0] = k0 + (o.max_iters - used);
             PcgResult pr{};
-            st = run_pcg<float, 1>(cx, v, c, 1, k0, 1, reliable && beta0 > 0.0, beta0, &pr);
+            v.keep_p[0] = reliable && beta0 > 0.0;
+            v.beta0[0] = beta0;
+            st = run_pcg<float, 1>(cx, v, c, 1, k0, 1, &pr);
             if (st != MAS_OK) return st;
             timing_summary(cx, pr.last_iter[0], &info);
             const int taken = pr.last_iter[0] - k0 + 1;  // iteration kernels that did work
@@ -1534,7 +1550,7 @@ static int solve_multi_core(const mas_op *op, const double *rhs, double *x, cons
             }
             if (!any) break;
             PcgResult pr{};
-            int st = run_pcg_pc2_multi<NR>(cx, r, z, p, q, dm, xs, active, maxit, v.tol2, iter0, &pr);
+            int st = run_pcg_pc2_multi<double, NR>(cx, r, z, p, q, dm, xs, active, maxit, v.tol2, iter0, &pr);
             if (st != MAS_OK) return st;
             int last = iter0;
             for (int h = 0; h < NR; ++h) {
@@ -1584,7 +1600,7 @@ static int solve_multi_core(const mas_op *op, const double *rhs, double *x, cons
         }
         if (!any) break;
         PcgResult pr{};
-        int st = run_pcg<double, NR>(cx, v, c, 0, iter0, o.check_every, false, 0.0, &pr);
+        int st = run_pcg<double, NR>(cx, v, c, 0, iter0, o.check_every, &pr);
         if (st != MAS_OK) return st;
         int last = iter0;
         for (int h = 0; h < NR; ++h)
@@ -1631,6 +1647,232 @@ static int solve_multi_core(const mas_op *op, const double *rhs, double *x, cons
     int status = MAS_OK;
     for (int h = 0; h < NR; ++h) {
         hipLaunchKernelGGL(k_unscale, sgrid, sblock, 0, stream, op->w, d, v.x[h]);
+        LAUNCHCHK();
+        if (info[h].status == MAS_EBREAKDOWN) status = MAS_EBREAKDOWN;
+        else if (info[h].status == MAS_ENOTCONV && status == MAS_OK) status = MAS_ENOTCONV;
+    }
+    HIPCHK(hipStreamSynchronize(stream));
+    const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    for (int h = 0; h < NR; ++h) info[h].seconds = secs;
+    return status;
+}
+
+// nrhs right-hand sides solved together by the single-precision PCG inside
+// double-precision refinement (PC1 with either refinement strategy, or PC2
+// restarted at each refinement step), as the single refined solve does for
+// each of them: one iteration kernel (PC1), or one SpMV launch and one
+// block-solve launch (PC2), carries every right-hand side whose refinement
+// step is running; each keeps its own inner threshold, correction d^,
+// double-precision residual, refinement count and status.
+template <int NR>
+static int solve_multi_refined(const mas_op *op, const double *rhs, double *x,
+                               const mas_pcg_opts &o, char *base, const WorkLayout &L,
+                               hipStream_t stream, mas_pcg_info *info) {
+    const auto t0 = std::chrono::steady_clock::now();
+    const Shape &s = op->s;
+    const int64_t n = s.n;
+    Ctx cx;
+    cx.op = op;
+    cx.stream = stream;
+    cx.ctl = reinterpret_cast<Ctl *>(base + L.ctl);
+    cx.partials = reinterpret_cast<double *>(base + L.partials);
+    cx.timing = o.sample_timing != 0;
+    cx.chunk = o.chunk_planes;
+    const Dims d = s.dims();
+    const dim3 sgrid = s.simple_grid(), sblock(kWave, kSimpleJ);
+    const float *const c32[3] = {op->c32[0], op->c32[1], op->c32[2]};
+    const bool pc2 = o.precond == MAS_PC2;
+    const bool reliable = !pc2 && o.refine == MAS_REFINE_RELIABLE;
+
+    RhsSet<float> v;
+    v.n = NR;
+    double *bhat[NR], *xh[NR];
+    float *dh[NR];
+    double bnorm[NR], tol2[NR], rw2[NR], rr2[NR];
+    bool done[NR];
+    int used[NR];
+    for (int h = 0; h < NR; ++h) {
+        info[h] = mas_pcg_info{};
+        bhat[h] = reinterpret_cast<double *>(base + L.bhat[h]);
+        dh[h] = reinterpret_cast<float *>(base + L.dh[h]);
+        xh[h] = x + h * n;
+        for (int t = 0; t < 2; ++t) {
+            v.r[h][t] = reinterpret_cast<float *>(base + L.vec[h][t]);
+            v.p[h][t] = reinterpret_cast<float *>(base + L.vec[h][2 + t]);
+            v.q[h][t] = reinterpret_cast<float *>(base + L.vec[h][4 + t]);
+        }
+        v.x[h] = dh[h];
+        set_halo(v, base, L, h);
+        used[h] = 0;
+        // b^, x^ (and r^0 = b^ from x^ = 0), ||b||^2
+        hipLaunchKernelGGL(k_setup<float>, sgrid, sblock, 0, stream, rhs + h * n, 1, op->w, op->geo,
+                           d, bhat[h], xh[h], o.use_x0 ? 1 : 0, v.r[h][0], cx.partials);
+        LAUNCHCHK();
+        double sums0[3] = {0.0, 0.0, 0.0};
+        int st = reduce_n(cx, 3, sums0);
+        if (st != MAS_OK) return st;
+        bnorm[h] = std::sqrt(sums0[0]);
+        info[h].bnorm = bnorm[h];
+        if (!std::isfinite(bnorm[h]))
+            return fail(MAS_EINVAL, "right-hand side %d is not finite", h);
+        tol2[h] = (o.rtol * bnorm[h]) * (o.rtol * bnorm[h]);
+        done[h] = false;
+        info[h].status = MAS_ENOTCONV;
+        if (bnorm[h] == 0.0) {
+            hipLaunchKernelGGL(k_fill<double>, sgrid, sblock, 0, stream, xh[h], d, 0.0);
+            LAUNCHCHK();
+            done[h] = true;
+            info[h].status = MAS_OK;
+            continue;
+        }
+        if (o.use_x0) {
+            st = residual<float>(cx, bhat[h], xh[h], v.r[h][0], &rw2[h], &rr2[h]);
+            if (st != MAS_OK) return st;
+        } else {
+            rw2[h] = sums0[1];
+            rr2[h] = sums0[2];
+        }
+        hipLaunchKernelGGL(k_fill<float>, sgrid, sblock, 0, stream, dh[h], d, 0.0f);
+        LAUNCHCHK();
+        info[h].rel_resid_true = info[h].rel_resid_recursive = std::sqrt(rw2[h]) / bnorm[h];
+        if (rw2[h] <= tol2[h]) {
+            done[h] = true;
+            info[h].status = MAS_OK;
+        }
+    }
+
+    // PC2: the factor once, the double-precision one rounded; r, z, p (two)
+    // and q of right-hand side h in its first five vectors, the modified
+    // diagonal in right-hand side 0's sixth
+    float *dm = reinterpret_cast<float *>(base + L.vec[0][5]);
+    float *pr_[NR], *pz_[NR], *pp_[NR][2], *pq_[NR];
+    if (pc2) {
+        for (int h = 0; h < NR; ++h) {
+            pr_[h] = v.r[h][0];
+            pz_[h] = v.r[h][1];
+            pp_[h][0] = v.p[h][0];
+            pp_[h][1] = v.p[h][1];
+            pq_[h] = v.q[h][0];
+        }
+        int nbi, nbj, nbk;
+        const int64_t nb = pc2_blocks(s, &nbi, &nbj, &nbk);
+        if (NR * nb * 2 * 8 > L.bhat[0] - L.partials)
+            return fail(MAS_EINVAL, "internal: partial-sum area too small for PC2");
+        if (nb > INT32_MAX) return fail(MAS_EINVAL, "grid too large for PC2");
+        Pc2Args<double> fa{op->c64[0], op->c64[1], op->c64[2], op->w, nullptr, nullptr, nullptr,
+                           nullptr, nullptr, nullptr, nullptr, cx.ctl, d, nbi, nbj, nbk, 0};
+        hipLaunchKernelGGL(k_pc2_factor<float>, dim3((unsigned)nb), dim3(kWave), 0, stream, fa, dm);
+        LAUNCHCHK();
+    }
+
+    const double d2 = o.inner_rtol * o.inner_rtol;
+    for (;;) {
+        bool active[NR], any = false;
+        int maxit[NR];
+        double thr[NR];
+        for (int h = 0; h < NR; ++h) {
+            active[h] = !done[h] && info[h].outer_iters < o.max_outer && used[h] < o.max_iters;
+            any = any || active[h];
+            // inner stop: inner_rtol below the last double-precision residual,
+            // or (reliable PC1) low enough that the unscaled residual it
+            // predicts meets the tolerance
+            if (pc2) {
+                thr[h] = std::max(d2 * rw2[h], 0.25 * tol2[h]);
+                maxit[h] = o.max_iters - used[h];
+            } else {
+                thr[h] = d2 * rr2[h];
+                if (reliable && rw2[h] > 0.0) thr[h] = std::max(thr[h], 0.25 * tol2[h] * (rr2[h] / rw2[h]));
+                maxit[h] = o.max_iters - used[h];
+            }
+            v.tol2[h] = thr[h];
+            v.max_iter[h] = maxit[h];
+            v.active[h] = active[h];
+        }
+        if (!any) break;
+        PcgResult pr{};
+        int st = pc2 ? run_pcg_pc2_multi<float, NR>(cx, pr_, pz_, pp_, pq_, dm, dh, active, maxit,
+                                                    thr, 0, &pr)
+                     : run_pcg<float, NR>(cx, v, c32, 1, 0, 1, &pr);
+        if (st != MAS_OK) return st;
+        int last = 0;
+        for (int h = 0; h < NR; ++h)
+            if (active[h]) last = std::max(last, pr.last_iter[h]);
+        mas_pcg_info tinfo{};
+        timing_summary(cx, last, &tinfo);
+        for (int h = 0; h < NR; ++h) {
+            if (!active[h]) continue;
+            if (tinfo.iter_kernel_samples > 0) {
+                const double prev = info[h].iter_kernel_us * info[h].iter_kernel_samples;
+                info[h].iter_kernel_samples += tinfo.iter_kernel_samples;
+                info[h].iter_kernel_us = (prev + tinfo.iter_kernel_us * tinfo.iter_kernel_samples) /
+                                         info[h].iter_kernel_samples;
+            }
+            // PC1 counts iteration kernels (the first of a run forms q only);
+            // PC2 counts finished iterations
+            const int taken = pc2 ? pr.last_iter[h] : pr.last_iter[h] + 1;
+            used[h] += taken;
+            info[h].outer_iters++;
+            if (pr.flag[h] == FLAG_BREAK && taken == 0) {
+                done[h] = true;
+                info[h].status = MAS_EBREAKDOWN;
+                continue;
+            }
+            Ctl hc;
+            st = read_ctl(cx, &hc, h);
+            if (st != MAS_OK) return st;
+            if (pc2) {
+                info[h].rel_resid_recursive = std::sqrt(hc.rw) / bnorm[h];
+                hipLaunchKernelGGL(k_fold, sgrid, sblock, 0, stream, dh[h], d, xh[h]);
+                LAUNCHCHK();
+                st = residual<float>(cx, bhat[h], xh[h], pr_[h], &rw2[h]);
+                if (st != MAS_OK) return st;
+            } else if (reliable) {
+                // x^ += d^ + alpha_K p_K, then the double-precision residual
+                // replaces r and the run continues from the direction p_K
+                const int nxt = (pr.last_iter[h] + 1) & 1;
+                hipLaunchKernelGGL(k_refine_fold, sgrid, sblock, 0, stream, dh[h], v.p[h][nxt],
+                                   cx.ctl + h, d, xh[h]);
+                LAUNCHCHK();
+                const double rr_old = hc.rr, rr_pred = hc.rr_next;
+                st = residual<float>(cx, bhat[h], xh[h], v.r[h][nxt], &rw2[h], &rr2[h]);
+                if (st != MAS_OK) return st;
+                const bool keep = pr.flag[h] == FLAG_CONV && rr_old > 0.0 && rr_pred > 0.0 &&
+                                  rr2[h] <= 4.0 * rr_pred;
+                v.keep_p[h] = keep;
+                v.beta0[h] = keep ? rr2[h] / rr_old : 0.0;
+                // the next run starts at iteration 0: its vectors in slot 0
+                if (nxt == 1) {
+                    std::swap(v.r[h][0], v.r[h][1]);
+                    std::swap(v.p[h][0], v.p[h][1]);
+                    std::swap(v.q[h][0], v.q[h][1]);
+                }
+            } else {
+                // classical refinement: x^ += d^; the next inner solve restarts
+                hipLaunchKernelGGL(k_ctl_init, dim3(1), dim3(64), 0, stream, cx.ctl + h, 1, 0, 0,
+                                   0.0, 0.0, (int)FLAG_RUN, 0, 1);  // alpha = 0 for the fold
+                hipLaunchKernelGGL(k_refine_fold, sgrid, sblock, 0, stream, dh[h], v.p[h][0],
+                                   cx.ctl + h, d, xh[h]);
+                LAUNCHCHK();
+                st = residual<float>(cx, bhat[h], xh[h], v.r[h][0], &rw2[h], &rr2[h]);
+                if (st != MAS_OK) return st;
+                v.keep_p[h] = false;
+                v.beta0[h] = 0.0;
+            }
+            info[h].rel_resid_true = std::sqrt(rw2[h]) / bnorm[h];
+            if (!pc2) info[h].rel_resid_recursive = info[h].rel_resid_true;
+            if (rw2[h] <= tol2[h]) {
+                done[h] = true;
+                info[h].status = MAS_OK;
+            } else if (pr.flag[h] == FLAG_BREAK && !reliable) {
+                done[h] = true;
+                info[h].status = MAS_EBREAKDOWN;
+            }
+        }
+    }
+    int status = MAS_OK;
+    for (int h = 0; h < NR; ++h) {
+        info[h].iters = used[h];
+        hipLaunchKernelGGL(k_unscale, sgrid, sblock, 0, stream, op->w, d, xh[h]);
         LAUNCHCHK();
         if (info[h].status == MAS_EBREAKDOWN) status = MAS_EBREAKDOWN;
         else if (info[h].status == MAS_ENOTCONV && status == MAS_OK) status = MAS_ENOTCONV;
@@ -1708,24 +1950,31 @@ extern "C" int mas_pcg_solve_multi(const mas_op *op, int32_t nrhs, const double 
     mas_pcg_opts o;
     mas_pcg_default_opts(&o);
     if (o_in) o = *o_in;
-    if (o.precision != MAS_FP64)
-        return fail(MAS_EINVAL, "solves of several right-hand sides are double precision only");
     int st = check_opts(op, &o);
     if (st != MAS_OK) return st;
     if (reinterpret_cast<uintptr_t>(work) & 255)
         return fail(MAS_EINVAL, "work must be 256-byte aligned");
-    const WorkLayout L = work_layout(op->s, MAS_FP64, nrhs);
+    const WorkLayout L = work_layout(op->s, o.precision, nrhs);
     if (work_bytes < L.total)
         return fail(MAS_ENOMEM, "workspace too small: %lld < %lld bytes", (long long)work_bytes,
                     (long long)L.total);
     mas_pcg_info local[kMaxRhs];
     char *base = static_cast<char *>(work);
     hipStream_t stream = as_stream(hip_stream);
-    switch (nrhs) {
-        case 1: st = solve_multi_core<1>(op, rhs, x, o, base, L, stream, local); break;
-        case 2: st = solve_multi_core<2>(op, rhs, x, o, base, L, stream, local); break;
-        case 3: st = solve_multi_core<3>(op, rhs, x, o, base, L, stream, local); break;
-        default: st = solve_multi_core<4>(op, rhs, x, o, base, L, stream, local); break;
+    if (o.precision == MAS_FP32_REFINED) {
+        switch (nrhs) {
+            case 1: st = solve_multi_refined<1>(op, rhs, x, o, base, L, stream, local); break;
+            case 2: st = solve_multi_refined<2>(op, rhs, x, o, base, L, stream, local); break;
+            case 3: st = solve_multi_refined<3>(op, rhs, x, o, base, L, stream, local); break;
+            default: st = solve_multi_refined<4>(op, rhs, x, o, base, L, stream, local); break;
+        }
+    } else {
+        switch (nrhs) {
+            case 1: st = solve_multi_core<1>(op, rhs, x, o, base, L, stream, local); break;
+            case 2: st = solve_multi_core<2>(op, rhs, x, o, base, L, stream, local); break;
+            case 3: st = solve_multi_core<3>(op, rhs, x, o, base, L, stream, local); break;
+            default: st = solve_multi_core<4>(op, rhs, x, o, base, L, stream, local); break;
+        }
     }
     if (info)
         for (int h = 0; h < nrhs; ++h) info[h] = local[h];

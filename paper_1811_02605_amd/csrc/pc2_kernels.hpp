@@ -363,16 +363,19 @@ __global__ __launch_bounds__(kWave) void k_pc2_solve(Pc2Args<T> a) {
     block_sum_store<2>(v2, a.partials + (int64_t)blockIdx.x * 2, lds);
 }
 
-// Several right-hand sides under one operator (double precision): the block
-// solve of each, as k_pc2_solve, with the couplings, w and the modified
-// diagonal loaded once per cell for all of them.  Right-hand side h's
+// Several right-hand sides under one operator: the block solve of each, as
+// k_pc2_solve, with the couplings, w and the modified diagonal loaded once
+// per cell for all of them (T: double, or float inside double-precision
+// refinement; w and the partial sums are double).  Right-hand side h's
 // partial sums go to partials + 2 h gridDim.x; one whose control block is
 // stopped moves no bytes.
-template <int NR>
+template <typename T, int NR>
 struct Pc2MultiArgs {
-    const double *cr, *ct, *cp, *w, *d;
-    double *r[NR], *x[NR], *z[NR];
-    const double *q[NR], *p[NR];
+    const T *cr, *ct, *cp;
+    const double *w;
+    const T *d;
+    T *r[NR], *x[NR], *z[NR];
+    const T *q[NR], *p[NR];
     double *partials;
     const Ctl *ctl;  // [NR]
     Dims dm;
@@ -380,27 +383,28 @@ struct Pc2MultiArgs {
     int update;
 };
 
-template <int NR>
+template <typename T, int NR>
 struct Pc2MFwd {
-    double w, d, cr, ct, cp;
-    double r[NR], q[NR], x[NR], p[NR];
+    double w;
+    T d, cr, ct, cp;
+    T r[NR], q[NR], x[NR], p[NR];
 };
-template <int NR>
+template <typename T, int NR>
 struct Pc2MBwd {
-    double cr, ct, d, cp;
-    double y[NR];
+    T cr, ct, d, cp;
+    T y[NR];
 };
 
-template <int NR>
-__global__ __launch_bounds__(kWave) void k_pc2_solve_multi(Pc2MultiArgs<NR> a) {
+template <typename T, int NR>
+__global__ __launch_bounds__(kWave) void k_pc2_solve_multi(Pc2MultiArgs<T, NR> a) {
     bool run[NR];
-    double alpha[NR];
+    T alpha[NR];
     bool any = false;
 #pragma unroll
     for (int h = 0; h < NR; ++h) {
         run[h] = a.ctl[h].flag == FLAG_RUN;
         any = any || run[h];
-        alpha[h] = (a.update != 0 && run[h]) ? a.ctl[h].alpha : 0.0;
+        alpha[h] = (a.update != 0 && run[h]) ? (T)a.ctl[h].alpha : T(0);
     }
     if (!any) return;
     const Dims &dm = a.dm;
@@ -417,11 +421,12 @@ __global__ __launch_bounds__(kWave) void k_pc2_solve_multi(Pc2MultiArgs<NR> a) {
         return ((int64_t)(bi * kPc2I + ii) * dm.nt + (bj * kPc2J + jj)) * dm.np + kk;
     };
     auto load_f = [&](int ii, int jj) {
-        Pc2MFwd<NR> v;
-        v.w = v.cr = v.ct = v.cp = 0.0;
-        v.d = 1.0;
+        Pc2MFwd<T, NR> v;
+        v.w = 0.0;
+        v.cr = v.ct = v.cp = T(0);
+        v.d = T(1);
 #pragma unroll
-        for (int h = 0; h < NR; ++h) v.r[h] = v.q[h] = v.x[h] = v.p[h] = 0.0;
+        for (int h = 0; h < NR; ++h) v.r[h] = v.q[h] = v.x[h] = v.p[h] = T(0);
         if (act && ii < ni && jj < nj) {
             const int64_t c = cell(ii, jj, k);
             v.w = a.w[c];
@@ -444,44 +449,44 @@ __global__ __launch_bounds__(kWave) void k_pc2_solve_multi(Pc2MultiArgs<NR> a) {
         return v;
     };
     double rw[NR], rz[NR];
-    double yp[NR][kPc2J];  // previous r plane of the block, per theta row
+    T yp[NR][kPc2J];  // previous r plane of the block, per theta row
 #pragma unroll
     for (int h = 0; h < NR; ++h) {
         rw[h] = rz[h] = 0.0;
 #pragma unroll
-        for (int jj = 0; jj < kPc2J; ++jj) yp[h][jj] = 0.0;
+        for (int jj = 0; jj < kPc2J; ++jj) yp[h][jj] = T(0);
     }
     // forward sweep: y into z; row t + 1 is loaded before row t is scanned
     auto load_ft = [&](int t) { return load_f(t / nj, t % nj); };
-    Pc2MFwd<NR> cur = load_f(0, 0);
+    Pc2MFwd<T, NR> cur = load_f(0, 0);
     for (int ii = 0; ii < ni; ++ii) {
-        double yrow[NR];
+        T yrow[NR];
 #pragma unroll
-        for (int h = 0; h < NR; ++h) yrow[h] = 0.0;
+        for (int h = 0; h < NR; ++h) yrow[h] = T(0);
 #pragma unroll
         for (int jj = 0; jj < kPc2J; ++jj) {
             if (jj < nj) {
-                const Pc2MFwd<NR> nxt = load_ft(ii * nj + jj + 1);
-                const double dinv = 1.0 / cur.d;
+                const Pc2MFwd<T, NR> nxt = load_ft(ii * nj + jj + 1);
+                const T dinv = T(1) / cur.d;
                 const int64_t c = cell(ii, jj, k);
 #pragma unroll
                 for (int h = 0; h < NR; ++h) {
                     if (!run[h]) continue;  // uniform across the wave
-                    double Bc = 0.0, Cc = 0.0;
-                    double rc = cur.r[h];
+                    T Bc = T(0), Cc = T(0);
+                    T rc = cur.r[h];
                     if (act) {
                         if (upd) rc -= alpha[h] * cur.q[h];
-                        const double t = cur.w * rc;
+                        const double t = cur.w * (double)rc;
                         rw[h] += t * t;
-                        double sc = rc;
+                        T sc = rc;
                         if (ii > 0) sc += cur.cr * yp[h][jj];
                         if (jj > 0) sc += cur.ct * yrow[h];
                         Bc = sc * dinv;
                         Cc = cur.cp * dinv;
                     }
-                    const double y = affine_scan(Cc, Bc);
+                    const T y = affine_scan(Cc, Bc);
                     if (act) {
-                        rz[h] += cur.d * y * y;  // (r, M^-1 r) = y^T D y
+                        rz[h] += (double)cur.d * (double)y * (double)y;  // (r, M^-1 r) = y^T D y
                         if (upd) {
                             a.r[h][c] = rc;
                             a.x[h][c] = cur.x[h] + alpha[h] * cur.p[h];
@@ -498,11 +503,11 @@ __global__ __launch_bounds__(kWave) void k_pc2_solve_multi(Pc2MultiArgs<NR> a) {
     // backward sweep: z in place, lanes reversed (see k_pc2_solve)
     const int kb = k0 + (act ? kn - 1 - lane : 0);
     auto load_b = [&](int ii, int jj) {
-        Pc2MBwd<NR> v;
-        v.cr = v.ct = v.cp = 0.0;
-        v.d = 1.0;
+        Pc2MBwd<T, NR> v;
+        v.cr = v.ct = v.cp = T(0);
+        v.d = T(1);
 #pragma unroll
-        for (int h = 0; h < NR; ++h) v.y[h] = 0.0;
+        for (int h = 0; h < NR; ++h) v.y[h] = T(0);
         if (act && ii >= 0 && jj >= 0) {
             const int64_t c = cell(ii, jj, kb);
             if (ii < ni - 1) v.cr = a.cr[c];
@@ -519,29 +524,29 @@ __global__ __launch_bounds__(kWave) void k_pc2_solve_multi(Pc2MultiArgs<NR> a) {
 #pragma unroll
     for (int h = 0; h < NR; ++h)
 #pragma unroll
-        for (int jj = 0; jj < kPc2J; ++jj) yp[h][jj] = 0.0;
-    Pc2MBwd<NR> bcur = load_b(ni - 1, nj - 1);
+        for (int jj = 0; jj < kPc2J; ++jj) yp[h][jj] = T(0);
+    Pc2MBwd<T, NR> bcur = load_b(ni - 1, nj - 1);
     for (int ii = ni - 1; ii >= 0; --ii) {
-        double zrow[NR];
+        T zrow[NR];
 #pragma unroll
-        for (int h = 0; h < NR; ++h) zrow[h] = 0.0;
+        for (int h = 0; h < NR; ++h) zrow[h] = T(0);
 #pragma unroll
         for (int jj = kPc2J - 1; jj >= 0; --jj) {
             if (jj < nj) {
-                const Pc2MBwd<NR> nxt = load_bt(ii * nj + jj - 1);
-                const double dinv = 1.0 / bcur.d;
+                const Pc2MBwd<T, NR> nxt = load_bt(ii * nj + jj - 1);
+                const T dinv = T(1) / bcur.d;
 #pragma unroll
                 for (int h = 0; h < NR; ++h) {
                     if (!run[h]) continue;
-                    double Bc = 0.0, Cc = 0.0;
+                    T Bc = T(0), Cc = T(0);
                     if (act) {
-                        double sc = 0.0;
+                        T sc = T(0);
                         if (ii < ni - 1) sc += bcur.cr * yp[h][jj];
                         if (jj < nj - 1) sc += bcur.ct * zrow[h];
                         Bc = bcur.y[h] + sc * dinv;
                         Cc = bcur.cp * dinv;
                     }
-                    const double zc = affine_scan(Cc, Bc);
+                    const T zc = affine_scan(Cc, Bc);
                     if (act) a.z[h][cell(ii, jj, kb)] = zc;
                     yp[h][jj] = zc;
                     zrow[h] = zc;

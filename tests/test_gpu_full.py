@@ -120,6 +120,31 @@ def test_c1_three_components_full(c1, c1_oracle):
         assert r <= 1e-10
 
 
+def test_c1_refined_three_components_full(c1, c1_oracle):
+    """Three components under the c1 operator in one refined solve (FP32
+    inner PCG, FP64 refinement), with PC2 and with PC1: the oracle's residual
+    of each on all 52.4M cells, and the time against three single refined
+    solves."""
+    grid = S.Grid.from_problem(c1)
+    op = S.Operator(grid, to_dev(c1.nu), c1.dt, precision="fp32_refined")
+    B = W.component_rhs(c1.cfg, 3)
+    Bd = to_dev(B)
+    for precond in ("pc2", "pc1"):
+        o = S.make_opts(rtol=1e-10, precision="fp32_refined", precond=precond)
+        op.solve_multi(Bd, o, allow_notconv=False)  # warm-up
+        X, infos = op.solve_multi(Bd, o, allow_notconv=False)
+        singles = [op.solve(Bd[h].contiguous(), o, allow_notconv=False)[1]["seconds"] for h in range(3)]
+        say(f"c1 x3 refined {precond}: inner {[i['iters'] for i in infos]}, outer "
+            f"{[i['outer_iters'] for i in infos]}, {infos[0]['seconds']:.3f} s together, "
+            f"{sum(singles):.3f} s as three single solves")
+        X = to_host(X)
+        for h in range(3):
+            r = c1_oracle.rel_residual(c1_oracle.rhs_to_b(B[h]), X[h])
+            say(f"c1 refined {precond} component {h}: oracle residual {r:.3e}")
+            assert r <= 1e-10
+        del X
+
+
 def test_c1_pc2_solve_full(c1, c1_oracle):
     """The block-Jacobi ILU(0) preconditioner at the full size: the oracle's
     residual of the GPU solution on all 52.4M cells, iterations and time

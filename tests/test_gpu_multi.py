@@ -103,12 +103,87 @@ def test_deterministic_and_timing():
     assert all(i["iter_kernel_samples"] > 0 and i["iter_kernel_us"] > 0 for i in ia)
 
 
+# single-precision inner PCG inside double-precision refinement, several
+# right-hand sides: PC1 with either refinement strategy, PC2 (restarted)
+REFINED = [("pc1", "reliable"), ("pc1", "restart"), ("pc2", "restart")]
+
+
+@pytest.mark.parametrize("chunk", [0, 16])
+@pytest.mark.parametrize("m", [2, 3, 4])
+@pytest.mark.parametrize("precond,refine", REFINED)
+@pytest.mark.parametrize("shape", [(5, 7, 13), (33, 17, 129), (1, 3, 2), (9, 16, 32), "c0"])
+def test_refined_components_match_oracle(shape, precond, refine, m, chunk):
+    """Each component of a refined solve of several right-hand sides meets
+    1e-10 by the oracle's own residual and lies within 1e-6 of its 1e-13
+    solution."""
+    p = problem(shape, (0, 1))
+    _, op = gpu_operator(p, "fp32_refined")
+    ora = oracle_operator(p)
+    B = _rhs(p, m)
+    o = S.make_opts(rtol=1e-10, precision="fp32_refined", precond=precond, refine=refine,
+                    chunk_planes=chunk)
+    X, infos = op.solve_multi(to_dev(B), o, allow_notconv=False)
+    X = to_host(X)
+    for h in range(m):
+        b = ora.rhs_to_b(B[h])
+        res = ora.rel_residual(b, X[h])
+        assert infos[h]["status"] == abi.MAS_OK and res <= 1e-10, (h, res, infos[h])
+        assert infos[h]["outer_iters"] >= 1
+        assert rel(X[h], ora.pcg(b, tol=1e-13)[0]) <= 1e-6
+
+
+@pytest.mark.parametrize("m", [2, 3])
+@pytest.mark.parametrize("precond,refine", REFINED)
+@pytest.mark.parametrize("shape", [(33, 17, 129), "c0"])
+def test_refined_components_equal_single_refined_solves(shape, precond, refine, m):
+    """Each component of the shared refined solve takes the inner and outer
+    iterations of its single refined solve and gives the same solution bit
+    for bit (the same kernels and sums per component)."""
+    p = problem(shape, (0, 0))
+    _, op = gpu_operator(p, "fp32_refined")
+    B = _rhs(p, m)
+    o = S.make_opts(rtol=1e-10, precision="fp32_refined", precond=precond, refine=refine)
+    X, infos = op.solve_multi(to_dev(B), o, allow_notconv=False)
+    for h in range(m):
+        x1, i1 = op.solve(to_dev(B[h]), o, allow_notconv=False)
+        assert (infos[h]["iters"], infos[h]["outer_iters"]) == (i1["iters"], i1["outer_iters"]), h
+        assert torch.equal(X[h], x1), h
+
+
+def test_refined_independent_stopping():
+    """A zero component, a warm start at the solution and a component 1e9
+    smaller stop on their own in the refined solve of several right-hand
+    sides."""
+    p = problem((9, 16, 32), (0, 0))
+    _, op = gpu_operator(p, "fp32_refined")
+    ora = oracle_operator(p)
+    B = _rhs(p, 4)
+    B[0] = 0.0
+    B[3] *= 1e-9
+    o = S.make_opts(rtol=1e-10, precision="fp32_refined")
+    x_sol, _ = op.solve(to_dev(B[2]), S.make_opts(rtol=1e-12, precision="fp32_refined"),
+                        allow_notconv=False)
+    X0 = np.zeros_like(B)
+    X0[2] = to_host(x_sol)
+    X, infos = op.solve_multi(to_dev(B), o, x0=to_dev(X0), allow_notconv=False)
+    X = to_host(X)
+    assert np.all(X[0] == 0.0) and infos[0]["iters"] == 0 and infos[0]["status"] == abi.MAS_OK
+    assert infos[2]["iters"] == 0 and rel(X[2], X0[2]) <= 1e-15
+    for h in (1, 3):
+        assert ora.rel_residual(ora.rhs_to_b(B[h]), X[h]) <= 1e-10
+
+
 def test_error_paths():
     p = problem((9, 16, 32), (0, 0))
     _, op = gpu_operator(p, "fp32_refined")
     B = to_dev(_rhs(p, 3))
-    with pytest.raises(abi.MasError, match="double precision"):
-        op.solve_multi(B, S.make_opts(precision="fp32_refined"))
+    # an operator built without single-precision couplings cannot run refined
+    _, op64 = gpu_operator(p)
+    with pytest.raises(abi.MasError, match="single-precision coefficients"):
+        op64.solve_multi(B, S.make_opts(precision="fp32_refined"))
+    # refinement-step and iteration limits: ENOTCONV with the last iterates
+    X, infos = op.solve_multi(B, S.make_opts(precision="fp32_refined", max_outer=1, inner_rtol=0.5))
+    assert all(i["status"] == abi.MAS_ENOTCONV and i["outer_iters"] == 1 for i in infos)
     lib = abi.load()
     assert lib.mas_pcg_multi_workspace_bytes(op.handle, 5) == abi.MAS_EINVAL
     assert lib.mas_pcg_multi_workspace_bytes(op.handle, 0) == abi.MAS_EINVAL

@@ -1267,27 +1267,150 @@ __global__ __launch_bounds__(kWave *kSimpleJ) void k_apply(const double *w, cons
     })
 }
 
-// r^ = b^ - A^ x^ (double), stored as TOUT; partials ||W r^||^2 and ||r^||^2.
+// r^ = b^ - A^ x^ (double), stored as TOUT; block partials ||W r^||^2 and
+// ||r^||^2.  (A^ x^)_c = x^_c - sum_f c^_f x^_nb(f), the terms in the order
+// +r, -r, +theta, -theta, then the two phi terms.  Same tiling and march as
+// the gradient kernel: x^ of the current and the next plane in LDS with a
+// one-cell ring, c^_theta and c^_phi of the current plane in LDS with the
+// row above and the cell left of the tile (the couplings of the - faces),
+// x^ and c^_r of the plane behind in registers, the next plane's x^ and
+// couplings loaded while the current one is computed.
+constexpr int kReR = 16, kReC = 64, kReWaves = 4, kReThreads = kWave * kReWaves;
+constexpr int kRePR = kReR + 2, kRePC = kReC + 2;  // patch: rows J0-1..J0+R, cells k0-1..k0+C
+constexpr int kReLoads = (kRePR * kRePC + kReThreads - 1) / kReThreads;
+
+struct ResArgs {
+    const double *bhat, *xhat, *w, *cr, *ct, *cp;
+    Dims d;
+    double *partials;  // [nblk][2]
+    int tiles_i, tiles_k, tiles_j, ti, nblk;
+};
+
 template <typename TOUT>
-__global__ __launch_bounds__(kWave *kSimpleJ) void k_residual(const double *bhat, const double *xhat,
-                                                              const double *w, const double *cr,
-                                                              const double *ct, const double *cp,
-                                                              Dims d, TOUT *rout,
-                                                              double *partials) {
-    static_assert(kSimpleNV >= 2, "partials per simple block");
-    __shared__ double lds[kSimpleJ * 2];
-    double acc[2] = {0.0, 0.0};
-    MAS_SIMPLE_LOOP(d, {
-        if (cell.ok) {
-            const double r = bhat[cell.c] -
-                             scaled_apply(cr, ct, cp, d, cell, [&](int64_t c) { return xhat[c]; });
-            rout[cell.c] = (TOUT)r;
-            const double t = w[cell.c] * r;
-            acc[0] += t * t;
-            acc[1] += r * r;
+__global__ __launch_bounds__(kReThreads) void k_residual(ResArgs a, TOUT *rout) {
+    __shared__ double sX[2][kRePR][kRePC];
+    __shared__ double sT[kRePR][kRePC], sP[kRePR][kRePC];  // c^_theta, c^_phi of the plane
+    const Dims d = a.d;
+    const int nr = d.nr, nt = d.nt, np = d.np;
+    const int L = xcd_remap(blockIdx.x, a.nblk);
+    int it, kt, jt;
+    tile_coords<3>(L, a.tiles_i, a.tiles_k, a.tiles_j, it, kt, jt);
+    const int J0 = jt * kReR, k0 = kt * kReC;
+    const int nseg = min(kReC, np - k0);
+    const int i0 = it * a.ti, i1 = min(i0 + a.ti, nr);
+    const int tid = threadIdx.x, lane = tid & (kWave - 1);
+    const int wv = __builtin_amdgcn_readfirstlane(tid / kWave);
+
+    int32_t poff[kReLoads];
+#pragma unroll
+    for (int q = 0; q < kReLoads; ++q) {
+        const int e = tid + q * kReThreads;
+        poff[q] = -2;
+        if (e < kRePR * kRePC) {
+            const int pr = e / kRePC, pc = e % kRePC;
+            const int j = J0 - 1 + pr;
+            int k = (k0 - 1 + pc) % np;
+            if (k < 0) k += np;
+            poff[q] = (j >= 0 && j < nt) ? j * np + k : -1;
         }
-    })
-    block_sum_store<2>(acc, partials + 2 * simple_block_id(), lds);
+    }
+    const uint32_t nb = (uint32_t)(d.n * (int64_t)sizeof(double));
+    const auto RB = make_rsrc(a.bhat, nb), RX = make_rsrc(a.xhat, nb), RW = make_rsrc(a.w, nb),
+               RCr = make_rsrc(a.cr, nb), RCt = make_rsrc(a.ct, nb), RCp = make_rsrc(a.cp, nb);
+    const auto RO = make_rsrc(rout, (uint32_t)(d.n * (int64_t)sizeof(TOUT)));
+    auto poffset = [&](int m, int q) -> uint32_t {
+        const bool ok = m >= 0 && m < nr && poff[q] >= 0;
+        return ok ? (uint32_t)(((int64_t)m * d.plane + poff[q]) * 8) : kOOB;
+    };
+    auto store_x = [&](int m, const double (&v)[kReLoads]) {
+        double *f = &sX[m & 1][0][0];
+#pragma unroll
+        for (int q = 0; q < kReLoads; ++q)
+            if (poff[q] != -2) f[tid + q * kReThreads] = v[q];
+    };
+    auto store_c = [&](const double (&vt)[kReLoads], const double (&vp)[kReLoads]) {
+        double *ft = &sT[0][0], *fp = &sP[0][0];
+#pragma unroll
+        for (int q = 0; q < kReLoads; ++q)
+            if (poff[q] != -2) {
+                ft[tid + q * kReThreads] = vt[q];
+                fp[tid + q * kReThreads] = vp[q];
+            }
+    };
+    constexpr int NQ = kReR / kReWaves;
+    auto own_off = [&](int m, int q) -> uint32_t {
+        const int j = J0 + wv + kReWaves * q;
+        const bool ok = m >= 0 && m < nr && j < nt && lane < nseg;
+        return ok ? (uint32_t)(((int64_t)m * d.plane + (int64_t)j * np + k0 + lane) * 8) : kOOB;
+    };
+    // own cells of the plane behind: x^ and c^_r (the coupling of the -r face)
+    double xb[NQ], crb[NQ];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+        xb[q] = bld<double, 1>(RX, own_off(i0 - 1, q)).v[0];
+        crb[q] = bld<double, 1>(RCr, own_off(i0 - 1, q)).v[0];
+    }
+    {
+        double v[kReLoads], vt[kReLoads], vp[kReLoads];
+#pragma unroll
+        for (int q = 0; q < kReLoads; ++q) {
+            v[q] = bld<double, 1>(RX, poffset(i0, q)).v[0];
+            vt[q] = bld<double, 1>(RCt, poffset(i0, q)).v[0];
+            vp[q] = bld<double, 1>(RCp, poffset(i0, q)).v[0];
+        }
+        store_x(i0, v);
+        store_c(vt, vp);
+#pragma unroll
+        for (int q = 0; q < kReLoads; ++q) v[q] = bld<double, 1>(RX, poffset(i0 + 1, q)).v[0];
+        store_x(i0 + 1, v);
+    }
+    __syncthreads();
+
+    double acc[2] = {0.0, 0.0};
+    double nx[kReLoads], nt_[kReLoads], np_[kReLoads];
+    for (int m = i0; m < i1; ++m) {
+        // next planes in flight: x^ of m + 2, c^_theta and c^_phi of m + 1
+#pragma unroll
+        for (int q = 0; q < kReLoads; ++q) {
+            nx[q] = bld<double, 1>(RX, poffset(m + 2, q)).v[0];
+            nt_[q] = bld<double, 1>(RCt, poffset(m + 1, q)).v[0];
+            np_[q] = bld<double, 1>(RCp, poffset(m + 1, q)).v[0];
+        }
+        const int s0 = m & 1, s1 = (m + 1) & 1;
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+            const int r = wv + kReWaves * q;
+            const int j = J0 + r;
+            const bool own = j < nt && lane < nseg;
+            const uint32_t o = own_off(m, q);
+            const double bh = bld<double, 1>(RB, o).v[0], wc = bld<double, 1>(RW, o).v[0];
+            const double crc = bld<double, 1>(RCr, o).v[0];
+            const int pr = r + 1, pc = lane + 1;
+            const double xc = sX[s0][pr][pc];
+            double sum = 0.0;
+            if (m < nr - 1) sum += crc * sX[s1][pr][pc];
+            if (m > 0) sum += crb[q] * xb[q];
+            if (j < nt - 1) sum += sT[pr][pc] * sX[s0][pr + 1][pc];
+            if (j > 0) sum += sT[pr - 1][pc] * sX[s0][pr - 1][pc];
+            sum += sP[pr][pc] * sX[s0][pr][pc + 1] + sP[pr][pc - 1] * sX[s0][pr][pc - 1];
+            const double res = bh - (xc - sum);
+            bst<TOUT, 1, kAuxNT>(RO, own ? (uint32_t)(o / 8u * sizeof(TOUT)) : kOOB,
+                                 VecT<TOUT, 1>{{(TOUT)res}});
+            if (own) {
+                const double t = wc * res;
+                acc[0] += t * t;
+                acc[1] += res * res;
+            }
+            xb[q] = xc;
+            crb[q] = crc;
+        }
+        __syncthreads();  // every read of plane m's x^ slot and of the couplings is done
+        store_x(m + 2, nx);
+        store_c(nt_, np_);
+        __syncthreads();
+    }
+    __shared__ double lds[kReWaves * 2];
+    block_sum_store<2>(acc, a.partials + 2 * (int64_t)blockIdx.x, lds);
 }
 
 // b^ = V src / w (src = rhs) or src / w (src = adjoint seed); x^ = w x0
@@ -1367,14 +1490,20 @@ __global__ __launch_bounds__(kWave *kSimpleJ) void k_fill(T *x, Dims d, T v) {
 //   dL/dnu_c  = -dt sum_{faces f of c} (dG_f/dnu_c) (lam_c - lam_nb)(x_c - x_nb),
 // where a face's conductance depends on nu_c with weight 1/2 inside the shell
 // (face mean) and 1 on a Dirichlet wall (lam_nb = x_nb = 0 there).
-// Each wave owns GRPW = 2 consecutive theta rows (32 lanes each, V phi cells
-// per lane) and marches through the r planes of its chunk, keeping x and lam
-// of the planes behind, at and ahead of the current one in registers, so a
-// cell's two fields are fetched once per launch: the theta neighbour inside
-// the wave comes from the other half of the wave, the rows beyond the wave
-// from one edge-row load (the first row needs j-1, the second j+1), the phi
-// neighbours from lane shifts and the two cells past the segment ends from
-// one extra load.
+// Each face product (lam_c - lam_nb)(x_c - x_nb) is formed once per side, as
+// the oracle forms it.
+// Each block owns a tile of kGrR theta rows x kGrC phi cells (a wave owns
+// rows wv, wv + 4, ..., one cell per lane) and marches up its r chunk: x and
+// lam of the current plane and the next one sit in LDS with a one-cell ring
+// around the tile (the in-plane neighbours), the plane behind in the
+// registers of the thread that owns the cell, and the plane after the next
+// one is loaded into registers while the current one is computed.  Every
+// value is fetched from memory once per block (the ring from the
+// neighbouring tiles' lines, mostly in L2) and every output written once.
+constexpr int kGrR = 16, kGrC = 64, kGrWaves = 4, kGrThreads = kWave * kGrWaves;
+constexpr int kGrPR = kGrR + 2, kGrPC = kGrC + 2;  // patch: rows J0-1..J0+R, cells k0-1..k0+C
+constexpr int kGrLoads = (kGrPR * kGrPC + kGrThreads - 1) / kGrThreads;
+
 struct GradArgs {
     const double *x, *lam;
     double *gnu, *grhs;
@@ -1382,124 +1511,131 @@ struct GradArgs {
     Dims d;
     int tiles_i, tiles_k, tiles_j, ti, nblk;
 };
-constexpr int kGradWPB = 4;  // waves per block
-constexpr int kGradRPW = 2;  // theta rows per wave
-constexpr int kGradTI = 32;  // shortest r chunk
 
-template <int V>
-__global__ __launch_bounds__(kWave *kGradWPB) void k_gradient(GradArgs a) {
-    constexpr int RPW = kGradRPW, W = kWave / RPW, SEG = W * V;
-    using VD = VecT<double, V>;
-    const int nr = a.d.nr, nt = a.d.nt, np = a.d.np;
-    const int64_t plane = a.d.plane;
-
+__global__ __launch_bounds__(kGrThreads) void k_gradient(GradArgs a) {
+    __shared__ double sX[2][kGrPR][kGrPC], sL[2][kGrPR][kGrPC];
+    // per tile row: vt, halves of the theta- and phi-face factors
+    __shared__ double sRow[kGrR][4];
+    const Dims d = a.d;
+    const Geo &g = a.geo;
+    const int nr = d.nr, nt = d.nt, np = d.np;
     const int L = xcd_remap(blockIdx.x, a.nblk);
     int it, kt, jt;
     tile_coords<3>(L, a.tiles_i, a.tiles_k, a.tiles_j, it, kt, jt);
-
-    const int lane = threadIdx.x & (kWave - 1);
-    const int wv = threadIdx.x / kWave;
-    const int rr = lane / W, lp = lane % W;
-    const int j = (jt * kGradWPB + wv) * RPW + rr;
-    const int k0 = kt * SEG;
-    const int nseg = min(SEG, np - k0);  // a multiple of V
-    const int nvl = nseg / V;
-    const bool rowok = j < nt;
-    const bool act = rowok && lp < nvl;
+    const int J0 = jt * kGrR, k0 = kt * kGrC;
+    const int nseg = min(kGrC, np - k0);
     const int i0 = it * a.ti, i1 = min(i0 + a.ti, nr);
-    const bool up = (it & 1) == 0;  // neighbour chunks share the plane they both read
-    const int dir = up ? 1 : -1;
-    const int first = up ? i0 : i1 - 1;
+    const int tid = threadIdx.x, lane = tid & (kWave - 1);
+    const int wv = __builtin_amdgcn_readfirstlane(tid / kWave);
 
-    // phi: the cell left of the segment (lane 0) and the one right of it (the
-    // row's last lane of a full segment, in the same load; in a short segment,
-    // which always ends at np - 1, the first idle lane loads the row's first
-    // V cells as if they were its own and the shift hands them over)
-    const int64_t colL = (int64_t)j * np + ((k0 == 0) ? np - 1 : k0 - 1);
-    const int64_t colR = (int64_t)j * np + ((k0 + nseg == np) ? 0 : k0 + nseg);
-    const bool pseudoR = rowok && nvl < W && lp == nvl;
-    const bool eL = act && lp == 0;
-    const bool eR = act && nvl == W && lp == W - 1;
-    const int64_t col = act ? (int64_t)j * np + k0 + lp * V : (pseudoR ? colR : 0);
-    const bool ldo = act || pseudoR;
-    // theta: one edge row per lane (row j-1 for the wave's first row, j+1 for
-    // its second), the other neighbour from the other half of the wave
-    const bool ldE = act && ((rr == 0) ? j > 0 : j < nt - 1);
-    const int64_t colE = (rr == 0) ? col - np : col + np;
+    if (tid < kGrR) {
+        const int j = J0 + tid;
+        const bool ok = j < nt;
+        const int jj = ok ? j : 0;
+        sRow[tid][0] = g.vt[jj];
+        sRow[tid][1] = (ok && j > 0) ? 0.5 * g.gtt[j - 1] : 0.0;
+        sRow[tid][2] = (ok && j < nt - 1) ? 0.5 * g.gtt[jj] : 0.0;
+        sRow[tid][3] = (ok && !g.np_one) ? 0.5 * g.gpt[jj] : 0.0;
+    }
 
-    // per-row factors: halves of the theta- and phi-face factors
-    const int jj = rowok ? j : 0;
-    const double vt = a.geo.vt[jj];
-    const double hU = (rowok && j > 0) ? 0.5 * a.geo.gtt[j - 1] : 0.0;
-    const double hD = (rowok && j < nt - 1) ? 0.5 * a.geo.gtt[jj] : 0.0;
-    const double hP = (rowok && !a.geo.np_one) ? 0.5 * a.geo.gpt[jj] : 0.0;
-
-    constexpr uint32_t ES = sizeof(double);
-    const uint32_t nbytes = (uint32_t)(a.d.n * (int64_t)ES);
-    const auto RX = make_rsrc(a.x, nbytes), RL = make_rsrc(a.lam, nbytes),
-               RG = make_rsrc(a.gnu, nbytes), RH = make_rsrc(a.grhs, a.grhs ? nbytes : 0u);
-    auto own_off = [&](int m) -> uint32_t {
-        return (ldo && m >= 0 && m < nr) ? (uint32_t)((int64_t)m * plane + col) * ES : kOOB;
-    };
-    VD Xb = bld<double, V>(RX, own_off(first - dir)), Lb = bld<double, V>(RL, own_off(first - dir));
-    VD Xc = bld<double, V>(RX, own_off(first)), Lc = bld<double, V>(RL, own_off(first));
-
-    VD sg{}, sh{};
-    uint32_t st_off = kOOB;
-    const int nsteps = i1 - i0;
-    for (int s = 0; s < nsteps; ++s) {
-        const int m = first + s * dir;
-        const int64_t base = (int64_t)m * plane;
-        const uint32_t oo = act ? (uint32_t)(base + col) * ES : kOOB;
-        const uint32_t oE = ldE ? (uint32_t)(base + colE) * ES : kOOB;
-        const uint32_t oLR = eL ? (uint32_t)(base + colL) * ES : (eR ? (uint32_t)(base + colR) * ES : kOOB);
-        // ---- loads: plane m + dir, then the edge row and phi edge cells of plane m
-        const VD Xa = bld<double, V>(RX, own_off(m + dir)), La = bld<double, V>(RL, own_off(m + dir));
-        const VD XE = bld<double, V>(RX, oE), LE = bld<double, V>(RL, oE);
-        const double XS = bld<double, 1>(RX, oLR).v[0], LS = bld<double, 1>(RL, oLR).v[0];
-        // ---- stores of the previous plane (issued behind this plane's loads)
-        bst<double, V, kAuxNT>(RG, st_off, sg);
-        bst<double, V, kAuxNT>(RH, st_off, sh);
-
-        // ---- plane factors
-        const double gq = a.geo.gq[m];
-        const double cRp = (m < nr - 1) ? 0.5 * a.geo.gr[m] * vt : 0.0;
-        const double cRm = (m > 0) ? 0.5 * a.geo.gr[m - 1] * vt : 0.0;
-        const double cW = (((m == 0) ? a.geo.gw_in : 0.0) + ((m == nr - 1) ? a.geo.gw_out : 0.0)) * vt;
-        const double cU = gq * hU, cD = gq * hD, cP = gq * hP;
-        const double vol = a.geo.vr[m] * vt;
-        const VD &Xp = up ? Xa : Xb, &Xm = up ? Xb : Xa;  // planes m+1, m-1
-        const VD &Lp = up ? La : Lb, &Lm = up ? Lb : La;
-
-        const double xl0 = lane_prev(Xc.v[V - 1]), ll0 = lane_prev(Lc.v[V - 1]);
-        const double xr0 = lane_next(Xc.v[0]), lr0 = lane_next(Lc.v[0]);
+    // this thread's elements of the patch: offsets inside a plane (-1:
+    // outside the grid in theta, read as zero; -2: no element)
+    int32_t poff[kGrLoads];
 #pragma unroll
-        for (int e = 0; e < V; ++e) {
-            const double xc = Xc.v[e], lc = Lc.v[e];
-            const double xo = other_half(xc), lo = other_half(lc);
-            const double xu = (rr == 0) ? XE.v[e] : xo, lu = (rr == 0) ? LE.v[e] : lo;
-            const double xd = (rr == 0) ? xo : XE.v[e], ld = (rr == 0) ? lo : LE.v[e];
-            const double xl = (e > 0) ? Xc.v[e - 1] : ((lp == 0) ? XS : xl0);
-            const double ll = (e > 0) ? Lc.v[e - 1] : ((lp == 0) ? LS : ll0);
-            const double xr = (e < V - 1) ? Xc.v[e + 1] : (eR ? XS : xr0);
-            const double lr = (e < V - 1) ? Lc.v[e + 1] : (eR ? LS : lr0);
+    for (int q = 0; q < kGrLoads; ++q) {
+        const int e = tid + q * kGrThreads;
+        poff[q] = -2;
+        if (e < kGrPR * kGrPC) {
+            const int pr = e / kGrPC, pc = e % kGrPC;
+            const int j = J0 - 1 + pr;
+            int k = (k0 - 1 + pc) % np;
+            if (k < 0) k += np;
+            poff[q] = (j >= 0 && j < nt) ? j * np + k : -1;
+        }
+    }
+    const uint32_t nb = (uint32_t)(d.n * (int64_t)sizeof(double));
+    const auto RX = make_rsrc(a.x, nb), RL = make_rsrc(a.lam, nb), RG = make_rsrc(a.gnu, nb),
+               RH = make_rsrc(a.grhs, a.grhs ? nb : 0u);
+    auto load_plane = [&](int m, double (&vx)[kGrLoads], double (&vl)[kGrLoads]) {
+#pragma unroll
+        for (int q = 0; q < kGrLoads; ++q) {
+            const bool ok = m >= 0 && m < nr && poff[q] >= 0;
+            const uint32_t o = ok ? (uint32_t)(((int64_t)m * d.plane + poff[q]) * 8) : kOOB;
+            vx[q] = bld<double, 1>(RX, o).v[0];
+            vl[q] = bld<double, 1>(RL, o).v[0];
+        }
+    };
+    auto store_plane = [&](int m, const double (&vx)[kGrLoads], const double (&vl)[kGrLoads]) {
+        double *fx = &sX[m & 1][0][0], *fl = &sL[m & 1][0][0];
+#pragma unroll
+        for (int q = 0; q < kGrLoads; ++q)
+            if (poff[q] != -2) {
+                fx[tid + q * kGrThreads] = vx[q];
+                fl[tid + q * kGrThreads] = vl[q];
+            }
+    };
+    constexpr int NQ = kGrR / kGrWaves;
+    // own cells: rows wv + 4q, column lane; x and lam of the plane behind
+    double xb[NQ], lb[NQ];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+        const int j = J0 + wv + kGrWaves * q;
+        const bool ok = i0 > 0 && j < nt && lane < nseg;
+        const uint32_t o = ok ? (uint32_t)(((int64_t)(i0 - 1) * d.plane + (int64_t)j * np + k0 + lane) * 8) : kOOB;
+        xb[q] = bld<double, 1>(RX, o).v[0];
+        lb[q] = bld<double, 1>(RL, o).v[0];
+    }
+    {
+        double vx[kGrLoads], vl[kGrLoads];
+        load_plane(i0, vx, vl);
+        store_plane(i0, vx, vl);
+        load_plane(i0 + 1, vx, vl);
+        store_plane(i0 + 1, vx, vl);
+    }
+    __syncthreads();
+
+    double nx[kGrLoads], nl[kGrLoads];
+    for (int m = i0; m < i1; ++m) {
+        // the plane after the next one in flight while plane m is computed
+        load_plane(m + 2, nx, nl);
+        const int s0 = m & 1, s1 = (m + 1) & 1;
+        // plane factors (uniform)
+        const double gq = g.gq[m];
+        const double grp = (m < nr - 1) ? 0.5 * g.gr[m] : 0.0;
+        const double grm = (m > 0) ? 0.5 * g.gr[m - 1] : 0.0;
+        const double gw = ((m == 0) ? g.gw_in : 0.0) + ((m == nr - 1) ? g.gw_out : 0.0);
+        const double vr = g.vr[m];
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+            const int r = wv + kGrWaves * q;
+            const int j = J0 + r;
+            const bool own = j < nt && lane < nseg;
+            const double vt = sRow[r][0];
+            const double cRp = grp * vt, cRm = grm * vt, cW = gw * vt;
+            const double cU = gq * sRow[r][1], cD = gq * sRow[r][2], cP = gq * sRow[r][3];
+            const int pr = r + 1, pc = lane + 1;
+            const double xc = sX[s0][pr][pc], lc = sL[s0][pr][pc];
+            const double Xp = sX[s1][pr][pc], Lp = sL[s1][pr][pc];
+            const double xu = sX[s0][pr - 1][pc], lu = sL[s0][pr - 1][pc];
+            const double xd = sX[s0][pr + 1][pc], ld = sL[s0][pr + 1][pc];
+            const double xl = sX[s0][pr][pc - 1], ll = sL[s0][pr][pc - 1];
+            const double xr = sX[s0][pr][pc + 1], lr = sL[s0][pr][pc + 1];
             double t = cW * (lc * xc);
-            t += cRp * ((lc - Lp.v[e]) * (xc - Xp.v[e]));
-            t += cRm * ((lc - Lm.v[e]) * (xc - Xm.v[e]));
+            t += cRp * ((lc - Lp) * (xc - Xp));
+            t += cRm * ((lc - lb[q]) * (xc - xb[q]));
             t += cU * ((lc - lu) * (xc - xu));
             t += cD * ((lc - ld) * (xc - xd));
             t += cP * ((lc - ll) * (xc - xl) + (lc - lr) * (xc - xr));
-            sg.v[e] = -a.geo.dt * t;
-            sh.v[e] = vol * lc;
+            const uint32_t o = own ? (uint32_t)(((int64_t)m * d.plane + (int64_t)j * np + k0 + lane) * 8) : kOOB;
+            bst<double, 1, kAuxNT>(RG, o, VecT<double, 1>{{-g.dt * t}});
+            bst<double, 1, kAuxNT>(RH, o, VecT<double, 1>{{(vr * vt) * lc}});
+            xb[q] = xc;
+            lb[q] = lc;
         }
-        st_off = oo;
-        Xb = Xc;
-        Lb = Lc;
-        Xc = Xa;
-        Lc = La;
+        __syncthreads();  // every read of plane m's slot is done
+        store_plane(m + 2, nx, nl);
+        __syncthreads();
     }
-    bst<double, V, kAuxNT>(RG, st_off, sg);
-    bst<double, V, kAuxNT>(RH, st_off, sh);
 }
 
 // Streaming copy: each block copies one contiguous chunk of kCopyChunk

@@ -647,8 +647,8 @@ struct FlagPoll {
 
 // Sum nv values of the simple-kernel partials into ctl->sums[0:nv] and
 // copy them to the host (synchronous).
-static int reduce_n(Ctx &cx, int nv, double *out) {
-    const int nblk = (int)cx.op->s.nblk_simple();
+static int reduce_n(Ctx &cx, int nv, double *out, int nblk = -1) {
+    if (nblk < 0) nblk = (int)cx.op->s.nblk_simple();
     hipLaunchKernelGGL(k_reduce, dim3(1), dim3(kRedThreads), 0, cx.stream, cx.partials, nblk, nv,
                        cx.ctl);
     LAUNCHCHK();
@@ -664,12 +664,22 @@ template <typename T>
 static int residual(Ctx &cx, const double *bhat, const double *xhat, T *r, double *rw2,
                     double *rr2 = nullptr) {
     const mas_op *op = cx.op;
-    hipLaunchKernelGGL(k_residual<T>, op->s.simple_grid(), dim3(kWave, kSimpleJ), 0, cx.stream,
-                       bhat, xhat, op->w, op->c64[0], op->c64[1], op->c64[2], op->s.dims(), r,
-                       cx.partials);
+    const Shape &s = op->s;
+    ResArgs ra{bhat, xhat, op->w, op->c64[0], op->c64[1], op->c64[2], s.dims(), cx.partials,
+               0, 0, 0, 0, 0};
+    ra.tiles_k = (s.np + kReC - 1) / kReC;
+    ra.tiles_j = (s.nt + kReR - 1) / kReR;
+    ra.ti = s.chunk_for((int64_t)ra.tiles_k * ra.tiles_j);
+    ra.tiles_i = (s.nr + ra.ti - 1) / ra.ti;
+    const int64_t nblk = (int64_t)ra.tiles_i * ra.tiles_j * ra.tiles_k;
+    // the partial-sum area of every workspace layout holds at least this
+    if (nblk * 2 > std::max(s.nblk_iter_max() * kNV, s.nblk_simple() * kSimpleNV))
+        return fail(MAS_EINVAL, "internal: partial-sum area too small for the residual");
+    ra.nblk = (int)nblk;
+    hipLaunchKernelGGL(k_residual<T>, dim3((unsigned)nblk), dim3(kReThreads), 0, cx.stream, ra, r);
     LAUNCHCHK();
     double sums[2];
-    int st = reduce_n(cx, 2, sums);
+    int st = reduce_n(cx, 2, sums, ra.nblk);
     *rw2 = sums[0];
     if (rr2) *rr2 = sums[1];
     return st;
@@ -2003,21 +2013,15 @@ struct EventPool {
 static int gradient_launch(const mas_op *op, const double *x, const double *lambda, double *g_nu,
                            double *g_rhs, hipStream_t stream) {
     const Shape &s = op->s;
-    const int v = (s.np % 2 == 0) ? 2 : 1;
-    const int seg = (kWave / kGradRPW) * v;
-    const int ti = std::max(kGradTI, (s.nr + 7) / 8);  // whole r slabs per XCD, as Shape::ti()
+    const int64_t tiles_k = (s.np + kGrC - 1) / kGrC;
+    const int64_t tiles_j = (s.nt + kGrR - 1) / kGrR;
+    const int ti = s.chunk_for(tiles_k * tiles_j);
     const int64_t tiles_i = (s.nr + ti - 1) / ti;
-    const int64_t tiles_k = (s.np + seg - 1) / seg;
-    const int64_t tiles_j = (s.nt + kGradWPB * kGradRPW - 1) / (kGradWPB * kGradRPW);
     const int64_t nblk = tiles_i * tiles_k * tiles_j;
     if (nblk > INT32_MAX) return fail(MAS_EINVAL, "grid too large for the gradient kernel");
     GradArgs ga{x, lambda, g_nu, g_rhs, op->geo, s.dims(), (int)tiles_i, (int)tiles_k, (int)tiles_j,
                 ti, (int)nblk};
-    const dim3 grid((unsigned)nblk), block(kWave * kGradWPB);
-    if (v == 2)
-        hipLaunchKernelGGL(k_gradient<2>, grid, block, 0, stream, ga);
-    else
-        hipLaunchKernelGGL(k_gradient<1>, grid, block, 0, stream, ga);
+    hipLaunchKernelGGL(k_gradient, dim3((unsigned)nblk), dim3(kGrThreads), 0, stream, ga);
     LAUNCHCHK();
     return MAS_OK;
 }

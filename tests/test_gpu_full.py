@@ -42,7 +42,10 @@ def test_c1_operator_and_apply_full(c1, c1_oracle):
     got = [to_host(t) for t in op.export()]
     want = oracle_plus_face_arrays(c1_oracle)
     for name, g, w in zip(("cr", "ct", "cp", "diag"), got, want):
-        np.testing.assert_allclose(g, w, rtol=64 * 2.0 ** -52, atol=0, err_msg=name)
+        nz = w != 0
+        say(f"c1 {name}: max {float(np.max(np.abs(g - w)[nz] / np.spacing(np.abs(w[nz])))):.1f} ulp")
+        # the bound of the small-grid export test (measured maximum + 2 ulp)
+        np.testing.assert_allclose(g, w, rtol=10 * 2.0 ** -52, atol=0, err_msg=name)
     del got, want
     x = np.random.default_rng(5).standard_normal(c1.shape)
     y = to_host(op.apply(to_dev(x)))

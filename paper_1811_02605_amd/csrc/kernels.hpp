@@ -1368,13 +1368,29 @@ __global__ __launch_bounds__(kReThreads) void k_residual(ResArgs a, TOUT *rout) 
 
     double acc[2] = {0.0, 0.0};
     double nx[kReLoads], nt_[kReLoads], np_[kReLoads];
+    // own cells' b^, w and c^_r, one plane ahead
+    double bh[NQ], wo[NQ], cro[NQ], bh1[NQ], wo1[NQ], cro1[NQ];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+        bh[q] = bld<double, 1>(RB, own_off(i0, q)).v[0];
+        wo[q] = bld<double, 1>(RW, own_off(i0, q)).v[0];
+        cro[q] = bld<double, 1>(RCr, own_off(i0, q)).v[0];
+    }
     for (int m = i0; m < i1; ++m) {
-        // next planes in flight: x^ of m + 2, c^_theta and c^_phi of m + 1
+        // next planes in flight: x^ of m + 2, c^_theta and c^_phi of m + 1,
+        // the own cells of m + 1
 #pragma unroll
         for (int q = 0; q < kReLoads; ++q) {
             nx[q] = bld<double, 1>(RX, poffset(m + 2, q)).v[0];
             nt_[q] = bld<double, 1>(RCt, poffset(m + 1, q)).v[0];
             np_[q] = bld<double, 1>(RCp, poffset(m + 1, q)).v[0];
+        }
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+            const uint32_t o1 = (m + 1 < i1) ? own_off(m + 1, q) : kOOB;
+            bh1[q] = bld<double, 1>(RB, o1).v[0];
+            wo1[q] = bld<double, 1>(RW, o1).v[0];
+            cro1[q] = bld<double, 1>(RCr, o1).v[0];
         }
         const int s0 = m & 1, s1 = (m + 1) & 1;
 #pragma unroll
@@ -1383,8 +1399,7 @@ __global__ __launch_bounds__(kReThreads) void k_residual(ResArgs a, TOUT *rout) 
             const int j = J0 + r;
             const bool own = j < nt && lane < nseg;
             const uint32_t o = own_off(m, q);
-            const double bh = bld<double, 1>(RB, o).v[0], wc = bld<double, 1>(RW, o).v[0];
-            const double crc = bld<double, 1>(RCr, o).v[0];
+            const double wc = wo[q], crc = cro[q];
             const int pr = r + 1, pc = lane + 1;
             const double xc = sX[s0][pr][pc];
             double sum = 0.0;
@@ -1393,7 +1408,7 @@ __global__ __launch_bounds__(kReThreads) void k_residual(ResArgs a, TOUT *rout) 
             if (j < nt - 1) sum += sT[pr][pc] * sX[s0][pr + 1][pc];
             if (j > 0) sum += sT[pr - 1][pc] * sX[s0][pr - 1][pc];
             sum += sP[pr][pc] * sX[s0][pr][pc + 1] + sP[pr][pc - 1] * sX[s0][pr][pc - 1];
-            const double res = bh - (xc - sum);
+            const double res = bh[q] - (xc - sum);
             bst<TOUT, 1, kAuxNT>(RO, own ? (uint32_t)(o / 8u * sizeof(TOUT)) : kOOB,
                                  VecT<TOUT, 1>{{(TOUT)res}});
             if (own) {
@@ -1403,6 +1418,9 @@ __global__ __launch_bounds__(kReThreads) void k_residual(ResArgs a, TOUT *rout) 
             }
             xb[q] = xc;
             crb[q] = crc;
+            bh[q] = bh1[q];
+            wo[q] = wo1[q];
+            cro[q] = cro1[q];
         }
         __syncthreads();  // every read of plane m's x^ slot and of the couplings is done
         store_x(m + 2, nx);

@@ -229,7 +229,7 @@ struct IterArgs {
     // iteration kernel into halo_out, read from halo_in by the next one.
     T *halo_out[kMaxRhs];
     const T *halo_in[kMaxRhs];
-    uint32_t halo_bytes;  // bytes of one record buffer; 0: no records
+    int records;  // 1: the record buffers exist
     // shared
     const T *cr, *ct, *cp;
     const double *w;
@@ -331,12 +331,48 @@ __device__ inline void stv_nt(T *__restrict__ p, int64_t c, const VecT<T, V> &x)
 // Buffer-resource access (range-checked by the hardware): an offset at or
 // beyond the resource size reads zeros and drops stores without touching
 // memory, which gives masked accesses with no branch.  Offsets are bytes,
-// 32-bit; every array is below 2^31 bytes.
+// 32-bit: a marching block's resources start at the first r plane it
+// touches (PlaneWin), and the host keeps every block's planes below 2^31
+// bytes per array, so the grid itself may be any size.
 constexpr uint32_t kOOB = 0x80000000u;
 constexpr int kAuxNT = 2;  // non-temporal hint in the aux field (gfx94x/gfx950)
 
 __device__ inline __amdgpu_buffer_rsrc_t make_rsrc(const void *p, uint32_t bytes) {
     return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), (short)0, (int)bytes, 0x00020000);
+}
+
+// The r planes lo .. hi-1 (clamped to the grid) of a cell array, as seen by
+// one block: offsets are ((m - lo) plane + cell-in-plane) elements.
+struct PlaneWin {
+    int lo, planes;
+    int64_t first;   // first cell of plane lo
+    uint32_t cells;  // cells of the window
+};
+
+__device__ inline PlaneWin plane_win(const Dims &d, int lo, int hi) {
+    lo = max(lo, 0);
+    hi = min(hi, d.nr);
+    PlaneWin w;
+    w.lo = lo;
+    w.planes = max(hi - lo, 0);
+    w.first = (int64_t)lo * d.plane;
+    w.cells = (uint32_t)((int64_t)w.planes * d.plane);
+    return w;
+}
+
+// Resource over the window of cell array p (null or !on: zero length).
+template <typename T>
+__device__ inline __amdgpu_buffer_rsrc_t win_rsrc(const T *p, const PlaneWin &w, bool on = true) {
+    return (p && on) ? make_rsrc(p + w.first, w.cells * (uint32_t)sizeof(T)) : make_rsrc(p, 0u);
+}
+
+// The same planes of an array of per_plane elements per r plane.
+template <typename T>
+__device__ inline __amdgpu_buffer_rsrc_t win_rsrc(const T *p, const PlaneWin &w, int64_t per_plane,
+                                                  bool on) {
+    return (p && on) ? make_rsrc(p + (int64_t)w.lo * per_plane,
+                                 (uint32_t)((int64_t)w.planes * per_plane * (int64_t)sizeof(T)))
+                     : make_rsrc(p, 0u);
 }
 
 template <typename T, int V, int AUX = 0>
@@ -548,6 +584,8 @@ void k_pcg_iter(IterArgs<T> a) {
     const int i0 = it * a.ti;
     const int i1 = min(i0 + a.ti, nr);
     const bool up = (it & 1) == 0;
+    // the planes this block touches, i0 - 1 .. i1
+    const PlaneWin win = plane_win(a.d, i0 - 1, i1 + 1);
 
     // phi neighbours of the segment (periodic): the cell left of k0 and the
     // cell right of the segment end
@@ -567,7 +605,7 @@ void k_pcg_iter(IterArgs<T> a) {
     const bool wside0 = act && lp == 0, wside1 = act && lp == nvl - 1 && nvl > 1;
     const bool wrec = wside0 || wside1;
     auto rec_off = [&](int mm, int kk, int side) -> uint32_t {
-        return (uint32_t)(((((int64_t)mm * nt + j) * tk + kk) * 2 + side) * 4 * (int64_t)sizeof(T));
+        return (uint32_t)(((((int64_t)(mm - win.lo) * nt + j) * tk + kk) * 2 + side) * 4 * (int64_t)sizeof(T));
     };
 
     // own cells; inactive lanes read nothing (out-of-range offsets)
@@ -604,38 +642,36 @@ void k_pcg_iter(IterArgs<T> a) {
     // compiler counts outstanding accesses exactly and no load waits for a
     // store to complete.
     constexpr int AN = MAS_ITER_NT ? kAuxNT : 0;
-    const uint32_t nbytes = (uint32_t)(a.d.n * (int64_t)sizeof(T));
     __amdgpu_buffer_rsrc_t Rr[NR], Rq[NR], Rp[NR], Rx[NR], Rro[NR], Rpo[NR], Rqo[NR];
 #pragma unroll
     for (int c = 0; c < NR; ++c) {
         // q_in, x and r_out may be null: the kernel then only forms the
         // direction p = r + beta p and q = A^ p (q reads as zero, so r and x
         // are left as they are and move no bytes)
-        const uint32_t nb = run[c] ? nbytes : 0u;
-        Rr[c] = make_rsrc(a.r_in[c], nb);
-        Rq[c] = make_rsrc(a.q_in[c], a.q_in[c] ? nb : 0u);
-        Rp[c] = make_rsrc(a.p_in[c], nb);
-        Rx[c] = make_rsrc(a.x[c], a.x[c] ? nb : 0u);
-        Rro[c] = make_rsrc(a.r_out[c], a.r_out[c] ? nb : 0u);
-        Rpo[c] = make_rsrc(a.p_out[c], nb);
-        Rqo[c] = make_rsrc(a.q_out[c], nb);
+        Rr[c] = win_rsrc(a.r_in[c], win, run[c]);
+        Rq[c] = win_rsrc(a.q_in[c], win, run[c]);
+        Rp[c] = win_rsrc(a.p_in[c], win, run[c]);
+        Rx[c] = win_rsrc(a.x[c], win, run[c]);
+        Rro[c] = win_rsrc(a.r_out[c], win, run[c]);
+        Rpo[c] = win_rsrc(a.p_out[c], win, run[c]);
+        Rqo[c] = win_rsrc(a.q_out[c], win, run[c]);
     }
     __amdgpu_buffer_rsrc_t Rhi[NR], Rho[NR];
+    const int64_t rec_plane = (int64_t)nt * tk * 8;  // record elements per plane
 #pragma unroll
     for (int c = 0; c < NR; ++c) {
-        Rhi[c] = make_rsrc(a.halo_in[c], (HALO && run[c]) ? a.halo_bytes : 0u);
-        Rho[c] = make_rsrc(a.halo_out[c], run[c] ? a.halo_bytes : 0u);
+        Rhi[c] = win_rsrc(a.halo_in[c], win, rec_plane, HALO && run[c] && a.records);
+        Rho[c] = win_rsrc(a.halo_out[c], win, rec_plane, run[c] && a.records);
     }
-    const auto Rcr = make_rsrc(a.cr, nbytes), Rct = make_rsrc(a.ct, nbytes),
-               Rcp = make_rsrc(a.cp, nbytes),
-               Rw = make_rsrc(a.w, check ? (uint32_t)(a.d.n * (int64_t)sizeof(double)) : 0u);
+    const auto Rcr = win_rsrc(a.cr, win), Rct = win_rsrc(a.ct, win), Rcp = win_rsrc(a.cp, win),
+               Rw = win_rsrc(a.w, win, check);
     constexpr uint32_t ES = sizeof(T);
     const int nsteps = i1 - i0 + 2;
     for (int s = 0; s < nsteps; ++s) {
         const int m = up ? i0 - 1 + s : i1 - s;
         const bool indom = (m >= 0) && (m < nr);
         const bool own = (m >= i0) && (m < i1);
-        const int64_t base = (int64_t)(indom ? m : 0) * plane;
+        const int64_t base = (int64_t)(indom ? m - win.lo : 0) * plane;
         const bool vin = indom && (act || pseudoR), vown = own && act;
         const uint32_t oc = vin ? (uint32_t)(base + col) * ES : kOOB;
         const uint32_t oo = vown ? (uint32_t)(base + col) * ES : kOOB;
@@ -1036,6 +1072,8 @@ __global__ __launch_bounds__(kBuThreads) void k_build(BuildArgs a) {
     const int J0 = jt * kBuR, k0 = kt * kBuC;
     const int nseg = min(kBuC, np - k0);
     const int i0 = it * a.ti, i1 = min(i0 + a.ti, nr);
+    // nu of planes i0 - 1 .. i1 + 2 is read, planes i0 .. i1 - 1 written
+    const PlaneWin win = plane_win(d, i0 - 1, i1 + 3);
     const int tid = threadIdx.x, lane = tid & (kWave - 1);
     const int wv = __builtin_amdgcn_readfirstlane(tid / kWave);
 
@@ -1079,12 +1117,12 @@ __global__ __launch_bounds__(kBuThreads) void k_build(BuildArgs a) {
             poff[q] = (j >= 0 && j < nt) ? j * np + k : -1;
         }
     }
-    const auto Rnu = make_rsrc(a.nu, (uint32_t)(d.n * (int64_t)sizeof(double)));
+    const auto Rnu = win_rsrc(a.nu, win);
     auto load_plane = [&](int m, double (&v)[kBuLoads]) {
 #pragma unroll
         for (int q = 0; q < kBuLoads; ++q) {
             const bool ok = m >= 0 && m < nr && poff[q] >= 0;
-            v[q] = bld<double, 1>(Rnu, ok ? (uint32_t)(((int64_t)m * d.plane + poff[q]) * 8) : kOOB).v[0];
+            v[q] = bld<double, 1>(Rnu, ok ? (uint32_t)(((int64_t)(m - win.lo) * d.plane + poff[q]) * 8) : kOOB).v[0];
         }
     };
     auto store_plane = [&](int m, const double (&v)[kBuLoads]) {
@@ -1138,11 +1176,10 @@ __global__ __launch_bounds__(kBuThreads) void k_build(BuildArgs a) {
         if (hasb) sIw[ber][bec] = iwb;
     };
 
-    const uint32_t ob = (uint32_t)(d.n * (int64_t)sizeof(double));
-    const auto Rw = make_rsrc(a.w, ob), Rcr = make_rsrc(a.cr, ob), Rct = make_rsrc(a.ct, ob),
-               Rcp = make_rsrc(a.cp, ob), Rnc = make_rsrc(a.nu_copy, ob);
-    const uint32_t of = F32 ? (uint32_t)(d.n * (int64_t)sizeof(float)) : 0u;
-    const auto Rcr32 = make_rsrc(a.cr32, of), Rct32 = make_rsrc(a.ct32, of), Rcp32 = make_rsrc(a.cp32, of);
+    const auto Rw = win_rsrc(a.w, win), Rcr = win_rsrc(a.cr, win), Rct = win_rsrc(a.ct, win),
+               Rcp = win_rsrc(a.cp, win), Rnc = win_rsrc(a.nu_copy, win);
+    const auto Rcr32 = win_rsrc(a.cr32, win, F32), Rct32 = win_rsrc(a.ct32, win, F32),
+               Rcp32 = win_rsrc(a.cp32, win, F32);
 
     // prologue: nu of planes i0 - 1, i0, i0 + 1; w of plane i0; nu of i0 + 2
     {
@@ -1184,7 +1221,7 @@ __global__ __launch_bounds__(kBuThreads) void k_build(BuildArgs a) {
             if (m < nr - 1) vr = face_c(g.dt, nc, sNu[s1][r + 1][c + 1], P.grp * R.vt) * iw[q] * iwn[q];
             if (j < nt - 1) vth = face_c(g.dt, nc, sNu[s0][r + 2][c + 1], P.gq * R.gttp) * iw[q] * sIw[r + 1][c];
             if (!g.np_one) vp = face_c(g.dt, nc, sNu[s0][r + 1][c + 2], P.gq * R.gpt) * iw[q] * sIw[r][c + 1];
-            const uint32_t o = own ? (uint32_t)(((int64_t)m * d.plane + (int64_t)j * np + k0 + c) * 8) : kOOB;
+            const uint32_t o = own ? (uint32_t)(((int64_t)(m - win.lo) * d.plane + (int64_t)j * np + k0 + c) * 8) : kOOB;
             bst<double, 1, kAuxNT>(Rw, o, VecT<double, 1>{{w[q]}});
             bst<double, 1, kAuxNT>(Rnc, o, VecT<double, 1>{{nc}});
             bst<double, 1, kAuxNT>(Rcr, o, VecT<double, 1>{{vr}});
@@ -1298,6 +1335,8 @@ __global__ __launch_bounds__(kReThreads) void k_residual(ResArgs a, TOUT *rout) 
     const int J0 = jt * kReR, k0 = kt * kReC;
     const int nseg = min(kReC, np - k0);
     const int i0 = it * a.ti, i1 = min(i0 + a.ti, nr);
+    // planes i0 - 1 .. i1 + 1 are read, planes i0 .. i1 - 1 written
+    const PlaneWin win = plane_win(d, i0 - 1, i1 + 2);
     const int tid = threadIdx.x, lane = tid & (kWave - 1);
     const int wv = __builtin_amdgcn_readfirstlane(tid / kWave);
 
@@ -1314,13 +1353,12 @@ __global__ __launch_bounds__(kReThreads) void k_residual(ResArgs a, TOUT *rout) 
             poff[q] = (j >= 0 && j < nt) ? j * np + k : -1;
         }
     }
-    const uint32_t nb = (uint32_t)(d.n * (int64_t)sizeof(double));
-    const auto RB = make_rsrc(a.bhat, nb), RX = make_rsrc(a.xhat, nb), RW = make_rsrc(a.w, nb),
-               RCr = make_rsrc(a.cr, nb), RCt = make_rsrc(a.ct, nb), RCp = make_rsrc(a.cp, nb);
-    const auto RO = make_rsrc(rout, (uint32_t)(d.n * (int64_t)sizeof(TOUT)));
+    const auto RB = win_rsrc(a.bhat, win), RX = win_rsrc(a.xhat, win), RW = win_rsrc(a.w, win),
+               RCr = win_rsrc(a.cr, win), RCt = win_rsrc(a.ct, win), RCp = win_rsrc(a.cp, win);
+    const auto RO = win_rsrc(rout, win);
     auto poffset = [&](int m, int q) -> uint32_t {
         const bool ok = m >= 0 && m < nr && poff[q] >= 0;
-        return ok ? (uint32_t)(((int64_t)m * d.plane + poff[q]) * 8) : kOOB;
+        return ok ? (uint32_t)(((int64_t)(m - win.lo) * d.plane + poff[q]) * 8) : kOOB;
     };
     auto store_x = [&](int m, const double (&v)[kReLoads]) {
         double *f = &sX[m & 1][0][0];
@@ -1341,7 +1379,7 @@ __global__ __launch_bounds__(kReThreads) void k_residual(ResArgs a, TOUT *rout) 
     auto own_off = [&](int m, int q) -> uint32_t {
         const int j = J0 + wv + kReWaves * q;
         const bool ok = m >= 0 && m < nr && j < nt && lane < nseg;
-        return ok ? (uint32_t)(((int64_t)m * d.plane + (int64_t)j * np + k0 + lane) * 8) : kOOB;
+        return ok ? (uint32_t)(((int64_t)(m - win.lo) * d.plane + (int64_t)j * np + k0 + lane) * 8) : kOOB;
     };
     // own cells of the plane behind: x^ and c^_r (the coupling of the -r face)
     double xb[NQ], crb[NQ];
@@ -1543,6 +1581,8 @@ __global__ __launch_bounds__(kGrThreads) void k_gradient(GradArgs a) {
     const int J0 = jt * kGrR, k0 = kt * kGrC;
     const int nseg = min(kGrC, np - k0);
     const int i0 = it * a.ti, i1 = min(i0 + a.ti, nr);
+    // planes i0 - 1 .. i1 + 1 are read, planes i0 .. i1 - 1 written
+    const PlaneWin win = plane_win(d, i0 - 1, i1 + 2);
     const int tid = threadIdx.x, lane = tid & (kWave - 1);
     const int wv = __builtin_amdgcn_readfirstlane(tid / kWave);
 
@@ -1571,14 +1611,13 @@ __global__ __launch_bounds__(kGrThreads) void k_gradient(GradArgs a) {
             poff[q] = (j >= 0 && j < nt) ? j * np + k : -1;
         }
     }
-    const uint32_t nb = (uint32_t)(d.n * (int64_t)sizeof(double));
-    const auto RX = make_rsrc(a.x, nb), RL = make_rsrc(a.lam, nb), RG = make_rsrc(a.gnu, nb),
-               RH = make_rsrc(a.grhs, a.grhs ? nb : 0u);
+    const auto RX = win_rsrc(a.x, win), RL = win_rsrc(a.lam, win), RG = win_rsrc(a.gnu, win),
+               RH = win_rsrc(a.grhs, win);
     auto load_plane = [&](int m, double (&vx)[kGrLoads], double (&vl)[kGrLoads]) {
 #pragma unroll
         for (int q = 0; q < kGrLoads; ++q) {
             const bool ok = m >= 0 && m < nr && poff[q] >= 0;
-            const uint32_t o = ok ? (uint32_t)(((int64_t)m * d.plane + poff[q]) * 8) : kOOB;
+            const uint32_t o = ok ? (uint32_t)(((int64_t)(m - win.lo) * d.plane + poff[q]) * 8) : kOOB;
             vx[q] = bld<double, 1>(RX, o).v[0];
             vl[q] = bld<double, 1>(RL, o).v[0];
         }
@@ -1599,7 +1638,7 @@ __global__ __launch_bounds__(kGrThreads) void k_gradient(GradArgs a) {
     for (int q = 0; q < NQ; ++q) {
         const int j = J0 + wv + kGrWaves * q;
         const bool ok = i0 > 0 && j < nt && lane < nseg;
-        const uint32_t o = ok ? (uint32_t)(((int64_t)(i0 - 1) * d.plane + (int64_t)j * np + k0 + lane) * 8) : kOOB;
+        const uint32_t o = ok ? (uint32_t)(((int64_t)(i0 - 1 - win.lo) * d.plane + (int64_t)j * np + k0 + lane) * 8) : kOOB;
         xb[q] = bld<double, 1>(RX, o).v[0];
         lb[q] = bld<double, 1>(RL, o).v[0];
     }
@@ -1644,7 +1683,7 @@ __global__ __launch_bounds__(kGrThreads) void k_gradient(GradArgs a) {
             t += cU * ((lc - lu) * (xc - xu));
             t += cD * ((lc - ld) * (xc - xd));
             t += cP * ((lc - ll) * (xc - xl) + (lc - lr) * (xc - xr));
-            const uint32_t o = own ? (uint32_t)(((int64_t)m * d.plane + (int64_t)j * np + k0 + lane) * 8) : kOOB;
+            const uint32_t o = own ? (uint32_t)(((int64_t)(m - win.lo) * d.plane + (int64_t)j * np + k0 + lane) * 8) : kOOB;
             bst<double, 1, kAuxNT>(RG, o, VecT<double, 1>{{-g.dt * t}});
             bst<double, 1, kAuxNT>(RH, o, VecT<double, 1>{{(vr * vt) * lc}});
             xb[q] = xc;

@@ -137,6 +137,13 @@ struct LayoutCursor {
     }
 };
 
+// The marching kernels address one block's r planes through buffer
+// resources based at its first plane, with 32-bit byte offsets: the planes a
+// block may touch, its chunk plus at most kWinHalo more, stay below
+// kWinBytes in every array, which bounds the chunk, not the grid.
+constexpr int64_t kWinBytes = (int64_t)1 << 31;
+constexpr int kWinHalo = 6;
+
 struct Shape {
     int nr, nt, np;
     int64_t plane, n;
@@ -152,16 +159,36 @@ struct Shape {
     // is latency-bound (each wave's plane steps run one after another), so
     // its chunks shrink, down to kSmallTI planes, until about kMinBlocks
     // blocks share the work.
+    // (a forced chunk, or the rule's, capped by max_chunk)
     int ti(int v, int forced = 0) const {
-        if (forced > 0) return forced;
-        return chunk_for((int64_t)tiles_k(v) * tiles_j());
+        const int cap = max_chunk(iter_plane_bytes(v));
+        if (forced > 0) return std::min(forced, cap);
+        return std::min(chunk_for((int64_t)tiles_k(v) * tiles_j()), cap);
     }
     // the same rule for any marching kernel with `tiles` tiles per plane
+    // (arrays of 8-byte elements)
     int chunk_for(int64_t tiles) const {
         const int big = std::max(kTI, (nr + 7) / 8);
-        if (tiles * ((nr + big - 1) / big) >= kMinBlocks) return big;
-        const int64_t want = (tiles * nr + kMinBlocks - 1) / kMinBlocks;
-        return (int)std::min<int64_t>(big, std::max<int64_t>(kSmallTI, want));
+        int t;
+        if (tiles * ((nr + big - 1) / big) >= kMinBlocks) {
+            t = big;
+        } else {
+            const int64_t want = (tiles * nr + kMinBlocks - 1) / kMinBlocks;
+            t = (int)std::min<int64_t>(big, std::max<int64_t>(kSmallTI, want));
+        }
+        return std::min(t, max_chunk());
+    }
+    // most r planes per chunk of a kernel whose arrays hold bytes_per_plane
+    // bytes per r plane (0: 8-byte cells), from the window bound; at least 1
+    // on every grid check_grid accepts
+    int max_chunk(int64_t bytes_per_plane = 0) const {
+        const int64_t b = bytes_per_plane > 0 ? bytes_per_plane : 8 * plane;
+        return (int)std::max<int64_t>(1, std::min<int64_t>(nr, (kWinBytes - 1) / b - kWinHalo));
+    }
+    // the iteration kernel's largest array per r plane: 8-byte cells or the
+    // segment-edge records (8 elements per row and segment)
+    int64_t iter_plane_bytes(int v) const {
+        return 8 * std::max<int64_t>(plane, (int64_t)nt * tiles_k(v) * 8);
     }
     int tiles_i(int v, int forced = 0) const { return (nr + ti(v, forced) - 1) / ti(v, forced); }
     int64_t nblk_iter(int v, int forced = 0) const {
@@ -170,13 +197,12 @@ struct Shape {
     // most blocks any launch of the iteration kernel can have (one-plane chunks)
     int64_t nblk_iter_max() const { return nblk_iter(1, 1); }
     // bytes of one segment-edge record buffer of the iteration kernel, and
-    // whether the records can be used (every segment spans two lanes, 32-bit
-    // offsets)
+    // whether the records can be used (every segment spans two lanes)
     int64_t halo_bytes(int v, int64_t es) const { return (int64_t)nr * nt * tiles_k(v) * 2 * 4 * es; }
-    bool halo_ok(int v, int64_t es) const {
+    bool halo_ok(int v) const {
         const int seg = (kWave / kRPW) * v;
         const int last = np - (tiles_k(v) - 1) * seg;
-        return last >= 2 * v && halo_bytes(v, es) < ((int64_t)1 << 31);
+        return last >= 2 * v;
     }
     dim3 simple_grid() const {
         return dim3((np + kWave - 1) / kWave, (nt + kSimpleJ - 1) / kSimpleJ,
@@ -231,11 +257,15 @@ static int check_grid(const mas_grid *g, Shape *out) {
     if (g->nr < 1 || g->nt < 1 || g->np < 1)
         return fail(MAS_EINVAL, "grid sizes must be >= 1 (got %d x %d x %d)", g->nr, g->nt, g->np);
     if (!g->r_faces || !g->t_faces) return fail(MAS_EINVAL, "face arrays must not be NULL");
-    const int64_t n = (int64_t)g->nr * g->nt * g->np;
-    // the iteration kernel addresses each array with 32-bit byte offsets
-    if (n * (int64_t)sizeof(double) >= ((int64_t)1 << 31))
-        return fail(MAS_EINVAL, "grid too large: at most 268435455 cells");
+    Shape sh{g->nr, g->nt, g->np, (int64_t)g->nt * g->np, (int64_t)g->nr * g->nt * g->np};
+    // a one-plane chunk and its halo planes must fit a block's 32-bit window
+    // (the records of one-cell segments are the largest per-plane array)
+    if ((int64_t)(1 + kWinHalo) * sh.iter_plane_bytes(1) >= kWinBytes)
+        return fail(MAS_EINVAL, "theta-phi plane too large: nt*np at most %lld cells",
+                    (long long)((kWinBytes - 1) / (8 * (1 + kWinHalo))));
     if ((int64_t)g->nt > 65535LL * kSimpleJ) return fail(MAS_EINVAL, "nt too large");
+    if ((int64_t)g->nr > 65535LL * kSimpleR) return fail(MAS_EINVAL, "nr too large");
+    if (sh.nblk_iter_max() > INT32_MAX) return fail(MAS_EINVAL, "grid too large");
     if (!(g->r_faces[0] > 0.0) || !std::isfinite(g->r_faces[0]))
         return fail(MAS_EINVAL, "r_faces[0] must be positive and finite");
     for (int i = 0; i < g->nr; ++i)
@@ -249,13 +279,7 @@ static int check_grid(const mas_grid *g, Shape *out) {
     for (int b : {g->bc_inner, g->bc_outer})
         if (b != MAS_BC_DIRICHLET0 && b != MAS_BC_NEUMANN0)
             return fail(MAS_EINVAL, "unknown boundary condition %d", b);
-    if (out) {
-        out->nr = g->nr;
-        out->nt = g->nt;
-        out->np = g->np;
-        out->plane = (int64_t)g->nt * g->np;
-        out->n = n;
-    }
+    if (out) *out = sh;
     return MAS_OK;
 }
 
@@ -495,7 +519,7 @@ static WorkLayout work_layout(const Shape &s, int precision, int nrhs = 1) {
     // segment-edge records of the iteration kernel, double-buffered
     const int v = (precision == MAS_FP32_REFINED) ? iter_vec<float>(s.np, nrhs)
                                                   : iter_vec<double>(s.np, nrhs);
-    L.halo_bytes = s.halo_ok(v, es) ? s.halo_bytes(v, es) : 0;
+    L.halo_bytes = s.halo_ok(v) ? s.halo_bytes(v, es) : 0;
     for (int c = 0; c < kMaxRhs; ++c) L.halo[c][0] = L.halo[c][1] = -1;
     if (L.halo_bytes > 0)
         for (int c = 0; c < nrhs; ++c)
@@ -693,7 +717,7 @@ struct RhsSet {
     T *r[kMaxRhs][2], *p[kMaxRhs][2], *q[kMaxRhs][2];
     T *x[kMaxRhs];
     T *halo[kMaxRhs][2];    // segment-edge record buffers (null: not used)
-    uint32_t halo_bytes = 0;
+    bool records = false;
     double tol2[kMaxRhs];
     int max_iter[kMaxRhs];  // last admissible iteration index of each
     bool active[kMaxRhs];
@@ -749,8 +773,8 @@ static int run_pcg(Ctx &cx, const RhsSet<T> &v, const T *const c[3], int mode, i
     a.ti = s.ti(V, cx.chunk);
     a.nblk = (int)s.nblk_iter(V, cx.chunk);
     for (int h = 0; h < NR; ++h) a.x[h] = v.x[h];
-    a.halo_bytes = v.halo_bytes;
-    const bool use_halo = v.halo_bytes > 0;
+    a.records = v.records ? 1 : 0;
+    const bool use_halo = v.records;
     const dim3 grid((unsigned)a.nblk), block(kWave * kTJ);
 
     // batches of launches; the host polls the device flags one batch behind
@@ -918,7 +942,7 @@ static int run_pcg_pc2(Ctx &cx, T *r, T *z, T *const p[2], T *q, T *d, T *x, int
     it.tiles_j = s.tiles_j();
     it.ti = s.ti(V, cx.chunk);
     it.nblk = (int)s.nblk_iter(V, cx.chunk);
-    it.halo_bytes = 0;
+    it.records = 0;
     constexpr int VW = vec_full<T>();
     const dim3 igrid((unsigned)it.nblk), iblock(kWave * kTJ);
     a.update = 1;
@@ -1047,7 +1071,7 @@ static int run_pcg_pc2_multi(Ctx &cx, T *const r[NR], T *const z[NR], T *const p
     it.tiles_j = s.tiles_j();
     it.ti = s.ti(V, cx.chunk);
     it.nblk = (int)s.nblk_iter(V, cx.chunk);
-    it.halo_bytes = 0;
+    it.records = 0;
     constexpr int VW = vec_full<T>();
     const dim3 igrid((unsigned)it.nblk), iblock(kWave * kTJ);
     int kmax = iter0;
@@ -1106,7 +1130,7 @@ static int run_pcg_pc2_multi(Ctx &cx, T *const r[NR], T *const z[NR], T *const p
 // Record buffers of right-hand side h from the workspace layout.
 template <typename T>
 static void set_halo(RhsSet<T> &v, char *base, const WorkLayout &L, int h = 0) {
-    v.halo_bytes = (uint32_t)L.halo_bytes;
+    v.records = L.halo_bytes > 0;
     for (int t = 0; t < 2; ++t)
         v.halo[h][t] = L.halo_bytes > 0 ? reinterpret_cast<T *>(base + L.halo[h][t]) : nullptr;
 }
@@ -2162,13 +2186,14 @@ static int sts_launch(const mas_op *op, hipStream_t stream, const double *X, con
     const Shape &s = op->s;
     const int v = (s.np % 2 == 0) ? 2 : 1;
     const int seg = (kWave / kStsRPW) * v;
-    const int64_t tiles_i = (s.nr + kStsTI - 1) / kStsTI;
+    const int ti = std::min(kStsTI, s.max_chunk());
+    const int64_t tiles_i = (s.nr + ti - 1) / ti;
     const int64_t tiles_k = (s.np + seg - 1) / seg;
     const int64_t tiles_j = (s.nt + kStsWPB * kStsRPW - 1) / (kStsWPB * kStsRPW);
     const int64_t nblk = tiles_i * tiles_k * tiles_j;
     if (nblk > INT32_MAX) return fail(MAS_EINVAL, "grid too large for the stage kernel");
     StsArgs args{X, op->nu, Z, L0, Y0, out, a, b, g, m * op->dt, op->geo, s.dims(),
-                 (int)tiles_i, (int)tiles_k, (int)tiles_j, kStsTI, (int)nblk};
+                 (int)tiles_i, (int)tiles_k, (int)tiles_j, ti, (int)nblk};
     const int in = (Z ? kStsZ : 0) | (L0 ? kStsL0 : 0) | (Y0 ? kStsY0 : 0);
     const dim3 grid((unsigned)nblk), block(kWave * kStsWPB);
     auto go = [&](auto vtag) {
@@ -2207,7 +2232,8 @@ static int sts_pair_launch(const mas_op *op, hipStream_t stream, const double *X
     constexpr int RO = 2 * kPairNW - 4;
     // r chunks: at least kPairTI planes, and long enough that there are at
     // most 8 of them (whole r slabs per XCD, as for the iteration kernel)
-    const int ti = MAS_PAIR_SLAB ? std::min(kPairMaxTI, std::max(kPairTI, (s.nr + 7) / 8)) : kPairTI;
+    const int ti = std::min(s.max_chunk(), MAS_PAIR_SLAB ? std::min(kPairMaxTI, std::max(kPairTI, (s.nr + 7) / 8))
+                                                         : kPairTI);
     const int64_t tiles_i = (s.nr + ti - 1) / ti;
     const int64_t tiles_k = (s.np + kPairOut - 1) / kPairOut;
     const int64_t tiles_j = (s.nt + RO - 1) / RO;

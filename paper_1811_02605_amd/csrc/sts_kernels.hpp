@@ -184,13 +184,13 @@ void k_sts_stage(StsArgs a) {
     const double hP = (rowok && !a.geo.np_one) ? 0.5 * a.geo.gpt[jj] : 0.0;
 
     constexpr uint32_t ES = sizeof(double);
-    const uint32_t nbytes = (uint32_t)(a.d.n * (int64_t)ES);
-    const auto RX = make_rsrc(a.X, nbytes), RN = make_rsrc(a.nu, nbytes),
-               RZ = make_rsrc(a.Z, HZ ? nbytes : 0u), RL = make_rsrc(a.L0, HL ? nbytes : 0u),
-               RY = make_rsrc(a.Y0, HY ? nbytes : 0u), RO = make_rsrc(a.out, nbytes);
+    // the planes this block touches, i0 - 1 .. i1
+    const PlaneWin win = plane_win(a.d, i0 - 1, i1 + 1);
+    const auto RX = win_rsrc(a.X, win), RN = win_rsrc(a.nu, win), RZ = win_rsrc(a.Z, win, HZ),
+               RL = win_rsrc(a.L0, win, HL), RY = win_rsrc(a.Y0, win, HY), RO = win_rsrc(a.out, win);
 
     auto own_off = [&](int m) -> uint32_t {
-        return (ldo && m >= 0 && m < nr) ? (uint32_t)((int64_t)m * plane + col) * ES : kOOB;
+        return (ldo && m >= 0 && m < nr) ? (uint32_t)((int64_t)(m - win.lo) * plane + col) * ES : kOOB;
     };
     // planes m - dir (behind) and m (current) of the first step
     VD Xb = bld<double, V, MAS_STS_AUX_XN>(RX, own_off(first - dir));
@@ -203,7 +203,7 @@ void k_sts_stage(StsArgs a) {
     const int nsteps = i1 - i0;
     for (int s = 0; s < nsteps; ++s) {
         const int m = first + s * dir;
-        const int64_t base = (int64_t)m * plane;
+        const int64_t base = (int64_t)(m - win.lo) * plane;
         const uint32_t oo = act ? (uint32_t)(base + col) * ES : kOOB;
         const uint32_t oE = ldU ? (uint32_t)(base + col - np) * ES
                                 : (ldD ? (uint32_t)(base + col + np) * ES : kOOB);
@@ -370,27 +370,27 @@ void k_sts_pair(StsPairArgs a) {
     const double hD = rowin ? 0.5 * a.geo.gtt[jj] : 0.0;
     const double hP = (rowin && !a.geo.np_one) ? 0.5 * a.geo.gpt[jj] : 0.0;
 
-    constexpr uint32_t ES = sizeof(double);
-    const uint32_t nbytes = (uint32_t)(a.d.n * (int64_t)ES);
-    const auto RX = make_rsrc(a.X, nbytes), RN = make_rsrc(a.nu, nbytes),
-               RZ = make_rsrc(a.Z, HZ ? nbytes : 0u), RL = make_rsrc(a.L0, HL ? nbytes : 0u),
-               RY = make_rsrc(a.Y0, HY ? nbytes : 0u), RA = make_rsrc(a.outA, HY ? 0u : nbytes),
-               RB = make_rsrc(a.outB, nbytes);
-
     const int i0 = it * a.ti;
     const int i1 = min(i0 + a.ti, nr);
     const int nsteps = i1 - i0 + 2;  // A runs from one plane before the chunk to one after
+    // the planes this block may address, i0 - 3 .. i1 + 2 (the outermost
+    // two are loaded for a step that never comes)
+    const PlaneWin win = plane_win(a.d, i0 - 3, i1 + 3);
+    constexpr uint32_t ES = sizeof(double);
+    const auto RX = win_rsrc(a.X, win), RN = win_rsrc(a.nu, win), RZ = win_rsrc(a.Z, win, HZ),
+               RL = win_rsrc(a.L0, win, HL), RY = win_rsrc(a.Y0, win, HY),
+               RA = win_rsrc(a.outA, win, !HY), RB = win_rsrc(a.outB, win);
     auto ldoff = [&](int m) -> uint32_t {
-        return (ld && m >= 0 && m < nr) ? (uint32_t)((int64_t)m * plane + col) * ES : kOOB;
+        return (ld && m >= 0 && m < nr) ? (uint32_t)((int64_t)(m - win.lo) * plane + col) * ES : kOOB;
     };
     // Z and L0 enter stage A only, whose values on the outermost tile rows
     // are never used: those rows do not load them
     const bool ldzl = ld && rho >= 1 && rho < R - 1;
     auto zloff = [&](int m) -> uint32_t {
-        return (ldzl && m >= 0 && m < nr) ? (uint32_t)((int64_t)m * plane + col) * ES : kOOB;
+        return (ldzl && m >= 0 && m < nr) ? (uint32_t)((int64_t)(m - win.lo) * plane + col) * ES : kOOB;
     };
     auto ownoff = [&](int m) -> uint32_t {
-        return (own && m >= i0 && m < i1) ? (uint32_t)((int64_t)m * plane + col) * ES : kOOB;
+        return (own && m >= i0 && m < i1) ? (uint32_t)((int64_t)(m - win.lo) * plane + col) * ES : kOOB;
     };
     auto lds2 = [&](const double *row) -> VD { return VD{{row[c], row[c + 1]}}; };
 

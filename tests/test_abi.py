@@ -52,6 +52,24 @@ def test_storage_bytes_scale_with_grid_and_precision():
     assert b32 - b64 >= 12 * n
 
 
+def test_grids_beyond_2_gib_per_array_are_accepted():
+    """No bound on the cell count: 272 x 1030 x 1002 cells (2.25 GB per FP64
+    array) is a valid grid; the bound is on one theta-phi plane (a block's
+    32-bit window holds one r plane and its halo planes), checked with the
+    largest plane accepted and the next one."""
+    lib = abi.load()
+    g, keep = _grid(272, 1030, 1002)
+    n = 272 * 1030 * 1002
+    assert n * 8 > 2 ** 31
+    assert lib.mas_op_storage_bytes(ctypes.byref(g), abi.MAS_FP64) >= 40 * n
+    limit = (2 ** 31 - 1) // (8 * 7)  # cells of the largest plane
+    g, keep = _grid(2, 1, limit)
+    assert lib.mas_op_storage_bytes(ctypes.byref(g), abi.MAS_FP64) >= 40 * 2 * limit
+    g, keep = _grid(2, 1, limit + 1)
+    assert lib.mas_op_storage_bytes(ctypes.byref(g), abi.MAS_FP64) == abi.MAS_EINVAL
+    assert "plane too large" in abi.last_error()
+
+
 @pytest.mark.parametrize("kw,msg", [
     (dict(nr=0), "sizes"),
     (dict(np_=0), "sizes"),

@@ -44,9 +44,11 @@ HBM_PEAK_GBS = 8000.0
 # two-kernel form (SpMV with the p update, then the r update with the Jacobi
 # step and the dots; the stored operator streamed once): 14 words.
 ALG_BYTES_PER_CELL = {"fp64": 14 * 8, "fp32": 14 * 4}
-# What this library's single-kernel iteration has to move per cell (reads r,
-# q, p, x, c_r, c_theta, c_phi; writes r, p, x, q): 11 words.
-KERNEL_BYTES_PER_CELL = {"fp64": 11 * 8, "fp32": 11 * 4}
+# What this library's single-kernel iteration has to move per cell: reads r,
+# q, p, c_r, c_theta, c_phi and writes r, p, q in every launch; every second
+# launch also reads x and the previous p and writes x (it moves x over two
+# iterations): 10.5 words on average (12 and 9 in alternate launches).
+KERNEL_BYTES_PER_CELL = {"fp64": 21 * 4, "fp32": 21 * 2}
 # One RKL2 stage kernel per cell: reads D_{j-1}, nu, D_{j-2}, L_0, writes D_j.
 STS_BYTES_PER_CELL = 5 * 8        # one-stage kernel: reads X, nu, Z, L0; writes the stage
 STS_PAIR_BYTES_PER_CELL = 6 * 8   # two-stage kernel: reads X, nu, Z, L0; writes both stages

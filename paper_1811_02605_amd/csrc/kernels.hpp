@@ -52,6 +52,8 @@ struct Ctl {
     double pq, rq, qq; // last sums (diagnostics)
     double sums[8];    // results of k_reduce
     double wratio;     // ||W r||^2 / (r,r) at the last check (predicts ||W r||^2 from (r,r))
+    double alpha_prev; // the alpha the last iteration kernel applied (its x update, when that
+                       // kernel left it to the next one or to k_x_catchup)
     int32_t flag;      // 0 running, 1 converged, 2 iteration limit, -2 breakdown
     int32_t iter;      // index of the next iteration kernel
     int32_t max_iter;  // last admissible iteration index
@@ -163,6 +165,7 @@ constexpr double kCheckMargin = 4.0;
 __device__ inline void pcg_finalize(Ctl *ctl, const double (&S)[kNV]) {
     const double PQ = S[0], RQ = S[1], QQ = S[2], RR = S[3], RW = S[4];
     const int k = ctl->iter;
+    ctl->alpha_prev = ctl->alpha;
     ctl->pq = PQ;
     ctl->rq = RQ;
     ctl->qq = QQ;
@@ -225,6 +228,10 @@ struct IterArgs {
     const T *r_in[kMaxRhs], *p_in[kMaxRhs], *q_in[kMaxRhs];
     T *r_out[kMaxRhs], *p_out[kMaxRhs], *q_out[kMaxRhs];
     T *x[kMaxRhs];
+    // 1: this launch brings x up to date over two iterations, the previous
+    // launch's update (alpha_prev times the p that launch read, still in
+    // p_out) and its own; 0: x is not touched (see k_pcg_iter)
+    int xstep;
     // Segment-edge records [r, p, cp, q] (see k_pcg_iter): written by every
     // iteration kernel into halo_out, read from halo_in by the next one.
     T *halo_out[kMaxRhs];
@@ -537,6 +544,14 @@ __device__ inline float lane_next(float v) { return lanes32<lane_next_u32>(v); }
 // the edges of a whole row into a few lines.  Without HALO (the first kernel
 // of a run, whose input no kernel wrote records for) the edge cells are
 // loaded directly.  HALO needs every segment to span at least two lanes.
+// x moves in every second launch only (a.xstep): x_{k+1} = (x_{k-1} +
+// alpha_{k-1} p_{k-1}) + alpha_k p_k, where p_{k-1} is still in the p_out
+// buffer (each cell read by its owner before this launch overwrites it with
+// its own p) and alpha_{k-1} is ctl->alpha_prev.  The two fused multiply-adds
+// are those two successive launches would do, in the same order, so x is
+// bitwise what an update in every launch gives, at 8 instead of 16 bytes of
+// x per cell and launch.  A run that stops after a launch without the update
+// gets it from k_x_catchup.
 template <typename T, int NR, int WPB, int RPW, int V, bool HALO>
 __global__ __launch_bounds__(kWave *WPB)
 #if MAS_ITER_WPE > 0
@@ -550,7 +565,7 @@ void k_pcg_iter(IterArgs<T> a) {
     using VT = VecT<T, V>;
 
     bool run[NR];
-    T alpha[NR], beta[NR];
+    T alpha[NR], beta[NR], alpha2[NR];
     bool any = false, check = false;
 #pragma unroll
     for (int c = 0; c < NR; ++c) {
@@ -560,6 +575,7 @@ void k_pcg_iter(IterArgs<T> a) {
         // ||W r||^2 is formed when any running right-hand side asks for it
         check = check || (run[c] && ctl->check);
         alpha[c] = (T)ctl->alpha;
+        alpha2[c] = (T)ctl->alpha_prev;
         beta[c] = (T)ctl->beta;
     }
     if (!any) return;
@@ -651,7 +667,7 @@ void k_pcg_iter(IterArgs<T> a) {
         Rr[c] = win_rsrc(a.r_in[c], win, run[c]);
         Rq[c] = win_rsrc(a.q_in[c], win, run[c]);
         Rp[c] = win_rsrc(a.p_in[c], win, run[c]);
-        Rx[c] = win_rsrc(a.x[c], win, run[c]);
+        Rx[c] = win_rsrc(a.x[c], win, run[c] && a.xstep);
         Rro[c] = win_rsrc(a.r_out[c], win, run[c]);
         Rpo[c] = win_rsrc(a.p_out[c], win, run[c]);
         Rqo[c] = win_rsrc(a.q_out[c], win, run[c]);
@@ -693,7 +709,7 @@ void k_pcg_iter(IterArgs<T> a) {
         constexpr bool kSplitUD = RPW == 1;
         constexpr int ND = kSplitUD ? NR : 1;
         const uint32_t oE = kSplitUD ? oU : (vU ? oU : oD);
-        VT r[NR], q[NR], p[NR], x[NR], rE[NR], qE[NR], pE[NR], rD[ND], qD[ND], pD[ND];
+        VT r[NR], q[NR], p[NR], x[NR], p2[NR], rE[NR], qE[NR], pE[NR], rD[ND], qD[ND], pD[ND];
         T lr[NR], lq[NR], lp_[NR];
         VecT<T, 4> hrec[NR];
 #pragma unroll
@@ -704,7 +720,10 @@ void k_pcg_iter(IterArgs<T> a) {
         }
         VT cr = bld<T, V, AN>(Rcr, ocr);
 #pragma unroll
-        for (int c = 0; c < NR; ++c) x[c] = bld<T, V, AN>(Rx[c], oo);
+        for (int c = 0; c < NR; ++c) {
+            x[c] = bld<T, V, AN>(Rx[c], oo);
+            p2[c] = bld<T, V, AN>(Rpo[c], a.xstep ? oo : kOOB);  // p_{k-1}
+        }
         VT ct = bld<T, V>(Rct, oo);
         VT cp = bld<T, V, AN>(Rcp, oo);
         // w only on check iterations (otherwise a zero-length resource: zeros, no bytes)
@@ -767,7 +786,8 @@ void k_pcg_iter(IterArgs<T> a) {
             for (int e = 0; e < V; ++e) {
                 rn.v[e] = r[c].v[e] - alpha[c] * q[c].v[e];
                 pn.v[e] = rn.v[e] + beta[c] * p[c].v[e];
-                xn.v[e] = x[c].v[e] + alpha[c] * p[c].v[e];
+                const T xm = x[c].v[e] + alpha2[c] * p2[c].v[e];
+                xn.v[e] = xm + alpha[c] * p[c].v[e];
                 if (!vin) pn.v[e] = T(0);
             }
             // (r_k, r_k) and ||W r_k||^2 over the cells this tile owns
@@ -907,6 +927,36 @@ __global__ __launch_bounds__(kRedThreads) void k_finalize(const double *partials
     double S[kNV];
     sum_partials<kRedThreads>(partials, nblk, nrhs, c, S, lds);
     if (threadIdx.x == 0) pcg_finalize(ctl, S);
+}
+
+// After a run of iteration kernels: a right-hand side whose last launch did
+// not move x (an odd launch of the run: a.xstep = 0) gets that launch's
+// update here, x += alpha_prev p with p the direction the launch read, the
+// same fused multiply-add.  blockIdx.y is the right-hand side; one that
+// needs nothing returns at once.
+template <typename T>
+struct CatchupArgs {
+    T *x[kMaxRhs];
+    const T *p[kMaxRhs][2];  // the p buffers: iteration kernel k reads p[k & 1]
+    const Ctl *ctl;          // [NR]
+    int64_t n;
+    int iter0;               // the run's first iteration index
+};
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_x_catchup(CatchupArgs<T> a) {
+    const int c = blockIdx.y;
+    const Ctl *ctl = a.ctl + c;
+    // the last launch that did work (after it the finalize either stopped
+    // the run at conv_iter or advanced iter)
+    const int last = (ctl->flag == FLAG_RUN) ? ctl->iter - 1 : ctl->conv_iter;
+    const int s = last - a.iter0;
+    T *x = a.x[c];
+    if (s < 1 || (s & 1) == 0 || !x) return;
+    const T al = (T)ctl->alpha_prev;
+    const T *p = a.p[c][last & 1];
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < a.n; i += (int64_t)gridDim.x * 256)
+        x[i] = x[i] + al * p[i];
 }
 
 // Generic fixed-order sum of [nblk][nv] partials into ctl->sums[0:nv].

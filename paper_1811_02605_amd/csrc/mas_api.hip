@@ -739,6 +739,8 @@ struct PcgResult {
 // iteration).  The first kernel uses alpha = 0 and beta = v.beta0[c]: with
 // v.keep_p[c] it continues the search direction in p[c][iter0 % 2]
 // (p = r + beta0 p), otherwise it starts afresh (p = r).
+constexpr int64_t kCatchupBlocks = 8192;  // grid-stride blocks of k_x_catchup
+
 template <typename T, int NR>
 static int run_pcg(Ctx &cx, const RhsSet<T> &v, const T *const c[3], int mode, int iter0,
                    int check_every, PcgResult *res) {
@@ -801,7 +803,11 @@ static int run_pcg(Ctx &cx, const RhsSet<T> &v, const T *const c[3], int mode, i
             // the first kernel of a run reads its edge cells directly (no
             // kernel wrote records for its input); later ones read records
             const bool halo = use_halo && k != iter0;
-            const bool sample = cx.timing && (k % 16 == 7) && cx.ev.size() < 128;
+            // x moves in the even launches of the run from the third on (the
+            // first applies alpha = 0)
+            a.xstep = (k - iter0 >= 2 && ((k - iter0) & 1) == 0) ? 1 : 0;
+            // timing samples of both kinds of launch
+            const bool sample = cx.timing && (k % 16 == 7 || k % 16 == 8) && cx.ev.size() < 128;
             if (sample) {
                 hipEvent_t e0, e1;
                 HIPCHK(hipEventCreate(&e0));
@@ -833,6 +839,19 @@ static int run_pcg(Ctx &cx, const RhsSet<T> &v, const T *const c[3], int mode, i
         e = poll.after_batch(NR, &stop);
         if (e != MAS_OK) return e;
     }
+    // the x update of a last launch that left it to the next one
+    CatchupArgs<T> ca{};
+    for (int h = 0; h < NR; ++h) {
+        ca.x[h] = v.x[h];
+        ca.p[h][0] = v.p[h][0];
+        ca.p[h][1] = v.p[h][1];
+    }
+    ca.ctl = cx.ctl;
+    ca.n = s.n;
+    ca.iter0 = iter0;
+    const int64_t cblk = std::min<int64_t>((s.n + 255) / 256, kCatchupBlocks);
+    hipLaunchKernelGGL(k_x_catchup<T>, dim3((unsigned)cblk, NR), dim3(256), 0, st, ca);
+    LAUNCHCHK();
     HIPCHK(hipStreamSynchronize(st));
     for (int h = 0; h < NR; ++h) {
         Ctl hc;

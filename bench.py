@@ -637,16 +637,27 @@ def main():
     if not args.no_probe:
         # achievable bandwidth of the byte mixes the kernels stream, at the
         # workload's size (streaming probes of the library), and a plain copy
-        stream_gbs = S.probe_stream(n, 7, 4, dev)
+        # the iteration kernel alternates launches moving 8 read / 4 written
+        # words per cell (with the x update) and 6 / 3 (without): its
+        # ceiling is the rate of that alternation, each launch at its mix's
+        # probe rate
+        g84 = S.probe_stream(n, 8, 4, dev)
+        g63 = S.probe_stream(n, 6, 3, dev)
+        stream_gbs = 2 * KERNEL_BYTES_PER_CELL["fp64"] / (12 * 8 / g84 + 9 * 8 / g63)
+        resid_mix_gbs = S.probe_stream(n, 6, 1, dev)
         grad_mix_gbs = S.probe_stream(n, 2, 2, dev)
         copy_gbs = S.probe_stream(n, 1, 1, dev)
         torch.cuda.empty_cache()
-        out["roofline"]["stream_7r4w_GBs"] = stream_gbs
+        out["roofline"]["stream_8r4w_GBs"] = g84
+        out["roofline"]["stream_6r3w_GBs"] = g63
+        out["roofline"]["stream_iter_mix_GBs"] = stream_gbs
         out["roofline"]["copy_probe_GBs"] = copy_gbs
         out["roofline"]["kernel_bytes_frac_of_stream"] = (kern_gbs / stream_gbs) if kern_gbs else None
+        out["roofline"]["stream_6r1w_GBs"] = resid_mix_gbs
         if "adjoint" in out:
             out["adjoint"]["gradient_kernel"]["stream_2r2w_GBs"] = grad_mix_gbs
-        print(f"[bench] stream probes: 7 read / 4 write {stream_gbs:.0f} GB/s, 2/2 "
+        print(f"[bench] stream probes: 8 read / 4 write {g84:.0f} GB/s, 6/3 {g63:.0f} GB/s "
+              f"(iteration mix {stream_gbs:.0f} GB/s), 6/1 {resid_mix_gbs:.0f} GB/s, 2/2 "
               f"{grad_mix_gbs:.0f} GB/s, copy {copy_gbs:.0f} GB/s", file=sys.stderr, flush=True)
 
     if not args.no_cpu_baseline:

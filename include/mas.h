@@ -347,8 +347,11 @@ int mas_probe_copy(const void *src, void *dst, int64_t bytes, void *hip_stream);
  * every array as the marching kernels walk their r chunks, non-temporal
  * accesses, out_t = in_0 + ... + in_{nin-1} + t.  The arrays are laid out
  * in buf (dev, 256-byte aligned, >= mas_probe_stream_bytes(n, nin, nout))
- * with the library's stagger.  Supported mixes: 7/4 (the PCG iteration
- * kernel), 2/2 (the gradient kernel), 4/1 (an RKL2 stage), 1/1 (a copy).
+ * with the library's stagger.  Supported mixes: 8/4 and 6/3 (the PCG
+ * iteration kernel's launches with and without the x update), 7/4 (an
+ * iteration that moves x every time), 6/1 (the FP64 residual), 2/2 (the
+ * gradient kernel), 4/1 (an RKL2 stage), 1/1 (a copy); any other mix is
+ * MAS_EINVAL.
  * It measures the bandwidth that access pattern reaches, the ceiling the
  * kernels are compared with beside the 8 TB/s peak.  Enqueues only.
  * Returns MAS_OK, MAS_EINVAL, MAS_ENOMEM or MAS_EHIP. */

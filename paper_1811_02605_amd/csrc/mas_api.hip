@@ -806,8 +806,10 @@ static int run_pcg(Ctx &cx, const RhsSet<T> &v, const T *const c[3], int mode, i
             // x moves in the even launches of the run from the third on (the
             // first applies alpha = 0)
             a.xstep = (k - iter0 >= 2 && ((k - iter0) & 1) == 0) ? 1 : 0;
-            // timing samples of both kinds of launch
-            const bool sample = cx.timing && (k % 16 == 7 || k % 16 == 8) && cx.ev.size() < 128;
+            // timing samples: 8 consecutive launches of every 16, so that
+            // launches with and without the x update and the check launches
+            // (every check_every-th) enter in their proportions
+            const bool sample = cx.timing && ((k / 8) & 1) == 1 && cx.ev.size() < 512;
             if (sample) {
                 hipEvent_t e0, e1;
                 HIPCHK(hipEventCreate(&e0));
@@ -2468,11 +2470,14 @@ extern "C" int mas_probe_stream(void *buf, int64_t bytes, int64_t n, int32_t nin
     hipStream_t st = as_stream(hip_stream);
     // the byte mixes the library's kernels stream (7 in / 4 out: the PCG
     // iteration; 2 / 2: the gradient; 4 / 1: an RKL2 stage)
-    if (nin == 7 && nout == 4) hipLaunchKernelGGL((k_stream<7, 4>), grid, block, 0, st, a);
+    if (nin == 8 && nout == 4) hipLaunchKernelGGL((k_stream<8, 4>), grid, block, 0, st, a);
+    else if (nin == 6 && nout == 3) hipLaunchKernelGGL((k_stream<6, 3>), grid, block, 0, st, a);
+    else if (nin == 7 && nout == 4) hipLaunchKernelGGL((k_stream<7, 4>), grid, block, 0, st, a);
+    else if (nin == 6 && nout == 1) hipLaunchKernelGGL((k_stream<6, 1>), grid, block, 0, st, a);
     else if (nin == 2 && nout == 2) hipLaunchKernelGGL((k_stream<2, 2>), grid, block, 0, st, a);
     else if (nin == 4 && nout == 1) hipLaunchKernelGGL((k_stream<4, 1>), grid, block, 0, st, a);
     else if (nin == 1 && nout == 1) hipLaunchKernelGGL((k_stream<1, 1>), grid, block, 0, st, a);
-    else return fail(MAS_EINVAL, "stream probe mixes: 7/4, 2/2, 4/1 or 1/1 (got %d/%d)", nin, nout);
+    else return fail(MAS_EINVAL, "stream probe mixes: 8/4, 6/3, 7/4, 6/1, 2/2, 4/1 or 1/1 (got %d/%d)", nin, nout);
     LAUNCHCHK();
     return MAS_OK;
 }

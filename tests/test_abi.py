@@ -122,6 +122,10 @@ def test_null_operator_and_bad_copy_are_rejected():
     assert lib.mas_probe_copy(16, 32, 17, None) == abi.MAS_EINVAL
     assert lib.mas_probe_copy(8, 32, 16, None) == abi.MAS_EINVAL
     assert lib.mas_probe_copy(None, 32, 16, None) == abi.MAS_EINVAL
+    assert lib.mas_probe_stream_bytes(0, 1, 1) == abi.MAS_EINVAL
+    assert lib.mas_probe_stream_bytes(16, 9, 1) == abi.MAS_EINVAL
+    assert lib.mas_probe_stream_bytes(16, 1, 5) == abi.MAS_EINVAL
+    assert lib.mas_probe_stream(None, 0, 16, 1, 1, None) == abi.MAS_EINVAL
     assert lib.mas_op_destroy(None) is None
 
 

@@ -316,6 +316,33 @@ def test_autograd_function():
     assert rel(to_host(rhs.grad), grhs_o) <= 1e-8
 
 
+@pytest.mark.parametrize("nin,nout", [(8, 4), (6, 3), (7, 4), (6, 1), (2, 2), (4, 1), (1, 1)])
+def test_probe_stream_writes_each_output_once(nin, nout):
+    """The streaming probe over n cells (odd, several blocks and a ragged
+    tail) on a buffer filled with 0.25: output array t holds 0.25 nin + t in
+    every cell, the inputs and the padding keep 0.25."""
+    lib = abi.load()
+    n = 3 * 16384 + 1001
+    nbytes = int(lib.mas_probe_stream_bytes(n, nin, nout))
+    assert nbytes >= (nin + nout) * 8 * n
+    buf = torch.full((nbytes // 8,), 0.25, dtype=torch.float64, device=DEV)
+    with torch.cuda.device(buf.device):
+        abi.check(lib.mas_probe_stream(buf.data_ptr(), nbytes, n, nin, nout,
+                                       torch.cuda.current_stream().cuda_stream), "mas_probe_stream")
+    torch.cuda.synchronize()
+    vals, counts = torch.unique(buf, return_counts=True)
+    got = dict(zip(vals.tolist(), counts.tolist()))
+    want = {}
+    for t in range(nout):
+        v = 0.25 * nin + t
+        want[v] = want.get(v, 0) + n
+    for v, c in want.items():
+        if v != 0.25:
+            assert got.get(v, 0) == c, (v, got)
+    assert set(got) <= set(want) | {0.25}
+    assert lib.mas_probe_stream(buf.data_ptr(), nbytes, n, 5, 5, None) == abi.MAS_EINVAL
+
+
 def test_probe_copy():
     src = torch.arange(1 << 20, dtype=torch.float64, device=DEV)
     dst = torch.empty_like(src)

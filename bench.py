@@ -250,9 +250,10 @@ def bench_c4(S, W, dev):
 
 
 # One iteration kernel with m right-hand sides: the couplings (3 words) once,
-# 8 words per right-hand side.
+# 7.5 words per right-hand side on average (6 in every launch, x and the
+# previous p read and x written in every second one).
 def multi_bytes_per_cell(m, word=8):
-    return (3 + 8 * m) * word
+    return (3 + 7.5 * m) * word
 
 
 def bench_multi(S, W, grid, nu, p, t_pcg, k_single_us, m=3):

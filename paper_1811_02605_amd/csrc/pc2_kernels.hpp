@@ -104,26 +104,36 @@ struct Mob {
 
 // Inclusive scan of such maps over the 64 lanes in lane order (the same DPP
 // moves as affine_scan; a lane that receives nothing composes with the
-// identity), each product rescaled by a power of two (exact) so that long
-// chains neither overflow nor underflow.
-template <int CTRL, int ROWS>
+// identity).  After the first three steps (products of up to eight maps)
+// the product is rescaled by a power of two, exactly, so that the longer
+// products of the last three steps neither overflow nor underflow: every
+// map [s, -c^2; 1, 0] has entries of magnitude at most 1 (unit diagonal,
+// diagonal dominance), so the entries of a product of eight stay within
+// [min(s)^8, 2^8].  A power-of-two scale commutes with every rounding here,
+// so the result is the same, bit for bit, as with a rescale after every
+// step; the map is applied as a ratio, which ignores the scale.
+template <int CTRL, int ROWS, bool RESCALE>
 __device__ inline void mobius_step(Mob &P) {
     const double q00 = dpp_or<CTRL, ROWS>(P.m00, 1.0), q01 = dpp_or<CTRL, ROWS>(P.m01, 0.0);
     const double q10 = dpp_or<CTRL, ROWS>(P.m10, 0.0), q11 = dpp_or<CTRL, ROWS>(P.m11, 1.0);
     const double r00 = P.m00 * q00 + P.m01 * q10, r01 = P.m00 * q01 + P.m01 * q11;
     const double r10 = P.m10 * q00 + P.m11 * q10, r11 = P.m10 * q01 + P.m11 * q11;
-    const double m = fmax(fmax(fabs(r00), fabs(r01)), fmax(fabs(r10), fabs(r11)));
-    const int ex = (m > 0.0) ? ilogb(m) : 0;
-    P = Mob{ldexp(r00, -ex), ldexp(r01, -ex), ldexp(r10, -ex), ldexp(r11, -ex)};
+    if constexpr (RESCALE) {
+        const double m = fmax(fmax(fabs(r00), fabs(r01)), fmax(fabs(r10), fabs(r11)));
+        const int ex = (m > 0.0) ? ilogb(m) : 0;
+        P = Mob{ldexp(r00, -ex), ldexp(r01, -ex), ldexp(r10, -ex), ldexp(r11, -ex)};
+    } else {
+        P = Mob{r00, r01, r10, r11};
+    }
 }
 
 __device__ inline Mob mobius_scan(Mob P) {
-    mobius_step<0x111, 0xf>(P);  // row_shr:1
-    mobius_step<0x112, 0xf>(P);  // row_shr:2
-    mobius_step<0x114, 0xf>(P);  // row_shr:4
-    mobius_step<0x118, 0xf>(P);  // row_shr:8
-    mobius_step<0x142, 0xa>(P);  // row_bcast:15 into rows 1 and 3
-    mobius_step<0x143, 0xc>(P);  // row_bcast:31 into rows 2 and 3
+    mobius_step<0x111, 0xf, false>(P);  // row_shr:1
+    mobius_step<0x112, 0xf, false>(P);  // row_shr:2
+    mobius_step<0x114, 0xf, true>(P);   // row_shr:4
+    mobius_step<0x118, 0xf, false>(P);  // row_shr:8
+    mobius_step<0x142, 0xa, false>(P);  // row_bcast:15 into rows 1 and 3
+    mobius_step<0x143, 0xc, false>(P);  // row_bcast:31 into rows 2 and 3
     return P;
 }
 
@@ -136,7 +146,7 @@ __device__ inline Mob mobius_scan(Mob P) {
 // is the composition of the maps d -> (s_k d - cp^2) / d, solved by a prefix
 // scan of their matrices [s_k, -cp^2; 1, 0] (the first lane of a block has
 // no phi term: [s_0, 0; 1, 0], which gives d_0 = s_0 from any start).  Each
-// row's couplings are loaded before the previous row is scanned.
+// row's couplings are loaded one plane (eight rows) before it is scanned.
 struct Pc2Fac {
     double cr, ct, cp;
 };
@@ -168,13 +178,19 @@ __global__ __launch_bounds__(kWave) void k_pc2_factor(Pc2Args<double> a, TOUT *d
     double dp[kPc2J];  // d of the previous r plane of the block, per theta row
 #pragma unroll
     for (int jj = 0; jj < kPc2J; ++jj) dp[jj] = 1.0;
-    Pc2Fac cur = load(0, 0);
+    // q[jj]: the couplings of row jj of the current plane; once a row has
+    // taken them, the same row of the next plane is loaded into its slot, a
+    // whole plane of rows (eight scans) before it is needed
+    Pc2Fac q[kPc2J];
+#pragma unroll
+    for (int jj = 0; jj < kPc2J; ++jj) q[jj] = load(0, jj);
     for (int ii = 0; ii < ni; ++ii) {
         double drow = 1.0;  // d of the previous theta row
 #pragma unroll
         for (int jj = 0; jj < kPc2J; ++jj) {
             if (jj < nj) {
-                const Pc2Fac nxt = (jj + 1 < nj) ? load(ii, jj + 1) : load(ii + 1, 0);
+                const Pc2Fac cur = q[jj];
+                q[jj] = load(ii + 1, jj);
                 Mob P{1.0, 0.0, 0.0, 1.0};
                 if (act) {
                     double sk = 1.0;
@@ -187,7 +203,6 @@ __global__ __launch_bounds__(kWave) void k_pc2_factor(Pc2Args<double> a, TOUT *d
                 if (act) dout[cell(ii, jj)] = (TOUT)dv;
                 dp[jj] = dv;
                 drow = dv;
-                cur = nxt;
             }
         }
     }

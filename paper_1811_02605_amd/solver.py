@@ -136,11 +136,14 @@ class Operator:
         abi.check(st, "mas_op_build")
         self._h = h
         self._work = {}
+        # bound now: at interpreter exit the module's globals may be gone
+        # before the last operator is collected
+        self._destroy = lib.mas_op_destroy
 
     def __del__(self):
         h = getattr(self, "_h", None)
         if h is not None and h.value:
-            abi.load().mas_op_destroy(h)
+            self._destroy(h)
             self._h = None
 
     @property

@@ -18,11 +18,13 @@ from paper_1811_02605_amd import _abi as abi
 pytestmark = pytest.mark.gpu
 
 SHAPES = [(4, 4, 8), (5, 7, 13), (3, 9, 70), (33, 17, 129), (65, 8, 64), (1, 3, 2), (6, 3, 1),
-          (2, 1, 5), (9, 16, 32), (17, 9, 66), (70, 25, 130)]
+          (2, 1, 5), (9, 16, 32), (17, 9, 66), (70, 25, 130), (600, 2, 4)]
 # spans of the two-stage kernel's tiles: 60 phi cells, 12 theta rows, 32 r
 # planes (more beyond 256 planes: 261 gives eight 33-plane chunks)
+# (600, 2, 4): 64-plane chunks of the two-stage kernel (its longest), ten of
+# them, the last one 24 planes marching down
 PAIR_SHAPES = [(70, 25, 130), (33, 13, 64), (3, 1, 2), (1, 12, 4), (40, 26, 122), (65, 8, 64),
-               (9, 16, 32), (2, 3, 6), (261, 2, 4)]
+               (9, 16, 32), (2, 3, 6), (261, 2, 4), (600, 2, 4)]
 BCS = [(0, 0), (1, 0), (1, 1)]
 
 # Both sides round each stage differently (the oracle forms u - (A u)/V from

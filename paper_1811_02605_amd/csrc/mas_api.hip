@@ -1428,9 +1428,12 @@ static int solve_core(const mas_op *op, const double *src, int src_is_rhs, doubl
             // Inner stop on the single-precision recursive (scaled) residual:
             // a factor inner_rtol below the last double-precision residual, or
             // low enough that the unscaled residual it predicts meets the
-            // tolerance (ratio ||W r||/||r|| taken at the last replacement).
+            // tolerance (ratio ||W r||/||r|| taken at the last double-precision
+            // residual), whichever comes first: the last step of either
+            // strategy then stops near the tolerance instead of a factor
+            // inner_rtol below the step before.
             double thr = d2 * rr2;
-            if (reliable && rw2 > 0.0) thr = std::max(thr, 0.25 * tol2 * (rr2 / rw2));
+            if (rw2 > 0.0) thr = std::max(thr, 0.25 * tol2 * (rr2 / rw2));
             v.tol2[0] = thr;
             v.max_iter[0] = k0 + (o.max_iters - used);
             PcgResult pr{};
@@ -1829,14 +1832,14 @@ static int solve_multi_refined(const mas_op *op, const double *rhs, double *x,
             active[h] = !done[h] && info[h].outer_iters < o.max_outer && used[h] < o.max_iters;
             any = any || active[h];
             // inner stop: inner_rtol below the last double-precision residual,
-            // or (reliable PC1) low enough that the unscaled residual it
-            // predicts meets the tolerance
+            // or low enough that the unscaled residual it predicts meets the
+            // tolerance
             if (pc2) {
                 thr[h] = std::max(d2 * rw2[h], 0.25 * tol2[h]);
                 maxit[h] = o.max_iters - used[h];
             } else {
                 thr[h] = d2 * rr2[h];
-                if (reliable && rw2[h] > 0.0) thr[h] = std::max(thr[h], 0.25 * tol2[h] * (rr2[h] / rw2[h]));
+                if (rw2[h] > 0.0) thr[h] = std::max(thr[h], 0.25 * tol2[h] * (rr2[h] / rw2[h]));
                 maxit[h] = o.max_iters - used[h];
             }
             v.tol2[h] = thr[h];

@@ -1,4 +1,4 @@
-"""A grid above 2^31 bytes per FP64 array: 272 x 1030 x 1002 = 280.7M cells
+"""Grids above 2^31 bytes per FP64 array.  272 x 1030 x 1002 = 280.7M cells
 (2.25 GB per array, ragged in theta and phi).  Every marching kernel
 addresses a block's r planes with 32-bit offsets from the block's first
 plane, so cells past the 2 GiB mark of an array must come out exactly as
@@ -92,15 +92,17 @@ def test_large_grid_adjoint_and_gradient(big, big_oracle):
 
 @pytest.mark.timeout(600)
 def test_large_grid_sts_step(big):
-    """One RKL2 step at dt/200 (a few stages, so that the oracle's step
-    stays short), by the two-stage kernel and by one stage per kernel."""
-    dt = big.dt / 200.0
+    """One RKL2 step at dt/10 (a few stages, so that the oracle's step
+    stays short, and at least three, so that the two-stage kernel runs), by
+    the two-stage kernel and by one stage per kernel."""
+    dt = big.dt / 10.0
     grid = S.Grid.from_problem(big)
     op = S.Operator(grid, to_dev(big.nu), dt)
     u0 = to_dev(big.rhs)
     u1, info = op.sts_step(u0)
     u1s, info_s = op.sts_step(u0, stage_pairs=False)
     s = info["stages"]
+    assert s >= 3 and info["stages_per_kernel"] == 2
     same = bool(torch.equal(u1, u1s))
     u1, u1s = to_host(u1), to_host(u1s)
     del op, u0
@@ -114,3 +116,46 @@ def test_large_grid_sts_step(big):
     say(f"large RKL2 ({s} stages): max error vs oracle {err:.2e} (pairs), {err_s:.2e} (single), "
         f"bitwise equal: {same}")
     assert err <= 1e-12 and err_s <= 1e-12 and same
+
+
+# 16M-cell theta-phi planes: a block's window of 16 planes plus halos would
+# pass 2 GiB, so every marching kernel's chunk is capped (at 9 planes here:
+# 2^31 bytes / 128 MiB per plane, less the halo allowance), and the grid,
+# 20 x 4000 x 4000 = 320M cells, has 2.56 GB per FP64 array.
+WIDE = (20, 4000, 4000)
+
+
+@pytest.fixture(scope="module")
+def wide():
+    p = W.make_problem(W.small_config(*WIDE, seed_index=8))
+    say(f"wide-plane inputs ready: {p.cfg.shape} = {p.cfg.n} cells")
+    return p
+
+
+@pytest.mark.timeout(900)
+def test_wide_planes_capped_chunks(wide):
+    grid = S.Grid.from_problem(wide)
+    op = S.Operator(grid, to_dev(wide.nu), wide.dt)
+    x, info = op.solve(to_dev(wide.rhs), S.make_opts(rtol=1e-10), allow_notconv=False)
+    say(f"wide FP64 solve: {info['iters']} iterations, {info['seconds']:.3f} s")
+    x = to_host(x)
+    dt = wide.dt / 10.0
+    del op
+    op = S.Operator(grid, to_dev(wide.nu), dt)
+    u0 = to_dev(wide.rhs)
+    u1, sinfo = op.sts_step(u0)
+    assert sinfo["stages"] >= 3 and sinfo["stages_per_kernel"] == 2
+    u1s, _ = op.sts_step(u0, stage_pairs=False)
+    same = bool(torch.equal(u1, u1s))
+    u1 = to_host(u1)
+    del op, u0, u1s
+    torch.cuda.empty_cache()
+    ora = oracle_operator(wide)
+    r = ora.rel_residual(ora.rhs_to_b(wide.rhs), x)
+    del ora, x
+    ora = oracle_operator(wide, dt=dt)
+    want = ora.rkl2_step(wide.rhs, stages=sinfo["stages"])
+    err = float(np.abs(u1 - want).max()) / float(np.abs(wide.rhs).max())
+    say(f"wide grid: oracle residual {r:.3e}; RKL2 ({sinfo['stages']} stages) max error {err:.2e}, "
+        f"pairs equal single stages: {same}")
+    assert r <= 1e-10 and err <= 1e-12 and same

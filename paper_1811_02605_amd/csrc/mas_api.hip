@@ -732,15 +732,16 @@ struct PcgResult {
     int last_iter[kMaxRhs];  // index of the last iteration kernel that did work
 };
 
+constexpr int64_t kCatchupBlocks = 8192;  // grid-stride blocks of k_x_catchup
+
 // PCG iterations on the scaled system in precision T for NR right-hand sides
 // sharing the operator.  Before the call, r[c][iter0 % 2] holds r_{iter0} and
 // x[c] holds x_{iter0}.  mode 0 stops on ||W r||^2 <= tol2 (checked on the
 // iterations the finalize asks for), mode 1 on (r,r) <= tol2 (every
 // iteration).  The first kernel uses alpha = 0 and beta = v.beta0[c]: with
 // v.keep_p[c] it continues the search direction in p[c][iter0 % 2]
-// (p = r + beta0 p), otherwise it starts afresh (p = r).
-constexpr int64_t kCatchupBlocks = 8192;  // grid-stride blocks of k_x_catchup
-
+// (p = r + beta0 p), otherwise it starts afresh (p = r).  x is complete
+// when it returns (k_x_catchup after the last launch).
 template <typename T, int NR>
 static int run_pcg(Ctx &cx, const RhsSet<T> &v, const T *const c[3], int mode, int iter0,
                    int check_every, PcgResult *res) {

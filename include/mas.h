@@ -118,7 +118,27 @@ typedef struct {
     int32_t chunk_planes; /* r planes each block of the PCG iteration kernel marches
                              through; 0: automatic (at least 16 and an eighth of nr,
                              fewer on grids too small to fill the GPU)             (0) */
+    int32_t launch;       /* MAS_LAUNCH_AUTO | MAS_LAUNCH_PER_ITERATION |
+                             MAS_LAUNCH_PERSISTENT                                  (AUTO) */
 } mas_pcg_opts;
+
+/* How a PC1 run of one right-hand side is launched.
+ *   MAS_LAUNCH_PER_ITERATION: an iteration kernel and a one-block finalize per
+ *     iteration, the host polling the run flags after each batch.
+ *   MAS_LAUNCH_PERSISTENT: the whole run in one cooperative launch whose
+ *     blocks are all resident at once, with a grid barrier per iteration and
+ *     every block applying the same finalize (the same results bit for bit).
+ *     Needs PC1, one right-hand side, no sample_timing and a grid whose
+ *     iteration kernel fits on the GPU at once (small grids, where launches
+ *     and latency, not bandwidth, set the time); MAS_EINVAL otherwise.
+ *     With chunk_planes = 0 its r chunks are long enough for about 64
+ *     blocks; with the same chunk_planes both modes give the same results
+ *     bit for bit (other chunks sum the partial dot products in another
+ *     order).
+ *   MAS_LAUNCH_AUTO: persistent where it is possible and the grid has at
+ *     most 2^17 cells, per iteration otherwise.
+ * Several right-hand sides and PC2 are always launched per iteration. */
+enum { MAS_LAUNCH_AUTO = 0, MAS_LAUNCH_PER_ITERATION = 1, MAS_LAUNCH_PERSISTENT = 2 };
 
 typedef struct {
     int32_t status;              /* the call's return value                                  */
@@ -131,7 +151,8 @@ typedef struct {
     double seconds;              /* host wall clock of the call                               */
     double iter_kernel_us;       /* mean duration of the sampled PCG iteration kernels (us)   */
     int32_t iter_kernel_samples; /* number of samples behind iter_kernel_us (0: not sampled) */
-    int32_t pad_;
+    int32_t launch;              /* how the last PC1 run was launched: MAS_LAUNCH_PER_ITERATION
+                                    or MAS_LAUNCH_PERSISTENT (0: no PC1 run)                  */
     double grad_kernel_us;       /* mas_pcg_solve_adjoint with sample_timing: duration of the
                                     gradient kernel (us), HIP events; otherwise 0             */
 } mas_pcg_info;

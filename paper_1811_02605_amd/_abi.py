@@ -33,6 +33,10 @@ MAS_REFINE_RELIABLE = 1
 MAS_PC1 = 0
 MAS_PC2 = 1
 
+MAS_LAUNCH_AUTO = 0
+MAS_LAUNCH_PER_ITERATION = 1
+MAS_LAUNCH_PERSISTENT = 2
+
 # workspace of the allocation-free solve (a static device array in the library)
 MAS_NOALLOC_WORK_BYTES = 64 * 1024 * 1024
 
@@ -50,7 +54,8 @@ class mas_pcg_opts(ctypes.Structure):
                 ("max_outer", ctypes.c_int32), ("check_every", ctypes.c_int32),
                 ("use_x0", ctypes.c_int32), ("max_restarts", ctypes.c_int32),
                 ("sample_timing", ctypes.c_int32), ("refine", ctypes.c_int32),
-                ("precond", ctypes.c_int32), ("chunk_planes", ctypes.c_int32)]
+                ("precond", ctypes.c_int32), ("chunk_planes", ctypes.c_int32),
+                ("launch", ctypes.c_int32)]
 
 
 class mas_pcg_info(ctypes.Structure):
@@ -59,10 +64,10 @@ class mas_pcg_info(ctypes.Structure):
                 ("rel_resid_true", ctypes.c_double), ("rel_resid_recursive", ctypes.c_double),
                 ("bnorm", ctypes.c_double), ("seconds", ctypes.c_double),
                 ("iter_kernel_us", ctypes.c_double), ("iter_kernel_samples", ctypes.c_int32),
-                ("pad_", ctypes.c_int32), ("grad_kernel_us", ctypes.c_double)]
+                ("launch", ctypes.c_int32), ("grad_kernel_us", ctypes.c_double)]
 
     def as_dict(self):
-        return {f: getattr(self, f) for f, _ in self._fields_ if f != "pad_"}
+        return {f: getattr(self, f) for f, _ in self._fields_}
 
 
 class mas_sts_opts(ctypes.Structure):

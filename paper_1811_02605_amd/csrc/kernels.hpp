@@ -515,6 +515,32 @@ __device__ inline float lane_prev(float v) { return lanes32<lane_prev_u32>(v); }
 __device__ inline double lane_next(double v) { return lanes64<lane_next_u32>(v); }
 __device__ inline float lane_next(float v) { return lanes32<lane_next_u32>(v); }
 
+// The scalars one iteration launch applies, per right-hand side.
+template <typename T, int NR>
+struct IterScalars {
+    bool run[NR];               // the right-hand side's run goes on
+    T alpha[NR], beta[NR], alpha2[NR];  // alpha, beta and alpha_prev of its control block
+    bool check;                 // some running right-hand side forms ||W r||^2
+};
+
+template <typename T, int NR>
+__device__ inline bool iter_scalars(const Ctl *ctl_all, IterScalars<T, NR> &sc) {
+    bool any = false;
+    sc.check = false;
+#pragma unroll
+    for (int c = 0; c < NR; ++c) {
+        const Ctl *ctl = ctl_all + c;
+        sc.run[c] = ctl->flag == FLAG_RUN;
+        any = any || sc.run[c];
+        // ||W r||^2 is formed when any running right-hand side asks for it
+        sc.check = sc.check || (sc.run[c] && ctl->check);
+        sc.alpha[c] = (T)ctl->alpha;
+        sc.alpha2[c] = (T)ctl->alpha_prev;
+        sc.beta[c] = (T)ctl->beta;
+    }
+    return any;
+}
+
 // Each wave owns RPW consecutive theta rows, 64/RPW lanes per row, each lane
 // V consecutive phi cells (a segment of SEG = (64/RPW) V cells per row), and
 // marches through the r planes of its chunk on its own.
@@ -552,12 +578,10 @@ __device__ inline float lane_next(float v) { return lanes32<lane_next_u32>(v); }
 // bitwise what an update in every launch gives, at 8 instead of 16 bytes of
 // x per cell and launch.  A run that stops after a launch without the update
 // gets it from k_x_catchup.
+// One PCG iteration over this block's tile (the body of k_pcg_iter, also
+// run in a loop by k_pcg_persist); writes the block's partial sums.
 template <typename T, int NR, int WPB, int RPW, int V, bool HALO>
-__global__ __launch_bounds__(kWave *WPB)
-#if MAS_ITER_WPE > 0
-__attribute__((amdgpu_waves_per_eu(MAS_ITER_WPE, 8)))
-#endif
-void k_pcg_iter(IterArgs<T> a) {
+__device__ __forceinline__ void pcg_iter_body(const IterArgs<T> &a, const IterScalars<T, NR> &sc) {
     static_assert(kWave % RPW == 0, "rows per wave");
     static_assert(NR >= 1 && NR <= kMaxRhs, "right-hand sides");
     constexpr int W = kWave / RPW;  // lanes per row
@@ -566,19 +590,14 @@ void k_pcg_iter(IterArgs<T> a) {
 
     bool run[NR];
     T alpha[NR], beta[NR], alpha2[NR];
-    bool any = false, check = false;
 #pragma unroll
     for (int c = 0; c < NR; ++c) {
-        const Ctl *ctl = a.ctl + c;
-        run[c] = ctl->flag == FLAG_RUN;
-        any = any || run[c];
-        // ||W r||^2 is formed when any running right-hand side asks for it
-        check = check || (run[c] && ctl->check);
-        alpha[c] = (T)ctl->alpha;
-        alpha2[c] = (T)ctl->alpha_prev;
-        beta[c] = (T)ctl->beta;
+        run[c] = sc.run[c];
+        alpha[c] = sc.alpha[c];
+        beta[c] = sc.beta[c];
+        alpha2[c] = sc.alpha2[c];
     }
-    if (!any) return;
+    const bool check = sc.check;
 
     const int nr = a.d.nr, nt = a.d.nt, np = a.d.np;
     const int64_t plane = a.d.plane;
@@ -912,6 +931,17 @@ void k_pcg_iter(IterArgs<T> a) {
     block_sum_store<NR * kNV>(acc, a.partials + (int64_t)L * NR * kNV, sRed);
 }
 
+template <typename T, int NR, int WPB, int RPW, int V, bool HALO>
+__global__ __launch_bounds__(kWave *WPB)
+#if MAS_ITER_WPE > 0
+__attribute__((amdgpu_waves_per_eu(MAS_ITER_WPE, 8)))
+#endif
+void k_pcg_iter(IterArgs<T> a) {
+    IterScalars<T, NR> sc;
+    if (!iter_scalars<T, NR>(a.ctl, sc)) return;
+    pcg_iter_body<T, NR, WPB, RPW, V, HALO>(a, sc);
+}
+
 // One block: the finalize of right-hand side blockIdx.x after an iteration
 // kernel (partials [nblk][gridDim.x][kNV]).  A launch of its own: folding it
 // into the iteration kernel (the last block to finish sums the partials
@@ -927,6 +957,113 @@ __global__ __launch_bounds__(kRedThreads) void k_finalize(const double *partials
     double S[kNV];
     sum_partials<kRedThreads>(partials, nblk, nrhs, c, S, lds);
     if (threadIdx.x == 0) pcg_finalize(ctl, S);
+}
+
+// ---------------------------------------------------------------- persistent PCG run
+// A whole PCG run of one right-hand side in one cooperative launch, for
+// grids small enough that every block of the iteration kernel is resident
+// at once (such a grid spends an iteration on launches and latency, not on
+// bandwidth).  Each pass of the loop is one iteration (pcg_iter_body, edge
+// cells loaded directly), then a grid barrier, then every block sums the
+// partial sums itself, in k_finalize's fixed order, and applies
+// pcg_finalize to its own copy of the control block (block 0 also writes it
+// back): every block takes the same decisions, and the results equal those
+// of k_pcg_iter and k_finalize launched per iteration, bit for bit.  The
+// vectors, partial sums and records are double-buffered by parity as
+// there, and a block starts iteration k + 1 only after every block has
+// finished iteration k, so no block overwrites what another still reads.
+struct PersistSync {
+    uint32_t bar;  // barrier arrivals, zero at launch
+    int32_t err;   // 1: a block gave up waiting at a barrier
+};
+
+template <typename T>
+struct PersistArgs {
+    IterArgs<T> it;         // shared fields; buffers and partials set per iteration
+    T *r[2], *p[2], *q[2];  // by parity: iteration k reads index k & 1
+    double *partials[2];    // by parity, [nblk][kNV] each
+    Ctl *ctl;               // the run's control block (k_ctl_init has set it)
+    PersistSync *sync;
+    int iter0;              // the run's first iteration index
+    int keep_p;             // the first iteration continues the direction in p[iter0 & 1]
+    uint64_t wait_ticks;    // longest wait at one barrier, in wall-clock ticks
+};
+
+// Grid barrier for co-resident blocks: the block's writes are released at
+// agent scope by the arrival, the wait ends once every block of this
+// generation has arrived, and an agent-scope acquire makes their writes
+// visible.  Returns false, with nothing acquired, if the wait exceeds
+// wait_ticks of the wall clock (a block that was never resident would
+// otherwise leave the others waiting for good).
+__device__ inline bool grid_barrier(PersistSync *sync, uint32_t target, uint64_t wait_ticks) {
+    __shared__ int ok;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __hip_atomic_fetch_add(&sync->bar, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        const uint64_t t0 = wall_clock64();
+        int good = 1;
+        while (__hip_atomic_load(&sync->bar, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+            if (wall_clock64() - t0 > wait_ticks) {
+                good = 0;
+                break;
+            }
+            __builtin_amdgcn_s_sleep(1);
+        }
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        ok = good;
+    }
+    __syncthreads();
+    return ok != 0;
+}
+
+template <typename T, int WPB, int RPW, int V>
+__global__ __launch_bounds__(kWave *WPB) void k_pcg_persist(PersistArgs<T> a) {
+    static_assert(kWave * WPB == kRedThreads, "one block sums the partials");
+    __shared__ Ctl lc;  // this block's copy of the control block
+    __shared__ double lds[(kRedThreads / kWave) * kNV];
+    if (threadIdx.x == 0) lc = *a.ctl;
+    __syncthreads();
+    IterArgs<T> it = a.it;
+    for (int k = a.iter0;; ++k) {
+        const int cur = k & 1, nxt = cur ^ 1;
+        const int s = k - a.iter0;
+        // the first iteration has alpha = 0 (and beta = 0 unless the
+        // direction is kept): q (and p) point at r, as in the launched form
+        it.r_in[0] = a.r[cur];
+        it.p_in[0] = (s == 0 && !a.keep_p) ? a.r[cur] : a.p[cur];
+        it.q_in[0] = (s == 0) ? a.r[cur] : a.q[cur];
+        it.r_out[0] = a.r[nxt];
+        it.p_out[0] = a.p[nxt];
+        it.q_out[0] = a.q[nxt];
+        it.partials = a.partials[cur];
+        it.xstep = (s >= 2 && (s & 1) == 0) ? 1 : 0;
+        IterScalars<T, 1> sc;
+        sc.run[0] = true;
+        sc.alpha[0] = (T)lc.alpha;
+        sc.beta[0] = (T)lc.beta;
+        sc.alpha2[0] = (T)lc.alpha_prev;
+        sc.check = lc.check != 0;
+        pcg_iter_body<T, 1, WPB, RPW, V, false>(it, sc);
+        if (!grid_barrier(a.sync, (uint32_t)(s + 1) * gridDim.x, a.wait_ticks)) {
+            if (threadIdx.x == 0) __hip_atomic_store(&a.sync->err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            return;
+        }
+        double S[kNV];
+        sum_partials<kRedThreads>(it.partials, it.nblk, 1, 0, S, lds);
+        if (threadIdx.x == 0) {
+            pcg_finalize(&lc, S);
+            if (blockIdx.x == 0) *a.ctl = lc;
+        }
+        __syncthreads();
+        if (lc.flag != FLAG_RUN) return;
+    }
+}
+
+__global__ void k_persist_init(PersistSync *sync) {
+    if (threadIdx.x == 0) {
+        sync->bar = 0u;
+        sync->err = 0;
+    }
 }
 
 // After a run of iteration kernels: a right-hand side whose last launch did

@@ -337,6 +337,7 @@ extern "C" void mas_pcg_default_opts(mas_pcg_opts *o) {
     o->refine = MAS_REFINE_RELIABLE;
     o->precond = MAS_PC1;
     o->chunk_planes = 0;
+    o->launch = MAS_LAUNCH_AUTO;
 }
 
 extern "C" int64_t mas_op_storage_bytes(const mas_grid *g, int32_t precision) {
@@ -491,7 +492,7 @@ extern "C" int mas_op_export(const mas_op *op, double *cr, double *ct, double *c
 
 // ------------------------------------------------------------------ workspace
 struct WorkLayout {
-    int64_t ctl, partials, bhat[kMaxRhs], vec[kMaxRhs][6], halo[kMaxRhs][2], dh[kMaxRhs], total;
+    int64_t ctl, sync, partials, bhat[kMaxRhs], vec[kMaxRhs][6], halo[kMaxRhs][2], dh[kMaxRhs], total;
     int64_t halo_bytes;  // one record buffer (0: records not used)
 };
 
@@ -504,8 +505,11 @@ static WorkLayout work_layout(const Shape &s, int precision, int nrhs = 1) {
     auto take_array = [&](int64_t bytes) { return cur.take_array(bytes); };
     // the iteration kernel writes nrhs * kNV partials per block (most blocks
     // with V = 1), the simple-tile kernels up to kSimpleNV
-    const int64_t nparts = std::max(s.nblk_iter_max() * kNV * nrhs, s.nblk_simple() * kSimpleNV);
+    // (a persistent run of one right-hand side keeps two sets, by parity)
+    const int64_t nparts = std::max(s.nblk_iter_max() * kNV * std::max(nrhs, 2),
+                                    s.nblk_simple() * kSimpleNV);
     L.ctl = take(sizeof(Ctl) * nrhs);
+    L.sync = take(sizeof(PersistSync));
     L.partials = take(8 * nparts);
     const int64_t es = (precision == MAS_FP32_REFINED) ? 4 : 8;
     for (int c = 0; c < kMaxRhs; ++c) {
@@ -550,6 +554,11 @@ static int check_opts(const mas_op *op, const mas_pcg_opts *o) {
     if (o->chunk_planes < 0) return fail(MAS_EINVAL, "chunk_planes must be >= 0");
     if (o->precond != MAS_PC1 && o->precond != MAS_PC2)
         return fail(MAS_EINVAL, "unknown preconditioner %d", o->precond);
+    if (o->launch != MAS_LAUNCH_AUTO && o->launch != MAS_LAUNCH_PER_ITERATION &&
+        o->launch != MAS_LAUNCH_PERSISTENT)
+        return fail(MAS_EINVAL, "unknown launch mode %d", o->launch);
+    if (o->launch == MAS_LAUNCH_PERSISTENT && (o->precond != MAS_PC1 || o->sample_timing))
+        return fail(MAS_EINVAL, "the persistent launch needs PC1 and no sample_timing");
     return MAS_OK;
 }
 
@@ -598,6 +607,9 @@ struct Ctx {
     bool timing;
     bool no_alloc = false;  // allocation-free entry point: no pinned buffer, no events
     int chunk = 0;          // r planes per chunk of the iteration kernel (0: automatic)
+    PersistSync *sync = nullptr;     // barrier words of the persistent launch
+    int launch = MAS_LAUNCH_AUTO;    // requested launch mode of PC1 runs
+    int launched = 0;                // mode of the last PC1 run (0: none yet)
     // event samples of the iteration kernel
     std::vector<hipEvent_t> ev;
     std::vector<int> ev_iter;
@@ -734,6 +746,147 @@ struct PcgResult {
 
 constexpr int64_t kCatchupBlocks = 8192;  // grid-stride blocks of k_x_catchup
 
+// The x update of a run's last launch when that launch left it to the next
+// one (see k_pcg_iter); enqueued after every run.
+template <typename T, int NR>
+static int launch_catchup(Ctx &cx, const RhsSet<T> &v, int iter0) {
+    CatchupArgs<T> ca{};
+    for (int h = 0; h < NR; ++h) {
+        ca.x[h] = v.x[h];
+        ca.p[h][0] = v.p[h][0];
+        ca.p[h][1] = v.p[h][1];
+    }
+    ca.ctl = cx.ctl;
+    ca.n = cx.op->s.n;
+    ca.iter0 = iter0;
+    const int64_t cblk = std::min<int64_t>((cx.op->s.n + 255) / 256, kCatchupBlocks);
+    hipLaunchKernelGGL(k_x_catchup<T>, dim3((unsigned)cblk, NR), dim3(256), 0, cx.stream, ca);
+    LAUNCHCHK();
+    return MAS_OK;
+}
+
+// Persistent launch (k_pcg_persist): the automatic choice takes it for
+// grids of at most kPersistAutoCells cells (latency-bound: a launch per
+// iteration costs about 14 us there whatever the size); unless chunk_planes
+// is set, its r chunks are as long as it takes to have at most about
+// kPersistBlocks blocks, since every block sums every block's partials and
+// arrives at the barrier (at 32 x 32 x 64 cells: 64 blocks 13.5 us per
+// iteration, 128 blocks 15.0 us, against 14.4 us launched per iteration).
+// A block gives up waiting at a grid barrier after kPersistWaitSec seconds.
+constexpr int64_t kPersistAutoCells = (int64_t)1 << 17;
+constexpr int64_t kPersistBlocks = 64;
+constexpr double kPersistWaitSec = 2.0;
+
+// r planes per chunk of a persistent run (cx.chunk when set)
+static int persist_chunk(const Ctx &cx, int V) {
+    if (cx.chunk > 0) return cx.chunk;
+    const Shape &s = cx.op->s;
+    const int64_t tiles = (int64_t)s.tiles_k(V) * s.tiles_j();
+    const int64_t want = (tiles * s.nr + kPersistBlocks - 1) / kPersistBlocks;
+    return (int)std::max<int64_t>(1, std::min<int64_t>(want, s.nr));
+}
+
+template <typename T>
+static const void *persist_kernel(int V) {
+    constexpr int VW = vec_full<T>();
+    return (V == VW) ? reinterpret_cast<const void *>(&k_pcg_persist<T, kTJ, kRPW, VW>)
+                     : reinterpret_cast<const void *>(&k_pcg_persist<T, kTJ, kRPW, 1>);
+}
+
+// Whether a PC1 run of one right-hand side goes into one persistent launch
+// (1) or a launch per iteration (0); MAS_EINVAL when the persistent launch
+// was asked for and is not possible.
+template <typename T>
+static int persist_choice(Ctx &cx, const RhsSet<T> &v, int iter0) {
+    if (cx.launch == MAS_LAUNCH_PER_ITERATION) return 0;
+    const bool forced = cx.launch == MAS_LAUNCH_PERSISTENT;
+    auto no = [&](const char *why) { return forced ? fail(MAS_EINVAL, "persistent launch: %s", why) : 0; };
+    if (cx.timing) return no("sample_timing is set");
+    const Shape &s = cx.op->s;
+    if (!forced && s.n > kPersistAutoCells) return 0;
+    const int V = iter_vec<T>(s.np, 1);
+    const int64_t nblk = s.nblk_iter(V, persist_chunk(cx, V));
+    if ((int64_t)(std::max(v.max_iter[0], iter0) - iter0 + 1) * nblk >= ((int64_t)1 << 32))
+        return no("max_iters too large for the barrier counter");
+    int dev = 0, coop = 0, ncu = 0, per_cu = 0;
+    HIPCHK(hipGetDevice(&dev));
+    HIPCHK(hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev));
+    if (!coop) return no("the device has no cooperative launch");
+    HIPCHK(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+    HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, persist_kernel<T>(V), kWave * kTJ, 0));
+    if ((int64_t)per_cu * ncu < nblk) return no("the iteration kernel's blocks do not fit on the GPU at once");
+    return 1;
+}
+
+// A PC1 run of one right-hand side in one cooperative launch of
+// k_pcg_persist: the same control-block set-up, iterations, stopping and
+// results as run_pcg's launches per iteration, bit for bit.
+template <typename T>
+static int run_pcg_persist(Ctx &cx, const RhsSet<T> &v, const T *const c[3], int mode, int iter0,
+                           int check_every, PcgResult *res) {
+    const mas_op *op = cx.op;
+    const Shape &s = op->s;
+    hipStream_t st = cx.stream;
+    const double beta0 = v.keep_p[0] ? v.beta0[0] : 0.0;
+    hipLaunchKernelGGL(k_ctl_init, dim3(1), dim3(64), 0, st, cx.ctl, mode, iter0, v.max_iter[0],
+                       v.tol2[0], beta0, v.active[0] ? FLAG_RUN : FLAG_CONV, mode == 0 ? 1 : 0,
+                       check_every);
+    hipLaunchKernelGGL(k_persist_init, dim3(1), dim3(64), 0, st, cx.sync);
+    LAUNCHCHK();
+    cx.launched = MAS_LAUNCH_PERSISTENT;
+    if (v.active[0] && v.max_iter[0] >= iter0) {
+        PersistArgs<T> pa{};
+        IterArgs<T> &a = pa.it;
+        a.cr = c[0];
+        a.ct = c[1];
+        a.cp = c[2];
+        a.w = op->w;
+        a.ctl = cx.ctl;
+        a.d = s.dims();
+        const int V = iter_vec<T>(s.np, 1);
+        const int ch = persist_chunk(cx, V);
+        a.tiles_i = s.tiles_i(V, ch);
+        a.tiles_k = s.tiles_k(V);
+        a.tiles_j = s.tiles_j();
+        a.ti = s.ti(V, ch);
+        a.nblk = (int)s.nblk_iter(V, ch);
+        a.x[0] = v.x[0];
+        a.records = 0;
+        for (int t = 0; t < 2; ++t) {
+            pa.r[t] = v.r[0][t];
+            pa.p[t] = v.p[0][t];
+            pa.q[t] = v.q[0][t];
+        }
+        pa.partials[0] = cx.partials;
+        pa.partials[1] = cx.partials + (int64_t)a.nblk * kNV;
+        pa.ctl = cx.ctl;
+        pa.sync = cx.sync;
+        pa.iter0 = iter0;
+        pa.keep_p = v.keep_p[0] ? 1 : 0;
+        int dev = 0, khz = 0;
+        HIPCHK(hipGetDevice(&dev));
+        HIPCHK(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev));
+        pa.wait_ticks = (uint64_t)((double)khz * 1000.0 * kPersistWaitSec);
+        void *args[] = {&pa};
+        HIPCHK(hipLaunchCooperativeKernel(persist_kernel<T>(V), dim3((unsigned)a.nblk),
+                                          dim3(kWave * kTJ), args, 0, st));
+    }
+    int e = launch_catchup<T, 1>(cx, v, iter0);
+    if (e != MAS_OK) return e;
+    PersistSync hs{};
+    HIPCHK(hipMemcpyAsync(&hs, cx.sync, sizeof hs, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    if (hs.err)
+        return fail(MAS_EHIP, "persistent PCG run: a block waited more than %g s at a grid barrier",
+                    kPersistWaitSec);
+    Ctl hc;
+    e = read_ctl(cx, &hc);
+    if (e != MAS_OK) return e;
+    res->flag[0] = hc.flag;
+    res->last_iter[0] = (hc.flag == FLAG_RUN) ? v.max_iter[0] : hc.conv_iter;
+    return MAS_OK;
+}
+
 // PCG iterations on the scaled system in precision T for NR right-hand sides
 // sharing the operator.  Before the call, r[c][iter0 % 2] holds r_{iter0} and
 // x[c] holds x_{iter0}.  mode 0 stops on ||W r||^2 <= tol2 (checked on the
@@ -745,6 +898,12 @@ constexpr int64_t kCatchupBlocks = 8192;  // grid-stride blocks of k_x_catchup
 template <typename T, int NR>
 static int run_pcg(Ctx &cx, const RhsSet<T> &v, const T *const c[3], int mode, int iter0,
                    int check_every, PcgResult *res) {
+    if constexpr (NR == 1) {
+        const int pc = persist_choice<T>(cx, v, iter0);
+        if (pc < 0) return pc;
+        if (pc == 1) return run_pcg_persist<T>(cx, v, c, mode, iter0, check_every, res);
+    }
+    cx.launched = MAS_LAUNCH_PER_ITERATION;
     const mas_op *op = cx.op;
     const Shape &s = op->s;
     hipStream_t st = cx.stream;
@@ -842,19 +1001,8 @@ static int run_pcg(Ctx &cx, const RhsSet<T> &v, const T *const c[3], int mode, i
         e = poll.after_batch(NR, &stop);
         if (e != MAS_OK) return e;
     }
-    // the x update of a last launch that left it to the next one
-    CatchupArgs<T> ca{};
-    for (int h = 0; h < NR; ++h) {
-        ca.x[h] = v.x[h];
-        ca.p[h][0] = v.p[h][0];
-        ca.p[h][1] = v.p[h][1];
-    }
-    ca.ctl = cx.ctl;
-    ca.n = s.n;
-    ca.iter0 = iter0;
-    const int64_t cblk = std::min<int64_t>((s.n + 255) / 256, kCatchupBlocks);
-    hipLaunchKernelGGL(k_x_catchup<T>, dim3((unsigned)cblk, NR), dim3(256), 0, st, ca);
-    LAUNCHCHK();
+    e = launch_catchup<T, NR>(cx, v, iter0);
+    if (e != MAS_OK) return e;
     HIPCHK(hipStreamSynchronize(st));
     for (int h = 0; h < NR; ++h) {
         Ctl hc;
@@ -1195,6 +1343,8 @@ static int solve_core(const mas_op *op, const double *src, int src_is_rhs, doubl
     cx.timing = o.sample_timing != 0;
     cx.no_alloc = no_alloc;
     cx.chunk = o.chunk_planes;
+    cx.sync = reinterpret_cast<PersistSync *>(base + L.sync);
+    cx.launch = o.launch;
     const Dims d = s.dims();
     const dim3 sgrid = s.simple_grid(), sblock(kWave, kSimpleJ);
 
@@ -1496,6 +1646,7 @@ static int solve_core(const mas_op *op, const double *src, int src_is_rhs, doubl
     LAUNCHCHK();
     HIPCHK(hipStreamSynchronize(cx.stream));
     info.status = status;
+    info.launch = cx.launched;
     info.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     if (info_out) *info_out = info;
     if (status == MAS_ENOTCONV)
@@ -1521,6 +1672,8 @@ static int solve_multi_core(const mas_op *op, const double *rhs, double *x, cons
     cx.partials = reinterpret_cast<double *>(base + L.partials);
     cx.timing = o.sample_timing != 0;
     cx.chunk = o.chunk_planes;
+    cx.sync = reinterpret_cast<PersistSync *>(base + L.sync);
+    cx.launch = o.launch;
     const Dims d = s.dims();
     const dim3 sgrid = s.simple_grid(), sblock(kWave, kSimpleJ);
     const double *const c[3] = {op->c64[0], op->c64[1], op->c64[2]};
@@ -1712,7 +1865,10 @@ static int solve_multi_core(const mas_op *op, const double *rhs, double *x, cons
     }
     HIPCHK(hipStreamSynchronize(stream));
     const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
-    for (int h = 0; h < NR; ++h) info[h].seconds = secs;
+    for (int h = 0; h < NR; ++h) {
+        info[h].seconds = secs;
+        info[h].launch = cx.launched;
+    }
     return status;
 }
 
@@ -1737,6 +1893,8 @@ static int solve_multi_refined(const mas_op *op, const double *rhs, double *x,
     cx.partials = reinterpret_cast<double *>(base + L.partials);
     cx.timing = o.sample_timing != 0;
     cx.chunk = o.chunk_planes;
+    cx.sync = reinterpret_cast<PersistSync *>(base + L.sync);
+    cx.launch = o.launch;
     const Dims d = s.dims();
     const dim3 sgrid = s.simple_grid(), sblock(kWave, kSimpleJ);
     const float *const c32[3] = {op->c32[0], op->c32[1], op->c32[2]};
@@ -1938,7 +2096,10 @@ static int solve_multi_refined(const mas_op *op, const double *rhs, double *x,
     }
     HIPCHK(hipStreamSynchronize(stream));
     const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
-    for (int h = 0; h < NR; ++h) info[h].seconds = secs;
+    for (int h = 0; h < NR; ++h) {
+        info[h].seconds = secs;
+        info[h].launch = cx.launched;
+    }
     return status;
 }
 
@@ -2011,6 +2172,8 @@ extern "C" int mas_pcg_solve_multi(const mas_op *op, int32_t nrhs, const double 
     if (o_in) o = *o_in;
     int st = check_opts(op, &o);
     if (st != MAS_OK) return st;
+    if (o.launch == MAS_LAUNCH_PERSISTENT && nrhs > 1)
+        return fail(MAS_EINVAL, "several right-hand sides are launched per iteration, not persistent");
     if (reinterpret_cast<uintptr_t>(work) & 255)
         return fail(MAS_EINVAL, "work must be 256-byte aligned");
     const WorkLayout L = work_layout(op->s, o.precision, nrhs);

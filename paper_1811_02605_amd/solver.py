@@ -59,14 +59,18 @@ class Grid:
 
 REFINES = {"restart": abi.MAS_REFINE_RESTART, "reliable": abi.MAS_REFINE_RELIABLE}
 PRECONDS = {"pc1": abi.MAS_PC1, "pc2": abi.MAS_PC2}
+LAUNCHES = {"auto": abi.MAS_LAUNCH_AUTO, "per_iteration": abi.MAS_LAUNCH_PER_ITERATION,
+            "persistent": abi.MAS_LAUNCH_PERSISTENT}
 
 
 def make_opts(rtol=None, max_iters=None, precision=None, inner_rtol=None, max_outer=None,
               check_every=None, use_x0=None, max_restarts=None, sample_timing=None, refine=None,
-              precond=None, chunk_planes=None):
+              precond=None, chunk_planes=None, launch=None):
     o = abi.default_opts()
     if isinstance(precision, str):
         precision = PRECISIONS[precision]
+    if isinstance(launch, str):
+        launch = LAUNCHES[launch]
     if isinstance(refine, str):
         refine = REFINES[refine]
     if isinstance(precond, str):
@@ -75,7 +79,7 @@ def make_opts(rtol=None, max_iters=None, precision=None, inner_rtol=None, max_ou
                         inner_rtol=inner_rtol, max_outer=max_outer, check_every=check_every,
                         use_x0=use_x0, max_restarts=max_restarts,
                         sample_timing=sample_timing, refine=refine, precond=precond,
-                        chunk_planes=chunk_planes).items():
+                        chunk_planes=chunk_planes, launch=launch).items():
         if v is not None:
             setattr(o, name, type(getattr(o, name))(v))
     return o

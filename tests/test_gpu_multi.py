@@ -54,12 +54,15 @@ def test_components_match_oracle(shape, m, chunk):
 @pytest.mark.parametrize("m", [1, 3])
 @pytest.mark.parametrize("shape", [(33, 17, 129), (9, 16, 32), "c0"])
 def test_components_match_single_solves(shape, m, chunk):
-    """The per-component iterations are those of the single solve: same
-    iteration counts, solutions equal to rounding."""
+    """The per-component iterations are those of the single solve launched
+    per iteration (the same blocking of the dot products): same iteration
+    counts, solutions equal to rounding."""
     p = problem(shape, (0, 0))
     _, op = gpu_operator(p)
     B = _rhs(p, m)
-    o = S.make_opts(rtol=1e-10, chunk_planes=chunk)
+    # (one right-hand side would otherwise go into the persistent launch,
+    # with its own chunks)
+    o = S.make_opts(rtol=1e-10, chunk_planes=chunk, launch="per_iteration")
     X, infos = op.solve_multi(to_dev(B), o, allow_notconv=False)
     for h in range(m):
         x1, i1 = op.solve(to_dev(B[h]), o, allow_notconv=False)
@@ -137,15 +140,18 @@ def test_refined_components_match_oracle(shape, precond, refine, m, chunk):
 @pytest.mark.parametrize("shape", [(33, 17, 129), "c0"])
 def test_refined_components_equal_single_refined_solves(shape, precond, refine, m):
     """Each component of the shared refined solve takes the inner and outer
-    iterations of its single refined solve and gives the same solution bit
-    for bit (the same kernels and sums per component)."""
+    iterations of its single refined solve launched per iteration and gives
+    the same solution bit for bit (the same kernels and sums per
+    component)."""
     p = problem(shape, (0, 0))
     _, op = gpu_operator(p, "fp32_refined")
     B = _rhs(p, m)
     o = S.make_opts(rtol=1e-10, precision="fp32_refined", precond=precond, refine=refine)
     X, infos = op.solve_multi(to_dev(B), o, allow_notconv=False)
+    o1 = S.make_opts(rtol=1e-10, precision="fp32_refined", precond=precond, refine=refine,
+                     launch="per_iteration")
     for h in range(m):
-        x1, i1 = op.solve(to_dev(B[h]), o, allow_notconv=False)
+        x1, i1 = op.solve(to_dev(B[h]), o1, allow_notconv=False)
         assert (infos[h]["iters"], infos[h]["outer_iters"]) == (i1["iters"], i1["outer_iters"]), h
         assert torch.equal(X[h], x1), h
 

@@ -189,21 +189,27 @@ def bench_c0(S, W, dev, reps=20):
     rhs0 = torch.from_numpy(q.rhs).to(dev)
     x0 = torch.empty_like(rhs0)
     op = S.Operator(g0, nu0, q.dt)
+
+    def timed(solve, o):
+        solve(rhs0, o, out=x0, allow_notconv=False)
+        runs = [solve(rhs0, o, out=x0, allow_notconv=False)[1] for _ in range(reps)]
+        return float(np.median([r["seconds"] for r in runs])), runs[-1]
+
     o = S.make_opts(rtol=q.cfg.rtol)
-    op.solve(rhs0, o, out=x0, allow_notconv=False)
-    runs = [op.solve(rhs0, o, out=x0, allow_notconv=False)[1] for _ in range(reps)]
-    t = float(np.median([r["seconds"] for r in runs]))
-    op.solve_noalloc(rhs0, o, out=x0, allow_notconv=False)
-    runs_na = [op.solve_noalloc(rhs0, o, out=x0, allow_notconv=False)[1] for _ in range(reps)]
-    t_na = float(np.median([r["seconds"] for r in runs_na]))
-    it = runs[-1]["iters"]
-    print(f"[bench] c0: {it} iterations, {1e3 * t:.2f} ms ({it / t:.0f} iters/s); allocation-free "
-          f"{1e3 * t_na:.2f} ms", file=sys.stderr, flush=True)
+    t, last = timed(op.solve, o)
+    t_pi, last_pi = timed(op.solve, S.make_opts(rtol=q.cfg.rtol, launch="per_iteration"))
+    t_na, last_na = timed(op.solve_noalloc, o)
+    it = last["iters"]
+    mode = {1: "per_iteration", 2: "persistent"}.get(last["launch"], "none")
+    print(f"[bench] c0: {it} iterations, {1e3 * t:.2f} ms ({it / t:.0f} iters/s, {mode} launch); "
+          f"launched per iteration {1e3 * t_pi:.2f} ms; allocation-free {1e3 * t_na:.2f} ms",
+          file=sys.stderr, flush=True)
     return {"what": "c0: 32x32x64 (65,536 cells) FP64 Jacobi-PCG to 1e-10, median of "
                     f"{reps} solves (cache-resident, latency-bound: no HBM fraction)",
             "cells": q.cfg.n, "iters": it, "time_to_tol_s": t, "iters_per_s": it / t,
-            "rel_resid_true": runs[-1]["rel_resid_true"],
-            "noalloc": {"time_to_tol_s": t_na, "iters_per_s": runs_na[-1]["iters"] / t_na}}
+            "launch": mode, "rel_resid_true": last["rel_resid_true"],
+            "per_iteration_launch": {"time_to_tol_s": t_pi, "iters_per_s": last_pi["iters"] / t_pi},
+            "noalloc": {"time_to_tol_s": t_na, "iters_per_s": last_na["iters"] / t_na}}
 
 
 def bench_c4(S, W, dev):

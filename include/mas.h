@@ -122,22 +122,22 @@ typedef struct {
                              MAS_LAUNCH_PERSISTENT                                  (AUTO) */
 } mas_pcg_opts;
 
-/* How a PC1 run of one right-hand side is launched.
+/* How a PC1 run (one to four right-hand sides) is launched.
  *   MAS_LAUNCH_PER_ITERATION: an iteration kernel and a one-block finalize per
  *     iteration, the host polling the run flags after each batch.
  *   MAS_LAUNCH_PERSISTENT: the whole run in one cooperative launch whose
  *     blocks are all resident at once, with a grid barrier per iteration and
  *     every block applying the same finalize (the same results bit for bit).
- *     Needs PC1, one right-hand side, no sample_timing and a grid whose
- *     iteration kernel fits on the GPU at once (small grids, where launches
- *     and latency, not bandwidth, set the time); MAS_EINVAL otherwise.
+ *     Needs PC1, no sample_timing and a grid whose iteration kernel fits on
+ *     the GPU at once (small grids, where launches and latency, not
+ *     bandwidth, set the time); MAS_EINVAL otherwise.
  *     With chunk_planes = 0 its r chunks are long enough for about 64
  *     blocks; with the same chunk_planes both modes give the same results
  *     bit for bit (other chunks sum the partial dot products in another
  *     order).
  *   MAS_LAUNCH_AUTO: persistent where it is possible and the grid has at
  *     most 2^17 cells, per iteration otherwise.
- * Several right-hand sides and PC2 are always launched per iteration. */
+ * PC2 is always launched per iteration. */
 enum { MAS_LAUNCH_AUTO = 0, MAS_LAUNCH_PER_ITERATION = 1, MAS_LAUNCH_PERSISTENT = 2 };
 
 typedef struct {

@@ -960,15 +960,16 @@ __global__ __launch_bounds__(kRedThreads) void k_finalize(const double *partials
 }
 
 // ---------------------------------------------------------------- persistent PCG run
-// A whole PCG run of one right-hand side in one cooperative launch, for
+// A whole PCG run of NR right-hand sides in one cooperative launch, for
 // grids small enough that every block of the iteration kernel is resident
 // at once (such a grid spends an iteration on launches and latency, not on
 // bandwidth).  Each pass of the loop is one iteration (pcg_iter_body, edge
 // cells loaded directly), then a grid barrier, then every block sums the
 // partial sums itself, in k_finalize's fixed order, and applies
-// pcg_finalize to its own copy of the control block (block 0 also writes it
-// back): every block takes the same decisions, and the results equal those
-// of k_pcg_iter and k_finalize launched per iteration, bit for bit.  The
+// pcg_finalize to its own copies of the control blocks (block 0 also writes
+// them back): every block takes the same decisions, and the results equal
+// those of k_pcg_iter and k_finalize launched per iteration, bit for bit.
+// The loop ends when no right-hand side runs any more.  The
 // vectors, partial sums and records are double-buffered by parity as
 // there, and a block starts iteration k + 1 only after every block has
 // finished iteration k, so no block overwrites what another still reads.
@@ -977,16 +978,16 @@ struct PersistSync {
     int32_t err;   // 1: a block gave up waiting at a barrier
 };
 
-template <typename T>
+template <typename T, int NR>
 struct PersistArgs {
-    IterArgs<T> it;         // shared fields; buffers and partials set per iteration
-    T *r[2], *p[2], *q[2];  // by parity: iteration k reads index k & 1
-    double *partials[2];    // by parity, [nblk][kNV] each
-    Ctl *ctl;               // the run's control block (k_ctl_init has set it)
+    IterArgs<T> it;                   // shared fields; buffers and partials set per iteration
+    T *r[NR][2], *p[NR][2], *q[NR][2];  // by parity: iteration k reads index k & 1
+    double *partials[2];              // by parity, [nblk][NR][kNV] each
+    Ctl *ctl;                         // [NR] (k_ctl_init has set them)
     PersistSync *sync;
-    int iter0;              // the run's first iteration index
-    int keep_p;             // the first iteration continues the direction in p[iter0 & 1]
-    uint64_t wait_ticks;    // longest wait at one barrier, in wall-clock ticks
+    int iter0;                        // the run's first iteration index
+    int keep_p[NR];                   // the first iteration continues the direction in p[c][iter0 & 1]
+    uint64_t wait_ticks;              // longest wait at one barrier, in wall-clock ticks
 };
 
 // Grid barrier for co-resident blocks: the block's writes are released at
@@ -1016,46 +1017,56 @@ __device__ inline bool grid_barrier(PersistSync *sync, uint32_t target, uint64_t
     return ok != 0;
 }
 
-template <typename T, int WPB, int RPW, int V>
-__global__ __launch_bounds__(kWave *WPB) void k_pcg_persist(PersistArgs<T> a) {
+template <typename T, int NR, int WPB, int RPW, int V>
+__global__ __launch_bounds__(kWave *WPB) void k_pcg_persist(PersistArgs<T, NR> a) {
     static_assert(kWave * WPB == kRedThreads, "one block sums the partials");
-    __shared__ Ctl lc;  // this block's copy of the control block
+    __shared__ Ctl lc[NR];  // this block's copies of the control blocks
     __shared__ double lds[(kRedThreads / kWave) * kNV];
-    if (threadIdx.x == 0) lc = *a.ctl;
+    if (threadIdx.x < NR) lc[threadIdx.x] = a.ctl[threadIdx.x];
     __syncthreads();
     IterArgs<T> it = a.it;
     for (int k = a.iter0;; ++k) {
         const int cur = k & 1, nxt = cur ^ 1;
         const int s = k - a.iter0;
-        // the first iteration has alpha = 0 (and beta = 0 unless the
-        // direction is kept): q (and p) point at r, as in the launched form
-        it.r_in[0] = a.r[cur];
-        it.p_in[0] = (s == 0 && !a.keep_p) ? a.r[cur] : a.p[cur];
-        it.q_in[0] = (s == 0) ? a.r[cur] : a.q[cur];
-        it.r_out[0] = a.r[nxt];
-        it.p_out[0] = a.p[nxt];
-        it.q_out[0] = a.q[nxt];
+        IterScalars<T, NR> sc;
+        sc.check = false;
+#pragma unroll
+        for (int c = 0; c < NR; ++c) {
+            // the first iteration has alpha = 0 (and beta = 0 unless the
+            // direction is kept): q (and p) point at r, as in the launched form
+            it.r_in[c] = a.r[c][cur];
+            it.p_in[c] = (s == 0 && !a.keep_p[c]) ? a.r[c][cur] : a.p[c][cur];
+            it.q_in[c] = (s == 0) ? a.r[c][cur] : a.q[c][cur];
+            it.r_out[c] = a.r[c][nxt];
+            it.p_out[c] = a.p[c][nxt];
+            it.q_out[c] = a.q[c][nxt];
+            sc.run[c] = lc[c].flag == FLAG_RUN;
+            sc.alpha[c] = (T)lc[c].alpha;
+            sc.beta[c] = (T)lc[c].beta;
+            sc.alpha2[c] = (T)lc[c].alpha_prev;
+            sc.check = sc.check || (sc.run[c] && lc[c].check);
+        }
         it.partials = a.partials[cur];
         it.xstep = (s >= 2 && (s & 1) == 0) ? 1 : 0;
-        IterScalars<T, 1> sc;
-        sc.run[0] = true;
-        sc.alpha[0] = (T)lc.alpha;
-        sc.beta[0] = (T)lc.beta;
-        sc.alpha2[0] = (T)lc.alpha_prev;
-        sc.check = lc.check != 0;
-        pcg_iter_body<T, 1, WPB, RPW, V, false>(it, sc);
+        pcg_iter_body<T, NR, WPB, RPW, V, false>(it, sc);
         if (!grid_barrier(a.sync, (uint32_t)(s + 1) * gridDim.x, a.wait_ticks)) {
             if (threadIdx.x == 0) __hip_atomic_store(&a.sync->err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             return;
         }
-        double S[kNV];
-        sum_partials<kRedThreads>(it.partials, it.nblk, 1, 0, S, lds);
-        if (threadIdx.x == 0) {
-            pcg_finalize(&lc, S);
-            if (blockIdx.x == 0) *a.ctl = lc;
+        bool any = false;
+#pragma unroll
+        for (int c = 0; c < NR; ++c) {
+            if (lc[c].flag != FLAG_RUN) continue;  // uniform: every thread reads the same flag
+            double S[kNV];
+            sum_partials<kRedThreads>(it.partials, it.nblk, NR, c, S, lds);
+            if (threadIdx.x == 0) {
+                pcg_finalize(&lc[c], S);
+                if (blockIdx.x == 0) a.ctl[c] = lc[c];
+            }
+            __syncthreads();
+            any = any || lc[c].flag == FLAG_RUN;
         }
-        __syncthreads();
-        if (lc.flag != FLAG_RUN) return;
+        if (!any) return;
     }
 }
 

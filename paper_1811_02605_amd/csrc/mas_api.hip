@@ -505,9 +505,8 @@ static WorkLayout work_layout(const Shape &s, int precision, int nrhs = 1) {
     auto take_array = [&](int64_t bytes) { return cur.take_array(bytes); };
     // the iteration kernel writes nrhs * kNV partials per block (most blocks
     // with V = 1), the simple-tile kernels up to kSimpleNV
-    // (a persistent run of one right-hand side keeps two sets, by parity)
-    const int64_t nparts = std::max(s.nblk_iter_max() * kNV * std::max(nrhs, 2),
-                                    s.nblk_simple() * kSimpleNV);
+    // (a persistent run keeps two sets, by parity)
+    const int64_t nparts = std::max(s.nblk_iter_max() * kNV * nrhs * 2, s.nblk_simple() * kSimpleNV);
     L.ctl = take(sizeof(Ctl) * nrhs);
     L.sync = take(sizeof(PersistSync));
     L.partials = take(8 * nparts);
@@ -786,17 +785,17 @@ static int persist_chunk(const Ctx &cx, int V) {
     return (int)std::max<int64_t>(1, std::min<int64_t>(want, s.nr));
 }
 
-template <typename T>
+template <typename T, int NR>
 static const void *persist_kernel(int V) {
     constexpr int VW = vec_full<T>();
-    return (V == VW) ? reinterpret_cast<const void *>(&k_pcg_persist<T, kTJ, kRPW, VW>)
-                     : reinterpret_cast<const void *>(&k_pcg_persist<T, kTJ, kRPW, 1>);
+    return (V == VW) ? reinterpret_cast<const void *>(&k_pcg_persist<T, NR, kTJ, kRPW, VW>)
+                     : reinterpret_cast<const void *>(&k_pcg_persist<T, NR, kTJ, kRPW, 1>);
 }
 
-// Whether a PC1 run of one right-hand side goes into one persistent launch
+// Whether a PC1 run of NR right-hand sides goes into one persistent launch
 // (1) or a launch per iteration (0); MAS_EINVAL when the persistent launch
 // was asked for and is not possible.
-template <typename T>
+template <typename T, int NR>
 static int persist_choice(Ctx &cx, const RhsSet<T> &v, int iter0) {
     if (cx.launch == MAS_LAUNCH_PER_ITERATION) return 0;
     const bool forced = cx.launch == MAS_LAUNCH_PERSISTENT;
@@ -804,38 +803,44 @@ static int persist_choice(Ctx &cx, const RhsSet<T> &v, int iter0) {
     if (cx.timing) return no("sample_timing is set");
     const Shape &s = cx.op->s;
     if (!forced && s.n > kPersistAutoCells) return 0;
-    const int V = iter_vec<T>(s.np, 1);
+    const int V = iter_vec<T>(s.np, NR);
     const int64_t nblk = s.nblk_iter(V, persist_chunk(cx, V));
-    if ((int64_t)(std::max(v.max_iter[0], iter0) - iter0 + 1) * nblk >= ((int64_t)1 << 32))
+    int max_iter = iter0;
+    for (int h = 0; h < NR; ++h) max_iter = std::max(max_iter, v.max_iter[h]);
+    if ((int64_t)(max_iter - iter0 + 1) * nblk >= ((int64_t)1 << 32))
         return no("max_iters too large for the barrier counter");
     int dev = 0, coop = 0, ncu = 0, per_cu = 0;
     HIPCHK(hipGetDevice(&dev));
     HIPCHK(hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev));
     if (!coop) return no("the device has no cooperative launch");
     HIPCHK(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
-    HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, persist_kernel<T>(V), kWave * kTJ, 0));
+    HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, persist_kernel<T, NR>(V), kWave * kTJ, 0));
     if ((int64_t)per_cu * ncu < nblk) return no("the iteration kernel's blocks do not fit on the GPU at once");
     return 1;
 }
 
-// A PC1 run of one right-hand side in one cooperative launch of
+// A PC1 run of NR right-hand sides in one cooperative launch of
 // k_pcg_persist: the same control-block set-up, iterations, stopping and
 // results as run_pcg's launches per iteration, bit for bit.
-template <typename T>
+template <typename T, int NR>
 static int run_pcg_persist(Ctx &cx, const RhsSet<T> &v, const T *const c[3], int mode, int iter0,
                            int check_every, PcgResult *res) {
     const mas_op *op = cx.op;
     const Shape &s = op->s;
     hipStream_t st = cx.stream;
-    const double beta0 = v.keep_p[0] ? v.beta0[0] : 0.0;
-    hipLaunchKernelGGL(k_ctl_init, dim3(1), dim3(64), 0, st, cx.ctl, mode, iter0, v.max_iter[0],
-                       v.tol2[0], beta0, v.active[0] ? FLAG_RUN : FLAG_CONV, mode == 0 ? 1 : 0,
-                       check_every);
+    bool work = false;
+    for (int h = 0; h < NR; ++h) {
+        const double beta0 = v.keep_p[h] ? v.beta0[h] : 0.0;
+        hipLaunchKernelGGL(k_ctl_init, dim3(1), dim3(64), 0, st, cx.ctl + h, mode, iter0,
+                           v.max_iter[h], v.tol2[h], beta0, v.active[h] ? FLAG_RUN : FLAG_CONV,
+                           mode == 0 ? 1 : 0, check_every);
+        work = work || (v.active[h] && v.max_iter[h] >= iter0);
+    }
     hipLaunchKernelGGL(k_persist_init, dim3(1), dim3(64), 0, st, cx.sync);
     LAUNCHCHK();
     cx.launched = MAS_LAUNCH_PERSISTENT;
-    if (v.active[0] && v.max_iter[0] >= iter0) {
-        PersistArgs<T> pa{};
+    if (work) {
+        PersistArgs<T, NR> pa{};
         IterArgs<T> &a = pa.it;
         a.cr = c[0];
         a.ct = c[1];
@@ -843,35 +848,37 @@ static int run_pcg_persist(Ctx &cx, const RhsSet<T> &v, const T *const c[3], int
         a.w = op->w;
         a.ctl = cx.ctl;
         a.d = s.dims();
-        const int V = iter_vec<T>(s.np, 1);
+        const int V = iter_vec<T>(s.np, NR);
         const int ch = persist_chunk(cx, V);
         a.tiles_i = s.tiles_i(V, ch);
         a.tiles_k = s.tiles_k(V);
         a.tiles_j = s.tiles_j();
         a.ti = s.ti(V, ch);
         a.nblk = (int)s.nblk_iter(V, ch);
-        a.x[0] = v.x[0];
         a.records = 0;
-        for (int t = 0; t < 2; ++t) {
-            pa.r[t] = v.r[0][t];
-            pa.p[t] = v.p[0][t];
-            pa.q[t] = v.q[0][t];
+        for (int h = 0; h < NR; ++h) {
+            a.x[h] = v.x[h];
+            for (int t = 0; t < 2; ++t) {
+                pa.r[h][t] = v.r[h][t];
+                pa.p[h][t] = v.p[h][t];
+                pa.q[h][t] = v.q[h][t];
+            }
+            pa.keep_p[h] = v.keep_p[h] ? 1 : 0;
         }
         pa.partials[0] = cx.partials;
-        pa.partials[1] = cx.partials + (int64_t)a.nblk * kNV;
+        pa.partials[1] = cx.partials + (int64_t)a.nblk * NR * kNV;
         pa.ctl = cx.ctl;
         pa.sync = cx.sync;
         pa.iter0 = iter0;
-        pa.keep_p = v.keep_p[0] ? 1 : 0;
         int dev = 0, khz = 0;
         HIPCHK(hipGetDevice(&dev));
         HIPCHK(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev));
         pa.wait_ticks = (uint64_t)((double)khz * 1000.0 * kPersistWaitSec);
         void *args[] = {&pa};
-        HIPCHK(hipLaunchCooperativeKernel(persist_kernel<T>(V), dim3((unsigned)a.nblk),
+        HIPCHK(hipLaunchCooperativeKernel(persist_kernel<T, NR>(V), dim3((unsigned)a.nblk),
                                           dim3(kWave * kTJ), args, 0, st));
     }
-    int e = launch_catchup<T, 1>(cx, v, iter0);
+    int e = launch_catchup<T, NR>(cx, v, iter0);
     if (e != MAS_OK) return e;
     PersistSync hs{};
     HIPCHK(hipMemcpyAsync(&hs, cx.sync, sizeof hs, hipMemcpyDeviceToHost, st));
@@ -879,11 +886,13 @@ static int run_pcg_persist(Ctx &cx, const RhsSet<T> &v, const T *const c[3], int
     if (hs.err)
         return fail(MAS_EHIP, "persistent PCG run: a block waited more than %g s at a grid barrier",
                     kPersistWaitSec);
-    Ctl hc;
-    e = read_ctl(cx, &hc);
-    if (e != MAS_OK) return e;
-    res->flag[0] = hc.flag;
-    res->last_iter[0] = (hc.flag == FLAG_RUN) ? v.max_iter[0] : hc.conv_iter;
+    for (int h = 0; h < NR; ++h) {
+        Ctl hc;
+        e = read_ctl(cx, &hc, h);
+        if (e != MAS_OK) return e;
+        res->flag[h] = hc.flag;
+        res->last_iter[h] = (hc.flag == FLAG_RUN) ? v.max_iter[h] : hc.conv_iter;
+    }
     return MAS_OK;
 }
 
@@ -898,10 +907,10 @@ static int run_pcg_persist(Ctx &cx, const RhsSet<T> &v, const T *const c[3], int
 template <typename T, int NR>
 static int run_pcg(Ctx &cx, const RhsSet<T> &v, const T *const c[3], int mode, int iter0,
                    int check_every, PcgResult *res) {
-    if constexpr (NR == 1) {
-        const int pc = persist_choice<T>(cx, v, iter0);
+    {
+        const int pc = persist_choice<T, NR>(cx, v, iter0);
         if (pc < 0) return pc;
-        if (pc == 1) return run_pcg_persist<T>(cx, v, c, mode, iter0, check_every, res);
+        if (pc == 1) return run_pcg_persist<T, NR>(cx, v, c, mode, iter0, check_every, res);
     }
     cx.launched = MAS_LAUNCH_PER_ITERATION;
     const mas_op *op = cx.op;
@@ -2172,8 +2181,6 @@ extern "C" int mas_pcg_solve_multi(const mas_op *op, int32_t nrhs, const double 
     if (o_in) o = *o_in;
     int st = check_opts(op, &o);
     if (st != MAS_OK) return st;
-    if (o.launch == MAS_LAUNCH_PERSISTENT && nrhs > 1)
-        return fail(MAS_EINVAL, "several right-hand sides are launched per iteration, not persistent");
     if (reinterpret_cast<uintptr_t>(work) & 255)
         return fail(MAS_EINVAL, "work must be 256-byte aligned");
     const WorkLayout L = work_layout(op->s, o.precision, nrhs);

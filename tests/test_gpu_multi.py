@@ -100,9 +100,15 @@ def test_deterministic_and_timing():
     p = problem("c0", (0, 0))
     _, op = gpu_operator(p)
     B = to_dev(_rhs(p, 3))
+    # timing samples need the launches per iteration; the untimed run is
+    # launched the same way (the automatic choice here is the persistent
+    # launch, whose chunks sum the dot products in another order)
     a, ia = op.solve_multi(B, S.make_opts(sample_timing=1))
-    b, _ = op.solve_multi(B)
+    b, _ = op.solve_multi(B, S.make_opts(launch="per_iteration"))
     assert torch.equal(a, b)
+    c, ic = op.solve_multi(B)
+    d, _ = op.solve_multi(B)
+    assert torch.equal(c, d) and ic[0]["launch"] == abi.MAS_LAUNCH_PERSISTENT
     assert all(i["iter_kernel_samples"] > 0 and i["iter_kernel_us"] > 0 for i in ia)
 
 
@@ -146,12 +152,12 @@ def test_refined_components_equal_single_refined_solves(shape, precond, refine, 
     p = problem(shape, (0, 0))
     _, op = gpu_operator(p, "fp32_refined")
     B = _rhs(p, m)
-    o = S.make_opts(rtol=1e-10, precision="fp32_refined", precond=precond, refine=refine)
+    # both launched per iteration (the same blocking of the dot products)
+    o = S.make_opts(rtol=1e-10, precision="fp32_refined", precond=precond, refine=refine,
+                    launch="per_iteration")
     X, infos = op.solve_multi(to_dev(B), o, allow_notconv=False)
-    o1 = S.make_opts(rtol=1e-10, precision="fp32_refined", precond=precond, refine=refine,
-                     launch="per_iteration")
     for h in range(m):
-        x1, i1 = op.solve(to_dev(B[h]), o1, allow_notconv=False)
+        x1, i1 = op.solve(to_dev(B[h]), o, allow_notconv=False)
         assert (infos[h]["iters"], infos[h]["outer_iters"]) == (i1["iters"], i1["outer_iters"]), h
         assert torch.equal(X[h], x1), h
 

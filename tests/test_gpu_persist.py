@@ -60,6 +60,36 @@ def test_persistent_equals_per_iteration_refined(shape, refine, chunk):
                 chunk_planes=chunk))
 
 
+@pytest.mark.parametrize("precision", ["fp64", "fp32_refined"])
+@pytest.mark.parametrize("m", [2, 3, 4])
+@pytest.mark.parametrize("shape", [(5, 7, 13), (9, 16, 32), "c0"])
+def test_persistent_several_rhs(shape, m, precision):
+    """Several right-hand sides, one of them zero (it stops at once while the
+    others run on): the same x and counts in both launch modes."""
+    p = problem(shape)
+    _, op = gpu_operator(p, precision)
+    rng = np.random.default_rng(40 + m)
+    B = to_dev(np.stack([rng.standard_normal(p.shape) for _ in range(m)]))
+    B[1].zero_()  # a zero right-hand side stops at once
+    outs = {}
+    for mode in ("per_iteration", "persistent"):
+        X, infos = op.solve_multi(B, S.make_opts(rtol=1e-10, precision=precision, launch=mode,
+                                                 chunk_planes=2))
+        outs[mode] = (X, infos)
+    (Xa, ia), (Xb, ib) = outs["per_iteration"], outs["persistent"]
+    assert torch.equal(Xa, Xb)
+    for h in range(m):
+        assert ia[h]["launch"] == abi.MAS_LAUNCH_PER_ITERATION
+        assert ib[h]["launch"] == abi.MAS_LAUNCH_PERSISTENT
+        for k in ("status", "iters", "outer_iters", "rel_resid_true"):
+            assert ia[h][k] == ib[h][k], (h, k, ia[h][k], ib[h][k])
+    ora = oracle_operator(p)
+    Xh = to_host(Xb)
+    for h in range(m):
+        if h != 1:
+            assert ora.rel_residual(ora.rhs_to_b(to_host(B[h])), Xh[h]) <= 1e-10
+
+
 @pytest.mark.parametrize("k", [0, 1, 2, 3, 6, 7])
 @pytest.mark.parametrize("shape", [(5, 7, 13), "c0"])
 def test_persistent_fixed_iteration_counts(shape, k):
@@ -132,8 +162,6 @@ def test_persistent_requests_refused():
         op.solve(rhs, S.make_opts(launch="persistent", sample_timing=1))
     with pytest.raises(abi.MasError, match="unknown launch mode"):
         op.solve(rhs, S.make_opts(launch=7))
-    with pytest.raises(abi.MasError, match="launched per iteration"):
-        op.solve_multi(torch.stack([rhs, rhs]), S.make_opts(launch="persistent"))
     # one-plane chunks of a grid whose iteration kernel then has more blocks
     # than the GPU holds at once
     q = problem((64, 256, 512))

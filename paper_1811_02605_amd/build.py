@@ -27,6 +27,26 @@ FLAGS = [
 ]
 
 
+C_PROGRAM_SRC = os.path.join(ROOT, "tests", "c_api_solve.c")
+C_PROGRAM = os.path.join(LIBDIR, "libc_api_solve.so")
+ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")
+
+
+def build_c_program(verbose: bool = False) -> str:
+    """The C99 code that solves through include/mas.h with no Python in
+    between (a GPU test calls its c_api_solve_run), as a shared library linked
+    against the library beside it."""
+    cmd = ["gcc", "-std=c99", "-O2", "-Wall", "-Wextra", "-Werror", "-fPIC", "-shared",
+           "-D__HIP_PLATFORM_AMD__",
+           "-I", os.path.join(ROOT, "include"), "-I", os.path.join(ROCM, "include"), C_PROGRAM_SRC,
+           "-L", LIBDIR, "-lmas_hip", "-L", os.path.join(ROCM, "lib"), "-lamdhip64", "-lm",
+           "-Wl,-rpath,$ORIGIN", "-Wl,-rpath," + os.path.join(ROCM, "lib"), "-o", C_PROGRAM]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.run(cmd, check=True)
+    return C_PROGRAM
+
+
 def build_library(verbose: bool = False) -> str:
     os.makedirs(LIBDIR, exist_ok=True)
     tmp = LIB + f".tmp{os.getpid()}"
@@ -41,3 +61,4 @@ def build_library(verbose: bool = False) -> str:
 
 if __name__ == "__main__":
     print(build_library(verbose="-v" in sys.argv))
+    print(build_c_program(verbose="-v" in sys.argv))

@@ -167,3 +167,52 @@ def test_solver_copies_options_instead_of_changing_them():
     assert c.rtol == 1e-8 and c.check_every == 4
     c.rtol = 1.0
     assert o.rtol == 1e-8
+
+
+def test_header_compiles_as_c99(tmp_path):
+    """include/mas.h is a C header: it compiles on its own as strict C99."""
+    import shutil
+    import subprocess
+    gcc = shutil.which("gcc")
+    if gcc is None:
+        pytest.skip("no gcc")
+    src = tmp_path / "use_mas.c"
+    src.write_text('#include "mas.h"\n'
+                   "int main(void) { mas_pcg_opts o; mas_pcg_default_opts(&o);\n"
+                   "  return o.launch == MAS_LAUNCH_AUTO && sizeof(mas_pcg_info) > 0 ? 0 : 1; }\n")
+    r = subprocess.run([gcc, "-std=c99", "-pedantic", "-Wall", "-Wextra", "-Werror",
+                        "-fsyntax-only", "-I", os.path.join(ROOT, "include"), str(src)],
+                       capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr
+
+
+def test_binding_structs_match_the_c_layout(tmp_path):
+    """Every struct the binding mirrors has the size and field offsets the C
+    compiler gives it from include/mas.h."""
+    import shutil
+    import subprocess
+    gcc = shutil.which("gcc")
+    if gcc is None:
+        pytest.skip("no gcc")
+    structs = {"mas_grid": abi.mas_grid, "mas_pcg_opts": abi.mas_pcg_opts,
+               "mas_pcg_info": abi.mas_pcg_info, "mas_sts_opts": abi.mas_sts_opts,
+               "mas_sts_info": abi.mas_sts_info}
+    lines = ['#include <stddef.h>', '#include <stdio.h>', '#include "mas.h"', "int main(void) {"]
+    for name, cls in structs.items():
+        lines.append(f'  printf("{name} size %zu\\n", sizeof({name}));')
+        for field, _ in cls._fields_:
+            lines.append(f'  printf("{name} {field} %zu\\n", offsetof({name}, {field}));')
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run([gcc, "-std=c99", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)],
+                   check=True)
+    got = {}
+    for line in subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.splitlines():
+        name, field, value = line.split()
+        got[(name, field)] = int(value)
+    for name, cls in structs.items():
+        assert got[(name, "size")] == ctypes.sizeof(cls), name
+        for field, _ in cls._fields_:
+            assert got[(name, field)] == getattr(cls, field).offset, (name, field)

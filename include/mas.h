@@ -134,7 +134,9 @@ typedef struct {
  *     With chunk_planes = 0 its r chunks are long enough for about 64
  *     blocks; with the same chunk_planes both modes give the same results
  *     bit for bit (other chunks sum the partial dot products in another
- *     order).
+ *     order).  Its blocks wait for each other at every iteration, at most
+ *     2 s: if kernels of other streams keep part of its blocks from
+ *     starting for longer, the call returns MAS_EHIP instead of hanging.
  *   MAS_LAUNCH_AUTO: persistent where it is possible and the grid has at
  *     most 2^17 cells, per iteration otherwise.
  * PC2 is always launched per iteration. */

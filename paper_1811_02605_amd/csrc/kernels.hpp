@@ -89,6 +89,18 @@ struct Geo {
     int np_one;  // 1 if np == 1 (the phi face joins a cell to itself: no coupling)
 };
 
+// Element i of a table that stays unchanged while kernels run (the geometric
+// factors, written before the first launch).  Read through the constant
+// address space, a load at an index that is the same for the whole wave (a
+// plane's factors) becomes a scalar load: it does not count against the
+// vector-memory counter, so using it does not wait for the vector loads a
+// marching kernel keeps in flight.  The compiler also need not prove that no
+// store of the kernel writes the table.
+template <typename T>
+__device__ inline T ld_table(const T *p, int64_t i) {
+    return ((const __attribute__((address_space(4))) T *)p)[i];
+}
+
 // ---------------------------------------------------------------- reductions
 __device__ inline double wave_sum(double v) {
 #pragma unroll
@@ -1750,10 +1762,12 @@ __global__ __launch_bounds__(kWave *kSimpleJ) void k_fill(T *x, Dims d, T v) {
 // rows wv, wv + 4, ..., one cell per lane) and marches up its r chunk: x and
 // lam of the current plane and the next one sit in LDS with a one-cell ring
 // around the tile (the in-plane neighbours), the plane behind in the
-// registers of the thread that owns the cell, and the plane after the next
-// one is loaded into registers while the current one is computed.  Every
-// value is fetched from memory once per block (the ring from the
-// neighbouring tiles' lines, mostly in L2) and every output written once.
+// registers of the thread that owns the cell.  The two planes after the next
+// one are in flight in two register sets while the current one is computed
+// (a plane's loads are waited for two plane steps after they are issued, so
+// a block keeps two plane patches of requests outstanding).  Every value is
+// fetched from memory once per block (the ring from the neighbouring tiles'
+// lines, mostly in L2) and every output written once.
 constexpr int kGrR = 16, kGrC = 64, kGrWaves = 4, kGrThreads = kWave * kGrWaves;
 constexpr int kGrPR = kGrR + 2, kGrPC = kGrC + 2;  // patch: rows J0-1..J0+R, cells k0-1..k0+C
 constexpr int kGrLoads = (kGrPR * kGrPC + kGrThreads - 1) / kGrThreads;
@@ -1767,7 +1781,7 @@ struct GradArgs {
 };
 
 __global__ __launch_bounds__(kGrThreads) void k_gradient(GradArgs a) {
-    __shared__ double sX[2][kGrPR][kGrPC], sL[2][kGrPR][kGrPC];
+    __shared__ double sX[2][kGrPR][kGrPC], sL[2][kGrPR][kGrPC], sNone[2];
     // per tile row: vt, halves of the theta- and phi-face factors
     __shared__ double sRow[kGrR][4];
     const Dims d = a.d;
@@ -1794,9 +1808,11 @@ __global__ __launch_bounds__(kGrThreads) void k_gradient(GradArgs a) {
         sRow[tid][3] = (ok && !g.np_one) ? 0.5 * g.gpt[jj] : 0.0;
     }
 
-    // this thread's elements of the patch: offsets inside a plane (-1:
-    // outside the grid in theta, read as zero; -2: no element)
+    // this thread's elements of the patch: byte offsets inside a plane, kOOB
+    // for an element outside the grid in theta (read as zero) or none (-2 in
+    // poff: not stored)
     int32_t poff[kGrLoads];
+    uint32_t pb[kGrLoads];
 #pragma unroll
     for (int q = 0; q < kGrLoads; ++q) {
         const int e = tid + q * kGrThreads;
@@ -1808,26 +1824,39 @@ __global__ __launch_bounds__(kGrThreads) void k_gradient(GradArgs a) {
             if (k < 0) k += np;
             poff[q] = (j >= 0 && j < nt) ? j * np + k : -1;
         }
+        pb[q] = poff[q] >= 0 ? (uint32_t)poff[q] * 8u : kOOB;
     }
     const auto RX = win_rsrc(a.x, win), RL = win_rsrc(a.lam, win), RG = win_rsrc(a.gnu, win),
                RH = win_rsrc(a.grhs, win);
+    // planes i0 .. min(i1 + 1, nr) - 1 are loaded into the patch; the
+    // prefetch runs one plane past the last of them and loads nothing there.
+    // The offset is the plane's part plus the element's, with bit 31 (out of
+    // range of every window, which stays below 2^31 bytes) set for a plane
+    // or an element that is not loaded: no branch, so the compiler tracks
+    // the loads in flight exactly.
+    const int m_end = min(i1 + 2, nr);
     auto load_plane = [&](int m, double (&vx)[kGrLoads], double (&vl)[kGrLoads]) {
+        const bool pin = m >= 0 && m < m_end;
+        const uint32_t base = pin ? (uint32_t)((int64_t)(m - win.lo) * d.plane * 8) : 0u;
+        const uint32_t bad = pin ? 0u : kOOB;
 #pragma unroll
         for (int q = 0; q < kGrLoads; ++q) {
-            const bool ok = m >= 0 && m < nr && poff[q] >= 0;
-            const uint32_t o = ok ? (uint32_t)(((int64_t)(m - win.lo) * d.plane + poff[q]) * 8) : kOOB;
+            const uint32_t o = (pb[q] + base) | bad;
             vx[q] = bld<double, 1>(RX, o).v[0];
             vl[q] = bld<double, 1>(RL, o).v[0];
         }
     };
+    // a thread with no element in a patch slot writes a slot of its own
+    // that nothing reads (no branch around the write, so the wait for the
+    // load it writes stands on every path)
     auto store_plane = [&](int m, const double (&vx)[kGrLoads], const double (&vl)[kGrLoads]) {
         double *fx = &sX[m & 1][0][0], *fl = &sL[m & 1][0][0];
 #pragma unroll
-        for (int q = 0; q < kGrLoads; ++q)
-            if (poff[q] != -2) {
-                fx[tid + q * kGrThreads] = vx[q];
-                fl[tid + q * kGrThreads] = vl[q];
-            }
+        for (int q = 0; q < kGrLoads; ++q) {
+            const bool el = poff[q] != -2;
+            *(el ? &fx[tid + q * kGrThreads] : &sNone[0]) = vx[q];
+            *(el ? &fl[tid + q * kGrThreads] : &sNone[1]) = vl[q];
+        }
     };
     constexpr int NQ = kGrR / kGrWaves;
     // own cells: rows wv + 4q, column lane; x and lam of the plane behind
@@ -1840,26 +1869,32 @@ __global__ __launch_bounds__(kGrThreads) void k_gradient(GradArgs a) {
         xb[q] = bld<double, 1>(RX, o).v[0];
         lb[q] = bld<double, 1>(RL, o).v[0];
     }
+    // two register sets, alternating by the parity of the step: planes i0
+    // and i0 + 1 go to the patch, plane i0 + 2 waits in the first set
+    double ax[kGrLoads], al[kGrLoads], bx[kGrLoads], bl[kGrLoads];
     {
         double vx[kGrLoads], vl[kGrLoads];
         load_plane(i0, vx, vl);
+        load_plane(i0 + 1, bx, bl);
+        load_plane(i0 + 2, ax, al);
         store_plane(i0, vx, vl);
-        load_plane(i0 + 1, vx, vl);
-        store_plane(i0 + 1, vx, vl);
+        store_plane(i0 + 1, bx, bl);
     }
     __syncthreads();
 
-    double nx[kGrLoads], nl[kGrLoads];
-    for (int m = i0; m < i1; ++m) {
-        // the plane after the next one in flight while plane m is computed
-        load_plane(m + 2, nx, nl);
+    // plane step m: computes plane m from the patch slots of m and m + 1,
+    // then moves plane m + 2 (loaded two steps earlier into `ready`) into the
+    // slot plane m leaves; plane m + 3 is issued into `fill` first
+    auto step = [&](int m, double (&ready_x)[kGrLoads], double (&ready_l)[kGrLoads],
+                    double (&fill_x)[kGrLoads], double (&fill_l)[kGrLoads]) {
+        load_plane(m + 3, fill_x, fill_l);
         const int s0 = m & 1, s1 = (m + 1) & 1;
         // plane factors (uniform)
-        const double gq = g.gq[m];
-        const double grp = (m < nr - 1) ? 0.5 * g.gr[m] : 0.0;
-        const double grm = (m > 0) ? 0.5 * g.gr[m - 1] : 0.0;
+        const double gq = ld_table(g.gq, m);
+        const double grp = (m < nr - 1) ? 0.5 * ld_table(g.gr, m) : 0.0;
+        const double grm = (m > 0) ? 0.5 * ld_table(g.gr, m - 1) : 0.0;
         const double gw = ((m == 0) ? g.gw_in : 0.0) + ((m == nr - 1) ? g.gw_out : 0.0);
-        const double vr = g.vr[m];
+        const double vr = ld_table(g.vr, m);
 #pragma unroll
         for (int q = 0; q < NQ; ++q) {
             const int r = wv + kGrWaves * q;
@@ -1888,8 +1923,12 @@ __global__ __launch_bounds__(kGrThreads) void k_gradient(GradArgs a) {
             lb[q] = lc;
         }
         __syncthreads();  // every read of plane m's slot is done
-        store_plane(m + 2, nx, nl);
+        store_plane(m + 2, ready_x, ready_l);
         __syncthreads();
+    };
+    for (int m = i0; m < i1; m += 2) {
+        step(m, ax, al, bx, bl);
+        if (m + 1 < i1) step(m + 1, bx, bl, ax, al);
     }
 }
 

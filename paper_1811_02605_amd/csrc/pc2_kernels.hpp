@@ -116,8 +116,11 @@ template <int CTRL, int ROWS, bool RESCALE>
 __device__ inline void mobius_step(Mob &P) {
     const double q00 = dpp_or<CTRL, ROWS>(P.m00, 1.0), q01 = dpp_or<CTRL, ROWS>(P.m01, 0.0);
     const double q10 = dpp_or<CTRL, ROWS>(P.m10, 0.0), q11 = dpp_or<CTRL, ROWS>(P.m11, 1.0);
-    const double r00 = P.m00 * q00 + P.m01 * q10, r01 = P.m00 * q01 + P.m01 * q11;
-    const double r10 = P.m10 * q00 + P.m11 * q10, r11 = P.m10 * q01 + P.m11 * q11;
+    // each entry a sum of two products, the first fused: written out, so
+    // that the rounding does not depend on which product the compiler would
+    // fuse in a given context
+    const double r00 = fma(P.m00, q00, P.m01 * q10), r01 = fma(P.m00, q01, P.m01 * q11);
+    const double r10 = fma(P.m10, q00, P.m11 * q10), r11 = fma(P.m10, q01, P.m11 * q11);
     if constexpr (RESCALE) {
         const double m = fmax(fmax(fabs(r00), fabs(r01)), fmax(fabs(r10), fabs(r11)));
         const int ex = (m > 0.0) ? ilogb(m) : 0;
@@ -145,10 +148,25 @@ __device__ inline Mob mobius_scan(Mob P) {
 //     d_k = s_k - cp_{k-1,k}^2 / d_{k-1},   s_k = 1 - (r and theta terms),
 // is the composition of the maps d -> (s_k d - cp^2) / d, solved by a prefix
 // scan of their matrices [s_k, -cp^2; 1, 0] (the first lane of a block has
-// no phi term: [s_0, 0; 1, 0], which gives d_0 = s_0 from any start).  Each
-// row's couplings are loaded one plane (eight rows) before it is scanned.
+// no phi term: [s_0, 0; 1, 0], which gives d_0 = s_0 from any start).
+// Each row's couplings are loaded one plane (eight rows) before it is
+// scanned, into one of two register sets that alternate by plane.  Every
+// access goes through a buffer resource over one r plane, and whatever is
+// not there (the -r coupling of the block's first plane, the -theta one of
+// its first row, the -phi one of its first lane, lanes and rows past the
+// grid, planes past the block) has bit 31 set in its offset or a resource of
+// size zero: it reads zero or is not stored.  The loop body has no branch:
+// a missing coupling enters as 0 against a previous d of 1, which leaves s_k
+// unchanged bit for bit (1 - 0 * 0 / 1 = 1); lanes past the grid are the
+// highest ones, and the scan only moves values to higher lanes, so their
+// maps never reach a lane in the grid; planes are taken in pairs, the
+// second of an odd last pair storing nothing.  So the compiler waits for
+// each plane's loads only where they are used.
 struct Pc2Fac {
     double cr, ct, cp;
+};
+struct Pc2FacPlane {
+    __amdgpu_buffer_rsrc_t cr, ct, cp;  // cr over the plane below, ct and cp over this one
 };
 
 template <typename TOUT>
@@ -157,54 +175,80 @@ __global__ __launch_bounds__(kWave) void k_pc2_factor(Pc2Args<double> a, TOUT *d
     const int blk = blockIdx.x;
     const int bk = blk % a.nbk, bj = (blk / a.nbk) % a.nbj, bi = blk / (a.nbk * a.nbj);
     const int lane = threadIdx.x;
-    const int k0 = bk * kPc2K;
+    const int I0 = bi * kPc2I, J0 = bj * kPc2J, k0 = bk * kPc2K;
     const int kn = min(kPc2K, dm.np - k0);
     const bool act = lane < kn;
-    const int k = k0 + (act ? lane : 0);
-    const int ni = min(kPc2I, dm.nr - bi * kPc2I), nj = min(kPc2J, dm.nt - bj * kPc2J);
-    auto cell = [&](int ii, int jj) -> int64_t {
-        return ((int64_t)(bi * kPc2I + ii) * dm.nt + (bj * kPc2J + jj)) * dm.np + k;
+    const int ni = min(kPc2I, dm.nr - I0), nj = min(kPc2J, dm.nt - J0);
+    // r planes hold fewer than 2^31 / 8 bytes: cell offsets in a plane stay
+    // below bit 31
+    const uint32_t pbytes = (uint32_t)(dm.plane * 8);
+    const uint32_t lbad = act ? 0u : kOOB;
+    const uint32_t pbad = (act && lane > 0) ? 0u : kOOB;
+    // this lane's cell of block row jj in a plane, and the bad bit of the row
+    auto cell = [&](int jj) -> int { return (J0 + jj) * dm.np + k0 + lane; };
+    auto rbad = [&](int jj) -> uint32_t { return (jj < nj ? 0u : kOOB) | lbad; };
+    auto plane_rsrc = [&](int ii) {
+        const bool in = ii < ni;
+        const int m = min(I0 + ii, dm.nr - 1), mb = max(I0 + ii - 1, 0);
+        return Pc2FacPlane{make_rsrc(a.cr + (int64_t)mb * dm.plane, (in && ii > 0) ? pbytes : 0u),
+                           make_rsrc(a.ct + (int64_t)m * dm.plane, in ? pbytes : 0u),
+                           make_rsrc(a.cp + (int64_t)m * dm.plane, in ? pbytes : 0u)};
     };
-    auto load = [&](int ii, int jj) {
-        Pc2Fac v{0.0, 0.0, 0.0};
-        if (act && ii < ni && jj < nj) {
-            const int64_t c = cell(ii, jj);
-            if (ii > 0) v.cr = a.cr[c - dm.plane];
-            if (jj > 0) v.ct = a.ct[c - dm.np];
-            if (lane > 0) v.cp = a.cp[c - 1];
-        }
+    auto load = [&](const Pc2FacPlane &R, int jj) {
+        const int c = cell(jj);
+        const uint32_t bad = rbad(jj);
+        Pc2Fac v;
+        v.cr = bld<double, 1>(R.cr, ((uint32_t)c * 8u) | bad).v[0];
+        v.ct = bld<double, 1>(R.ct, ((uint32_t)(c - dm.np) * 8u) | bad | (jj > 0 ? 0u : kOOB)).v[0];
+        v.cp = bld<double, 1>(R.cp, ((uint32_t)(c - 1) * 8u) | bad | pbad).v[0];
         return v;
     };
     double dp[kPc2J];  // d of the previous r plane of the block, per theta row
 #pragma unroll
     for (int jj = 0; jj < kPc2J; ++jj) dp[jj] = 1.0;
-    // q[jj]: the couplings of row jj of the current plane; once a row has
-    // taken them, the same row of the next plane is loaded into its slot, a
-    // whole plane of rows (eight scans) before it is needed
-    Pc2Fac q[kPc2J];
-#pragma unroll
-    for (int jj = 0; jj < kPc2J; ++jj) q[jj] = load(0, jj);
-    for (int ii = 0; ii < ni; ++ii) {
+    // plane ii: rows from `cur`, the rows of plane ii + 1 issued into `nxt`
+    auto plane_step = [&](int ii, const Pc2Fac (&cur)[kPc2J], Pc2Fac (&nxt)[kPc2J]) {
+        const Pc2FacPlane Rn = plane_rsrc(ii + 1);
+        const auto Rd = make_rsrc(dout + (int64_t)min(I0 + ii, dm.nr - 1) * dm.plane,
+                                  ii < ni ? (uint32_t)(dm.plane * (int64_t)sizeof(TOUT)) : 0u);
         double drow = 1.0;  // d of the previous theta row
 #pragma unroll
         for (int jj = 0; jj < kPc2J; ++jj) {
-            if (jj < nj) {
-                const Pc2Fac cur = q[jj];
-                q[jj] = load(ii + 1, jj);
-                Mob P{1.0, 0.0, 0.0, 1.0};
-                if (act) {
-                    double sk = 1.0;
-                    if (ii > 0) sk -= cur.cr * cur.cr / dp[jj];
-                    if (jj > 0) sk -= cur.ct * cur.ct / drow;
-                    P = Mob{sk, -(cur.cp * cur.cp), 1.0, 0.0};
-                }
-                P = mobius_scan(P);
-                const double dv = (P.m00 + P.m01) / (P.m10 + P.m11);  // the map of d = 1
-                if (act) dout[cell(ii, jj)] = (TOUT)dv;
-                dp[jj] = dv;
-                drow = dv;
-            }
+            const Pc2Fac c = cur[jj];
+            nxt[jj] = load(Rn, jj);
+            // keeps the loads here: the scheduler would otherwise sink them
+            // towards their use a plane later, where they would be waited for
+            // right after being issued
+            __builtin_amdgcn_sched_barrier(0);
+            double sk = 1.0;
+            sk -= c.cr * c.cr / dp[jj];  // no -r neighbour in the block: 0
+            sk -= c.ct * c.ct / drow;    // no -theta neighbour: 0
+            Mob P{sk, -(c.cp * c.cp), 1.0, 0.0};
+            P = mobius_scan(P);
+            const double dv = (P.m00 + P.m01) / (P.m10 + P.m11);  // the map of d = 1
+            bst<TOUT, 1>(Rd, ((uint32_t)cell(jj) * (uint32_t)sizeof(TOUT)) | rbad(jj),
+                         VecT<TOUT, 1>{{(TOUT)dv}});
+            dp[jj] = dv;
+            drow = dv;
         }
+    };
+    Pc2Fac qa[kPc2J], qb[kPc2J];
+    {
+        const Pc2FacPlane R0 = plane_rsrc(0);
+#pragma unroll
+        for (int jj = 0; jj < kPc2J; ++jj) qa[jj] = load(R0, jj);
+        // the first plane's rows are waited for here, once per block (an
+        // empty statement that takes them as register operands: the
+        // compiler waits for their loads before it): the loop is then
+        // entered with no loads in flight, and the waits the compiler
+        // places in it are those of its own loads, a plane after issue
+#pragma unroll
+        for (int jj = 0; jj < kPc2J; ++jj)
+            asm volatile("" ::"v"(qa[jj].cr), "v"(qa[jj].ct), "v"(qa[jj].cp));
+    }
+    for (int ii = 0; ii < ni; ii += 2) {
+        plane_step(ii, qa, qb);
+        plane_step(ii + 1, qb, qa);
     }
 }
 

@@ -1793,8 +1793,8 @@ __global__ __launch_bounds__(kGrThreads) void k_gradient(GradArgs a) {
     const int J0 = jt * kGrR, k0 = kt * kGrC;
     const int nseg = min(kGrC, np - k0);
     const int i0 = it * a.ti, i1 = min(i0 + a.ti, nr);
-    // planes i0 - 1 .. i1 + 1 are read, planes i0 .. i1 - 1 written
-    const PlaneWin win = plane_win(d, i0 - 1, i1 + 2);
+    // planes i0 - 1 .. i1 are read, planes i0 .. i1 - 1 written
+    const PlaneWin win = plane_win(d, i0 - 1, i1 + 1);
     const int tid = threadIdx.x, lane = tid & (kWave - 1);
     const int wv = __builtin_amdgcn_readfirstlane(tid / kWave);
 
@@ -1828,13 +1828,14 @@ __global__ __launch_bounds__(kGrThreads) void k_gradient(GradArgs a) {
     }
     const auto RX = win_rsrc(a.x, win), RL = win_rsrc(a.lam, win), RG = win_rsrc(a.gnu, win),
                RH = win_rsrc(a.grhs, win);
-    // planes i0 .. min(i1 + 1, nr) - 1 are loaded into the patch; the
-    // prefetch runs one plane past the last of them and loads nothing there.
+    // planes i0 .. min(i1, nr - 1) are loaded into the patch (plane i1, the
+    // +r neighbour of the last plane computed, is the last one used); the
+    // prefetch runs past them and loads nothing there.
     // The offset is the plane's part plus the element's, with bit 31 (out of
     // range of every window, which stays below 2^31 bytes) set for a plane
     // or an element that is not loaded: no branch, so the compiler tracks
     // the loads in flight exactly.
-    const int m_end = min(i1 + 2, nr);
+    const int m_end = min(i1 + 1, nr);
     auto load_plane = [&](int m, double (&vx)[kGrLoads], double (&vl)[kGrLoads]) {
         const bool pin = m >= 0 && m < m_end;
         const uint32_t base = pin ? (uint32_t)((int64_t)(m - win.lo) * d.plane * 8) : 0u;

@@ -3,9 +3,9 @@
 addresses a block's r planes with 32-bit offsets from the block's first
 plane, so cells past the 2 GiB mark of an array must come out exactly as
 below it.  Checked through what the FP64 oracle computes at any size: its
-residual of the GPU solutions (FP64 PCG and FP32/FP64 refinement), its
-gradient formula at the GPU's x and lambda, and its RKL2 step (both the
-two-stage and the one-stage kernels) on every cell."""
+residual of the GPU solutions (FP64 PCG, FP32/FP64 refinement, and PC2 in
+both), its gradient formula at the GPU's x and lambda, and its RKL2 step
+(both the two-stage and the one-stage kernels) on every cell."""
 import sys
 
 import numpy as np
@@ -63,6 +63,31 @@ def test_large_grid_fp64_and_refined_solves(big, big_oracle):
     # the reported FP64 residual is the oracle's up to rounding
     floor = residual_rounding_floor(big_oracle, b, x64)
     assert abs(i64["rel_resid_true"] - r64) <= floor, (i64["rel_resid_true"], r64, floor)
+
+
+@pytest.mark.timeout(600)
+def test_large_grid_pc2_solves(big, big_oracle):
+    """PC2 (block ILU(0) factor and block solves, ragged blocks in theta and
+    phi) in FP64 and inside refinement: the factor and the solve address each
+    r plane through its own resource, so planes past the 2 GiB mark must
+    come out as below it."""
+    grid = S.Grid.from_problem(big)
+    op = S.Operator(grid, to_dev(big.nu), big.dt, precision="fp32_refined")
+    rhs = to_dev(big.rhs)
+    xs = {}
+    for prec in ("fp64", "fp32_refined"):
+        x, info = op.solve(rhs, S.make_opts(rtol=1e-10, precond="pc2", precision=prec),
+                           allow_notconv=False)
+        say(f"large PC2 solve ({prec}): {info['iters']} iterations, {info['outer_iters']} outer, "
+            f"{info['seconds']:.3f} s")
+        xs[prec] = to_host(x)
+    del op, rhs
+    torch.cuda.empty_cache()
+    b = big_oracle.rhs_to_b(big.rhs)
+    for prec, x in xs.items():
+        r = big_oracle.rel_residual(b, x)
+        say(f"large PC2 ({prec}) oracle residual {r:.3e}")
+        assert r <= 1e-10, prec
 
 
 @pytest.mark.timeout(600)

@@ -179,7 +179,8 @@ __global__ __launch_bounds__(kWave) void k_pc2_factor(Pc2Args<double> a, TOUT *d
     const int kn = min(kPc2K, dm.np - k0);
     const bool act = lane < kn;
     const int ni = min(kPc2I, dm.nr - I0), nj = min(kPc2J, dm.nt - J0);
-    // r planes hold fewer than 2^31 / 8 bytes: cell offsets in a plane stay
+    // an r plane of one array holds fewer than 2^31 / 7 bytes (the grid
+    // check keeps seven planes below 2 GiB): byte offsets of its cells stay
     // below bit 31
     const uint32_t pbytes = (uint32_t)(dm.plane * 8);
     const uint32_t lbad = act ? 0u : kOOB;

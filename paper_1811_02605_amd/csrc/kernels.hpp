@@ -1884,8 +1884,9 @@ __global__ __launch_bounds__(kGrThreads) void k_gradient(GradArgs a) {
     __syncthreads();
 
     // plane step m: computes plane m from the patch slots of m and m + 1,
-    // then moves plane m + 2 (loaded two steps earlier into `ready`) into the
-    // slot plane m leaves; plane m + 3 is issued into `fill` first
+    // then moves plane m + 2 (issued into `ready` at the start of the step
+    // before) into the slot plane m leaves; plane m + 3 is issued into
+    // `fill` first
     auto step = [&](int m, double (&ready_x)[kGrLoads], double (&ready_l)[kGrLoads],
                     double (&fill_x)[kGrLoads], double (&fill_l)[kGrLoads]) {
         load_plane(m + 3, fill_x, fill_l);
